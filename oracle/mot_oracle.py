@@ -1,0 +1,309 @@
+"""Plain FP64 CPU oracle of the qHP TD-PMCHWT marching-on-in-time scheme.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this module; the solver library
+never does, and this module imports nothing from it.
+
+Every function follows one passage of the paper (Le, Muenger, Andriulli,
+Cools, "A Stable, Accurate, and Well-Conditioned Time-Domain PMCHWT
+Formulation"):
+
+* incidence matrices Lambda, Sigma ......... Section IV (opening)
+* quasi-Helmholtz projectors ............... Section IV-B (projector defs)
+* static preconditioner, loop-star form .... Section III, eq. (CP)
+* media sum of the PMCHWT blocks ........... Section II, eq. (PMCHWT)
+* lag matrices Q_i = Q^ll + Q^ls + Q^sl + Q^ss and the truncations
+  ............................................. Section V-B
+* right-hand side, loop and star parts ..... Section V-C, eq. (rhs), (hin)
+* marching-on-in-time recurrence ........... Section V-A, eq. (MOT)
+* current recovery, loop/star kept apart ... Section V-A, eq. (dis_jm)
+
+Dense linear algebra throughout: pseudo-inverses by numpy.linalg.pinv, G^-1
+and Q_0^-1 by LU (scipy.linalg), no blocking or fusion.
+
+Readings where the paper is silent (also listed in the design notes):
+* exterior c = eta = 1; interior c' = 1/sqrt(eps_r mu_r), eta' = sqrt(mu_r/eps_r);
+* D = largest vertex distance, T_max = D / min(c, c'), k_max = ceil(T_max/dt);
+* the raw hat and tilde blocks arrive without their T_max, 1/T_max factors;
+* RWG testing of the incident field uses the 7-point degree-5 triangle rule;
+* the star part of the RHS is set to zero once the pulse has passed every
+  point of the surface: t > t0 + (max_x k.x + 1.6 w)/c (erfc(6.4) ~ 1e-19).
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+import scipy.linalg as sla
+from scipy.special import erf, erfc
+
+__all__ = [
+    "medium", "time_constants", "incidence", "projectors", "preconditioner",
+    "media_sum", "lag_matrices", "tri_rule7", "tested_fields", "rhs",
+    "march", "recover", "Oracle", "block_toeplitz_solve", "star_cut",
+]
+
+
+# ------------------------------------------------------------------ media ---
+def medium(eps_r, mu_r):
+    """Section II: eta = sqrt(mu/eps), c = 1/sqrt(mu eps) per medium."""
+    return 1.0, 1.0, 1.0 / math.sqrt(eps_r * mu_r), math.sqrt(mu_r / eps_r)
+
+
+def time_constants(V, dt, eps_r, mu_r):
+    """Section IV-C eq. (alpha): T_max = D / c_min; Section V-B: k_max = ceil(T_max/dt)."""
+    V = np.asarray(V, dtype=np.float64)
+    diff = V[:, None, :] - V[None, :, :]
+    D = float(np.sqrt((diff ** 2).sum(-1)).max())
+    _, _, cp, _ = medium(eps_r, mu_r)
+    Tmax = D / min(1.0, cp)
+    kmax = int(math.ceil(Tmax / dt - 1e-12))
+    return D, Tmax, kmax
+
+
+# ------------------------------------------------------------- incidence ---
+def incidence(E, nv, nf):
+    """Section IV: Lambda[m, v] = +1 at v_plus, -1 at v_minus;
+    Sigma[m, f] = +1 at c_plus, -1 at c_minus."""
+    E = np.asarray(E)
+    ne = E.shape[0]
+    Lam = np.zeros((ne, nv))
+    Sig = np.zeros((ne, nf))
+    for m in range(ne):
+        Lam[m, E[m, 1]] += 1.0
+        Lam[m, E[m, 0]] -= 1.0
+        Sig[m, E[m, 2]] += 1.0
+        Sig[m, E[m, 3]] -= 1.0
+    return Lam, Sig
+
+
+def projectors(Lam, Sig):
+    """Section IV-B: P^Sigma = Sigma (Sigma^T Sigma)^+ Sigma^T, P^{Lambda H} = I - P^Sigma
+    (RWG space); PP^Lambda = Lambda (Lambda^T Lambda)^+ Lambda^T, PP^{Sigma H} = I - PP^Lambda
+    (BC space)."""
+    ne = Lam.shape[0]
+    I = np.eye(ne)
+    PS = Sig @ np.linalg.pinv(Sig.T @ Sig) @ Sig.T
+    BL = Lam @ np.linalg.pinv(Lam.T @ Lam) @ Lam.T
+    return dict(PS=PS, PL=I - PS, BL=BL, BSH=I - BL)
+
+
+def preconditioner(T0s, T0h, G, P):
+    """Section III eq. (CP): T^{Sigma H} = PP^{Sigma H} T0s PP^{Sigma H},
+    T^Lambda = PP^Lambda T0h PP^Lambda.  The left factors of the lag matrices
+    (Section V-B) and of the RHS (Section V-C):
+        C1 = T^{Sigma H} G^-1,   C2 = T^Lambda G^-1 P^{Lambda H}."""
+    Tsh = P["BSH"] @ T0s @ P["BSH"]
+    Tl = P["BL"] @ T0h @ P["BL"]
+    lu = sla.lu_factor(G)
+    Ginv = sla.lu_solve(lu, np.eye(G.shape[0]))
+    C1 = Tsh @ Ginv
+    C2 = Tl @ Ginv @ P["PL"]
+    return dict(Tsh=Tsh, Tl=Tl, Ginv=Ginv, C1=C1, C2=C2)
+
+
+def media_sum(T_ext, T_int, K_ext, K_int, eta, etap):
+    """Section II eq. (PMCHWT) block pattern with both media:
+    [[eta T + eta' T', -(K + K')], [K + K', T/eta + T'/eta']]."""
+    M1 = eta * T_ext + etap * T_int
+    M2 = T_ext / eta + T_int / etap
+    Ks = K_ext + K_int
+    return np.block([[M1, -Ks], [Ks, M2]])
+
+
+def blk(X):
+    """Block-wise action on the (j; m) halves: diag(X, X)."""
+    Z = np.zeros_like(X)
+    return np.block([[X, Z], [Z, X]])
+
+
+def lag_matrices(raw, pre, P, eps_r, mu_r, Tmax, kmax):
+    """Section V-B: Q_i for i = 0 .. k_max + 1,
+
+        Q_i^ll = C1 Z_i^h  P^{Lambda H}      (h family, i <= k_max)
+        Q_i^ls = C1 Z_i^hat P^Sigma          (hat family times T_max, i <= k_max + 1)
+        Q_i^ss = C2 Z_i^h  P^Sigma           (h family, i <= k_max)
+        Q_i^sl = C2 Z_i^til P^{Lambda H}     (tilde family over T_max, i <= k_max - 1,
+                                              truncated beyond as the paper enforces)
+    each acting block-wise on the (u; v) halves.
+    raw[medium][name] has shape (nlags, ne, ne), name in T_h, K_h, T_hat, K_hat,
+    T_tilde, K_tilde; medium in ext, int.
+    """
+    _, eta, _, etap = medium(eps_r, mu_r)
+    ne = pre["C1"].shape[0]
+    n = 2 * ne
+    C1b, C2b = blk(pre["C1"]), blk(pre["C2"])
+    PLb, PSb = blk(P["PL"]), blk(P["PS"])
+
+    def Z(fam, i, limit, scale):
+        if i > limit or i >= raw["ext"]["T_" + fam].shape[0]:
+            return np.zeros((n, n))
+        return scale * media_sum(raw["ext"]["T_" + fam][i], raw["int"]["T_" + fam][i],
+                                 raw["ext"]["K_" + fam][i], raw["int"]["K_" + fam][i], eta, etap)
+
+    Q = []
+    for i in range(kmax + 2):
+        Zh = Z("h", i, kmax, 1.0)
+        Zhat = Z("hat", i, kmax + 1, Tmax)
+        Ztil = Z("tilde", i, kmax - 1, 1.0 / Tmax)
+        Q.append(C1b @ (Zh @ PLb + Zhat @ PSb) + C2b @ (Zh @ PSb + Ztil @ PLb))
+    return Q
+
+
+# ------------------------------------------------------------------- RHS ---
+def tri_rule7():
+    """Radon's 7-point degree-5 rule on a triangle (barycentric, weights sum 1)."""
+    s = math.sqrt(15.0)
+    a, b = (6 - s) / 21, (6 + s) / 21
+    wa, wb = (155 - s) / 1200, (155 + s) / 1200
+    L = [(1 / 3, 1 / 3, 1 / 3)]
+    W = [9 / 40]
+    for x, w in ((a, wa), (b, wb)):
+        L += [(1 - 2 * x, x, x), (x, 1 - 2 * x, x), (x, x, 1 - 2 * x)]
+        W += [w, w, w]
+    return np.array(L), np.array(W)
+
+
+def _erf_diff(s1, s0):
+    """erf(s1) - erf(s0) without cancellation in the tails."""
+    out = np.empty_like(s1)
+    pos = s0 >= 0
+    neg = s1 <= 0
+    mid = ~(pos | neg)
+    out[pos] = erfc(s0[pos]) - erfc(s1[pos])
+    out[neg] = erfc(-s1[neg]) - erfc(-s0[neg])
+    out[mid] = erf(s1[mid]) - erf(s0[mid])
+    return out
+
+
+def star_cut(V, wave):
+    """Time after which the star RHS is truncated (Section V-C)."""
+    kx = np.asarray(V) @ wave.dir
+    return wave.t0 + (kx.max() + 1.6 * wave.width) / 1.0
+
+
+def tested_fields(V, F, E, waves, dt, k):
+    """Section II (RHS vectors) and Section V-C (eq. rhs, hin), at step k:
+
+        ebar_k = (1/dt) int_{(k-1)dt}^{k dt} (e; h)(t) dt     (loop part, p_k testing)
+        Ebar_k = int_{-inf}^{k dt} (e; h)(t) dt                 (star part, delta_k testing)
+
+    with [e(t)]_m = <n x f_m, e_in x n> = -<f_m, e_in> and likewise h with
+    h_in = k x e_in / eta.  The Gaussian time integral is closed-form:
+    int_{-inf}^t e_in = A/(2c) p (1 + erf s),  s = (4/w)(c (t - t0) - k.x).
+    Returns ebar, Ebar of shape (2 ne, R); Ebar is zeroed after star_cut.
+    """
+    V = np.asarray(V, dtype=np.float64)
+    F = np.asarray(F)
+    E = np.asarray(E)
+    ne = E.shape[0]
+    L, W = tri_rule7()
+    R = len(waves)
+    ebar = np.zeros((2 * ne, R))
+    Ebar = np.zeros((2 * ne, R))
+    for m in range(ne):
+        for side, sgn in ((2, 1.0), (3, -1.0)):
+            f = E[m, side]
+            tv = V[F[f]]
+            area = 0.5 * np.linalg.norm(np.cross(tv[1] - tv[0], tv[2] - tv[0]))
+            opp = [v for v in F[f] if v != E[m, 0] and v != E[m, 1]][0]
+            X = L @ tv                                     # quadrature points
+            fm = sgn * (X - V[opp]) / (2 * area)           # RWG values (Section II)
+            for r, wv in enumerate(waves):
+                c = 1.0
+                s1 = (4 / wv.width) * (c * (k * dt - wv.t0) - X @ wv.dir)
+                s0 = (4 / wv.width) * (c * ((k - 1) * dt - wv.t0) - X @ wv.dir)
+                amp = wv.amp / (2 * c)
+                ep = wv.pol
+                hp = np.cross(wv.dir, wv.pol)             # eta = 1
+                te = amp * _erf_diff(s1, s0) / dt          # time average over the step
+                tE = amp * erfc(-s1)                       # running integral
+                if k * dt > star_cut(V, wv):
+                    tE = np.zeros_like(tE)
+                wq = W * area
+                ebar[m, r] += -np.sum(wq * te * (fm @ ep))
+                ebar[ne + m, r] += -np.sum(wq * te * (fm @ hp))
+                Ebar[m, r] += -np.sum(wq * tE * (fm @ ep))
+                Ebar[ne + m, r] += -np.sum(wq * tE * (fm @ hp))
+    return ebar, Ebar
+
+
+def rhs(pre, Tmax, ebar, Ebar):
+    """Section V-C eq. (rhs): r = C1 ebar + (1/T_max) C2 Ebar, block-wise."""
+    return blk(pre["C1"]) @ ebar + blk(pre["C2"]) @ Ebar / Tmax
+
+
+# ------------------------------------------------------------------ march ---
+def march(Q, rhs_vectors):
+    """Section V-A eq. (MOT): Q_0 w_i = r_i - sum_{k=1}^{i-1} Q_k w_{i-k},
+    with Q_k = 0 beyond the last stored lag.  rhs_vectors: (N_t, n, R)."""
+    Nt = rhs_vectors.shape[0]
+    lu = sla.lu_factor(Q[0])
+    W = np.zeros_like(rhs_vectors)
+    for i in range(Nt):                      # step i+1 in the paper's numbering
+        b = rhs_vectors[i].copy()
+        for k in range(1, min(i, len(Q) - 1) + 1):
+            b -= Q[k] @ W[i - k]
+        W[i] = sla.lu_solve(lu, b)
+    return W
+
+
+def block_toeplitz_solve(Q, rhs_vectors):
+    """The whole lower block-triangular Toeplitz system eq. (fulldis_PMCHWT)
+    assembled and solved at once (tiny problems only)."""
+    Nt, n, R = rhs_vectors.shape
+    A = np.zeros((Nt * n, Nt * n))
+    for i in range(Nt):
+        for j in range(i + 1):
+            k = i - j
+            if k < len(Q):
+                A[i * n:(i + 1) * n, j * n:(j + 1) * n] = Q[k]
+    x = np.linalg.solve(A, rhs_vectors.reshape(Nt * n, R))
+    return x.reshape(Nt, n, R)
+
+
+def recover(P, Tmax, dt, W):
+    """Section V-A eq. (dis_jm), loop and star parts kept apart:
+    j_i^loop = P^{Lambda H} u_i,  j_i^star = (T_max/dt) P^Sigma (u_i - u_{i-1}),
+    u_0 = 0; the same for m from v.  W: (N_t, 2 ne, R)."""
+    ne = P["PS"].shape[0]
+    Nt = W.shape[0]
+    prev = np.zeros_like(W[0])
+    loop = np.zeros_like(W)
+    star = np.zeros_like(W)
+    for i in range(Nt):
+        for h in (slice(0, ne), slice(ne, 2 * ne)):
+            loop[i, h] = P["PL"] @ W[i, h]
+            star[i, h] = (Tmax / dt) * (P["PS"] @ (W[i, h] - prev[h]))
+        prev = W[i]
+    return loop, star
+
+
+# ------------------------------------------------------------ convenience ---
+class Oracle:
+    """All oracle stages for one problem dict (see fixture.problem)."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        V, F, E = prob["V"], prob["F"], prob["E"]
+        self.D, self.Tmax, self.kmax = time_constants(V, prob["dt"], prob["eps_r"], prob["mu_r"])
+        Lam, Sig = incidence(E, V.shape[0], F.shape[0])
+        self.Lam, self.Sig = Lam, Sig
+        self.P = projectors(Lam, Sig)
+        self.pre = preconditioner(prob["T0s"], prob["T0h"], prob["G"], self.P)
+        self.Q = lag_matrices(prob["raw"], self.pre, self.P, prob["eps_r"], prob["mu_r"],
+                              self.Tmax, self.kmax)
+
+    def rhs_all(self, nsteps):
+        p = self.prob
+        out = []
+        for k in range(1, nsteps + 1):
+            eb, Eb = tested_fields(p["V"], p["F"], p["E"], p["waves"], p["dt"], k)
+            out.append(rhs(self.pre, self.Tmax, eb, Eb))
+        return np.array(out)
+
+    def run(self, nsteps=None):
+        nsteps = self.prob["nsteps"] if nsteps is None else nsteps
+        r = self.rhs_all(nsteps)
+        W = march(self.Q, r)
+        loop, star = recover(self.P, self.Tmax, self.prob["dt"], W)
+        return dict(r=r, W=W, loop=loop, star=star)

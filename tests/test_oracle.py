@@ -1,0 +1,171 @@
+"""The oracle pinned to what the paper and the mathematics fix."""
+import numpy as np
+import pytest
+from scipy.special import erf
+
+from oracle import mot_oracle as mo
+from tests._problems import problem, oracle
+
+
+@pytest.mark.parametrize("name,genus", [("tiny", 0), ("tiny_torus", 1), ("tiny_box", 0)])
+def test_projector_identities(name, genus):
+    O = oracle(name)
+    P = O.P
+    ne = P["PS"].shape[0]
+    I = np.eye(ne)
+    nv, nf = O.Lam.shape[1], O.Sig.shape[1]
+    for X in (P["PS"], P["BL"]):
+        assert np.allclose(X @ X, X, atol=1e-12)
+        assert np.allclose(X, X.T, atol=1e-12)
+    assert np.allclose(P["PS"] + P["PL"], I)
+    assert abs(P["PS"] @ P["BL"]).max() < 1e-12          # loop-star orthogonality
+    assert abs(P["BL"] @ P["BSH"]).max() < 1e-12
+    assert abs(np.trace(P["PS"]) - (nf - 1)) < 1e-9
+    assert abs(np.trace(P["BL"]) - (nv - 1)) < 1e-9
+    assert abs(np.trace(I - P["PS"] - P["BL"]) - 2 * genus) < 1e-9   # global loops
+    # Gram-matrix structure used in eq. (decomposition): PP^Lambda G^-1 P^Sigma = 0
+    assert abs(P["BL"] @ O.pre["Ginv"] @ P["PS"]).max() < 1e-12
+    # L T = T L (loop-star diagonal preconditioner), any alpha
+    T = O.pre["Tsh"] + O.pre["Tl"]
+    L = P["BSH"] + 0.37 * P["BL"]
+    assert np.allclose(L @ T, T @ L, atol=1e-12)
+
+
+def test_march_equals_block_toeplitz_solve():
+    O = oracle("tiny")
+    r = O.rhs_all(40)
+    W = mo.march(O.Q, r)
+    W2 = mo.block_toeplitz_solve(O.Q, r)
+    assert np.linalg.norm(W - W2) / np.linalg.norm(W2) < 1e-12
+
+
+def test_lag_truncation():
+    O = oracle("tiny")
+    assert len(O.Q) == O.kmax + 2
+    # Q^sl vanishes beyond k_max - 1 and Q^ll, Q^ss beyond k_max: only Q^ls remains
+    Q = O.Q[O.kmax + 1]
+    ne = O.P["PS"].shape[0]
+    Cb = mo.blk(O.P["BL"])
+    assert np.abs(Cb @ Q).max() < 1e-12 * np.abs(Q).max()   # no star-tested part
+    assert np.abs(Q @ mo.blk(O.P["PL"])).max() < 1e-10 * np.abs(Q).max()
+
+
+def _exact_vacuum(prob):
+    """Section VI-A: for eps' = eps, mu' = mu the exact currents are the traces
+    (n x h_in, e_in x n), projected to the RWG space as -G^-T (h_i; e_i) with
+    [h_i]_m = int g_m . h_in, [e_i]_m = -int g_m . e_in (time-averaged over step i)."""
+    R = prob["refinement"]
+    L, Wq = mo.tri_rule7()
+    xq = np.einsum("qk,tkd->tqd", L, R.fverts)
+    wv = prob["waves"][0]
+    dt = prob["dt"]
+    ne = prob["E"].shape[0]
+    GinvT = np.linalg.inv(prob["G"]).T
+    out = np.zeros((prob["nsteps"], 2 * ne))
+    gvals = R.bc_a[:, None, None] * xq[R.bc_t] - R.bc_b[:, None, :]
+    hp = np.cross(wv.dir, wv.pol)
+    for k in range(1, prob["nsteps"] + 1):
+        x = xq[R.bc_t]
+        s1 = (4 / wv.width) * ((k * dt - wv.t0) - x @ wv.dir)
+        s0 = (4 / wv.width) * (((k - 1) * dt - wv.t0) - x @ wv.dir)
+        a = wv.amp / 2 * (erf(s1) - erf(s0)) / dt
+        wa = R.farea[R.bc_t][:, None] * Wq[None, :] * a
+        ev = np.bincount(R.bc_n, weights=-(wa * (gvals @ wv.pol)).sum(1), minlength=ne)
+        hv = np.bincount(R.bc_n, weights=(wa * (gvals @ hp)).sum(1), minlength=ne)
+        out[k - 1, :ne] = -GinvT @ hv
+        out[k - 1, ne:] = -GinvT @ ev
+    return out
+
+
+def test_vacuum_interior_exact_solution():
+    prob = problem("sphere_vacuum")
+    O = oracle("sphere_vacuum")
+    res = O.run()
+    J = (res["loop"] + res["star"])[:, :, 0]
+    ex = _exact_vacuum(prob)
+    err = np.linalg.norm(J - ex) / np.linalg.norm(ex)
+    assert err < 0.05, err
+    # decays towards zero after the pulse: late values tiny against the peak
+    nrm = np.linalg.norm(res["W"][:, :, 0], axis=1)
+    assert nrm[-1] < 1e-6 * nrm.max()
+
+
+def test_vacuum_pin_catches_swapped_projectors(monkeypatch):
+    """Plant a mistake in the oracle (swap P^Sigma and P^{Lambda H} in the fold):
+    the exact-solution pin must fail."""
+    from fixture.problem import build_problem
+    prob = problem("sphere_vacuum")
+    real = mo.projectors
+
+    def swapped(Lam, Sig):
+        P = real(Lam, Sig)
+        P["PS"], P["PL"] = P["PL"], P["PS"]
+        return P
+    monkeypatch.setattr(mo, "projectors", swapped)
+    O = mo.Oracle(prob)
+    res = O.run(40)
+    J = (res["loop"] + res["star"])[:, :, 0]
+    ex = _exact_vacuum(dict(prob, nsteps=40))
+    assert np.linalg.norm(J - ex) / np.linalg.norm(ex) > 0.2
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_torus", "tiny_box"])
+def test_companion_spectrum_inside_unit_circle(name):
+    """Section VI-A: every eigenvalue of the companion matrix lies strictly inside
+    the unit circle, none near 1."""
+    O = oracle(name)
+    Q = O.Q
+    L, n = len(Q), Q[0].shape[0]
+    Q0i = np.linalg.inv(Q[0])
+    C = np.zeros(((L - 1) * n, (L - 1) * n))
+    for j in range(1, L):
+        C[:n, (j - 1) * n:j * n] = -Q0i @ Q[j]
+    C[n:, :-n] = np.eye((L - 2) * n)
+    ev = np.linalg.eigvals(C)
+    assert np.abs(ev).max() < 0.98
+    assert np.abs(1 - ev).min() > 0.1
+
+
+def test_late_time_decay():
+    O = oracle("tiny")
+    res = O.run(400)
+    nrm = np.linalg.norm(res["W"][:, :, 0], axis=1)
+    late = np.log10(nrm[-100:] + 1e-300)
+    slope = np.polyfit(np.arange(100), late, 1)[0]
+    assert slope < 0
+    assert nrm[-1] < 1e-12 * nrm.max()
+
+
+def test_rhs_time_integral_and_star_tail():
+    """Section V-C: int e_in dt = (A/c) p, and the tested constant tail lies in
+    range(Sigma) so P^{Lambda H} annihilates it."""
+    prob = problem("tiny")
+    O = oracle("tiny")
+    V, F, E = prob["V"], prob["F"], prob["E"]
+    wv = prob["waves"][0]
+    big = 10_000
+    import copy
+    w2 = copy.copy(wv)
+    w2.t0 = -1e9 * 0 + wv.t0
+    # far after the pulse, before the cut is applied: evaluate with cut disabled
+    orig = mo.star_cut
+    try:
+        mo.star_cut = lambda V_, w_: np.inf
+        _, Eb = mo.tested_fields(V, F, E, [wv], prob["dt"], big)
+    finally:
+        mo.star_cut = orig
+    ne = E.shape[0]
+    # -<f_m, (A/c) p> with int f_m = (c+ centroid - x+)/2 - (c- centroid - x-)/2 ... compare directly
+    ref = np.zeros(ne)
+    for m in range(ne):
+        for side, sgn in ((2, 1.0), (3, -1.0)):
+            f = E[m, side]
+            tv = V[F[f]]
+            opp = [v for v in F[f] if v not in E[m, :2]][0]
+            area = 0.5 * np.linalg.norm(np.cross(tv[1] - tv[0], tv[2] - tv[0]))
+            ref[m] += -sgn * area * (tv.mean(0) - V[opp]) @ wv.pol / (2 * area) * wv.amp
+    assert np.allclose(Eb[:ne, 0], ref, atol=1e-13)
+    assert abs(O.P["PL"] @ Eb[:ne, 0]).max() < 1e-13
+    # after the cut the star part is exactly zero
+    _, Eb2 = mo.tested_fields(V, F, E, [wv], prob["dt"], big)
+    assert not Eb2.any()
