@@ -1,0 +1,183 @@
+/*
+ * mot.h - C ABI of the MI355X marching-on-in-time (MOT) solver for the
+ * quasi-Helmholtz-projected, Calderon-preconditioned TD-PMCHWT equation
+ * (Le, Muenger, Andriulli, Cools, "A Stable, Accurate, and Well-Conditioned
+ * Time-Domain PMCHWT Formulation").
+ *
+ * The library solves, for one closed surface and R incident plane waves,
+ * the lower block-triangular Toeplitz system of eq. (fulldis_PMCHWT) by the
+ * recurrence of eq. (MOT):  Q_0 w_i = r_i - sum_{k>=1} Q_k w_{i-k},
+ * and recovers the physical currents of eq. (dis_jm) with loop and star
+ * parts kept apart.  All arithmetic runs in HIP kernels on the current
+ * device; the host only validates, copies and launches.
+ *
+ * Conventions shared by every call
+ *  - Units: exterior eps = mu = 1 (c = eta = 1); interior eps_r, mu_r.
+ *  - Unknown vector w = (u; v) of length n = 2 ne, u first (Section IV-B:
+ *    u = R^-1 j, v = R^-1 m).  Multi-RHS arrays are [n][nrhs] row-major
+ *    (the RHS index fastest) unless stated otherwise.
+ *  - Dense matrices are row-major float64.
+ *  - Host pointers are owned by the caller and may be freed when the call
+ *    returns; the library copies what it needs.
+ *  - Return codes: MOT_OK (0) or a negative MOT_E* value; mot_last_error()
+ *    then describes the failure.  A failed call leaves the handle usable
+ *    unless the code is MOT_EHIP.
+ *  - A handle is bound to one HIP stream and is not thread-safe.
+ */
+#ifndef MOT_H
+#define MOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MOT_OK = 0,
+    MOT_EINVAL = -1,   /* bad argument, bad mesh, lag out of range          */
+    MOT_ENOMEM = -2,   /* device allocation failed or over mem_cap_bytes    */
+    MOT_ENOCONV = -3,  /* GMRES hit its iteration cap; the step is kept     */
+    MOT_EHIP = -4,     /* a HIP runtime call failed                         */
+    MOT_ESTATE = -5    /* call out of order (e.g. a required lag missing)   */
+};
+
+enum { MOT_FP64 = 0, MOT_MIXED = 1 };                 /* history precision      */
+enum { MOT_FAM_H = 0, MOT_FAM_HAT = 1, MOT_FAM_TILDE = 2 };
+enum { MOT_EXT = 0, MOT_INT = 1 };
+enum { MOT_OP_T = 0, MOT_OP_K = 1 };
+
+/* Surface mesh (Section II).  Triangles counter-clockwise w.r.t. the outward
+ * normal.  edges[m] = (v_minus, v_plus, c_plus, c_minus): edge m runs
+ * v_minus -> v_plus (Lambda: +1 at v_plus, -1 at v_minus) and RWG f_m flows
+ * from c_plus to c_minus (Sigma: +1 at c_plus, -1 at c_minus); c_plus must
+ * traverse v_minus -> v_plus counter-clockwise.  f_m carries unit flux
+ * (no edge-length factor): f_m = (x - x_plus)/(2 A_plus) on c_plus. */
+typedef struct {
+    int32_t nv, nf, ne;
+    const double* verts;     /* [nv][3]  host */
+    const int32_t* tris;     /* [nf][3]  host */
+    const int32_t* edges;    /* [ne][4]  host */
+} mot_mesh;
+
+/* Gaussian plane wave of eq. (hin): e_in = 4A/(w sqrt(pi)) p exp(-((4/w)(c(t - t0) - k.x))^2),
+ * h_in = k x e_in / eta.  pol and dir are unit vectors, pol . dir = 0. */
+typedef struct {
+    double amp;
+    double pol[3];
+    double dir[3];
+    double width;            /* w  */
+    double t0;
+} mot_planewave;
+
+typedef struct {
+    int32_t precision;       /* MOT_FP64 (default) or MOT_MIXED              */
+    double gmres_tol;        /* relative residual of each Q_0 solve (1e-13)  */
+    int32_t gmres_restart;   /* Krylov dimension m (40)                      */
+    int32_t gmres_maxit;     /* total iterations per step (400)              */
+    double cg_tol;           /* graph-Laplacian and Gram solves (1e-13)      */
+    int32_t cg_maxit;        /* (20000)                                      */
+    double diameter;         /* D; <= 0: largest vertex distance             */
+    int32_t keep_history;    /* keep every w_k on the device (1)             */
+    int32_t max_steps;       /* capacity of the kept history (0: 20000)      */
+    uint64_t mem_cap_bytes;  /* 0: no cap                                     */
+    int32_t reserved[8];
+} mot_options;
+
+typedef struct {
+    int32_t step;            /* index k of the step just taken (1-based)     */
+    int32_t gmres_iters;     /* iterations of the Q_0 solve                  */
+    double gmres_relres;     /* final relative residual estimate             */
+    int32_t converged;       /* 1 if the tolerance was met                   */
+} mot_step_info;
+
+typedef struct {
+    double D, Tmax, dt;      /* diameter, T_max = D / c_min (eq. alpha)      */
+    int32_t kmax;            /* ceil(T_max / dt)                              */
+    int32_t nlags;           /* k_max + 2: Q_0 .. Q_{k_max+1}                 */
+    int32_t ne, n, nrhs;
+    int32_t genus;
+    int32_t folded;          /* 1 once every lag matrix is formed            */
+    int32_t steps_done;
+    uint64_t device_bytes;   /* device memory held by the handle             */
+    double setup_ms;         /* preconditioner construction time             */
+    double fold_ms;          /* lag-matrix fold time (sum over lags)         */
+} mot_info;
+
+typedef struct mot_handle mot_handle;
+
+/* Fill *opt with the defaults listed above. */
+void mot_default_options(mot_options* opt);
+
+/* Create a solver (Section III-V).  Validates the mesh (Sigma^T Lambda = 0,
+ * closed 2-manifold), derives D, T_max and k_max, and on the device builds
+ * the projectors of Section IV-B (graph-Laplacian CG), G^-1 (CG on the normal
+ * equations of the Gram matrix), and the factors
+ *     C1 = PP^{Sigma H} T0s PP^{Sigma H} G^-1,
+ *     C2 = PP^Lambda T0h PP^Lambda G^-1 P^{Lambda H}
+ * of the lag matrices and RHS.
+ *   T0s, T0h: dense [ne][ne] host, the static EFIO blocks of Section III on the
+ *             BC basis (T0s SPD, T0h PSD).
+ *   G: CSR [ne][ne] host, G_mn = <n x f_m, g_n>; g_rowptr has ne+1 entries.
+ *   waves: nrhs plane waves (host).   stream: hipStream_t or NULL.
+ * Returns MOT_EINVAL on a bad mesh or argument, MOT_ENOMEM, MOT_ENOCONV if a
+ * setup solve fails to converge, MOT_EHIP. */
+int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt,
+               const double* T0s, const double* T0h,
+               const int32_t* g_rowptr, const int32_t* g_col, const double* g_val,
+               int32_t nrhs, const mot_planewave* waves, const mot_options* opt,
+               void* stream, mot_handle** out);
+
+/* Upload one raw retarded block of Section V-B (host, dense [ne][ne]):
+ *   family MOT_FAM_H:     T_i  = <n x f_m, T^s(h0 f_n)>|_{i dt},       K_i  likewise,  lags 0..k_max
+ *   family MOT_FAM_HAT:   <n x f_m, d/dt T(q0 f_n)>|_{i dt} (no T_max factor), lags 0..k_max+1
+ *   family MOT_FAM_TILDE: <n x f_m, d/dt^-1 T^s(p0 f_n)>|_{i dt} (no 1/T_max factor), lags 0..k_max-1
+ * medium MOT_EXT / MOT_INT, op MOT_OP_T / MOT_OP_K.  The library applies the
+ * T_max scalings and the media sum of eq. (PMCHWT).  Once the twelve blocks
+ * of lag i (or the subset its range requires) have arrived, Q_i is folded on
+ * the device and the raw blocks are dropped.  A lag outside its family's
+ * range is MOT_EINVAL (the truncation is part of the method); uploading a
+ * block twice is MOT_ESTATE. */
+int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
+                const double* block);
+
+/* The same with a CSR block (row pointers ne+1, int32 columns, float64 values). */
+int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
+                    const int64_t* rowptr, const int32_t* col, const double* val);
+
+/* One MOT step (eq. MOT): tested incident fields, RHS, history convolution,
+ * GMRES on Q_0 (warm start 2 w_{k-1} - w_{k-2}), ring update.  MOT_ESTATE if
+ * a lag is missing.  info may be NULL. */
+int mot_step(mot_handle* h, mot_step_info* info);
+
+/* nsteps MOT steps followed by the current recovery of eq. (dis_jm) for
+ * those steps.  Output arrays are [nsteps][n][nrhs]; any may be NULL:
+ *   w_out     the auxiliary unknowns (u; v) per step,
+ *   loop_out  (P^{Lambda H} u_k; P^{Lambda H} v_k),
+ *   star_out  (T_max/dt) (P^Sigma (u_k - u_{k-1}); P^Sigma (v_k - v_{k-1})).
+ * out_on_device: 1 if the output pointers are device memory.  Steps continue
+ * from the handle's current time.  Returns the worst step's code. */
+int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out,
+            double* star_out, int32_t out_on_device, mot_step_info* last);
+
+/* Copy internal operators to host memory (diagnostics and parity checks):
+ *   which 0: Q_lag as dense [n][n]; 1: C1 [ne][ne]; 2: C2 [ne][ne];
+ *   3: P^Sigma [ne][ne]; 4: PP^Lambda [ne][ne]; 5: G^-1 [ne][ne];
+ *   6: RHS r_lag of step 'lag' as [n][nrhs] (computed, not stored state). */
+int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out);
+
+int mot_get_info(const mot_handle* h, mot_info* info);
+
+/* Restart the march at step 0 (keeps every operator). */
+int mot_reset(mot_handle* h);
+
+void mot_destroy(mot_handle* h);
+
+/* Text of the last error on this handle, or of the last failed create when h is NULL. */
+const char* mot_last_error(const mot_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOT_H */

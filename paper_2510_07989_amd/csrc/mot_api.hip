@@ -1,0 +1,869 @@
+// C ABI of the MOT solver: validation, device setup, lag fold, march, recovery.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <algorithm>
+
+#include "mot_internal.h"
+
+namespace motk_step {
+void rhs_fields(mot_handle* h);
+void history(mot_handle* h);
+void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done);
+void gm_residual(mot_handle* h, const double* b, double* r, int first);
+void gm_dots(mot_handle* h, const double* w);
+void gm_orth(mot_handle* h, double* w, int final_pass);
+void gm_update_x(mot_handle* h, double* x);
+void warm_start(mot_handle* h);
+void push(mot_handle* h);
+void inc_step(mot_handle* h);
+void rec_gather(mot_handle* h, int s0, int ns, double* X);
+void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, double* loop, double* star);
+void pack(mot_handle* h, int ns, const double* src, double* dst);
+}  // namespace motk_step
+
+static std::string g_create_err;
+
+int mot_fail(mot_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg; else g_create_err = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return mot_fail(h, MOT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+namespace {
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+int dalloc(mot_handle* h, T** p, size_t count, bool zero = true) {
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 16;
+    if (h->opt.mem_cap_bytes && h->bytes + bytes > h->opt.mem_cap_bytes)
+        return mot_fail(h, MOT_ENOMEM, "device memory cap exceeded");
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return mot_fail(h, MOT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    if (zero && hipMemsetAsync(q, 0, bytes, h->stream) != hipSuccess)
+        return mot_fail(h, MOT_EHIP, "hipMemsetAsync failed");
+    h->allocs.push_back(q);
+    h->sizes.push_back(bytes);
+    h->bytes += bytes;
+    *p = static_cast<T*>(q);
+    return MOT_OK;
+}
+
+void dfree(mot_handle* h, void* p) {
+    if (!p) return;
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+    if (it != h->allocs.end()) {
+        size_t i = it - h->allocs.begin();
+        h->bytes -= h->sizes[i];
+        h->allocs.erase(it);
+        h->sizes.erase(h->sizes.begin() + i);
+    }
+    (void)hipFree(p);
+}
+
+template <class T>
+int upload(mot_handle* h, T** d, const T* src, size_t count) {
+    int rc = dalloc(h, d, count, false);
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(*d, src, count * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    return MOT_OK;
+}
+
+// Build an incidence graph: nodes with incident signed edges and neighbours.
+int make_graph(mot_handle* h, DevGraph& g, int nnode, const std::vector<int>& plus,
+               const std::vector<int>& minus) {
+    int ne = (int)plus.size();
+    std::vector<int> deg(nnode, 0);
+    for (int m = 0; m < ne; ++m) { deg[plus[m]]++; deg[minus[m]]++; }
+    std::vector<int> ptr(nnode + 1, 0);
+    for (int i = 0; i < nnode; ++i) ptr[i + 1] = ptr[i] + deg[i];
+    std::vector<int> edge(ptr[nnode]), adj(ptr[nnode]);
+    std::vector<double> sign(ptr[nnode]);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int m = 0; m < ne; ++m) {
+        int a = plus[m], b = minus[m];
+        edge[fill[a]] = m; sign[fill[a]] = 1.0; adj[fill[a]] = b; fill[a]++;
+        edge[fill[b]] = m; sign[fill[b]] = -1.0; adj[fill[b]] = a; fill[b]++;
+    }
+    g.nnode = nnode;
+    g.ne = ne;
+    int rc;
+    if ((rc = upload(h, &g.plus, plus.data(), ne))) return rc;
+    if ((rc = upload(h, &g.minus, minus.data(), ne))) return rc;
+    if ((rc = upload(h, &g.inc_ptr, ptr.data(), nnode + 1))) return rc;
+    if ((rc = upload(h, &g.inc_edge, edge.data(), edge.size()))) return rc;
+    if ((rc = upload(h, &g.inc_sign, sign.data(), sign.size()))) return rc;
+    if ((rc = upload(h, &g.adj_ptr, ptr.data(), nnode + 1))) return rc;
+    if ((rc = upload(h, &g.adj, adj.data(), adj.size()))) return rc;
+    return MOT_OK;
+}
+
+// Column-batched CG.  op(X) -> Y on [rows][ncol]; solves op(X) = B from X = 0.
+// Returns MOT_OK or MOT_ENOCONV.
+template <class Op>
+int batched_cg(mot_handle* h, int rows, int ncol, const double* B, double* X, Op op, double tol,
+               int maxit) {
+    hipStream_t s = h->stream;
+    size_t N = (size_t)rows * ncol;
+    double *R, *P, *Q, *part, *rr, *rr0, *alpha, *beta, *pq;
+    int *active, *dcount;
+    int rc;
+    if ((rc = dalloc(h, &R, N, false)) || (rc = dalloc(h, &P, N, false)) || (rc = dalloc(h, &Q, N, false)) ||
+        (rc = dalloc(h, &part, (size_t)MOT_CG_CHUNKS * ncol, false)) || (rc = dalloc(h, &rr, ncol)) ||
+        (rc = dalloc(h, &rr0, ncol)) || (rc = dalloc(h, &alpha, ncol)) || (rc = dalloc(h, &beta, ncol)) ||
+        (rc = dalloc(h, &pq, ncol)) || (rc = dalloc(h, &active, ncol)) || (rc = dalloc(h, &dcount, 1)))
+        return rc;
+    HIPCHK(h, hipMemsetAsync(X, 0, N * sizeof(double), s));
+    HIPCHK(h, hipMemcpyAsync(R, B, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(P, B, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    motk::coldot(s, rows, ncol, R, R, part, pq);   // pq used as scratch for the sums
+    motk::cg_scalars(s, ncol, pq, part, MOT_CG_CHUNKS, rr, rr0, alpha, beta, active, tol, 2);
+    int it = 0, hcount = ncol;
+    int result = MOT_OK;
+    for (; it < maxit; ++it) {
+        op(P, Q);
+        motk::coldot(s, rows, ncol, P, Q, part, pq);
+        motk::cg_scalars(s, ncol, pq, part, MOT_CG_CHUNKS, rr, rr0, alpha, beta, active, tol, 0);
+        motk::cg_update(s, rows, ncol, alpha, P, Q, X, R, part);
+        motk::cg_scalars(s, ncol, pq, part, MOT_CG_CHUNKS, rr, rr0, alpha, beta, active, tol, 1);
+        motk::cg_pupdate(s, rows, ncol, beta, R, P);
+        if ((it + 1) % 16 == 0) {
+            if (motk::count_active(s, ncol, active, dcount, &hcount)) return mot_fail(h, MOT_EHIP, "cg sync");
+            if (hcount == 0) break;
+        }
+    }
+    if (it == maxit) {
+        if (motk::count_active(s, ncol, active, dcount, &hcount)) return mot_fail(h, MOT_EHIP, "cg sync");
+        if (hcount) result = mot_fail(h, MOT_ENOCONV, "CG did not converge on " + std::to_string(hcount) + " columns");
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (void* p : {(void*)R, (void*)P, (void*)Q, (void*)part, (void*)rr, (void*)rr0, (void*)alpha,
+                    (void*)beta, (void*)pq, (void*)active, (void*)dcount})
+        dfree(h, p);
+    return result;
+}
+
+// Dense projector Inc (Inc^T Inc)^+ Inc^T as [ne][hs] (Section IV-B), in column chunks.
+int dense_projector(mot_handle* h, const DevGraph& g, double* Pout) {
+    const int ne = h->ne, hs = h->hs;
+    const int chunk = std::min(ne, 4096);
+    double *E, *S, *Z, *Y;
+    int rc;
+    if ((rc = dalloc(h, &E, (size_t)ne * chunk)) || (rc = dalloc(h, &S, (size_t)g.nnode * chunk)) ||
+        (rc = dalloc(h, &Z, (size_t)g.nnode * chunk)) || (rc = dalloc(h, &Y, (size_t)ne * chunk)))
+        return rc;
+    for (int c0 = 0; c0 < ne; c0 += chunk) {
+        int nc = std::min(chunk, ne - c0);
+        // E = identity columns c0 .. c0+nc
+        motk::fill2d(h->stream, ne, nc, 0.0, E, nc);
+        motk::set_identity(h->stream, nc, E + (size_t)c0 * nc, nc);   // E[c0 + i][i] = 1
+        motk::inc_T(h->stream, g, nc, E, nc, S);
+        auto lap = [&](const double* X, double* Yo) { motk::spmm_lap(h->stream, g, nc, X, Yo); };
+        rc = batched_cg(h, g.nnode, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
+        if (rc) return rc;
+        motk::inc_apply(h->stream, g, nc, Z, Y, nc);
+        // column c0 + i of the projector: P[m][c0 + i] = Y[m][i]
+        HIPCHK(h, hipMemcpy2DAsync(Pout + c0, hs * sizeof(double), Y, nc * sizeof(double), nc * sizeof(double), ne,
+                         hipMemcpyDeviceToDevice, h->stream));
+    }
+    dfree(h, E); dfree(h, S); dfree(h, Z); dfree(h, Y);
+    return MOT_OK;
+}
+
+// G^-1 as [ne][hs]: CG on G^T G X = G^T I (normal equations; kappa(G) is small).
+int gram_inverse(mot_handle* h) {
+    const int ne = h->ne, hs = h->hs;
+    const int chunk = std::min(ne, 4096);
+    double *Bm, *X, *T;
+    int rc;
+    if ((rc = dalloc(h, &Bm, (size_t)ne * chunk)) || (rc = dalloc(h, &X, (size_t)ne * chunk)) ||
+        (rc = dalloc(h, &T, (size_t)ne * chunk)))
+        return rc;
+    for (int c0 = 0; c0 < ne; c0 += chunk) {
+        int nc = std::min(chunk, ne - c0);
+        // B = G^T e_{c0+i}: rows of G^T ... computed as spmm with G^T on identity columns
+        motk::fill2d(h->stream, ne, nc, 0.0, X, nc);
+        motk::set_identity(h->stream, nc, X + (size_t)c0 * nc, nc);
+        motk::spmm_csr(h->stream, h->GT, nc, X, Bm);
+        auto op = [&](const double* P, double* Yo) {
+            motk::spmm_csr(h->stream, h->G, nc, P, T);
+            motk::spmm_csr(h->stream, h->GT, nc, T, Yo);
+        };
+        rc = batched_cg(h, ne, nc, Bm, X, op, h->opt.cg_tol * 1e-1, h->opt.cg_maxit);
+        if (rc) return rc;
+        HIPCHK(h, hipMemcpy2DAsync(h->Ginv + c0, hs * sizeof(double), X, nc * sizeof(double), nc * sizeof(double), ne,
+                         hipMemcpyDeviceToDevice, h->stream));
+    }
+    dfree(h, Bm); dfree(h, X); dfree(h, T);
+    return MOT_OK;
+}
+
+int fam_limit(const mot_handle* h, int fam) {
+    return fam == MOT_FAM_H ? h->kmax : (fam == MOT_FAM_HAT ? h->kmax + 1 : h->kmax - 1);
+}
+
+uint32_t required_bits(const mot_handle* h, int lag) {
+    uint32_t b = 0;
+    for (int f = 0; f < 3; ++f)
+        if (lag <= fam_limit(h, f)) b |= 0xFu << (4 * f);
+    return b;
+}
+
+// Section V-B fold of lag i:  with blocks X in {1 = eta T + eta' T', k = K + K', 2 = T/eta + T'/eta'}
+//   a_X = Zh_X + (Zhat_X - Zh_X) P^Sigma,  b_X = Ztil_X + (Zh_X - Ztil_X) P^Sigma
+//   q_X = C1 a_X + C2 b_X                 (Q_i = [[q_1, -q_k], [q_k, q_2]])
+int fold_lag(mot_handle* h, int lag) {
+    double t0 = now_ms();
+    const int ne = h->ne, hs = h->hs;
+    const size_t blk = (size_t)ne * hs;
+    hipStream_t s = h->stream;
+    double* Zf[3];
+    for (int f = 0; f < 3; ++f) Zf[f] = h->stage[(size_t)lag * 3 + f];   // may be null (zero)
+    double* D = h->tmp;
+    double* A = h->tmp + blk;
+    double* Bv = h->tmp + 2 * blk;
+    for (int x = 0; x < 3; ++x) {
+        const double* zh = Zf[0] ? Zf[0] + x * blk : nullptr;
+        const double* zt = Zf[1] ? Zf[1] + x * blk : nullptr;   // hat
+        const double* zl = Zf[2] ? Zf[2] + x * blk : nullptr;   // tilde
+        // D = Zhat - Zh ; A = Zh + D PS
+        motk::fill2d(s, ne, hs, 0.0, D, hs);
+        if (zt) motk::axpby2d(s, ne, hs, 1.0, zt, hs, 1.0, D, hs);
+        if (zh) motk::axpby2d(s, ne, hs, -1.0, zh, hs, 1.0, D, hs);
+        motk::fill2d(s, ne, hs, 0.0, A, hs);
+        if (zh) motk::axpby2d(s, ne, hs, 1.0, zh, hs, 0.0, A, hs);
+        motk::gemm(s, ne, ne, ne, 1.0, D, hs, h->PS, hs, 1.0, A, hs);
+        // D = Zh - Ztil ; B = Ztil + D PS
+        motk::fill2d(s, ne, hs, 0.0, D, hs);
+        if (zh) motk::axpby2d(s, ne, hs, 1.0, zh, hs, 1.0, D, hs);
+        if (zl) motk::axpby2d(s, ne, hs, -1.0, zl, hs, 1.0, D, hs);
+        motk::fill2d(s, ne, hs, 0.0, Bv, hs);
+        if (zl) motk::axpby2d(s, ne, hs, 1.0, zl, hs, 0.0, Bv, hs);
+        motk::gemm(s, ne, ne, ne, 1.0, D, hs, h->PS, hs, 1.0, Bv, hs);
+        // q = C1 A + C2 B
+        double* q = h->Q + ((size_t)lag * 3 + x) * blk;
+        motk::gemm(s, ne, ne, ne, 1.0, h->C1, hs, A, hs, 0.0, q, hs);
+        motk::gemm(s, ne, ne, ne, 1.0, h->C2, hs, Bv, hs, 1.0, q, hs);
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (int f = 0; f < 3; ++f) {
+        if (Zf[f]) dfree(h, Zf[f]);
+        h->stage[(size_t)lag * 3 + f] = nullptr;
+    }
+    h->lag_done[lag] = 1;
+    h->fold_ms += now_ms() - t0;
+    return MOT_OK;
+}
+
+bool all_folded(const mot_handle* h) {
+    for (int i = 0; i < h->nlags; ++i)
+        if (!h->lag_done[i]) return false;
+    return true;
+}
+
+int stage_add(mot_handle* h, int family, int lag, int medium, int op, const double* dev_block) {
+    const int ne = h->ne, hs = h->hs;
+    const size_t blk = (size_t)ne * hs;
+    double*& S = h->stage[(size_t)lag * 3 + family];
+    if (!S) {
+        int rc = dalloc(h, &S, 3 * blk);
+        if (rc) return rc;
+    }
+    double sc = family == MOT_FAM_HAT ? h->Tmax : (family == MOT_FAM_TILDE ? 1.0 / h->Tmax : 1.0);
+    double et = medium == MOT_EXT ? h->eta : h->etap;
+    if (op == MOT_OP_T) {
+        motk::axpby2d(h->stream, ne, ne, sc * et, dev_block, hs, 1.0, S, hs);          // q1 slot
+        motk::axpby2d(h->stream, ne, ne, sc / et, dev_block, hs, 1.0, S + 2 * blk, hs); // q2 slot
+    } else {
+        motk::axpby2d(h->stream, ne, ne, sc, dev_block, hs, 1.0, S + blk, hs);         // qk slot
+    }
+    return MOT_OK;
+}
+
+int check_lag_args(mot_handle* h, int family, int lag, int medium, int op) {
+    if (!h) return MOT_EINVAL;
+    if (family < 0 || family > 2 || medium < 0 || medium > 1 || op < 0 || op > 1)
+        return mot_fail(h, MOT_EINVAL, "bad family/medium/op");
+    if (lag < 0 || lag > fam_limit(h, family))
+        return mot_fail(h, MOT_EINVAL, "lag " + std::to_string(lag) + " outside the range of family " +
+                                           std::to_string(family) + " (0.." + std::to_string(fam_limit(h, family)) + ")");
+    if (h->lag_done[lag]) return mot_fail(h, MOT_ESTATE, "lag already folded");
+    uint32_t bit = 1u << (4 * family + 2 * medium + op);
+    if (h->got[lag] & bit) return mot_fail(h, MOT_ESTATE, "block uploaded twice");
+    return MOT_OK;
+}
+
+int after_block(mot_handle* h, int family, int lag, int medium, int op) {
+    h->got[lag] |= 1u << (4 * family + 2 * medium + op);
+    if ((h->got[lag] & required_bits(h, lag)) == required_bits(h, lag)) return fold_lag(h, lag);
+    return MOT_OK;
+}
+
+// Wait until the device has published progress word 'want' (bounded: a
+// failed kernel turns into MOT_EHIP instead of a hang).
+int wait_flag(mot_handle* h, int want) {
+    if (h->hflag->seq >= want) return MOT_OK;
+    double t0 = now_ms();
+    unsigned spins = 0;
+    while (h->hflag->seq < want) {
+        if ((++spins & 1023u) == 0) {
+            hipError_t e = hipStreamQuery(h->stream);
+            if (e != hipSuccess && e != hipErrorNotReady)
+                return mot_fail(h, MOT_EHIP, std::string("stream error while waiting: ") + hipGetErrorString(e));
+            if (e == hipSuccess && h->hflag->seq < want)
+                return mot_fail(h, MOT_EHIP, "stream idle but GMRES progress word not written");
+            if (now_ms() - t0 > 60000.0) return mot_fail(h, MOT_EHIP, "timeout waiting for GMRES progress");
+        }
+    }
+    return MOT_OK;
+}
+
+// Single right-hand-side GMRES on Q0 x = y (x holds the warm start).
+int gmres_solve(mot_handle* h) {
+    using namespace motk_step;
+    hipStream_t s = h->stream;
+    const int M = h->M;
+    int maxit = h->opt.gmres_maxit;
+    h->hflag->seq = 0;
+    h->hflag->done = 0;
+    int seq_target = 0;
+    bool first = true;
+    int iters = 0;
+    for (;;) {
+        // r = y - Q0 x
+        q0_matvec(h, h->x, nullptr, h->wA, 0);
+        gm_residual(h, h->y, h->wA, first ? 1 : 0);
+        first = false;
+        seq_target++;
+        double* src = h->wA;
+        double* dst = h->wB;
+        bool cycle_done = false;
+        int j = 0;
+        for (; j < M && iters + j < maxit; ++j) {
+            // V[j] = src * inv_h ; dst = Q0 V[j]
+            q0_matvec(h, src, h->V + (size_t)j * h->n2, dst, 1);
+            gm_dots(h, dst);
+            gm_orth(h, dst, 0);
+            gm_orth(h, dst, 1);
+            std::swap(src, dst);
+            // wait for the previous step's flag (one step of look-ahead)
+            int want = seq_target + j;   // flag of step j-1 (residual counts as one)
+            int wrc = wait_flag(h, want);
+            if (wrc) return wrc;
+            if (h->hflag->done) { cycle_done = true; break; }
+        }
+        if (!cycle_done) {
+            int wrc = wait_flag(h, seq_target + j);
+            if (wrc) return wrc;
+        }
+        HIPCHK(h, hipGetLastError());
+        // settle: read the state of the cycle
+        int total = h->hflag->total;
+        iters = total;
+        seq_target = h->hflag->seq;
+        gm_update_x(h, h->x);
+        int conv = h->hflag->converged;
+        if (conv || iters >= maxit) {
+            h->last_iters = iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = conv;
+            break;
+        }
+    }
+    return h->last_conv ? MOT_OK : MOT_ENOCONV;
+}
+
+int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
+    // columns per batch: 4 R per step
+    const int per = 4 * h->R;
+    const int maxcol = 8192;
+    int bs = std::max(1, maxcol / per);
+    double *X, *S, *Z, *PX;
+    int rc;
+    int ncmax = std::min(ns, bs) * per;
+    if ((rc = dalloc(h, &X, (size_t)h->ne * ncmax, false)) || (rc = dalloc(h, &S, (size_t)h->nf * ncmax, false)) ||
+        (rc = dalloc(h, &Z, (size_t)h->nf * ncmax, false)) || (rc = dalloc(h, &PX, (size_t)h->ne * ncmax, false)))
+        return rc;
+    int worst = MOT_OK;
+    for (int b0 = 0; b0 < ns; b0 += bs) {
+        int nb = std::min(bs, ns - b0);
+        int nc = nb * per;
+        motk_step::rec_gather(h, s0 + b0, nb, X);
+        motk::inc_T(h->stream, h->gf, nc, X, nc, S);
+        auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
+        rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        if (rc) worst = rc;
+        motk::inc_apply(h->stream, h->gf, nc, Z, PX, nc);
+        size_t off = (size_t)b0 * 2 * h->ne * h->R;
+        motk_step::rec_scatter(h, nb, X, PX, loop ? loop + off : nullptr, star ? star + off : nullptr);
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    dfree(h, X); dfree(h, S); dfree(h, Z); dfree(h, PX);
+    return worst;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void mot_default_options(mot_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->precision = MOT_FP64;
+    o->gmres_tol = 1e-13;
+    o->gmres_restart = 40;
+    o->gmres_maxit = 400;
+    o->cg_tol = 1e-13;
+    o->cg_maxit = 20000;
+    o->diameter = 0.0;
+    o->keep_history = 1;
+    o->max_steps = 0;
+    o->mem_cap_bytes = 0;
+}
+
+const char* mot_last_error(const mot_handle* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+
+void mot_destroy(mot_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->hflag) (void)hipHostFree(h->hflag);
+    delete h;
+}
+
+int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const double* T0s,
+               const double* T0h, const int32_t* g_rowptr, const int32_t* g_col, const double* g_val,
+               int32_t nrhs, const mot_planewave* waves, const mot_options* opt, void* stream,
+               mot_handle** out) {
+    g_create_err.clear();
+    if (!out) return mot_fail(nullptr, MOT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mesh || !mesh->verts || !mesh->tris || !mesh->edges || !T0s || !T0h || !g_rowptr || !g_col ||
+        !g_val || !waves)
+        return mot_fail(nullptr, MOT_EINVAL, "NULL argument");
+    if (!(eps_r > 0) || !(mu_r > 0) || !(dt > 0) || !std::isfinite(eps_r + mu_r + dt))
+        return mot_fail(nullptr, MOT_EINVAL, "eps_r, mu_r, dt must be positive");
+    const int nv = mesh->nv, nf = mesh->nf, ne = mesh->ne;
+    if (nv < 4 || nf < 4 || ne < 6 || 2 * ne != 3 * nf)
+        return mot_fail(nullptr, MOT_EINVAL, "mesh sizes are not those of a closed triangulation");
+    if (nrhs != 1) return mot_fail(nullptr, MOT_EINVAL, "this build marches one right-hand side per handle");
+    // ---- mesh validation (host, integers) ----
+    const int32_t* E = mesh->edges;
+    const int32_t* F = mesh->tris;
+    for (int f = 0; f < 3 * nf; ++f)
+        if (F[f] < 0 || F[f] >= nv) return mot_fail(nullptr, MOT_EINVAL, "triangle vertex out of range");
+    std::vector<int> fdeg(nf, 0);
+    for (int m = 0; m < ne; ++m) {
+        int vm = E[4 * m], vp = E[4 * m + 1], cp = E[4 * m + 2], cm = E[4 * m + 3];
+        if (vm < 0 || vm >= nv || vp < 0 || vp >= nv || vm == vp || cp < 0 || cp >= nf || cm < 0 || cm >= nf || cp == cm)
+            return mot_fail(nullptr, MOT_EINVAL, "edge table entry out of range at edge " + std::to_string(m));
+        fdeg[cp]++; fdeg[cm]++;
+        // c_plus traverses v_minus -> v_plus counter-clockwise
+        bool okp = false, okm = false;
+        for (int k = 0; k < 3; ++k) {
+            if (F[3 * cp + k] == vm && F[3 * cp + (k + 1) % 3] == vp) okp = true;
+            if (F[3 * cm + k] == vp && F[3 * cm + (k + 1) % 3] == vm) okm = true;
+        }
+        if (!okp || !okm) return mot_fail(nullptr, MOT_EINVAL, "edge orientation inconsistent at edge " + std::to_string(m));
+    }
+    for (int f = 0; f < nf; ++f)
+        if (fdeg[f] != 3) return mot_fail(nullptr, MOT_EINVAL, "triangle without three edges");
+    // Sigma^T Lambda = 0: each face's signed edges cancel at every vertex
+    {
+        std::vector<std::map<int, int>> acc(nf);
+        for (int m = 0; m < ne; ++m) {
+            int vm = E[4 * m], vp = E[4 * m + 1], cp = E[4 * m + 2], cm = E[4 * m + 3];
+            acc[cp][vp] += 1; acc[cp][vm] -= 1;
+            acc[cm][vp] -= 1; acc[cm][vm] += 1;
+        }
+        for (int f = 0; f < nf; ++f)
+            for (auto& kv : acc[f])
+                if (kv.second != 0) return mot_fail(nullptr, MOT_EINVAL, "Sigma^T Lambda != 0");
+    }
+    int chi = nv - ne + nf;
+    if (chi > 2 || chi % 2) return mot_fail(nullptr, MOT_EINVAL, "Euler characteristic of a closed orientable surface expected");
+    for (size_t i = 0; i < (size_t)ne * ne; ++i)
+        if (!std::isfinite(T0s[i]) || !std::isfinite(T0h[i])) return mot_fail(nullptr, MOT_EINVAL, "non-finite static block");
+
+    mot_handle* h = new mot_handle();
+    if (opt) h->opt = *opt; else mot_default_options(&h->opt);
+    if (h->opt.gmres_restart < 2 || h->opt.gmres_restart > MOT_MAXM) h->opt.gmres_restart = 40;
+    h->M = h->opt.gmres_restart;
+    if (h->opt.gmres_maxit <= 0) h->opt.gmres_maxit = 400;
+    if (h->opt.cg_maxit <= 0) h->opt.cg_maxit = 20000;
+    if (!(h->opt.cg_tol > 0)) h->opt.cg_tol = 1e-13;
+    if (!(h->opt.gmres_tol > 0)) h->opt.gmres_tol = 1e-13;
+    h->stream = (hipStream_t)stream;
+    h->nv = nv; h->nf = nf; h->ne = ne; h->R = nrhs;
+    h->hs = (ne + 7) & ~7;
+    h->n2 = 2 * h->hs;
+    h->genus = (2 - chi) / 2;
+    h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
+    h->c = 1.0; h->eta = 1.0;
+    h->cp = 1.0 / std::sqrt(eps_r * mu_r);
+    h->etap = std::sqrt(mu_r / eps_r);
+    // D, T_max, k_max (eq. alpha; Section V-B)
+    double D = h->opt.diameter;
+    if (!(D > 0)) {
+        D = 0;
+        const double* V = mesh->verts;
+        for (int a = 0; a < nv; ++a)
+            for (int b = a + 1; b < nv; ++b) {
+                double dx = V[3 * a] - V[3 * b], dy = V[3 * a + 1] - V[3 * b + 1], dz = V[3 * a + 2] - V[3 * b + 2];
+                D = std::max(D, dx * dx + dy * dy + dz * dz);
+            }
+        D = std::sqrt(D);
+    }
+    h->D = D;
+    h->Tmax = D / std::min(h->c, h->cp);
+    h->kmax = (int)std::ceil(h->Tmax / dt - 1e-12);
+    h->nlags = h->kmax + 2;
+    h->nh = h->nlags - 1;
+    double t_start = now_ms();
+    int rc = MOT_OK;
+    auto bail = [&](int code) { g_create_err = h->err; mot_destroy(h); return code; };
+
+    // ---- graphs ----
+    {
+        std::vector<int> fp(ne), fm(ne), vp(ne), vm(ne);
+        for (int m = 0; m < ne; ++m) { fp[m] = E[4 * m + 2]; fm[m] = E[4 * m + 3]; vp[m] = E[4 * m + 1]; vm[m] = E[4 * m]; }
+        if ((rc = make_graph(h, h->gf, nf, fp, fm))) return bail(rc);
+        if ((rc = make_graph(h, h->gv, nv, vp, vm))) return bail(rc);
+    }
+    // ---- Gram matrix and its transpose (CSR) ----
+    {
+        int nnz = g_rowptr[ne];
+        if (nnz <= 0 || g_rowptr[0] != 0) { h->err = "bad Gram CSR"; return bail(MOT_EINVAL); }
+        for (int i = 0; i < nnz; ++i)
+            if (g_col[i] < 0 || g_col[i] >= ne || !std::isfinite(g_val[i])) { h->err = "bad Gram CSR entry"; return bail(MOT_EINVAL); }
+        std::vector<int> tp(ne + 1, 0), tc(nnz);
+        std::vector<double> tv(nnz);
+        for (int i = 0; i < nnz; ++i) tp[g_col[i] + 1]++;
+        for (int i = 0; i < ne; ++i) tp[i + 1] += tp[i];
+        std::vector<int> fill(tp.begin(), tp.end() - 1);
+        for (int r = 0; r < ne; ++r)
+            for (int k = g_rowptr[r]; k < g_rowptr[r + 1]; ++k) { int c = g_col[k]; tc[fill[c]] = r; tv[fill[c]] = g_val[k]; fill[c]++; }
+        h->G.n = h->GT.n = ne; h->G.nnz = h->GT.nnz = nnz;
+        if ((rc = upload(h, &h->G.ptr, g_rowptr, ne + 1)) || (rc = upload(h, &h->G.col, g_col, nnz)) ||
+            (rc = upload(h, &h->G.val, g_val, nnz)) || (rc = upload(h, &h->GT.ptr, tp.data(), ne + 1)) ||
+            (rc = upload(h, &h->GT.col, tc.data(), nnz)) || (rc = upload(h, &h->GT.val, tv.data(), nnz)))
+            return bail(rc);
+    }
+    // ---- RHS quadrature geometry (7-point degree-5 rule per triangle) ----
+    {
+        const double s15 = std::sqrt(15.0), qa = (6 - s15) / 21, qb = (6 + s15) / 21;
+        const double L[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3},
+                                {1 - 2 * qa, qa, qa}, {qa, 1 - 2 * qa, qa}, {qa, qa, 1 - 2 * qa},
+                                {1 - 2 * qb, qb, qb}, {qb, 1 - 2 * qb, qb}, {qb, qb, 1 - 2 * qb}};
+        const double W[7] = {9.0 / 40, (155 - s15) / 1200, (155 - s15) / 1200, (155 - s15) / 1200,
+                             (155 + s15) / 1200, (155 + s15) / 1200, (155 + s15) / 1200};
+        std::vector<double> X((size_t)ne * 14 * 3), Fw((size_t)ne * 14 * 3);
+        const double* V = mesh->verts;
+        for (int m = 0; m < ne; ++m)
+            for (int side = 0; side < 2; ++side) {
+                int f = E[4 * m + 2 + side];
+                int opp = -1;
+                for (int k = 0; k < 3; ++k) { int v = F[3 * f + k]; if (v != E[4 * m] && v != E[4 * m + 1]) opp = v; }
+                const double* a = V + 3 * F[3 * f];
+                const double* b = V + 3 * F[3 * f + 1];
+                const double* c = V + 3 * F[3 * f + 2];
+                double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+                double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+                double sg = side == 0 ? 1.0 : -1.0;
+                for (int q = 0; q < 7; ++q) {
+                    size_t o = ((size_t)m * 14 + side * 7 + q) * 3;
+                    for (int d = 0; d < 3; ++d) {
+                        double x = L[q][0] * a[d] + L[q][1] * b[d] + L[q][2] * c[d];
+                        X[o + d] = x;
+                        Fw[o + d] = W[q] * area * sg * (x - V[3 * opp + d]) / (2 * area);
+                    }
+                }
+            }
+        if ((rc = upload(h, &h->rq_x, X.data(), X.size())) || (rc = upload(h, &h->rq_f, Fw.data(), Fw.size())))
+            return bail(rc);
+        std::vector<double> wv(9 * nrhs), tc(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            const mot_planewave& w = waves[r];
+            if (!(w.width > 0) || !std::isfinite(w.t0 + w.amp)) { h->err = "bad plane wave"; return bail(MOT_EINVAL); }
+            wv[9 * r] = w.amp;
+            for (int d = 0; d < 3; ++d) { wv[9 * r + 1 + d] = w.pol[d]; wv[9 * r + 4 + d] = w.dir[d]; }
+            wv[9 * r + 7] = w.width;
+            wv[9 * r + 8] = w.t0;
+            // star RHS cut (Section V-C): after the pulse has left every vertex
+            double kmaxx = -1e300;
+            for (int v = 0; v < nv; ++v)
+                kmaxx = std::max(kmaxx, w.dir[0] * V[3 * v] + w.dir[1] * V[3 * v + 1] + w.dir[2] * V[3 * v + 2]);
+            tc[r] = w.t0 + (kmaxx + 1.6 * w.width) / h->c;
+        }
+        if ((rc = upload(h, &h->waves, wv.data(), wv.size())) || (rc = upload(h, &h->tcut, tc.data(), tc.size())))
+            return bail(rc);
+    }
+    // ---- projectors, G^-1, C1, C2 (Section III, IV-B) ----
+    const int hs = h->hs;
+    const size_t blk = (size_t)ne * hs;
+    if ((rc = dalloc(h, &h->PS, blk)) || (rc = dalloc(h, &h->BL, blk)) || (rc = dalloc(h, &h->Ginv, blk)) ||
+        (rc = dalloc(h, &h->C1, blk)) || (rc = dalloc(h, &h->C2, blk)))
+        return bail(rc);
+    if ((rc = dense_projector(h, h->gf, h->PS))) return bail(rc);
+    if ((rc = dense_projector(h, h->gv, h->BL))) return bail(rc);
+    if ((rc = gram_inverse(h))) return bail(rc);
+    {
+        double *T0, *A, *Bm;
+        if ((rc = dalloc(h, &T0, blk)) || (rc = dalloc(h, &A, blk)) || (rc = dalloc(h, &Bm, blk))) return bail(rc);
+        hipStream_t s = h->stream;
+        // T^{Sigma H} = (I - BL) T0s (I - BL) ; C1 = T^{Sigma H} G^-1
+        HIPCHK(h, hipMemcpy2DAsync(T0, hs * sizeof(double), T0s, ne * sizeof(double), ne * sizeof(double), ne,
+                                   hipMemcpyHostToDevice, s));
+        motk::axpby2d(s, ne, ne, 1.0, T0, hs, 0.0, A, hs);
+        motk::gemm(s, ne, ne, ne, -1.0, h->BL, hs, T0, hs, 1.0, A, hs);     // A = (I - BL) T0s
+        motk::axpby2d(s, ne, ne, 1.0, A, hs, 0.0, Bm, hs);
+        motk::gemm(s, ne, ne, ne, -1.0, A, hs, h->BL, hs, 1.0, Bm, hs);     // Bm = A (I - BL)
+        motk::gemm(s, ne, ne, ne, 1.0, Bm, hs, h->Ginv, hs, 0.0, h->C1, hs);
+        // T^Lambda = BL T0h BL ; C2 = T^Lambda G^-1 (I - PS)
+        HIPCHK(h, hipMemcpy2DAsync(T0, hs * sizeof(double), T0h, ne * sizeof(double), ne * sizeof(double), ne,
+                                   hipMemcpyHostToDevice, s));
+        motk::gemm(s, ne, ne, ne, 1.0, h->BL, hs, T0, hs, 0.0, A, hs);
+        motk::gemm(s, ne, ne, ne, 1.0, A, hs, h->BL, hs, 0.0, Bm, hs);
+        motk::gemm(s, ne, ne, ne, 1.0, Bm, hs, h->Ginv, hs, 0.0, A, hs);    // A = T^Lambda G^-1
+        motk::axpby2d(s, ne, ne, 1.0, A, hs, 0.0, h->C2, hs);
+        motk::gemm(s, ne, ne, ne, -1.0, A, hs, h->PS, hs, 1.0, h->C2, hs);  // C2 = A (I - PS)
+        HIPCHK(h, hipStreamSynchronize(s));
+        dfree(h, T0); dfree(h, A); dfree(h, Bm);
+    }
+    // ---- lag storage and march state ----
+    h->stage.assign((size_t)h->nlags * 3, nullptr);
+    h->got.assign(h->nlags, 0);
+    h->lag_done.assign(h->nlags, 0);
+    if ((rc = dalloc(h, &h->Q, (size_t)h->nlags * 3 * blk)) || (rc = dalloc(h, &h->tmp, 3 * blk, false)) ||
+        (rc = dalloc(h, &h->raw, blk)))
+        return bail(rc);
+    const int n2 = h->n2;
+    h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
+    if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
+        (rc = dalloc(h, &h->ebar, n2)) || (rc = dalloc(h, &h->Ebar, n2)) || (rc = dalloc(h, &h->y, n2)) ||
+        (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) ||
+        (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
+        return bail(rc);
+    if (h->hist_cap && (rc = dalloc(h, &h->hist, (size_t)h->hist_cap * n2))) return bail(rc);
+    if (hipHostMalloc((void**)&h->hflag, sizeof(GmFlag), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        h->err = "hipHostMalloc failed";
+        return bail(MOT_EHIP);
+    }
+    std::memset((void*)h->hflag, 0, sizeof(GmFlag));
+    if (hipHostGetDevicePointer((void**)&h->dflag, h->hflag, 0) != hipSuccess) {
+        h->err = "hipHostGetDevicePointer failed";
+        return bail(MOT_EHIP);
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) { h->err = "stream sync failed"; return bail(MOT_EHIP); }
+    h->setup_ms = now_ms() - t_start;
+    *out = h;
+    return MOT_OK;
+}
+
+int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op, const double* block) {
+    int rc = check_lag_args(h, family, lag, medium, op);
+    if (rc) return rc;
+    if (!block) return mot_fail(h, MOT_EINVAL, "NULL block");
+    const int ne = h->ne, hs = h->hs;
+    HIPCHK(h, hipMemcpy2DAsync(h->raw, hs * sizeof(double), block, ne * sizeof(double), ne * sizeof(double), ne,
+                               hipMemcpyHostToDevice, h->stream));
+    if ((rc = stage_add(h, family, lag, medium, op, h->raw))) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return after_block(h, family, lag, medium, op);
+}
+
+int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
+                    const int64_t* rowptr, const int32_t* col, const double* val) {
+    int rc = check_lag_args(h, family, lag, medium, op);
+    if (rc) return rc;
+    if (!rowptr || !col || !val) return mot_fail(h, MOT_EINVAL, "NULL CSR array");
+    const int ne = h->ne, hs = h->hs;
+    int64_t nnz = rowptr[ne];
+    if (rowptr[0] != 0 || nnz < 0) return mot_fail(h, MOT_EINVAL, "bad CSR row pointers");
+    for (int r = 0; r < ne; ++r)
+        if (rowptr[r + 1] < rowptr[r]) return mot_fail(h, MOT_EINVAL, "CSR row pointers decrease");
+    for (int64_t i = 0; i < nnz; ++i)
+        if (col[i] < 0 || col[i] >= ne || !std::isfinite(val[i])) return mot_fail(h, MOT_EINVAL, "bad CSR entry");
+    int64_t* dptr; int* dcol; double* dval;
+    if ((rc = upload(h, &dptr, rowptr, ne + 1)) || (rc = upload(h, &dcol, col, nnz ? nnz : 1)) ||
+        (rc = upload(h, &dval, val, nnz ? nnz : 1)))
+        return rc;
+    motk::fill2d(h->stream, ne, hs, 0.0, h->raw, hs);
+    motk::scatter_csr_add(h->stream, ne, dptr, dcol, dval, 1.0, h->raw, hs);
+    if ((rc = stage_add(h, family, lag, medium, op, h->raw))) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    dfree(h, dptr); dfree(h, dcol); dfree(h, dval);
+    return after_block(h, family, lag, medium, op);
+}
+
+int mot_reset(mot_handle* h) {
+    if (!h) return MOT_EINVAL;
+    h->k = 0;
+    HIPCHK(h, hipMemsetAsync(h->d_k, 0, sizeof(int), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ring, 0, (size_t)h->nh * h->n2 * sizeof(double), h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MOT_OK;
+}
+
+int mot_step(mot_handle* h, mot_step_info* info) {
+    if (!h) return MOT_EINVAL;
+    if (!all_folded(h)) return mot_fail(h, MOT_ESTATE, "lag matrices missing: upload every block first");
+    using namespace motk_step;
+    inc_step(h);
+    h->k += 1;
+    rhs_fields(h);
+    history(h);
+    warm_start(h);
+    int rc = gmres_solve(h);
+    if (rc && rc != MOT_ENOCONV) return rc;
+    push(h);
+    HIPCHK(h, hipGetLastError());
+    if (info) {
+        info->step = h->k;
+        info->gmres_iters = h->last_iters;
+        info->gmres_relres = h->last_relres;
+        info->converged = h->last_conv;
+    }
+    if (rc) mot_fail(h, rc, "GMRES did not reach the tolerance at step " + std::to_string(h->k));
+    return rc;
+}
+
+int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, double* star_out,
+            int32_t out_on_device, mot_step_info* last) {
+    if (!h) return MOT_EINVAL;
+    if (nsteps < 0) return mot_fail(h, MOT_EINVAL, "nsteps < 0");
+    if ((w_out || loop_out || star_out) && (!h->hist || h->k + nsteps > h->hist_cap))
+        return mot_fail(h, MOT_EINVAL, "outputs need keep_history and max_steps >= steps taken");
+    int s0 = h->k;
+    int worst = MOT_OK;
+    mot_step_info inf{};
+    for (int i = 0; i < nsteps; ++i) {
+        int rc = mot_step(h, &inf);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        if (rc) worst = rc;
+    }
+    if (last) *last = inf;
+    if (!(w_out || loop_out || star_out) || nsteps == 0) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return worst;
+    }
+    const size_t per = (size_t)2 * h->ne * h->R;
+    const size_t tot = per * nsteps;
+    double *dw = nullptr, *dl = nullptr, *ds = nullptr;
+    int rc;
+    if (w_out) {
+        if (out_on_device) dw = w_out; else if ((rc = dalloc(h, &dw, tot, false))) return rc;
+        motk_step::pack(h, nsteps, h->hist + (size_t)s0 * h->n2 * h->R, dw);
+    }
+    if (loop_out) { if (out_on_device) dl = loop_out; else if ((rc = dalloc(h, &dl, tot, false))) return rc; }
+    if (star_out) { if (out_on_device) ds = star_out; else if ((rc = dalloc(h, &ds, tot, false))) return rc; }
+    if (loop_out || star_out) {
+        rc = recover(h, s0, nsteps, dl, ds);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        if (rc) worst = rc;
+    }
+    if (!out_on_device) {
+        if (w_out) { HIPCHK(h, hipMemcpyAsync(w_out, dw, tot * sizeof(double), hipMemcpyDeviceToHost, h->stream)); }
+        if (loop_out) { HIPCHK(h, hipMemcpyAsync(loop_out, dl, tot * sizeof(double), hipMemcpyDeviceToHost, h->stream)); }
+        if (star_out) { HIPCHK(h, hipMemcpyAsync(star_out, ds, tot * sizeof(double), hipMemcpyDeviceToHost, h->stream)); }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (!out_on_device) { dfree(h, dw); dfree(h, dl); dfree(h, ds); }
+    return worst;
+}
+
+int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
+    if (!h || !out) return MOT_EINVAL;
+    const int ne = h->ne, hs = h->hs;
+    const size_t blk = (size_t)ne * hs;
+    hipStream_t s = h->stream;
+    auto copy_blk = [&](const double* src, double* dst, int ldd) -> int {
+        HIPCHK(h, hipMemcpy2DAsync(dst, ldd * sizeof(double), src, hs * sizeof(double), ne * sizeof(double), ne,
+                                   hipMemcpyDeviceToHost, s));
+        return MOT_OK;
+    };
+    int rc = MOT_OK;
+    if (which == 0) {
+        if (lag < 0 || lag >= h->nlags) return mot_fail(h, MOT_EINVAL, "lag out of range");
+        if (!h->lag_done[lag]) return mot_fail(h, MOT_ESTATE, "lag not folded yet");
+        const double* q = h->Q + (size_t)lag * 3 * blk;
+        const int n = 2 * ne;
+        std::vector<double> buf((size_t)ne * ne);
+        // Q = [[q1, -qk], [qk, q2]]
+        for (int b = 0; b < 3; ++b) {
+            if ((rc = copy_blk(q + b * blk, buf.data(), ne))) return rc;
+            HIPCHK(h, hipStreamSynchronize(s));
+            for (int i = 0; i < ne; ++i)
+                for (int j = 0; j < ne; ++j) {
+                    double v = buf[(size_t)i * ne + j];
+                    if (b == 0) out[(size_t)i * n + j] = v;
+                    else if (b == 2) out[(size_t)(ne + i) * n + ne + j] = v;
+                    else { out[(size_t)i * n + ne + j] = -v; out[(size_t)(ne + i) * n + j] = v; }
+                }
+        }
+        return MOT_OK;
+    }
+    const double* src = which == 1 ? h->C1 : which == 2 ? h->C2 : which == 3 ? h->PS : which == 4 ? h->BL :
+                        which == 5 ? h->Ginv : nullptr;
+    if (src) {
+        if ((rc = copy_blk(src, out, ne))) return rc;
+        HIPCHK(h, hipStreamSynchronize(s));
+        return MOT_OK;
+    }
+    if (which == 6) {
+        // r_lag = C1 ebar + C2 Ebar / T_max at step 'lag' (history terms excluded)
+        if (lag < 1) return mot_fail(h, MOT_EINVAL, "step >= 1");
+        int kk = lag;
+        HIPCHK(h, hipMemcpyAsync(h->d_k, &kk, sizeof(int), hipMemcpyHostToDevice, s));
+        motk_step::rhs_fields(h);
+        // history with k = 1 has no lag terms: temporarily use a device int of 1
+        int one = 1;
+        int* save = h->d_k;
+        int* d1;
+        if ((rc = upload(h, &d1, &one, 1))) return rc;
+        h->d_k = d1;
+        motk_step::history(h);
+        h->d_k = save;
+        std::vector<double> tmp(h->n2);
+        HIPCHK(h, hipMemcpyAsync(tmp.data(), h->y, h->n2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(h->d_k, &h->k, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        dfree(h, d1);
+        for (int i = 0; i < ne; ++i) { out[i] = tmp[i]; out[ne + i] = tmp[hs + i]; }
+        return MOT_OK;
+    }
+    return mot_fail(h, MOT_EINVAL, "unknown matrix id");
+}
+
+int mot_get_info(const mot_handle* h, mot_info* info) {
+    if (!h || !info) return MOT_EINVAL;
+    info->D = h->D; info->Tmax = h->Tmax; info->dt = h->dt;
+    info->kmax = h->kmax; info->nlags = h->nlags;
+    info->ne = h->ne; info->n = 2 * h->ne; info->nrhs = h->R;
+    info->genus = h->genus;
+    info->folded = all_folded(h) ? 1 : 0;
+    info->steps_done = h->k;
+    info->device_bytes = h->bytes;
+    info->setup_ms = h->setup_ms;
+    info->fold_ms = h->fold_ms;
+    return MOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal declarations of the MOT library (device kernels and host glue).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/mot.h"
+
+#define MOT_MAXM 64          // largest GMRES restart length
+#define MOT_GM_BLOCKS 64     // blocks of the GMRES reduction kernels
+#define MOT_CG_CHUNKS 32     // row chunks of column-batched reductions
+
+// ---------------------------------------------------------------- graphs ---
+// Incidence of one family of nodes (faces for Sigma, vertices for Lambda):
+// edge m joins node plus[m] (+1) and minus[m] (-1).  inc_*: node -> incident
+// edges (CSR) with signs; adj_*: node -> neighbour nodes (CSR, one per edge).
+struct DevGraph {
+    int nnode = 0, ne = 0;
+    int* plus = nullptr;
+    int* minus = nullptr;
+    int* inc_ptr = nullptr;
+    int* inc_edge = nullptr;
+    double* inc_sign = nullptr;
+    int* adj_ptr = nullptr;
+    int* adj = nullptr;
+};
+
+struct DevCSR {
+    int n = 0, nnz = 0;
+    int* ptr = nullptr;
+    int* col = nullptr;
+    double* val = nullptr;
+};
+
+// GMRES state in device memory (one right-hand side).
+struct GmState {
+    double H[(MOT_MAXM + 1) * MOT_MAXM];   // column j at H[j*(M+1) + i]
+    double h1[MOT_MAXM + 1];
+    double cs[MOT_MAXM], sn[MOT_MAXM], g[MOT_MAXM + 1], y[MOT_MAXM];
+    double beta, bnorm, relres, inv_h;
+    int j, done, converged, total, cycle_iters, breakdown;
+    unsigned int counter;
+    int pad;
+    double partial[(MOT_MAXM + 1) * MOT_GM_BLOCKS];
+};
+
+// Host-visible progress word written by the device after each Arnoldi step.
+struct GmFlag {
+    volatile int seq;
+    volatile int done;
+    volatile int converged;
+    volatile int total;
+    volatile double relres;
+};
+
+// --------------------------------------------------------- kernel entry ---
+namespace motk {
+// dense
+void gemm(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc);
+void axpby2d(hipStream_t s, int rows, int cols, double a, const double* X, int ldx, double b,
+             double* Y, int ldy);                       // Y = a X + b Y
+void fill2d(hipStream_t s, int rows, int cols, double v, double* Y, int ldy);
+void set_identity(hipStream_t s, int n, double* Y, int ldy);
+void scatter_csr_add(hipStream_t s, int n, const int64_t* ptr, const int* col, const double* val,
+                     double a, double* Y, int ldy);     // Y += a * CSR
+// column-batched ops on [rows][ncol] row-major arrays (ld = ncol)
+void spmm_csr(hipStream_t s, const DevCSR& A, int ncol, const double* X, double* Y);
+void spmm_lap(hipStream_t s, const DevGraph& g, int ncol, const double* X, double* Y);
+void inc_T(hipStream_t s, const DevGraph& g, int ncol, const double* X, int ldx, double* S);
+void inc_apply(hipStream_t s, const DevGraph& g, int ncol, const double* Z, double* Y, int ldy);
+void coldot(hipStream_t s, int rows, int ncol, const double* A, const double* B, double* part,
+            double* out);                               // out[c] = sum_i A[i,c] B[i,c]
+void cg_update(hipStream_t s, int rows, int ncol, const double* alpha, const double* P,
+               const double* Q, double* X, double* R, double* part);
+void cg_scalars(hipStream_t s, int ncol, const double* pq, const double* rr_new_part, int nchunk,
+                double* rr, double* rr0, double* alpha, double* beta, int* active, double tol,
+                int phase);
+void cg_pupdate(hipStream_t s, int rows, int ncol, const double* beta, const double* R, double* P);
+int count_active(hipStream_t s, int ncol, const int* active, int* d_count, int* h_count);
+}  // namespace motk
+
+// ------------------------------------------------------------ the handle ---
+struct mot_handle {
+    hipStream_t stream = nullptr;
+    std::string err;
+    mot_options opt;
+    int nv = 0, nf = 0, ne = 0, hs = 0, n2 = 0, R = 1;
+    double eps_r = 1, mu_r = 1, dt = 1, D = 0, Tmax = 0;
+    double c = 1, eta = 1, cp = 1, etap = 1;
+    int kmax = 0, nlags = 0, nh = 0, genus = 0;
+    double setup_ms = 0, fold_ms = 0;
+    uint64_t bytes = 0;
+    std::vector<void*> allocs;
+    std::vector<size_t> sizes;
+
+    DevGraph gf, gv;                 // faces (Sigma), vertices (Lambda)
+    DevCSR G, GT;
+    // RHS quadrature geometry: per (edge, side, point)
+    double* rq_x = nullptr;          // [ne][2][7][3]
+    double* rq_f = nullptr;          // [ne][2][7][3]   weight * RWG value
+    double* waves = nullptr;         // [R][9]: amp, pol(3), dir(3), width, t0
+    double* tcut = nullptr;          // [R]
+
+    double *PS = nullptr, *BL = nullptr, *Ginv = nullptr, *C1 = nullptr, *C2 = nullptr;
+    double* Q = nullptr;             // [nlags][3][ne][hs]: q1, qk, q2 per lag
+
+    // lag staging: per lag, per family, 3 media-summed blocks [3][ne][hs]
+    std::vector<double*> stage;      // index lag*3 + family
+    std::vector<uint32_t> got;       // arrival bits per lag: family*4 + medium*2 + op
+    std::vector<char> lag_done;
+    double* tmp = nullptr;           // [3][ne][hs] fold temporaries
+    double* raw = nullptr;           // [ne][hs] upload buffer
+
+    // march state
+    int* d_k = nullptr;              // current step (device)
+    int k = 0;
+    double* ring = nullptr;          // [nh][n2][R]
+    double* hist = nullptr;          // [max_steps][n2][R]
+    int hist_cap = 0;
+    double* ebar = nullptr;          // [n2][R]
+    double* Ebar = nullptr;
+    double* y = nullptr;             // rhs - history
+    double* x = nullptr;             // solution of the step
+    // GMRES workspace (R = 1 path)
+    double* V = nullptr;             // [M+1][n2]
+    double* wA = nullptr;
+    double* wB = nullptr;
+    GmState* gm = nullptr;
+    GmFlag* hflag = nullptr;         // pinned, device-mapped
+    GmFlag* dflag = nullptr;
+    int M = 40;
+    int last_iters = 0;
+    double last_relres = 0;
+    int last_conv = 1;
+};
+
+// host glue implemented in mot_api.hip
+int mot_fail(mot_handle* h, int code, const std::string& msg);

@@ -1,0 +1,547 @@
+// Per-step kernels of the marching-on-in-time loop (single right-hand side).
+#include "mot_internal.h"
+
+namespace {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------ tested incident ---
+// Section V-C: ebar_k = (1/dt) int_{(k-1)dt}^{k dt} (e; h) dt and
+// Ebar_k = int_{-inf}^{k dt} (e; h) dt, tested with n x f_m (= -<f_m, .>).
+// Gaussian time integral: A/(2c) p (1 + erf s), s = (4/w)(c(t - t0) - k.x).
+__device__ __forceinline__ double erf_diff(double s1, double s0) {
+    if (s0 >= 0.0) return erfc(s0) - erfc(s1);
+    if (s1 <= 0.0) return erfc(-s1) - erfc(-s0);
+    return erf(s1) - erf(s0);
+}
+
+__global__ void k_rhs_fields(int ne, int hs, int R, const int* __restrict__ dk, double dt,
+                             const double* __restrict__ X, const double* __restrict__ Fw,
+                             const double* __restrict__ waves, const double* __restrict__ tcut,
+                             double* __restrict__ ebar, double* __restrict__ Ebar) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * R) return;
+    int m = t / R, r = t % R;
+    const int k = *dk;
+    const double* wv = waves + 9 * r;
+    const double amp = wv[0], w = wv[7], t0 = wv[8];
+    const double px = wv[1], py = wv[2], pz = wv[3];
+    const double kx = wv[4], ky = wv[5], kz = wv[6];
+    // h polarisation k x p (eta = 1)
+    const double hx = ky * pz - kz * py, hy = kz * px - kx * pz, hz = kx * py - ky * px;
+    const double c4 = 4.0 / w;
+    const double tk = k * dt, tk1 = (k - 1) * dt;
+    const bool star_on = tk <= tcut[r];
+    double ee = 0, eh = 0, Ee = 0, Eh = 0;
+    for (int q = 0; q < 14; ++q) {
+        const double* x = X + ((size_t)m * 14 + q) * 3;
+        const double* f = Fw + ((size_t)m * 14 + q) * 3;
+        double kdx = kx * x[0] + ky * x[1] + kz * x[2];
+        double s1 = c4 * ((tk - t0) - kdx), s0 = c4 * ((tk1 - t0) - kdx);
+        double te = erf_diff(s1, s0) / dt;
+        double tE = star_on ? erfc(-s1) : 0.0;
+        double fp = f[0] * px + f[1] * py + f[2] * pz;
+        double fh = f[0] * hx + f[1] * hy + f[2] * hz;
+        ee += te * fp; eh += te * fh;
+        Ee += tE * fp; Eh += tE * fh;
+    }
+    const double a = -0.5 * amp;   // -(A / (2c)), the minus from n x f testing
+    ebar[(size_t)m * R + r] = a * ee;
+    ebar[(size_t)(hs + m) * R + r] = a * eh;
+    Ebar[(size_t)m * R + r] = a * Ee;
+    Ebar[(size_t)(hs + m) * R + r] = a * Eh;
+}
+
+// ------------------------------------------------ streamed row products ---
+// One wavefront per output row m; two accumulators (u-half row m, v-half row m).
+// acc += A[m, :] . x with 16-byte loads, four in flight per lane.
+__device__ __forceinline__ void row2(const double* __restrict__ A, const double* __restrict__ xa,
+                                     const double* __restrict__ xb, int len, int lane, double& sa,
+                                     double& sb) {
+    const d2v* a2 = reinterpret_cast<const d2v*>(A);
+    const d2v* x2 = reinterpret_cast<const d2v*>(xa);
+    const d2v* y2 = reinterpret_cast<const d2v*>(xb);
+    const int n2 = len >> 1;
+    int c = lane;
+    for (; c + 192 < n2; c += 256) {
+        d2v a0 = __builtin_nontemporal_load(a2 + c), a1 = __builtin_nontemporal_load(a2 + c + 64);
+        d2v a2_ = __builtin_nontemporal_load(a2 + c + 128), a3 = __builtin_nontemporal_load(a2 + c + 192);
+        d2v u0 = x2[c], u1 = x2[c + 64], u2 = x2[c + 128], u3 = x2[c + 192];
+        d2v v0 = y2[c], v1 = y2[c + 64], v2 = y2[c + 128], v3 = y2[c + 192];
+        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
+        sa = fma(a1.x, u1.x, sa); sa = fma(a1.y, u1.y, sa);
+        sa = fma(a2_.x, u2.x, sa); sa = fma(a2_.y, u2.y, sa);
+        sa = fma(a3.x, u3.x, sa); sa = fma(a3.y, u3.y, sa);
+        sb = fma(a0.x, v0.x, sb); sb = fma(a0.y, v0.y, sb);
+        sb = fma(a1.x, v1.x, sb); sb = fma(a1.y, v1.y, sb);
+        sb = fma(a2_.x, v2.x, sb); sb = fma(a2_.y, v2.y, sb);
+        sb = fma(a3.x, v3.x, sb); sb = fma(a3.y, v3.y, sb);
+    }
+    for (; c < n2; c += 64) {
+        d2v a0 = __builtin_nontemporal_load(a2 + c);
+        d2v u0 = x2[c], v0 = y2[c];
+        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
+        sb = fma(a0.x, v0.x, sb); sb = fma(a0.y, v0.y, sb);
+    }
+}
+
+__device__ __forceinline__ void row1(const double* __restrict__ A, const double* __restrict__ xa,
+                                     int len, int lane, double& sa) {
+    const d2v* a2 = reinterpret_cast<const d2v*>(A);
+    const d2v* x2 = reinterpret_cast<const d2v*>(xa);
+    const int n2 = len >> 1;
+    int c = lane;
+    for (; c + 192 < n2; c += 256) {
+        d2v a0 = __builtin_nontemporal_load(a2 + c), a1 = __builtin_nontemporal_load(a2 + c + 64);
+        d2v a2_ = __builtin_nontemporal_load(a2 + c + 128), a3 = __builtin_nontemporal_load(a2 + c + 192);
+        d2v u0 = x2[c], u1 = x2[c + 64], u2 = x2[c + 128], u3 = x2[c + 192];
+        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
+        sa = fma(a1.x, u1.x, sa); sa = fma(a1.y, u1.y, sa);
+        sa = fma(a2_.x, u2.x, sa); sa = fma(a2_.y, u2.y, sa);
+        sa = fma(a3.x, u3.x, sa); sa = fma(a3.y, u3.y, sa);
+    }
+    for (; c < n2; c += 64) {
+        d2v a0 = __builtin_nontemporal_load(a2 + c);
+        d2v u0 = x2[c];
+        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
+    }
+}
+
+// y = C1 ebar + (1/T_max) C2 Ebar - sum_{j=1}^{min(k-1, nh)} Q_j w_{k-j}
+// (eq. MOT right-hand side, eq. rhs).  Q_j = [[q1, -qk], [qk, q2]] in three
+// [ne][hs] blocks; ring slot of w_{k-j} is (k-j) mod nh.
+__global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __restrict__ dk, int nh,
+                                                 const double* __restrict__ Q,
+                                                 const double* __restrict__ ring,
+                                                 const double* __restrict__ C1,
+                                                 const double* __restrict__ C2, double invT,
+                                                 const double* __restrict__ ebar,
+                                                 const double* __restrict__ Ebar,
+                                                 double* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= ne) return;
+    const int k = *dk;
+    const size_t blk = (size_t)ne * hs;
+    const int n2 = 2 * hs;
+    double su = 0, sv = 0, tu = 0, tv = 0;
+    row2(C1 + (size_t)m * hs, ebar, ebar + hs, hs, lane, su, sv);
+    row2(C2 + (size_t)m * hs, Ebar, Ebar + hs, hs, lane, tu, tv);
+    su += invT * tu;
+    sv += invT * tv;
+    int nact = k - 1 < nh ? k - 1 : nh;
+    double hu = 0, hv = 0;
+    for (int j = 1; j <= nact; ++j) {
+        int slot = (k - j) % nh;
+        const double* wu = ring + (size_t)slot * n2;
+        const double* wv = wu + hs;
+        const double* Qj = Q + (size_t)j * 3 * blk + (size_t)m * hs;
+        double a = 0, b = 0, cc = 0, d = 0;
+        row1(Qj, wu, hs, lane, a);                      // q1 u
+        row2(Qj + blk, wv, wu, hs, lane, b, cc);        // qk v, qk u
+        row1(Qj + 2 * blk, wv, hs, lane, d);            // q2 v
+        hu += a - b;
+        hv += cc + d;
+    }
+    su = wave_sum(su - hu);
+    sv = wave_sum(sv - hv);
+    if (lane == 0) {
+        y[m] = su;
+        y[hs + m] = sv;
+    }
+}
+
+// ------------------------------------------------------------------ GMRES ---
+// Arnoldi with classical Gram-Schmidt and one re-orthogonalisation, Givens
+// rotations and the triangular solve on the device.  Reductions use per-block
+// partials and a last-block-done finish (fixed summation order).
+
+__device__ __forceinline__ bool last_block(unsigned int* counter) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// y = Q0 * (scale * src); when vout != nullptr also write vout = scale * src
+// (rows this wave owns).  scale is read from gm->inv_h when use_inv.
+__global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double* __restrict__ Q0,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ vout, double* __restrict__ y,
+                                                   const GmState* __restrict__ gm, int check_done) {
+    if (check_done && gm->done) return;
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= ne) return;
+    const size_t blk = (size_t)ne * hs;
+    const double sc = check_done ? gm->inv_h : 1.0;
+    const double* xu = src;
+    const double* xv = src + hs;
+    double a = 0, b = 0, cc = 0, d = 0;
+    row1(Q0 + (size_t)m * hs, xu, hs, lane, a);
+    row2(Q0 + blk + (size_t)m * hs, xv, xu, hs, lane, b, cc);
+    row1(Q0 + 2 * blk + (size_t)m * hs, xv, hs, lane, d);
+    a = wave_sum(a - b);
+    cc = wave_sum(cc + d);
+    if (lane == 0) {
+        y[m] = sc * a;
+        y[hs + m] = sc * cc;
+        if (vout) {
+            vout[m] = sc * src[m];
+            vout[hs + m] = sc * src[hs + m];
+        }
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+// r = b - r ; beta = ||r||, bnorm = ||b|| ; start a cycle.
+__global__ __launch_bounds__(256) void k_gm_residual(int n2, const double* __restrict__ b,
+                                                     double* __restrict__ r, GmState* gm,
+                                                     GmFlag* flag, double tol, int first) {
+    __shared__ double sh[8];
+    double s1 = 0, s2 = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double bi = b[i];
+        double ri = bi - r[i];
+        r[i] = ri;
+        s1 = fma(ri, ri, s1);
+        s2 = fma(bi, bi, s2);
+    }
+    s1 = block_sum(s1, sh);
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        gm->partial[blockIdx.x] = s1;
+        gm->partial[MOT_GM_BLOCKS + blockIdx.x] = s2;
+    }
+    if (!last_block(&gm->counter)) return;
+    if (threadIdx.x == 0) {
+        double rr = 0, bb = 0;
+        for (int i = 0; i < (int)gridDim.x; ++i) { rr += gm->partial[i]; bb += gm->partial[MOT_GM_BLOCKS + i]; }
+        double beta = sqrt(rr);
+        if (first) { gm->bnorm = sqrt(bb); gm->total = 0; }
+        gm->beta = beta;
+        gm->g[0] = beta;
+        gm->j = 0;
+        gm->cycle_iters = 0;
+        gm->breakdown = 0;
+        double bn = gm->bnorm;
+        gm->relres = bn > 0 ? beta / bn : 0.0;
+        int conv = (bn == 0.0) || (beta <= tol * bn);
+        gm->converged = conv;
+        gm->done = conv;
+        gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+        gm->counter = 0;
+        flag->relres = gm->relres;
+        flag->converged = conv;
+        flag->done = conv;
+        flag->total = gm->total;
+        __threadfence_system();
+        flag->seq = flag->seq + 1;
+    }
+}
+
+// h1[l] = V[l] . w  for l <= j
+__global__ __launch_bounds__(256) void k_gm_dots(int n2, const double* __restrict__ V,
+                                                 const double* __restrict__ w, GmState* gm) {
+    if (gm->done) return;
+    const int j = gm->j;
+    const int nb = gridDim.x;
+    const int i0 = (int)((int64_t)n2 * blockIdx.x / nb), i1 = (int)((int64_t)n2 * (blockIdx.x + 1) / nb);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int l = wv; l <= j; l += nw) {
+        const double* v = V + (size_t)l * n2;
+        double s = 0;
+        for (int i = i0 + lane; i < i1; i += 64) s = fma(v[i], w[i], s);
+        s = wave_sum(s);
+        if (lane == 0) gm->partial[(size_t)l * MOT_GM_BLOCKS + blockIdx.x] = s;
+    }
+    if (!last_block(&gm->counter)) return;
+    for (int l = threadIdx.x; l <= j; l += blockDim.x) {
+        double s = 0;
+        for (int b = 0; b < nb; ++b) s += gm->partial[(size_t)l * MOT_GM_BLOCKS + b];
+        gm->h1[l] = s;
+    }
+    if (threadIdx.x == 0) gm->counter = 0;
+}
+
+// w -= V h1 ; then h2 = V . w (stored into H column j), or ||w||^2 for the final pass
+__global__ __launch_bounds__(256) void k_gm_orth(int n2, const double* __restrict__ V,
+                                                 double* __restrict__ w, GmState* gm, GmFlag* flag,
+                                                 double tol, int M, int final_pass) {
+    if (gm->done) return;
+    const int j = gm->j;
+    const int nb = gridDim.x;
+    const int i0 = (int)((int64_t)n2 * blockIdx.x / nb), i1 = (int)((int64_t)n2 * (blockIdx.x + 1) / nb);
+    __shared__ double hl[MOT_MAXM + 1];
+    for (int l = threadIdx.x; l <= j; l += blockDim.x) hl[l] = gm->h1[l];
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        double s = w[i];
+        for (int l = 0; l <= j; ++l) s = fma(-hl[l], V[(size_t)l * n2 + i], s);
+        w[i] = s;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (!final_pass) {
+        for (int l = wv; l <= j; l += nw) {
+            const double* v = V + (size_t)l * n2;
+            double s = 0;
+            for (int i = i0 + lane; i < i1; i += 64) s = fma(v[i], w[i], s);
+            s = wave_sum(s);
+            if (lane == 0) gm->partial[(size_t)l * MOT_GM_BLOCKS + blockIdx.x] = s;
+        }
+    } else {
+        __shared__ double sh[8];
+        double s = 0;
+        for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) s = fma(w[i], w[i], s);
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) gm->partial[blockIdx.x] = s;
+    }
+    if (!last_block(&gm->counter)) return;
+    if (!final_pass) {
+        // H[:, j] = h1 (first pass) ; keep h1 <- h2 for the second update
+        for (int l = threadIdx.x; l <= j; l += blockDim.x) {
+            double s = 0;
+            for (int b = 0; b < nb; ++b) s += gm->partial[(size_t)l * MOT_GM_BLOCKS + b];
+            gm->H[(size_t)j * (M + 1) + l] = hl[l];
+            gm->h1[l] = s;
+        }
+        if (threadIdx.x == 0) gm->counter = 0;
+        return;
+    }
+    if (threadIdx.x != 0) return;
+    double nn = 0;
+    for (int b = 0; b < nb; ++b) nn += gm->partial[b];
+    double hn = sqrt(nn);
+    double* col = gm->H + (size_t)j * (M + 1);
+    for (int l = 0; l <= j; ++l) col[l] += hl[l];      // h1 + h2
+    col[j + 1] = hn;
+    // apply previous rotations
+    for (int l = 0; l < j; ++l) {
+        double a = col[l], b = col[l + 1];
+        col[l] = gm->cs[l] * a + gm->sn[l] * b;
+        col[l + 1] = -gm->sn[l] * a + gm->cs[l] * b;
+    }
+    double a = col[j], b = col[j + 1];
+    double r = hypot(a, b);
+    double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
+    gm->cs[j] = cs;
+    gm->sn[j] = sn;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    double gj = gm->g[j];
+    gm->g[j] = cs * gj;
+    gm->g[j + 1] = -sn * gj;
+    int jj = j + 1;
+    gm->j = jj;
+    gm->cycle_iters = jj;
+    gm->total += 1;
+    double rel = gm->bnorm > 0 ? fabs(gm->g[jj]) / gm->bnorm : 0.0;
+    gm->relres = rel;
+    int conv = rel <= tol;
+    int brk = !(hn > 1e-300 * (gm->beta + 1e-300));
+    gm->breakdown = brk;
+    gm->converged = conv || brk;
+    gm->done = conv || brk || jj >= M;
+    gm->inv_h = hn > 0 ? 1.0 / hn : 0.0;
+    // triangular solve for the cycle so far (cheap; used when done)
+    if (gm->done) {
+        for (int i = jj - 1; i >= 0; --i) {
+            double s = gm->g[i];
+            for (int l = i + 1; l < jj; ++l) s -= gm->H[(size_t)l * (M + 1) + i] * gm->y[l];
+            double d = gm->H[(size_t)i * (M + 1) + i];
+            gm->y[i] = d != 0 ? s / d : 0.0;
+        }
+    }
+    gm->counter = 0;
+    flag->relres = rel;
+    flag->converged = gm->converged;
+    flag->done = gm->done;
+    flag->total = gm->total;
+    __threadfence_system();
+    flag->seq = flag->seq + 1;
+}
+
+// x += sum_l y[l] V[l]   (l < cycle length)
+__global__ void k_gm_update_x(int n2, const double* __restrict__ V, const GmState* __restrict__ gm,
+                              double* __restrict__ x) {
+    const int jj = gm->cycle_iters;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double s = x[i];
+        for (int l = 0; l < jj; ++l) s = fma(gm->y[l], V[(size_t)l * n2 + i], s);
+        x[i] = s;
+    }
+}
+
+// ------------------------------------------------------------ ring / misc ---
+// x0 = 2 w_{k-1} - w_{k-2} (or w_{k-1}, or 0) from the ring
+__global__ void k_warm_start(int n2, const int* __restrict__ dk, int nh,
+                             const double* __restrict__ ring, double* __restrict__ x) {
+    const int k = *dk;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (k >= 3 && nh >= 2) {
+            v = 2.0 * ring[(size_t)((k - 1) % nh) * n2 + i] - ring[(size_t)((k - 2) % nh) * n2 + i];
+        } else if (k >= 2) {
+            v = ring[(size_t)((k - 1) % nh) * n2 + i];
+        }
+        x[i] = v;
+    }
+}
+
+// ring[k mod nh] = x ; hist[k-1] = x (if hist)
+__global__ void k_push(int n2, const int* __restrict__ dk, int nh, const double* __restrict__ x,
+                       double* __restrict__ ring, double* __restrict__ hist, int hist_cap) {
+    const int k = *dk;
+    double* slot = ring + (size_t)(k % nh) * n2;
+    double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 : nullptr;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double v = x[i];
+        slot[i] = v;
+        if (hs) hs[i] = v;
+    }
+}
+
+__global__ void k_inc_step(int* dk) { *dk += 1; }
+
+// recovery gather: columns (step s in [s0, s1), half h, kind t, rhs r) of
+// X[ne][ncol], kind 0 = u_k, kind 1 = u_k - u_{k-1} (u_0 = 0)
+__global__ void k_rec_gather(int ne, int hs, int n2, int R, int s0, int ns,
+                             const double* __restrict__ hist, double* __restrict__ X) {
+    const int ncol = ns * 4 * R;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int m = blockIdx.y;
+    if (c >= ncol) return;
+    int r = c % R, t = (c / R) % 2, hh = (c / (2 * R)) % 2, s = c / (4 * R);
+    int step = s0 + s;     // 0-based index into hist
+    size_t off = (size_t)(hh * hs + m) * R + r;
+    double v = hist[(size_t)step * n2 * R + off];
+    if (t == 1 && step > 0) v -= hist[(size_t)(step - 1) * n2 * R + off];
+    X[(size_t)m * ncol + c] = v;
+}
+
+// loop = u - P^Sigma u ; star = (Tmax/dt) P^Sigma (u_k - u_{k-1}); outputs [ns][n][R] packed (n = 2 ne)
+__global__ void k_rec_scatter(int ne, int R, int ns, const double* __restrict__ X,
+                              const double* __restrict__ PX, double scale, double* __restrict__ loop,
+                              double* __restrict__ star) {
+    const int ncol = ns * 4 * R;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int m = blockIdx.y;
+    if (c >= ncol) return;
+    int r = c % R, t = (c / R) % 2, hh = (c / (2 * R)) % 2, s = c / (4 * R);
+    size_t o = ((size_t)s * 2 * ne + (size_t)hh * ne + m) * R + r;
+    double px = PX[(size_t)m * ncol + c];
+    if (t == 0) {
+        if (loop) loop[o] = X[(size_t)m * ncol + c] - px;
+    } else {
+        if (star) star[o] = scale * px;
+    }
+}
+
+// pack w from the internal padded layout [n2][R] to [n][R]
+__global__ void k_pack(int ne, int hs, int R, int ns, const double* __restrict__ src,
+                       double* __restrict__ dst) {
+    size_t total = (size_t)ns * 2 * ne * R;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        int r = (int)(t % R);
+        size_t q = t / R;
+        int i = (int)(q % (2 * ne));
+        size_t s = q / (2 * ne);
+        int row = i < ne ? i : hs + (i - ne);
+        dst[t] = src[(s * 2 * hs + row) * R + r];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ---
+namespace motk_step {
+
+void rhs_fields(mot_handle* h) {
+    int tot = h->ne * h->R;
+    hipLaunchKernelGGL(k_rhs_fields, dim3((tot + 127) / 128), dim3(128), 0, h->stream, h->ne, h->hs, h->R,
+                       h->d_k, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
+}
+
+void history(mot_handle* h) {
+    hipLaunchKernelGGL(k_history, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
+                       h->nh, h->Q, h->ring, h->C1, h->C2, 1.0 / h->Tmax, h->ebar, h->Ebar, h->y);
+}
+
+void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done) {
+    hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
+                       src, vout, y, h->gm, check_done);
+}
+
+void gm_residual(mot_handle* h, const double* b, double* r, int first) {
+    hipLaunchKernelGGL(k_gm_residual, dim3(MOT_GM_BLOCKS), dim3(256), 0, h->stream, h->n2, b, r, h->gm,
+                       h->dflag, h->opt.gmres_tol, first);
+}
+
+void gm_dots(mot_handle* h, const double* w) {
+    hipLaunchKernelGGL(k_gm_dots, dim3(MOT_GM_BLOCKS), dim3(256), 0, h->stream, h->n2, h->V, w, h->gm);
+}
+
+void gm_orth(mot_handle* h, double* w, int final_pass) {
+    hipLaunchKernelGGL(k_gm_orth, dim3(MOT_GM_BLOCKS), dim3(256), 0, h->stream, h->n2, h->V, w, h->gm,
+                       h->dflag, h->opt.gmres_tol, h->M, final_pass);
+}
+
+void gm_update_x(mot_handle* h, double* x) {
+    hipLaunchKernelGGL(k_gm_update_x, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->V,
+                       h->gm, x);
+}
+
+void warm_start(mot_handle* h) {
+    hipLaunchKernelGGL(k_warm_start, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->d_k,
+                       h->nh, h->ring, h->x);
+}
+
+void push(mot_handle* h) {
+    hipLaunchKernelGGL(k_push, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->d_k, h->nh,
+                       h->x, h->ring, h->hist, h->hist_cap);
+}
+
+void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 0, h->stream, h->d_k); }
+
+void rec_gather(mot_handle* h, int s0, int ns, double* X) {
+    int ncol = ns * 4 * h->R;
+    dim3 grid((ncol + 255) / 256, h->ne);
+    hipLaunchKernelGGL(k_rec_gather, grid, dim3(256), 0, h->stream, h->ne, h->hs, h->n2, h->R, s0, ns,
+                       h->hist, X);
+}
+
+void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, double* loop, double* star) {
+    int ncol = ns * 4 * h->R;
+    dim3 grid((ncol + 255) / 256, h->ne);
+    hipLaunchKernelGGL(k_rec_scatter, grid, dim3(256), 0, h->stream, h->ne, h->R, ns, X, PX,
+                       h->Tmax / h->dt, loop, star);
+}
+
+void pack(mot_handle* h, int ns, const double* src, double* dst) {
+    size_t total = (size_t)ns * 2 * h->ne * h->R;
+    int nb = (int)((total + 255) / 256);
+    if (nb > 65535 * 8) nb = 65535 * 8;
+    hipLaunchKernelGGL(k_pack, dim3(nb), dim3(256), 0, h->stream, h->ne, h->hs, h->R, ns, src, dst);
+}
+
+}  // namespace motk_step

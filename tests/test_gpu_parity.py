@@ -1,0 +1,108 @@
+"""HIP path against the FP64 oracle, through the C ABI (MI355X only)."""
+import sys
+
+import numpy as np
+import pytest
+
+from tests._problems import problem, oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(name, **opts):
+    import paper_2510_07989_amd as p
+    prob = problem(name)
+    o = p.default_options(**opts)
+    s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                 prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=o)
+    s.load_raw(prob["raw"], prob["kmax"])
+    return s
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_torus", "sphere_480"])
+def test_setup_operators(name):
+    print("case", name, flush=True)
+    O = oracle(name)
+    s = _solver(name)
+    inf = s.info()
+    assert inf["kmax"] == O.kmax and inf["nlags"] == O.kmax + 2
+    assert abs(inf["Tmax"] - O.Tmax) < 1e-12 * O.Tmax
+    assert _rel(s.matrix(3), O.P["PS"]) < 1e-11
+    assert _rel(s.matrix(4), O.P["BL"]) < 1e-11
+    assert _rel(s.matrix(5), O.pre["Ginv"]) < 1e-11
+    assert _rel(s.matrix(1), O.pre["C1"]) < 1e-10
+    assert _rel(s.matrix(2), O.pre["C2"]) < 1e-10
+    for i in range(O.kmax + 2):
+        assert _rel(s.matrix(0, i), O.Q[i]) < 1e-10, i
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["tiny", "sphere_480"])
+def test_rhs(name):
+    print("case", name, flush=True)
+    O = oracle(name)
+    prob = problem(name)
+    s = _solver(name)
+    from oracle import mot_oracle as mo
+    for k in (1, 5, 17, 40):
+        eb, Eb = mo.tested_fields(prob["V"], prob["F"], prob["E"], prob["waves"], prob["dt"], k)
+        r = mo.rhs(O.pre, O.Tmax, eb, Eb)
+        assert _rel(s.matrix(6, k), r) < 1e-11, k
+    s.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("tiny", 40), ("tiny_torus", 60), ("sphere_480", 200)])
+def test_march_parity(name, nsteps):
+    print("case", name, nsteps, flush=True)
+    O = oracle(name)
+    ref = O.run(nsteps)
+    s = _solver(name)
+    out = s.run(nsteps)
+    assert out["rc"] == 0
+    e_w = _rel(out["w"], ref["W"])
+    e_l = _rel(out["loop"], ref["loop"])
+    e_s = _rel(out["star"], ref["star"])
+    print("errors w %.3e loop %.3e star %.3e" % (e_w, e_l, e_s), flush=True)
+    assert e_w < 1e-10 and e_l < 1e-10 and e_s < 1e-10
+    # e_max: worst step error against the peak
+    dw = np.linalg.norm((out["w"] - ref["W"]).reshape(nsteps, -1), axis=1).max()
+    assert dw < 1e-10 * np.linalg.norm(ref["W"].reshape(nsteps, -1), axis=1).max()
+    s.close()
+
+
+def test_step_api_matches_run():
+    s = _solver("tiny")
+    infos = [s.step() for _ in range(10)]
+    assert all(i["converged"] for i in infos)
+    assert infos[-1]["step"] == 10
+    s.reset()
+    out = s.run(10)
+    s2 = _solver("tiny")
+    out2 = s2.run(10)
+    assert np.array_equal(out["w"], out2["w"])        # deterministic reductions
+    s.close(); s2.close()
+
+
+def test_lag_errors():
+    import paper_2510_07989_amd as p
+    from paper_2510_07989_amd import _lib as L
+    prob = problem("tiny")
+    s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                 prob["T0s"], prob["T0h"], prob["G"], prob["waves"])
+    ne = prob["E"].shape[0]
+    z = np.zeros((ne, ne))
+    with pytest.raises(p.MotError) as e:
+        s.set_lag(L.FAM_TILDE, prob["kmax"], L.MED_EXT, L.OP_T, z)      # beyond k_max - 1
+    assert e.value.code == L.MOT_EINVAL
+    with pytest.raises(p.MotError) as e:
+        s.step()                                                          # lags missing
+    assert e.value.code == L.MOT_ESTATE
+    s.set_lag(L.FAM_H, 0, L.MED_EXT, L.OP_T, z)
+    with pytest.raises(p.MotError) as e:
+        s.set_lag(L.FAM_H, 0, L.MED_EXT, L.OP_T, z)                      # twice
+    assert e.value.code == L.MOT_ESTATE
+    s.close()
