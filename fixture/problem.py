@@ -109,7 +109,14 @@ def make_waves(nrhs, sigma, seeded, seed=MASTER_SEED):
 
 def build_problem(name=None, cfg=None, nsteps=None, with_raw=True, threads=None, verbose=False):
     """Assemble every input of a configuration (CPU, OpenMP)."""
+    import sys
+    import time
     from . import retarded_blocks, static_blocks
+
+    def say(msg):
+        if verbose:
+            print("[inputs] " + msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     if threads:
         os.environ["OMP_NUM_THREADS"] = str(threads)
     cfg = dict(CONFIGS[name] if cfg is None else cfg)
@@ -118,9 +125,12 @@ def build_problem(name=None, cfg=None, nsteps=None, with_raw=True, threads=None,
     D = geo.diameter(V)
     Tmax, kmax = tmax_kmax(D, dt, eps_r, mu_r)
     c, eta, cp, etap = medium(eps_r, mu_r)
+    say("%s: %d triangles, %d edges, k_max %d" % (name, F.shape[0], E.shape[0], kmax))
     R = bcmod.refine(V, F, E)
     G = bcmod.gram_bc(V, F, E, R)
+    say("BC basis and Gram matrix (%.1f s)" % (time.perf_counter() - t0))
     T0s, T0h = static_blocks(R, D, nq=6)
+    say("static blocks (%.1f s)" % (time.perf_counter() - t0))
     prob = dict(name=name, V=V, F=F, E=E, eps_r=eps_r, mu_r=mu_r, dt=dt, D=D, Tmax=Tmax,
                 kmax=kmax, G=G, T0s=T0s, T0h=T0h, refinement=R,
                 nsteps=cfg["nsteps"] if nsteps is None else nsteps,
@@ -129,5 +139,6 @@ def build_problem(name=None, cfg=None, nsteps=None, with_raw=True, threads=None,
         raw = {}
         for med, speed in (("ext", c), ("int", cp)):
             raw[med] = retarded_blocks(V, F, E, dt, speed, kmax + 1, kmax + 2, kmax, nq=cfg.get("nq", 7))
+            say("retarded blocks, %s medium (%.1f s)" % (med, time.perf_counter() - t0))
         prob["raw"] = raw
     return prob

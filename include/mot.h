@@ -82,7 +82,14 @@ typedef struct {
     int32_t keep_history;    /* keep every w_k on the device (1)             */
     int32_t max_steps;       /* capacity of the kept history (0: 20000)      */
     uint64_t mem_cap_bytes;  /* 0: no cap                                     */
-    int32_t reserved[8];
+    int32_t profile;         /* 1: time the history kernel and every Q_0
+                                product with HIP events on the handle's stream
+                                (results in mot_info)                          */
+    int32_t precond;         /* right preconditioner of the Q_0 GMRES: an
+                                approximate inverse of Q_0 built once on the
+                                device by Newton-Schulz iteration;
+                                0 none, 1 stored FP32 (default), 2 FP64       */
+    int32_t reserved[6];
 } mot_options;
 
 typedef struct {
@@ -103,6 +110,14 @@ typedef struct {
     uint64_t device_bytes;   /* device memory held by the handle             */
     double setup_ms;         /* preconditioner construction time             */
     double fold_ms;          /* lag-matrix fold time (sum over lags)         */
+    int64_t gmres_iters_total;  /* Arnoldi steps over all steps taken        */
+    double hist_ms;          /* profile: summed history-kernel time          */
+    int64_t hist_launches;
+    double q0_ms;            /* profile: summed Q_0 product time (GMRES)     */
+    int64_t q0_launches;
+    double recover_ms;       /* wall time of the last recovery (host clock)  */
+    int32_t precond_iters;   /* Newton-Schulz iterations of the preconditioner */
+    double precond_resid;    /* ||I - M Q_0||_F of the stored preconditioner  */
 } mot_info;
 
 typedef struct mot_handle mot_handle;

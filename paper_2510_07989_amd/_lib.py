@@ -27,7 +27,8 @@ class MotPlaneWave(ctypes.Structure):
 class MotOptions(ctypes.Structure):
     _fields_ = [("precision", _I), ("gmres_tol", _D), ("gmres_restart", _I), ("gmres_maxit", _I),
                 ("cg_tol", _D), ("cg_maxit", _I), ("diameter", _D), ("keep_history", _I),
-                ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("reserved", _I * 8)]
+                ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
+                ("precond", _I), ("reserved", _I * 6)]
 
 
 class MotStepInfo(ctypes.Structure):
@@ -37,7 +38,10 @@ class MotStepInfo(ctypes.Structure):
 class MotInfo(ctypes.Structure):
     _fields_ = [("D", _D), ("Tmax", _D), ("dt", _D), ("kmax", _I), ("nlags", _I), ("ne", _I),
                 ("n", _I), ("nrhs", _I), ("genus", _I), ("folded", _I), ("steps_done", _I),
-                ("device_bytes", ctypes.c_uint64), ("setup_ms", _D), ("fold_ms", _D)]
+                ("device_bytes", ctypes.c_uint64), ("setup_ms", _D), ("fold_ms", _D),
+                ("gmres_iters_total", ctypes.c_int64), ("hist_ms", _D), ("hist_launches", ctypes.c_int64),
+                ("q0_ms", _D), ("q0_launches", ctypes.c_int64), ("recover_ms", _D),
+                ("precond_iters", _I), ("precond_resid", _D)]
 
 
 EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr", "mot_step",

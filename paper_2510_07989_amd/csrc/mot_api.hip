@@ -11,11 +11,17 @@
 namespace motk_step {
 void rhs_fields(mot_handle* h);
 void history(mot_handle* h);
-void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done);
+void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
+void precond(mot_handle* h, const double* src, double* vj, double* z);
+void dense_q0(mot_handle* h, double* D);
+void transpose_scale(mot_handle* h, int n, double alpha, const double* A, double* X);
+void abs_sums(mot_handle* h, int n, const double* A, double* rs, double* cs);
+void eye_residual(mot_handle* h, int n, const double* T, double* out);
+void to_f32(mot_handle* h, size_t n, const double* X, float* Y);
 void gm_residual(mot_handle* h, const double* b, double* r, int first);
 void gm_dots(mot_handle* h, const double* w);
 void gm_orth(mot_handle* h, double* w, int final_pass);
-void gm_update_x(mot_handle* h, double* x);
+void gm_update_x(mot_handle* h, const double* basis, double* x);
 void warm_start(mot_handle* h);
 void push(mot_handle* h);
 void inc_step(mot_handle* h);
@@ -224,6 +230,63 @@ uint32_t required_bits(const mot_handle* h, int lag) {
     return b;
 }
 
+// Approximate inverse of Q_0 by the Newton-Schulz iteration
+//   X_0 = Q_0^T / (||Q_0||_1 ||Q_0||_inf),  X_{k+1} = 2 X_k - X_k Q_0 X_k,
+// whose residual I - X_k Q_0 squares every step; stopped when ||I - X Q_0||_F
+// stops decreasing or drops below 1e-13 sqrt(n).  Used only as the right
+// preconditioner of the FP64 GMRES, so its accuracy sets the iteration count,
+// never the solution.
+int build_precond(mot_handle* h) {
+    if (h->opt.precond == 0) return MOT_OK;
+    const int n = h->n2;
+    const size_t nn = (size_t)n * n;
+    hipStream_t s = h->stream;
+    double *Q0, *X, *T, *Xn, *rs, *cs, *acc;
+    int rc;
+    if ((rc = dalloc(h, &Q0, nn, false)) || (rc = dalloc(h, &X, nn, false)) || (rc = dalloc(h, &T, nn, false)) ||
+        (rc = dalloc(h, &Xn, nn, false)) || (rc = dalloc(h, &rs, n)) || (rc = dalloc(h, &cs, n)) ||
+        (rc = dalloc(h, &acc, 1)))
+        return rc;
+    motk_step::dense_q0(h, Q0);
+    motk_step::abs_sums(h, n, Q0, rs, cs);
+    std::vector<double> hr(n), hc(n);
+    HIPCHK(h, hipMemcpyAsync(hr.data(), rs, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(hc.data(), cs, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    double ninf = *std::max_element(hr.begin(), hr.end()), n1 = *std::max_element(hc.begin(), hc.end());
+    motk_step::transpose_scale(h, n, 1.0 / (n1 * ninf), Q0, X);
+    double best = 1e300;
+    int it = 0;
+    for (; it < 120; ++it) {
+        motk::gemm(s, n, n, n, 1.0, X, n, Q0, n, 0.0, T, n);               // T = X Q0
+        HIPCHK(h, hipMemsetAsync(acc, 0, sizeof(double), s));
+        motk_step::eye_residual(h, n, T, acc);
+        double e2 = 0;
+        HIPCHK(h, hipMemcpyAsync(&e2, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        double e = std::sqrt(e2);
+        if (!std::isfinite(e)) return mot_fail(h, MOT_ENOCONV, "Newton-Schulz diverged");
+        if (e < 1e-13 * std::sqrt((double)n) || (e > 0.5 * best && best < 1e-6)) { best = std::min(best, e); break; }
+        best = std::min(best, e);
+        HIPCHK(h, hipMemcpyAsync(Xn, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        motk::gemm(s, n, n, n, -1.0, T, n, X, n, 2.0, Xn, n);              // Xn = 2X - T X
+        std::swap(X, Xn);
+    }
+    h->ns_iters = it;
+    h->ns_resid = best;
+    if (!(best < 0.5)) return mot_fail(h, MOT_ENOCONV, "Newton-Schulz did not converge");
+    if (h->opt.precond == 2) {
+        if ((rc = dalloc(h, &h->M64, nn, false))) return rc;
+        HIPCHK(h, hipMemcpyAsync(h->M64, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        if ((rc = dalloc(h, &h->M32, nn, false))) return rc;
+        motk_step::to_f32(h, nn, X, h->M32);
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, Q0); dfree(h, X); dfree(h, T); dfree(h, Xn); dfree(h, rs); dfree(h, cs); dfree(h, acc);
+    return MOT_OK;
+}
+
 // Section V-B fold of lag i:  with blocks X in {1 = eta T + eta' T', k = K + K', 2 = T/eta + T'/eta'}
 //   a_X = Zh_X + (Zhat_X - Zh_X) P^Sigma,  b_X = Ztil_X + (Zh_X - Ztil_X) P^Sigma
 //   q_X = C1 a_X + C2 b_X                 (Q_i = [[q_1, -q_k], [q_k, q_2]])
@@ -267,6 +330,7 @@ int fold_lag(mot_handle* h, int lag) {
     }
     h->lag_done[lag] = 1;
     h->fold_ms += now_ms() - t0;
+    if (lag == 0) return build_precond(h);
     return MOT_OK;
 }
 
@@ -314,6 +378,53 @@ int after_block(mot_handle* h, int family, int lag, int medium, int op) {
     return MOT_OK;
 }
 
+// ------------------------------------------------------------- profiling ---
+constexpr int kEvCap = 2048;
+
+int ev_flush(mot_handle* h, EvPool& p) {
+    if (!p.used) return MOT_OK;
+    HIPCHK(h, hipEventSynchronize(p.b[p.used - 1]));
+    for (int i = 0; i < p.used; ++i) {
+        float ms = 0;
+        HIPCHK(h, hipEventElapsedTime(&ms, p.a[i], p.b[i]));
+        p.ms += ms;
+        p.n += 1;
+    }
+    p.used = 0;
+    return MOT_OK;
+}
+
+int ev_begin(mot_handle* h, EvPool& p) {
+    if (!h->opt.profile) return MOT_OK;
+    if (p.a.empty()) {
+        p.a.resize(kEvCap);
+        p.b.resize(kEvCap);
+        for (int i = 0; i < kEvCap; ++i) {
+            HIPCHK(h, hipEventCreate(&p.a[i]));
+            HIPCHK(h, hipEventCreate(&p.b[i]));
+        }
+    }
+    if (p.used == kEvCap) {
+        int rc = ev_flush(h, p);
+        if (rc) return rc;
+    }
+    HIPCHK(h, hipEventRecord(p.a[p.used], h->stream));
+    return MOT_OK;
+}
+
+int ev_end(mot_handle* h, EvPool& p) {
+    if (!h->opt.profile) return MOT_OK;
+    HIPCHK(h, hipEventRecord(p.b[p.used], h->stream));
+    p.used++;
+    return MOT_OK;
+}
+
+void ev_destroy(EvPool& p) {
+    for (auto e : p.a) (void)hipEventDestroy(e);
+    for (auto e : p.b) (void)hipEventDestroy(e);
+    p.a.clear(); p.b.clear();
+}
+
 // Wait until the device has published progress word 'want' (bounded: a
 // failed kernel turns into MOT_EHIP instead of a hang).
 int wait_flag(mot_handle* h, int want) {
@@ -346,7 +457,10 @@ int gmres_solve(mot_handle* h) {
     int iters = 0;
     for (;;) {
         // r = y - Q0 x
-        q0_matvec(h, h->x, nullptr, h->wA, 0);
+        int prc = ev_begin(h, h->ev_q0);
+        if (prc) return prc;
+        q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
         gm_residual(h, h->y, h->wA, first ? 1 : 0);
         first = false;
         seq_target++;
@@ -355,8 +469,19 @@ int gmres_solve(mot_handle* h) {
         bool cycle_done = false;
         int j = 0;
         for (; j < M && iters + j < maxit; ++j) {
-            // V[j] = src * inv_h ; dst = Q0 V[j]
-            q0_matvec(h, src, h->V + (size_t)j * h->n2, dst, 1);
+            // V[j] = src * inv_h ; Z[j] = M V[j] (or V[j]) ; dst = Q0 Z[j]
+            double* vj = h->V + (size_t)j * h->n2;
+            if (h->M32 || h->M64) {
+                double* zj = h->Z + (size_t)j * h->n2;
+                precond(h, src, vj, zj);
+                if ((prc = ev_begin(h, h->ev_q0))) return prc;
+                q0_matvec(h, zj, nullptr, dst, 1, 0);
+                if ((prc = ev_end(h, h->ev_q0))) return prc;
+            } else {
+                if ((prc = ev_begin(h, h->ev_q0))) return prc;
+                q0_matvec(h, src, vj, dst, 1, 1);
+                if ((prc = ev_end(h, h->ev_q0))) return prc;
+            }
             gm_dots(h, dst);
             gm_orth(h, dst, 0);
             gm_orth(h, dst, 1);
@@ -376,9 +501,10 @@ int gmres_solve(mot_handle* h) {
         int total = h->hflag->total;
         iters = total;
         seq_target = h->hflag->seq;
-        gm_update_x(h, h->x);
+        gm_update_x(h, (h->M32 || h->M64) ? h->Z : h->V, h->x);
         int conv = h->hflag->converged;
         if (conv || iters >= maxit) {
+            h->iters_total += iters;
             h->last_iters = iters;
             h->last_relres = h->hflag->relres;
             h->last_conv = conv;
@@ -435,6 +561,8 @@ void mot_default_options(mot_options* o) {
     o->keep_history = 1;
     o->max_steps = 0;
     o->mem_cap_bytes = 0;
+    o->profile = 0;
+    o->precond = 1;
 }
 
 const char* mot_last_error(const mot_handle* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
@@ -442,6 +570,8 @@ const char* mot_last_error(const mot_handle* h) { return h ? h->err.c_str() : g_
 void mot_destroy(mot_handle* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    ev_destroy(h->ev_hist);
+    ev_destroy(h->ev_q0);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->hflag) (void)hipHostFree(h->hflag);
     delete h;
@@ -504,6 +634,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     mot_handle* h = new mot_handle();
     if (opt) h->opt = *opt; else mot_default_options(&h->opt);
     if (h->opt.gmres_restart < 2 || h->opt.gmres_restart > MOT_MAXM) h->opt.gmres_restart = 40;
+    if (h->opt.precond < 0 || h->opt.precond > 2) h->opt.precond = 1;
     h->M = h->opt.gmres_restart;
     if (h->opt.gmres_maxit <= 0) h->opt.gmres_maxit = 400;
     if (h->opt.cg_maxit <= 0) h->opt.cg_maxit = 20000;
@@ -658,7 +789,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
     if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
         (rc = dalloc(h, &h->ebar, n2)) || (rc = dalloc(h, &h->Ebar, n2)) || (rc = dalloc(h, &h->y, n2)) ||
-        (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) ||
+        (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
         (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
         return bail(rc);
     if (h->hist_cap && (rc = dalloc(h, &h->hist, (size_t)h->hist_cap * n2))) return bail(rc);
@@ -716,6 +847,11 @@ int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, 
 int mot_reset(mot_handle* h) {
     if (!h) return MOT_EINVAL;
     h->k = 0;
+    h->iters_total = 0;
+    (void)ev_flush(h, h->ev_hist);
+    (void)ev_flush(h, h->ev_q0);
+    h->ev_hist.ms = h->ev_q0.ms = 0;
+    h->ev_hist.n = h->ev_q0.n = 0;
     HIPCHK(h, hipMemsetAsync(h->d_k, 0, sizeof(int), h->stream));
     HIPCHK(h, hipMemsetAsync(h->ring, 0, (size_t)h->nh * h->n2 * sizeof(double), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -729,7 +865,10 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     inc_step(h);
     h->k += 1;
     rhs_fields(h);
+    int prc = ev_begin(h, h->ev_hist);
+    if (prc) return prc;
     history(h);
+    if ((prc = ev_end(h, h->ev_hist))) return prc;
     warm_start(h);
     int rc = gmres_solve(h);
     if (rc && rc != MOT_ENOCONV) return rc;
@@ -775,7 +914,9 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
     if (loop_out) { if (out_on_device) dl = loop_out; else if ((rc = dalloc(h, &dl, tot, false))) return rc; }
     if (star_out) { if (out_on_device) ds = star_out; else if ((rc = dalloc(h, &ds, tot, false))) return rc; }
     if (loop_out || star_out) {
+        double tr = now_ms();
         rc = recover(h, s0, nsteps, dl, ds);
+        h->recover_ms = now_ms() - tr;
         if (rc && rc != MOT_ENOCONV) return rc;
         if (rc) worst = rc;
     }
@@ -852,8 +993,12 @@ int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
     return mot_fail(h, MOT_EINVAL, "unknown matrix id");
 }
 
-int mot_get_info(const mot_handle* h, mot_info* info) {
-    if (!h || !info) return MOT_EINVAL;
+int mot_get_info(const mot_handle* hc, mot_info* info) {
+    if (!hc || !info) return MOT_EINVAL;
+    mot_handle* h = const_cast<mot_handle*>(hc);
+    int rc = ev_flush(h, h->ev_hist);
+    if (rc) return rc;
+    if ((rc = ev_flush(h, h->ev_q0))) return rc;
     info->D = h->D; info->Tmax = h->Tmax; info->dt = h->dt;
     info->kmax = h->kmax; info->nlags = h->nlags;
     info->ne = h->ne; info->n = 2 * h->ne; info->nrhs = h->R;
@@ -863,6 +1008,14 @@ int mot_get_info(const mot_handle* h, mot_info* info) {
     info->device_bytes = h->bytes;
     info->setup_ms = h->setup_ms;
     info->fold_ms = h->fold_ms;
+    info->gmres_iters_total = h->iters_total;
+    info->hist_ms = h->ev_hist.ms;
+    info->hist_launches = h->ev_hist.n;
+    info->q0_ms = h->ev_q0.ms;
+    info->q0_launches = h->ev_q0.n;
+    info->recover_ms = h->recover_ms;
+    info->precond_iters = h->ns_iters;
+    info->precond_resid = h->ns_resid;
     return MOT_OK;
 }
 

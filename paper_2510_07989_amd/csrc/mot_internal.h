@@ -81,6 +81,14 @@ void cg_pupdate(hipStream_t s, int rows, int ncol, const double* beta, const dou
 int count_active(hipStream_t s, int ncol, const int* active, int* d_count, int* h_count);
 }  // namespace motk
 
+// Event pairs bracketing one kernel's launches (profile mode).
+struct EvPool {
+    std::vector<hipEvent_t> a, b;
+    int used = 0;
+    double ms = 0;
+    long long n = 0;
+};
+
 // ------------------------------------------------------------ the handle ---
 struct mot_handle {
     hipStream_t stream = nullptr;
@@ -125,12 +133,20 @@ struct mot_handle {
     double* x = nullptr;             // solution of the step
     // GMRES workspace (R = 1 path)
     double* V = nullptr;             // [M+1][n2]
+    double* Z = nullptr;             // [M+1][n2]  preconditioned basis M v_j
+    float* M32 = nullptr;            // [n2][n2]   approximate Q_0^-1 (FP32)
+    double* M64 = nullptr;           // [n2][n2]   approximate Q_0^-1 (FP64)
+    int ns_iters = 0;                // Newton-Schulz iterations used
+    double ns_resid = 0;             // ||I - M Q_0||_F reached
     double* wA = nullptr;
     double* wB = nullptr;
     GmState* gm = nullptr;
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;
     int M = 40;
+    long long iters_total = 0;
+    double recover_ms = 0;
+    EvPool ev_hist, ev_q0;
     int last_iters = 0;
     double last_relres = 0;
     int last_conv = 1;

@@ -177,13 +177,14 @@ __device__ __forceinline__ bool last_block(unsigned int* counter) {
 __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double* __restrict__ Q0,
                                                    const double* __restrict__ src,
                                                    double* __restrict__ vout, double* __restrict__ y,
-                                                   const GmState* __restrict__ gm, int check_done) {
+                                                   const GmState* __restrict__ gm, int check_done,
+                                                   int use_inv) {
     if (check_done && gm->done) return;
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m >= ne) return;
     const size_t blk = (size_t)ne * hs;
-    const double sc = check_done ? gm->inv_h : 1.0;
+    const double sc = use_inv ? gm->inv_h : 1.0;
     const double* xu = src;
     const double* xv = src + hs;
     double a = 0, b = 0, cc = 0, d = 0;
@@ -200,6 +201,120 @@ __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double*
             vout[hs + m] = sc * src[hs + m];
         }
     }
+}
+
+// z = M (inv_h src), V_j = inv_h src : the right preconditioner of the Q_0 solve,
+// an approximate inverse of Q_0 stored dense [n2][n2] in FP32 or FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M,
+                                                 const double* __restrict__ src, double* __restrict__ vj,
+                                                 double* __restrict__ z, const GmState* __restrict__ gm) {
+    if (gm->done) return;
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n2) return;
+    const double sc = gm->inv_h;
+    const T* row = M + (size_t)m * n2;
+    double s0 = 0, s1 = 0;
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        typedef double d4v __attribute__((ext_vector_type(4)));
+        const f4v* a4 = reinterpret_cast<const f4v*>(row);
+        const d4v* x4 = reinterpret_cast<const d4v*>(src);
+        const int n4 = n2 >> 2;
+        int c = lane;
+        for (; c + 64 < n4; c += 128) {
+            f4v a0 = __builtin_nontemporal_load(a4 + c), a1 = __builtin_nontemporal_load(a4 + c + 64);
+            d4v u0 = x4[c], u1 = x4[c + 64];
+            s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
+            s0 = fma((double)a0.z, u0.z, s0); s0 = fma((double)a0.w, u0.w, s0);
+            s1 = fma((double)a1.x, u1.x, s1); s1 = fma((double)a1.y, u1.y, s1);
+            s1 = fma((double)a1.z, u1.z, s1); s1 = fma((double)a1.w, u1.w, s1);
+        }
+        for (; c < n4; c += 64) {
+            f4v a0 = __builtin_nontemporal_load(a4 + c);
+            d4v u0 = x4[c];
+            s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
+            s0 = fma((double)a0.z, u0.z, s0); s0 = fma((double)a0.w, u0.w, s0);
+        }
+    } else {
+        row1(reinterpret_cast<const double*>(row), src, n2, lane, s0);
+    }
+    double s = wave_sum(s0 + s1);
+    if (lane == 0) {
+        z[m] = sc * s;
+        vj[m] = sc * src[m];
+    }
+}
+
+// Dense padded Q_0 = [[q1, -qk], [qk, q2]] on the index space [0, 2 hs), identity on padding.
+__global__ void k_dense_q0(int ne, int hs, const double* __restrict__ Q, double* __restrict__ D) {
+    const int n2 = 2 * hs;
+    const size_t blk = (size_t)ne * hs;
+    size_t total = (size_t)n2 * n2;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(t / n2), j = (int)(t % n2);
+        int hi = i >= hs, hj = j >= hs;
+        int ii = i - hi * hs, jj = j - hj * hs;
+        double v;
+        if (ii >= ne || jj >= ne) v = (i == j) ? 1.0 : 0.0;
+        else if (!hi && !hj) v = Q[(size_t)ii * hs + jj];
+        else if (!hi && hj) v = -Q[blk + (size_t)ii * hs + jj];
+        else if (hi && !hj) v = Q[blk + (size_t)ii * hs + jj];
+        else v = Q[2 * blk + (size_t)ii * hs + jj];
+        D[t] = v;
+    }
+}
+
+// X = alpha A^T (square n)
+__global__ void k_transpose_scale(int n, double alpha, const double* __restrict__ A, double* __restrict__ X) {
+    __shared__ double tile[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    int tx = threadIdx.x, ty = threadIdx.y;
+    for (int k = ty; k < 32; k += 8) {
+        int r = by + k, c = bx + tx;
+        tile[k][tx] = (r < n && c < n) ? A[(size_t)r * n + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        int r = bx + k, c = by + tx;
+        if (r < n && c < n) X[(size_t)r * n + c] = alpha * tile[tx][k];
+    }
+}
+
+// out[0] += sum |row sums| max ... : per-row abs sums -> rs[i], per-column abs sums -> cs[j]
+__global__ void k_abs_sums(int n, const double* __restrict__ A, double* __restrict__ rs, double* __restrict__ cs) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = 0, c = 0;
+    for (int j = 0; j < n; ++j) { r += fabs(A[(size_t)i * n + j]); c += fabs(A[(size_t)j * n + i]); }
+    rs[i] = r;
+    cs[i] = c;
+}
+
+// out += sum_{ij} (delta_ij - T_ij)^2   (atomic; setup only)
+__global__ void k_eye_residual(int n, const double* __restrict__ T, double* __restrict__ out) {
+    __shared__ double sh[8];
+    double s = 0;
+    size_t total = (size_t)n * n;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(t / n), j = (int)(t % n);
+        double d = (i == j ? 1.0 : 0.0) - T[t];
+        s = fma(d, d, s);
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += sh[w];
+        atomicAdd(out, a);
+    }
+}
+
+__global__ void k_to_f32(size_t n, const double* __restrict__ X, float* __restrict__ Y) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        Y[t] = (float)X[t];
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -383,7 +498,7 @@ __global__ __launch_bounds__(256) void k_gm_orth(int n2, const double* __restric
 
 // x += sum_l y[l] V[l]   (l < cycle length)
 __global__ void k_gm_update_x(int n2, const double* __restrict__ V, const GmState* __restrict__ gm,
-                              double* __restrict__ x) {
+                              double* __restrict__ x) {   // V: the stored M v_l (or v_l)
     const int jj = gm->cycle_iters;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
         double s = x[i];
@@ -487,9 +602,37 @@ void history(mot_handle* h) {
                        h->nh, h->Q, h->ring, h->C1, h->C2, 1.0 / h->Tmax, h->ebar, h->Ebar, h->y);
 }
 
-void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done) {
+void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
     hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
-                       src, vout, y, h->gm, check_done);
+                       src, vout, y, h->gm, check_done, use_inv);
+}
+
+void precond(mot_handle* h, const double* src, double* vj, double* z) {
+    dim3 grid((h->n2 + 3) / 4);
+    if (h->M32)
+        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm);
+    else
+        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm);
+}
+
+void dense_q0(mot_handle* h, double* D) {
+    hipLaunchKernelGGL(k_dense_q0, dim3(4096), dim3(256), 0, h->stream, h->ne, h->hs, h->Q, D);
+}
+
+void transpose_scale(mot_handle* h, int n, double alpha, const double* A, double* X) {
+    hipLaunchKernelGGL(k_transpose_scale, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, h->stream, n, alpha, A, X);
+}
+
+void abs_sums(mot_handle* h, int n, const double* A, double* rs, double* cs) {
+    hipLaunchKernelGGL(k_abs_sums, dim3((n + 255) / 256), dim3(256), 0, h->stream, n, A, rs, cs);
+}
+
+void eye_residual(mot_handle* h, int n, const double* T, double* out) {
+    hipLaunchKernelGGL(k_eye_residual, dim3(2048), dim3(256), 0, h->stream, n, T, out);
+}
+
+void to_f32(mot_handle* h, size_t n, const double* X, float* Y) {
+    hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, h->stream, n, X, Y);
 }
 
 void gm_residual(mot_handle* h, const double* b, double* r, int first) {
@@ -506,8 +649,8 @@ void gm_orth(mot_handle* h, double* w, int final_pass) {
                        h->dflag, h->opt.gmres_tol, h->M, final_pass);
 }
 
-void gm_update_x(mot_handle* h, double* x) {
-    hipLaunchKernelGGL(k_gm_update_x, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->V,
+void gm_update_x(mot_handle* h, const double* basis, double* x) {
+    hipLaunchKernelGGL(k_gm_update_x, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, basis,
                        h->gm, x);
 }
 

@@ -106,3 +106,23 @@ def test_lag_errors():
         s.set_lag(L.FAM_H, 0, L.MED_EXT, L.OP_T, z)                      # twice
     assert e.value.code == L.MOT_ESTATE
     s.close()
+
+
+@pytest.mark.parametrize("pc", [0, 1, 2])
+def test_preconditioner_variants(pc):
+    """Unpreconditioned, FP32 and FP64 approximate-inverse right preconditioning
+    of the Q_0 GMRES all reach the oracle's solution."""
+    print("precond", pc, flush=True)
+    O = oracle("sphere_480")
+    ref = O.run(120)
+    s = _solver("sphere_480", precond=pc)
+    out = s.run(120)
+    inf = s.info()
+    its = inf["gmres_iters_total"] / 120
+    print("precond %d: %.2f iterations/step, NS iterations %d, resid %.2e, err %.2e"
+          % (pc, its, inf["precond_iters"], inf["precond_resid"], _rel(out["w"], ref["W"])), flush=True)
+    assert _rel(out["w"], ref["W"]) < 1e-10
+    assert _rel(out["star"], ref["star"]) < 1e-10
+    if pc:
+        assert its < 6
+    s.close()
