@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--workload", default="torus_3072", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the MOT march of one problem runs on one device "
@@ -93,7 +94,7 @@ def main():
     t_fixture = time.perf_counter() - t
     log("inputs assembled on the host in %.1f s" % t_fixture)
 
-    opts = mot.default_options(profile=1, max_steps=W_ + K + 8)
+    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond)
     t = time.perf_counter()
     s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
                    prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
@@ -120,11 +121,11 @@ def main():
     ne, n = s.ne, s.n
     L = b["nlags"]
     iters = (b["gmres_iters_total"] - a["gmres_iters_total"]) / K
-    # algorithmic bytes (FP64): Q_0 product reads q1, qk, q2 (3 ne^2) and the
-    # two half vectors, writes n; the history kernel reads (L-1) 3 ne^2 of
-    # Q_1..Q_{L-1} plus C1, C2 (2 ne^2) and the ring / RHS vectors.
+    # algorithmic bytes (FP64): the Q_0 product reads q1, qk, q2 (3 ne^2) and the
+    # input vector, writes n; the history kernel reads the (L-1) 3 ne^2 entries
+    # of Q_1..Q_{L-1}, the L-1 history vectors and r_k, writes n.
     q0_bytes = 8.0 * (3 * ne * ne + 2 * n)
-    hist_bytes = 8.0 * ((L - 1) * 3 * ne * ne + 2 * ne * ne + (L - 1) * n + 2 * n + n)
+    hist_bytes = 8.0 * ((L - 1) * 3 * ne * ne + (L - 1) * n + 2 * n)
     q0_ms = (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
     hist_ms = (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
     q0_tot = b["q0_ms"] - a["q0_ms"]
@@ -134,7 +135,7 @@ def main():
     if q0_tot >= hist_tot:
         dom = dict(kernel="k_q0_matvec (GMRES Q_0 product)", bytes=q0_bytes, ms=q0_ms, gbs=q0_gbs)
     else:
-        dom = dict(kernel="k_history (RHS + history convolution)", bytes=hist_bytes, ms=hist_ms, gbs=hist_gbs)
+        dom = dict(kernel="k_history (history convolution)", bytes=hist_bytes, ms=hist_ms, gbs=hist_gbs)
     log("timed %d steps in %.3f s: %.1f steps/s, %.2f GMRES its/step; Q0 product %.1f us (%.0f GB/s), "
         "history %.1f us (%.0f GB/s); recovery %.1f ms"
         % (K, el, steps_s, iters, q0_ms * 1e3, q0_gbs, hist_ms * 1e3, hist_gbs, b["recover_ms"]))
@@ -153,7 +154,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "nrhs": 1,
-                   "unknowns": n, "lags": L, "kmax": b["kmax"], "precision": "fp64"},
+                   "unknowns": n, "lags": L, "kmax": b["kmax"], "precision": "fp64",
+                   "q0_preconditioner": ["none", "fp32 approximate inverse", "fp64 approximate inverse"][args.precond]},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": dom["bytes"], "avg_launch_us": round(dom["ms"] * 1e3, 2)},

@@ -9,8 +9,11 @@
 #include "mot_internal.h"
 
 namespace motk_step {
-void rhs_fields(mot_handle* h);
+void rhs_batch(mot_handle* h, int k0, double* rb);
 void history(mot_handle* h);
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first);
+void gm_orth1(mot_handle* h, double* w);
+void gm_finish(mot_handle* h, const double* basis, int force);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void dense_q0(mot_handle* h, double* D);
@@ -444,6 +447,83 @@ int wait_flag(mot_handle* h, int want) {
     return MOT_OK;
 }
 
+// Right-preconditioned GMRES with single-workgroup orthogonalisation (the
+// approximate inverse keeps the Krylov space at one or two vectors).  With the
+// FP64 preconditioner the solve starts from x0 = 0, with the FP32 one from the
+// extrapolation 2 w_{k-1} - w_{k-2}.  The finishing kernel (x += Z y, ring and
+// history push) is queued right after the first Arnoldi step and acts only if
+// that step met the tolerance.
+int gmres_solve_pc(mot_handle* h) {
+    using namespace motk_step;
+    const int M = h->M;
+    const int maxit = h->opt.gmres_maxit;
+    h->hflag->seq = 0;
+    int prc;
+    const bool warm = h->M32 != nullptr;
+    if (warm) {
+        warm_start(h);
+        if ((prc = ev_begin(h, h->ev_q0))) return prc;
+        q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
+        gm_start1(h, h->y, h->wA, 1, 1);
+    } else {
+        HIPCHK(h, hipMemsetAsync(h->x, 0, (size_t)h->n2 * sizeof(double), h->stream));
+        gm_start1(h, h->y, h->wA, 0, 1);
+    }
+    int seq = 1, iters = 0;
+    bool first_cycle = true;
+    for (;;) {
+        double* src = h->wA;
+        double* dst = h->wB;
+        int j = 0;
+        bool done = false;
+        for (; j < M && iters + j < maxit; ++j) {
+            double* vj = h->V + (size_t)j * h->n2;
+            double* zj = h->Z + (size_t)j * h->n2;
+            precond(h, src, vj, zj);
+            if ((prc = ev_begin(h, h->ev_q0))) return prc;
+            q0_matvec(h, zj, nullptr, dst, 1, 0);
+            if ((prc = ev_end(h, h->ev_q0))) return prc;
+            gm_orth1(h, dst);
+            if (j == 0 && first_cycle) gm_finish(h, h->Z, 0);
+            std::swap(src, dst);
+            if ((prc = wait_flag(h, seq + j + 1))) return prc;
+            if (h->hflag->done) { done = true; ++j; break; }
+        }
+        iters += j;
+        seq += j;
+        bool conv = done && h->hflag->converged;
+        if (!(done && j == 1 && first_cycle)) {
+            // the speculative finisher did nothing: finish (or update for a restart) now
+            gm_finish(h, h->Z, (!done && iters >= maxit) ? 1 : 0);
+        }
+        if (conv || iters >= maxit) {
+            h->iters_total += iters;
+            h->last_iters = iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = conv;
+            break;
+        }
+        // restart from the updated x
+        first_cycle = false;
+        if ((prc = ev_begin(h, h->ev_q0))) return prc;
+        q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
+        gm_start1(h, h->y, h->wA, 1, 0);
+        seq += 1;
+        if ((prc = wait_flag(h, seq))) return prc;
+        if (h->hflag->done) {      // restart residual already below the tolerance
+            gm_finish(h, h->Z, 1);
+            h->iters_total += iters;
+            h->last_iters = iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = 1;
+            break;
+        }
+    }
+    return h->last_conv ? MOT_OK : MOT_ENOCONV;
+}
+
 // Single right-hand-side GMRES on Q0 x = y (x holds the warm start).
 int gmres_solve(mot_handle* h) {
     using namespace motk_step;
@@ -788,7 +868,8 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     const int n2 = h->n2;
     h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
     if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
-        (rc = dalloc(h, &h->ebar, n2)) || (rc = dalloc(h, &h->Ebar, n2)) || (rc = dalloc(h, &h->y, n2)) ||
+        (rc = dalloc(h, &h->ebar, (size_t)2 * h->hs * h->B)) || (rc = dalloc(h, &h->Ebar, (size_t)2 * h->hs * h->B)) ||
+        (rc = dalloc(h, &h->rb, (size_t)2 * h->ne * h->B)) || (rc = dalloc(h, &h->y, n2)) ||
         (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
         (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
         return bail(rc);
@@ -864,15 +945,21 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     using namespace motk_step;
     inc_step(h);
     h->k += 1;
-    rhs_fields(h);
+    if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
     int prc = ev_begin(h, h->ev_hist);
     if (prc) return prc;
     history(h);
     if ((prc = ev_end(h, h->ev_hist))) return prc;
-    warm_start(h);
-    int rc = gmres_solve(h);
-    if (rc && rc != MOT_ENOCONV) return rc;
-    push(h);
+    int rc;
+    if ((h->M32 || h->M64) && h->n2 <= 32768) {
+        rc = gmres_solve_pc(h);           // pushes w_k itself
+        if (rc && rc != MOT_ENOCONV) return rc;
+    } else {
+        warm_start(h);
+        rc = gmres_solve(h);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        push(h);
+    }
     HIPCHK(h, hipGetLastError());
     if (info) {
         info->step = h->k;
@@ -969,25 +1056,16 @@ int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
         return MOT_OK;
     }
     if (which == 6) {
-        // r_lag = C1 ebar + C2 Ebar / T_max at step 'lag' (history terms excluded)
+        // r_lag = C1 ebar + C2 Ebar / T_max of step 'lag' (Section V-C)
         if (lag < 1) return mot_fail(h, MOT_EINVAL, "step >= 1");
-        int kk = lag;
-        HIPCHK(h, hipMemcpyAsync(h->d_k, &kk, sizeof(int), hipMemcpyHostToDevice, s));
-        motk_step::rhs_fields(h);
-        // history with k = 1 has no lag terms: temporarily use a device int of 1
-        int one = 1;
-        int* save = h->d_k;
-        int* d1;
-        if ((rc = upload(h, &d1, &one, 1))) return rc;
-        h->d_k = d1;
-        motk_step::history(h);
-        h->d_k = save;
-        std::vector<double> tmp(h->n2);
-        HIPCHK(h, hipMemcpyAsync(tmp.data(), h->y, h->n2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(h, hipMemcpyAsync(h->d_k, &h->k, sizeof(int), hipMemcpyHostToDevice, s));
+        double* rb2;
+        if ((rc = dalloc(h, &rb2, (size_t)2 * ne * h->B))) return rc;
+        motk_step::rhs_batch(h, lag, rb2);
+        std::vector<double> tmp((size_t)2 * ne * h->B);
+        HIPCHK(h, hipMemcpyAsync(tmp.data(), rb2, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
-        dfree(h, d1);
-        for (int i = 0; i < ne; ++i) { out[i] = tmp[i]; out[ne + i] = tmp[hs + i]; }
+        dfree(h, rb2);    // only the field temporaries were reused; the current batch r is intact
+        for (int i = 0; i < ne; ++i) { out[i] = tmp[(size_t)i * h->B]; out[ne + i] = tmp[(size_t)(ne + i) * h->B]; }
         return MOT_OK;
     }
     return mot_fail(h, MOT_EINVAL, "unknown matrix id");

@@ -127,8 +127,10 @@ struct mot_handle {
     double* ring = nullptr;          // [nh][n2][R]
     double* hist = nullptr;          // [max_steps][n2][R]
     int hist_cap = 0;
-    double* ebar = nullptr;          // [n2][R]
+    int B = 128;                     // steps per RHS batch
+    double* ebar = nullptr;          // [2][hs][B] tested fields of a batch
     double* Ebar = nullptr;
+    double* rb = nullptr;            // [2][ne][B] r_k = C1 ebar + C2 Ebar / T_max
     double* y = nullptr;             // rhs - history
     double* x = nullptr;             // solution of the step
     // GMRES workspace (R = 1 path)

@@ -21,15 +21,16 @@ __device__ __forceinline__ double erf_diff(double s1, double s0) {
     return erf(s1) - erf(s0);
 }
 
-__global__ void k_rhs_fields(int ne, int hs, int R, const int* __restrict__ dk, double dt,
+__global__ void k_rhs_fields(int ne, int hs, int k0, int B, double dt,
                              const double* __restrict__ X, const double* __restrict__ Fw,
                              const double* __restrict__ waves, const double* __restrict__ tcut,
                              double* __restrict__ ebar, double* __restrict__ Ebar) {
+    // thread per (edge m, batch column s); step k = k0 + s; outputs [half][hs][B]
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * R) return;
-    int m = t / R, r = t % R;
-    const int k = *dk;
-    const double* wv = waves + 9 * r;
+    if (t >= ne * B) return;
+    int m = t / B, sc = t % B;
+    const int k = k0 + sc;
+    const double* wv = waves;
     const double amp = wv[0], w = wv[7], t0 = wv[8];
     const double px = wv[1], py = wv[2], pz = wv[3];
     const double kx = wv[4], ky = wv[5], kz = wv[6];
@@ -37,7 +38,7 @@ __global__ void k_rhs_fields(int ne, int hs, int R, const int* __restrict__ dk, 
     const double hx = ky * pz - kz * py, hy = kz * px - kx * pz, hz = kx * py - ky * px;
     const double c4 = 4.0 / w;
     const double tk = k * dt, tk1 = (k - 1) * dt;
-    const bool star_on = tk <= tcut[r];
+    const bool star_on = tk <= tcut[0];
     double ee = 0, eh = 0, Ee = 0, Eh = 0;
     for (int q = 0; q < 14; ++q) {
         const double* x = X + ((size_t)m * 14 + q) * 3;
@@ -52,15 +53,15 @@ __global__ void k_rhs_fields(int ne, int hs, int R, const int* __restrict__ dk, 
         Ee += tE * fp; Eh += tE * fh;
     }
     const double a = -0.5 * amp;   // -(A / (2c)), the minus from n x f testing
-    ebar[(size_t)m * R + r] = a * ee;
-    ebar[(size_t)(hs + m) * R + r] = a * eh;
-    Ebar[(size_t)m * R + r] = a * Ee;
-    Ebar[(size_t)(hs + m) * R + r] = a * Eh;
+    const size_t hb = (size_t)hs * B;
+    ebar[(size_t)m * B + sc] = a * ee;
+    ebar[hb + (size_t)m * B + sc] = a * eh;
+    Ebar[(size_t)m * B + sc] = a * Ee;
+    Ebar[hb + (size_t)m * B + sc] = a * Eh;
 }
 
 // ------------------------------------------------ streamed row products ---
-// One wavefront per output row m; two accumulators (u-half row m, v-half row m).
-// acc += A[m, :] . x with 16-byte loads, four in flight per lane.
+// One wavefront per output row; 16-byte loads, eight in flight per lane.
 __device__ __forceinline__ void row2(const double* __restrict__ A, const double* __restrict__ xa,
                                      const double* __restrict__ xb, int len, int lane, double& sa,
                                      double& sb) {
@@ -69,19 +70,16 @@ __device__ __forceinline__ void row2(const double* __restrict__ A, const double*
     const d2v* y2 = reinterpret_cast<const d2v*>(xb);
     const int n2 = len >> 1;
     int c = lane;
-    for (; c + 192 < n2; c += 256) {
-        d2v a0 = __builtin_nontemporal_load(a2 + c), a1 = __builtin_nontemporal_load(a2 + c + 64);
-        d2v a2_ = __builtin_nontemporal_load(a2 + c + 128), a3 = __builtin_nontemporal_load(a2 + c + 192);
-        d2v u0 = x2[c], u1 = x2[c + 64], u2 = x2[c + 128], u3 = x2[c + 192];
-        d2v v0 = y2[c], v1 = y2[c + 64], v2 = y2[c + 128], v3 = y2[c + 192];
-        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
-        sa = fma(a1.x, u1.x, sa); sa = fma(a1.y, u1.y, sa);
-        sa = fma(a2_.x, u2.x, sa); sa = fma(a2_.y, u2.y, sa);
-        sa = fma(a3.x, u3.x, sa); sa = fma(a3.y, u3.y, sa);
-        sb = fma(a0.x, v0.x, sb); sb = fma(a0.y, v0.y, sb);
-        sb = fma(a1.x, v1.x, sb); sb = fma(a1.y, v1.y, sb);
-        sb = fma(a2_.x, v2.x, sb); sb = fma(a2_.y, v2.y, sb);
-        sb = fma(a3.x, v3.x, sb); sb = fma(a3.y, v3.y, sb);
+    for (; c + 448 < n2; c += 512) {
+        d2v a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(a2 + c + 64 * u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            d2v xu = x2[c + 64 * u], yv = y2[c + 64 * u];
+            sa = fma(a[u].x, xu.x, sa); sa = fma(a[u].y, xu.y, sa);
+            sb = fma(a[u].x, yv.x, sb); sb = fma(a[u].y, yv.y, sb);
+        }
     }
     for (; c < n2; c += 64) {
         d2v a0 = __builtin_nontemporal_load(a2 + c);
@@ -97,14 +95,15 @@ __device__ __forceinline__ void row1(const double* __restrict__ A, const double*
     const d2v* x2 = reinterpret_cast<const d2v*>(xa);
     const int n2 = len >> 1;
     int c = lane;
-    for (; c + 192 < n2; c += 256) {
-        d2v a0 = __builtin_nontemporal_load(a2 + c), a1 = __builtin_nontemporal_load(a2 + c + 64);
-        d2v a2_ = __builtin_nontemporal_load(a2 + c + 128), a3 = __builtin_nontemporal_load(a2 + c + 192);
-        d2v u0 = x2[c], u1 = x2[c + 64], u2 = x2[c + 128], u3 = x2[c + 192];
-        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
-        sa = fma(a1.x, u1.x, sa); sa = fma(a1.y, u1.y, sa);
-        sa = fma(a2_.x, u2.x, sa); sa = fma(a2_.y, u2.y, sa);
-        sa = fma(a3.x, u3.x, sa); sa = fma(a3.y, u3.y, sa);
+    for (; c + 448 < n2; c += 512) {
+        d2v a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(a2 + c + 64 * u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            d2v xu = x2[c + 64 * u];
+            sa = fma(a[u].x, xu.x, sa); sa = fma(a[u].y, xu.y, sa);
+        }
     }
     for (; c < n2; c += 64) {
         d2v a0 = __builtin_nontemporal_load(a2 + c);
@@ -113,16 +112,14 @@ __device__ __forceinline__ void row1(const double* __restrict__ A, const double*
     }
 }
 
-// y = C1 ebar + (1/T_max) C2 Ebar - sum_{j=1}^{min(k-1, nh)} Q_j w_{k-j}
-// (eq. MOT right-hand side, eq. rhs).  Q_j = [[q1, -qk], [qk, q2]] in three
-// [ne][hs] blocks; ring slot of w_{k-j} is (k-j) mod nh.
+// y = r_k - sum_{j=1}^{min(k-1, nh)} Q_j w_{k-j}   (eq. MOT right-hand side).
+// r_k comes from the batched RHS [half][ne][B] (column (k-1) mod B).
+// Q_j = [[q1, -qk], [qk, q2]] in three [ne][hs] blocks; ring slot of w_{k-j}
+// is (k-j) mod nh.
 __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __restrict__ dk, int nh,
                                                  const double* __restrict__ Q,
                                                  const double* __restrict__ ring,
-                                                 const double* __restrict__ C1,
-                                                 const double* __restrict__ C2, double invT,
-                                                 const double* __restrict__ ebar,
-                                                 const double* __restrict__ Ebar,
+                                                 const double* __restrict__ rb, int B,
                                                  double* __restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -130,11 +127,6 @@ __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __re
     const int k = *dk;
     const size_t blk = (size_t)ne * hs;
     const int n2 = 2 * hs;
-    double su = 0, sv = 0, tu = 0, tv = 0;
-    row2(C1 + (size_t)m * hs, ebar, ebar + hs, hs, lane, su, sv);
-    row2(C2 + (size_t)m * hs, Ebar, Ebar + hs, hs, lane, tu, tv);
-    su += invT * tu;
-    sv += invT * tv;
     int nact = k - 1 < nh ? k - 1 : nh;
     double hu = 0, hv = 0;
     for (int j = 1; j <= nact; ++j) {
@@ -149,11 +141,12 @@ __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __re
         hu += a - b;
         hv += cc + d;
     }
-    su = wave_sum(su - hu);
-    sv = wave_sum(sv - hv);
+    hu = wave_sum(hu);
+    hv = wave_sum(hv);
     if (lane == 0) {
-        y[m] = su;
-        y[hs + m] = sv;
+        const int sc = (k - 1) % B;
+        y[m] = rb[(size_t)m * B + sc] - hu;
+        y[hs + m] = rb[(size_t)ne * B + (size_t)m * B + sc] - hv;
     }
 }
 
@@ -496,6 +489,191 @@ __global__ __launch_bounds__(256) void k_gm_orth(int n2, const double* __restric
     flag->seq = flag->seq + 1;
 }
 
+// Single-workgroup variants used when a good preconditioner keeps the Krylov
+// space small: the whole classical Gram-Schmidt pass with re-orthogonalisation,
+// the norm and the Givens update run in one 1024-thread workgroup.
+constexpr int kSW = 1024;
+constexpr int kSWE = 32;     // elements per thread: n2 <= 32768
+
+__device__ __forceinline__ double block_sum_sw(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < kSW / 64; ++i) s += sh[i];
+    return s;
+}
+
+// r = y - t (t = Q0 x0, or nothing for x0 = 0); beta, bnorm; start a cycle.
+__global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restrict__ b,
+                                                    double* __restrict__ r, int have_t, GmState* gm,
+                                                    GmFlag* flag, double tol, int first) {
+    __shared__ double sh[kSW / 64];
+    double s1 = 0, s2 = 0;
+    for (int i = threadIdx.x; i < n2; i += kSW) {
+        double bi = b[i];
+        double ri = have_t ? bi - r[i] : bi;
+        r[i] = ri;
+        s1 = fma(ri, ri, s1);
+        s2 = fma(bi, bi, s2);
+    }
+    s1 = block_sum_sw(s1, sh);
+    s2 = block_sum_sw(s2, sh);
+    if (threadIdx.x == 0) {
+        double beta = sqrt(s1);
+        if (first) { gm->bnorm = sqrt(s2); gm->total = 0; }
+        gm->beta = beta;
+        gm->g[0] = beta;
+        gm->j = 0;
+        gm->cycle_iters = 0;
+        gm->breakdown = 0;
+        double bn = gm->bnorm;
+        gm->relres = bn > 0 ? beta / bn : 0.0;
+        int conv = (bn == 0.0) || (beta <= tol * bn);
+        gm->converged = conv;
+        gm->done = conv;
+        gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+        flag->relres = gm->relres;
+        flag->converged = conv;
+        flag->done = conv;
+        flag->total = gm->total;
+        __threadfence_system();
+        flag->seq = flag->seq + 1;
+    }
+}
+
+__device__ void givens_finish(GmState* gm, GmFlag* flag, double* col, double hn, int j, int M, double tol) {
+    col[j + 1] = hn;
+    for (int l = 0; l < j; ++l) {
+        double a = col[l], b = col[l + 1];
+        col[l] = gm->cs[l] * a + gm->sn[l] * b;
+        col[l + 1] = -gm->sn[l] * a + gm->cs[l] * b;
+    }
+    double a = col[j], b = col[j + 1];
+    double r = hypot(a, b);
+    double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
+    gm->cs[j] = cs;
+    gm->sn[j] = sn;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    double gj = gm->g[j];
+    gm->g[j] = cs * gj;
+    gm->g[j + 1] = -sn * gj;
+    int jj = j + 1;
+    gm->j = jj;
+    gm->cycle_iters = jj;
+    gm->total += 1;
+    double rel = gm->bnorm > 0 ? fabs(gm->g[jj]) / gm->bnorm : 0.0;
+    gm->relres = rel;
+    int conv = rel <= tol;
+    int brk = !(hn > 1e-300 * (gm->beta + 1e-300));
+    gm->breakdown = brk;
+    gm->converged = conv || brk;
+    gm->done = conv || brk || jj >= M;
+    gm->inv_h = hn > 0 ? 1.0 / hn : 0.0;
+    if (gm->done) {
+        for (int i = jj - 1; i >= 0; --i) {
+            double s = gm->g[i];
+            for (int l = i + 1; l < jj; ++l) s -= gm->H[(size_t)l * (M + 1) + i] * gm->y[l];
+            double d = gm->H[(size_t)i * (M + 1) + i];
+            gm->y[i] = d != 0 ? s / d : 0.0;
+        }
+    }
+    flag->relres = rel;
+    flag->converged = gm->converged;
+    flag->done = gm->done;
+    flag->total = gm->total;
+    __threadfence_system();
+    flag->seq = flag->seq + 1;
+}
+
+// CGS2 of w against V[0..j], norm, Givens: one workgroup.
+__global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restrict__ V,
+                                                   double* __restrict__ w, GmState* gm, GmFlag* flag,
+                                                   double tol, int M) {
+    if (gm->done) {
+        // nothing to do, but every launch publishes one progress word
+        if (threadIdx.x == 0) {
+            flag->relres = gm->relres;
+            flag->converged = gm->converged;
+            flag->done = 1;
+            flag->total = gm->total;
+            __threadfence_system();
+            flag->seq = flag->seq + 1;
+        }
+        return;
+    }
+    __shared__ double sh[kSW / 64];
+    __shared__ double hc[MOT_MAXM + 1];
+    const int j = gm->j;
+    double wv[kSWE];
+    const int ne_t = (n2 + kSW - 1) / kSW;
+#pragma unroll
+    for (int e = 0; e < kSWE; ++e) {
+        int i = threadIdx.x + e * kSW;
+        wv[e] = (e < ne_t && i < n2) ? w[i] : 0.0;
+    }
+    if (threadIdx.x <= j) hc[threadIdx.x] = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int l = 0; l <= j; ++l) {
+            const double* v = V + (size_t)l * n2;
+            double s = 0;
+#pragma unroll
+            for (int e = 0; e < kSWE; ++e) {
+                int i = threadIdx.x + e * kSW;
+                if (e < ne_t && i < n2) s = fma(v[i], wv[e], s);
+            }
+            s = block_sum_sw(s, sh);
+#pragma unroll
+            for (int e = 0; e < kSWE; ++e) {
+                int i = threadIdx.x + e * kSW;
+                if (e < ne_t && i < n2) wv[e] = fma(-s, v[i], wv[e]);
+            }
+            if (threadIdx.x == 0) hc[l] += s;
+        }
+    }
+    double nn = 0;
+#pragma unroll
+    for (int e = 0; e < kSWE; ++e) nn = fma(wv[e], wv[e], nn);
+    nn = block_sum_sw(nn, sh);
+#pragma unroll
+    for (int e = 0; e < kSWE; ++e) {
+        int i = threadIdx.x + e * kSW;
+        if (e < ne_t && i < n2) w[i] = wv[e];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* col = gm->H + (size_t)j * (M + 1);
+        for (int l = 0; l <= j; ++l) col[l] = hc[l];
+        givens_finish(gm, flag, col, sqrt(nn), j, M, tol);
+    }
+}
+
+// When the cycle is done: x += sum_l y_l Z_l ; when converged (or forced) also
+// push x into the ring and the kept history.
+__global__ void k_gm_finish(int n2, const double* __restrict__ Zb, const GmState* __restrict__ gm,
+                            double* __restrict__ x, const int* __restrict__ dk, int nh,
+                            double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force) {
+    if (!gm->done && !force) return;
+    const int jj = gm->done ? gm->cycle_iters : 0;
+    const int push = gm->converged || force;
+    const int k = *dk;
+    double* slot = ring + (size_t)(k % nh) * n2;
+    double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 : nullptr;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double s = x[i];
+        for (int l = 0; l < jj; ++l) s = fma(gm->y[l], Zb[(size_t)l * n2 + i], s);
+        x[i] = s;
+        if (push) {
+            slot[i] = s;
+            if (hs) hs[i] = s;
+        }
+    }
+}
+
 // x += sum_l y[l] V[l]   (l < cycle length)
 __global__ void k_gm_update_x(int n2, const double* __restrict__ V, const GmState* __restrict__ gm,
                               double* __restrict__ x) {   // V: the stored M v_l (or v_l)
@@ -591,15 +769,39 @@ __global__ void k_pack(int ne, int hs, int R, int ns, const double* __restrict__
 // ------------------------------------------------------------ launchers ---
 namespace motk_step {
 
-void rhs_fields(mot_handle* h) {
-    int tot = h->ne * h->R;
-    hipLaunchKernelGGL(k_rhs_fields, dim3((tot + 127) / 128), dim3(128), 0, h->stream, h->ne, h->hs, h->R,
-                       h->d_k, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
+// RHS of steps k0 .. k0+B-1: fields, then r = C1 ebar + C2 Ebar / T_max per half
+void rhs_batch(mot_handle* h, int k0, double* rb) {
+    const int ne = h->ne, hs = h->hs, B = h->B;
+    int tot = ne * B;
+    hipLaunchKernelGGL(k_rhs_fields, dim3((tot + 255) / 256), dim3(256), 0, h->stream, ne, hs, k0, B, h->dt,
+                       h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
+    for (int half = 0; half < 2; ++half) {
+        const double* eb = h->ebar + (size_t)half * hs * B;
+        const double* Eb = h->Ebar + (size_t)half * hs * B;
+        double* out = rb + (size_t)half * ne * B;
+        motk::gemm(h->stream, ne, B, ne, 1.0, h->C1, hs, eb, B, 0.0, out, B);
+        motk::gemm(h->stream, ne, B, ne, 1.0 / h->Tmax, h->C2, hs, Eb, B, 1.0, out, B);
+    }
 }
 
 void history(mot_handle* h) {
     hipLaunchKernelGGL(k_history, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, h->Q, h->ring, h->C1, h->C2, 1.0 / h->Tmax, h->ebar, h->Ebar, h->y);
+                       h->nh, h->Q, h->ring, h->rb, h->B, h->y);
+}
+
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first) {
+    hipLaunchKernelGGL(k_gm_start1, dim3(1), dim3(kSW), 0, h->stream, h->n2, b, r, have_t, h->gm, h->dflag,
+                       h->opt.gmres_tol, first);
+}
+
+void gm_orth1(mot_handle* h, double* w) {
+    hipLaunchKernelGGL(k_gm_orth1, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm, h->dflag,
+                       h->opt.gmres_tol, h->M);
+}
+
+void gm_finish(mot_handle* h, const double* basis, int force) {
+    hipLaunchKernelGGL(k_gm_finish, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, basis, h->gm,
+                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force);
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
