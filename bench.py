@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
+    ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the MOT march of one problem runs on one device "
@@ -94,7 +95,7 @@ def main():
     t_fixture = time.perf_counter() - t
     log("inputs assembled on the host in %.1f s" % t_fixture)
 
-    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond)
+    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond, stream_split=args.split)
     t = time.perf_counter()
     s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
                    prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,

@@ -89,7 +89,12 @@ typedef struct {
                                 approximate inverse of Q_0 built once on the
                                 device by Newton-Schulz iteration;
                                 0 none, 1 stored FP32 (default), 2 FP64       */
-    int32_t reserved[6];
+    int32_t stream_split;    /* wavefronts sharing one matrix row in the
+                                streaming products: 1, 2 or 4 (0: 1)          */
+    int32_t history_order;   /* history kernel loop order: 1 (or 0) column
+                                slices across all blocks, 2 whole rows of one
+                                block at a time                               */
+    int32_t reserved[4];
 } mot_options;
 
 typedef struct {

@@ -224,6 +224,17 @@ __global__ void k_cg_pupdate(int rows, int ncol, const double* __restrict__ beta
     }
 }
 
+// subtract each column's mean: the RHS of a graph-Laplacian pseudo-inverse solve
+// is projected onto the complement of the constant null vector
+__global__ void k_col_center(int rows, int ncol, double* __restrict__ X) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s += X[(size_t)r * ncol + c];
+    s /= rows;
+    for (int r = 0; r < rows; ++r) X[(size_t)r * ncol + c] -= s;
+}
+
 __global__ void k_count(int ncol, const int* __restrict__ active, int* __restrict__ out) {
     __shared__ int s;
     if (threadIdx.x == 0) s = 0;
@@ -314,6 +325,10 @@ void cg_scalars(hipStream_t s, int ncol, const double* pq, const double* part, i
 void cg_pupdate(hipStream_t s, int rows, int ncol, const double* beta, const double* R, double* P) {
     hipLaunchKernelGGL(k_cg_pupdate, dim3(nblk((size_t)rows * ncol)), dim3(256), 0, s, rows, ncol, beta,
                        R, P);
+}
+
+void col_center(hipStream_t s, int rows, int ncol, double* X) {
+    hipLaunchKernelGGL(k_col_center, dim3((ncol + 255) / 256), dim3(256), 0, s, rows, ncol, X);
 }
 
 int count_active(hipStream_t s, int ncol, const int* active, int* d_count, int* h_count) {

@@ -11,7 +11,7 @@
 namespace motk_step {
 void rhs_batch(mot_handle* h, int k0, double* rb);
 void history(mot_handle* h);
-void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first);
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero);
 void gm_orth1(mot_handle* h, double* w);
 void gm_finish(mot_handle* h, const double* basis, int force);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
@@ -182,6 +182,7 @@ int dense_projector(mot_handle* h, const DevGraph& g, double* Pout) {
         motk::fill2d(h->stream, ne, nc, 0.0, E, nc);
         motk::set_identity(h->stream, nc, E + (size_t)c0 * nc, nc);   // E[c0 + i][i] = 1
         motk::inc_T(h->stream, g, nc, E, nc, S);
+        motk::col_center(h->stream, g.nnode, nc, S);
         auto lap = [&](const double* X, double* Yo) { motk::spmm_lap(h->stream, g, nc, X, Yo); };
         rc = batched_cg(h, g.nnode, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
         if (rc) return rc;
@@ -465,10 +466,9 @@ int gmres_solve_pc(mot_handle* h) {
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
-        gm_start1(h, h->y, h->wA, 1, 1);
+        gm_start1(h, h->y, h->wA, 1, 1, nullptr);
     } else {
-        HIPCHK(h, hipMemsetAsync(h->x, 0, (size_t)h->n2 * sizeof(double), h->stream));
-        gm_start1(h, h->y, h->wA, 0, 1);
+        gm_start1(h, h->y, h->wA, 0, 1, h->x);
     }
     int seq = 1, iters = 0;
     bool first_cycle = true;
@@ -509,7 +509,7 @@ int gmres_solve_pc(mot_handle* h) {
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
-        gm_start1(h, h->y, h->wA, 1, 0);
+        gm_start1(h, h->y, h->wA, 1, 0, nullptr);
         seq += 1;
         if ((prc = wait_flag(h, seq))) return prc;
         if (h->hflag->done) {      // restart residual already below the tolerance
@@ -531,6 +531,7 @@ int gmres_solve(mot_handle* h) {
     const int M = h->M;
     int maxit = h->opt.gmres_maxit;
     h->hflag->seq = 0;
+    HIPCHK(h, hipMemsetAsync(&h->gm->seq, 0, sizeof(int), h->stream));
     h->hflag->done = 0;
     int seq_target = 0;
     bool first = true;
@@ -611,6 +612,7 @@ int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
         int nc = nb * per;
         motk_step::rec_gather(h, s0 + b0, nb, X);
         motk::inc_T(h->stream, h->gf, nc, X, nc, S);
+        motk::col_center(h->stream, h->nf, nc, S);
         auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
         rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
         if (rc && rc != MOT_ENOCONV) return rc;
@@ -724,6 +726,12 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     h->nv = nv; h->nf = nf; h->ne = ne; h->R = nrhs;
     h->hs = (ne + 7) & ~7;
     h->n2 = 2 * h->hs;
+    {
+        int sp = h->opt.stream_split;
+        if (sp != 1 && sp != 2 && sp != 4) sp = 1;
+        h->wpr = sp;
+        h->hist_variant = h->opt.history_order == 2 ? 0 : 1;
+    }
     h->genus = (2 - chi) / 2;
     h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
     h->c = 1.0; h->eta = 1.0;

@@ -41,7 +41,7 @@ struct GmState {
     double beta, bnorm, relres, inv_h;
     int j, done, converged, total, cycle_iters, breakdown;
     unsigned int counter;
-    int pad;
+    int seq;                                // progress words published so far
     double partial[(MOT_MAXM + 1) * MOT_GM_BLOCKS];
 };
 
@@ -79,6 +79,7 @@ void cg_scalars(hipStream_t s, int ncol, const double* pq, const double* rr_new_
                 int phase);
 void cg_pupdate(hipStream_t s, int rows, int ncol, const double* beta, const double* R, double* P);
 int count_active(hipStream_t s, int ncol, const int* active, int* d_count, int* h_count);
+void col_center(hipStream_t s, int rows, int ncol, double* X);
 }  // namespace motk
 
 // Event pairs bracketing one kernel's launches (profile mode).
@@ -128,6 +129,8 @@ struct mot_handle {
     double* hist = nullptr;          // [max_steps][n2][R]
     int hist_cap = 0;
     int B = 128;                     // steps per RHS batch
+    int wpr = 1;                     // wavefronts per matrix row in the streaming kernels
+    int hist_variant = 0;            // 0 row-outer, 1 column-outer history kernel
     double* ebar = nullptr;          // [2][hs][B] tested fields of a batch
     double* Ebar = nullptr;
     double* rb = nullptr;            // [2][ne][B] r_k = C1 ebar + C2 Ebar / T_max

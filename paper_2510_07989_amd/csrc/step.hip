@@ -120,26 +120,96 @@ __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __re
                                                  const double* __restrict__ Q,
                                                  const double* __restrict__ ring,
                                                  const double* __restrict__ rb, int B,
-                                                 double* __restrict__ y) {
+                                                 double* __restrict__ y, int wpr) {
+    // wpr wavefronts share one row, each streaming a contiguous 1/wpr of it
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = blockIdx.x * (4 / wpr) + wv / wpr;
+    const int part = wv % wpr;
+    const int plen = hs / wpr, off = part * plen;
+    __shared__ double red[4][2];
+    const int k = *dk;
+    double hu = 0, hv = 0;
+    if (m < ne) {
+        const size_t blk = (size_t)ne * hs;
+        const int n2 = 2 * hs;
+        int nact = k - 1 < nh ? k - 1 : nh;
+        for (int j = 1; j <= nact; ++j) {
+            int slot = (k - j) % nh;
+            const double* wu = ring + (size_t)slot * n2 + off;
+            const double* wvv = ring + (size_t)slot * n2 + hs + off;
+            const double* Qj = Q + (size_t)j * 3 * blk + (size_t)m * hs + off;
+            double a = 0, b = 0, cc = 0, d = 0;
+            row1(Qj, wu, plen, lane, a);                     // q1 u
+            row2(Qj + blk, wvv, wu, plen, lane, b, cc);      // qk v, qk u
+            row1(Qj + 2 * blk, wvv, plen, lane, d);          // q2 v
+            hu += a - b;
+            hv += cc + d;
+        }
+    }
+    hu = wave_sum(hu);
+    hv = wave_sum(hv);
+    if (lane == 0) { red[wv][0] = hu; red[wv][1] = hv; }
+    __syncthreads();
+    if (lane == 0 && part == 0 && m < ne) {
+        double su = 0, sv = 0;
+        for (int p = 0; p < wpr; ++p) { su += red[wv + p][0]; sv += red[wv + p][1]; }
+        const int sc = (k - 1) % B;
+        y[m] = rb[(size_t)m * B + sc] - su;
+        y[hs + m] = rb[(size_t)ne * B + (size_t)m * B + sc] - sv;
+    }
+}
+
+// Variant with the columns outermost: every lane walks the same column slice of
+// all 3 (L-1) row blocks, so each iteration has several independent 16-byte
+// loads from different blocks in flight.
+__global__ __launch_bounds__(256) void k_history_co(int ne, int hs, const int* __restrict__ dk, int nh,
+                                                    const double* __restrict__ Q,
+                                                    const double* __restrict__ ring,
+                                                    const double* __restrict__ rb, int B,
+                                                    double* __restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m >= ne) return;
     const int k = *dk;
     const size_t blk = (size_t)ne * hs;
     const int n2 = 2 * hs;
-    int nact = k - 1 < nh ? k - 1 : nh;
+    const int nact = k - 1 < nh ? k - 1 : nh;
+    const int np = hs >> 1;
     double hu = 0, hv = 0;
-    for (int j = 1; j <= nact; ++j) {
-        int slot = (k - j) % nh;
-        const double* wu = ring + (size_t)slot * n2;
-        const double* wv = wu + hs;
-        const double* Qj = Q + (size_t)j * 3 * blk + (size_t)m * hs;
-        double a = 0, b = 0, cc = 0, d = 0;
-        row1(Qj, wu, hs, lane, a);                      // q1 u
-        row2(Qj + blk, wv, wu, hs, lane, b, cc);        // qk v, qk u
-        row1(Qj + 2 * blk, wv, hs, lane, d);            // q2 v
-        hu += a - b;
-        hv += cc + d;
+    for (int c = lane; c < np; c += 64) {
+        int j = 1;
+        for (; j + 1 <= nact; j += 2) {
+            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
+            const d2v* A1 = reinterpret_cast<const d2v*>(Q + (size_t)(j + 1) * 3 * blk + (size_t)m * hs);
+            const size_t b2 = blk >> 1;
+            d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
+                q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
+            d2v a1 = __builtin_nontemporal_load(A1 + c), k1 = __builtin_nontemporal_load(A1 + b2 + c),
+                q1 = __builtin_nontemporal_load(A1 + 2 * b2 + c);
+            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+            const d2v* w1 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j - 1) % nh) * n2);
+            d2v u0 = w0[c], v0 = w0[(hs >> 1) + c], u1 = w1[c], v1 = w1[(hs >> 1) + c];
+            hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
+            hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
+            hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
+            hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
+            hu = fma(a1.x, u1.x, hu); hu = fma(a1.y, u1.y, hu);
+            hu = fma(-k1.x, v1.x, hu); hu = fma(-k1.y, v1.y, hu);
+            hv = fma(k1.x, u1.x, hv); hv = fma(k1.y, u1.y, hv);
+            hv = fma(q1.x, v1.x, hv); hv = fma(q1.y, v1.y, hv);
+        }
+        for (; j <= nact; ++j) {
+            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
+            const size_t b2 = blk >> 1;
+            d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
+                q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
+            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+            d2v u0 = w0[c], v0 = w0[(hs >> 1) + c];
+            hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
+            hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
+            hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
+            hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
+        }
     }
     hu = wave_sum(hu);
     hv = wave_sum(hv);
@@ -171,24 +241,32 @@ __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double*
                                                    const double* __restrict__ src,
                                                    double* __restrict__ vout, double* __restrict__ y,
                                                    const GmState* __restrict__ gm, int check_done,
-                                                   int use_inv) {
+                                                   int use_inv, int wpr) {
     if (check_done && gm->done) return;
-    const int lane = threadIdx.x & 63;
-    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= ne) return;
-    const size_t blk = (size_t)ne * hs;
-    const double sc = use_inv ? gm->inv_h : 1.0;
-    const double* xu = src;
-    const double* xv = src + hs;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = blockIdx.x * (4 / wpr) + wv / wpr;
+    const int part = wv % wpr;
+    const int plen = hs / wpr, off = part * plen;
+    __shared__ double red[4][2];
     double a = 0, b = 0, cc = 0, d = 0;
-    row1(Q0 + (size_t)m * hs, xu, hs, lane, a);
-    row2(Q0 + blk + (size_t)m * hs, xv, xu, hs, lane, b, cc);
-    row1(Q0 + 2 * blk + (size_t)m * hs, xv, hs, lane, d);
+    if (m < ne) {
+        const size_t blk = (size_t)ne * hs;
+        const double* xu = src + off;
+        const double* xv = src + hs + off;
+        row1(Q0 + (size_t)m * hs + off, xu, plen, lane, a);
+        row2(Q0 + blk + (size_t)m * hs + off, xv, xu, plen, lane, b, cc);
+        row1(Q0 + 2 * blk + (size_t)m * hs + off, xv, plen, lane, d);
+    }
     a = wave_sum(a - b);
     cc = wave_sum(cc + d);
-    if (lane == 0) {
-        y[m] = sc * a;
-        y[hs + m] = sc * cc;
+    if (lane == 0) { red[wv][0] = a; red[wv][1] = cc; }
+    __syncthreads();
+    if (lane == 0 && part == 0 && m < ne) {
+        double su = 0, sv = 0;
+        for (int p = 0; p < wpr; ++p) { su += red[wv + p][0]; sv += red[wv + p][1]; }
+        const double sc = use_inv ? gm->inv_h : 1.0;
+        y[m] = sc * su;
+        y[hs + m] = sc * sv;
         if (vout) {
             vout[m] = sc * src[m];
             vout[hs + m] = sc * src[hs + m];
@@ -201,41 +279,54 @@ __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double*
 template <typename T>
 __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M,
                                                  const double* __restrict__ src, double* __restrict__ vj,
-                                                 double* __restrict__ z, const GmState* __restrict__ gm) {
+                                                 double* __restrict__ z, const GmState* __restrict__ gm,
+                                                 int wpr) {
     if (gm->done) return;
-    const int lane = threadIdx.x & 63;
-    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= n2) return;
-    const double sc = gm->inv_h;
-    const T* row = M + (size_t)m * n2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = blockIdx.x * (4 / wpr) + wv / wpr;
+    const int part = wv % wpr;
+    const int plen = n2 / wpr, off = part * plen;
+    __shared__ double red[4];
     double s0 = 0, s1 = 0;
-    if constexpr (sizeof(T) == 4) {
-        typedef float f4v __attribute__((ext_vector_type(4)));
-        typedef double d4v __attribute__((ext_vector_type(4)));
-        const f4v* a4 = reinterpret_cast<const f4v*>(row);
-        const d4v* x4 = reinterpret_cast<const d4v*>(src);
-        const int n4 = n2 >> 2;
-        int c = lane;
-        for (; c + 64 < n4; c += 128) {
-            f4v a0 = __builtin_nontemporal_load(a4 + c), a1 = __builtin_nontemporal_load(a4 + c + 64);
-            d4v u0 = x4[c], u1 = x4[c + 64];
-            s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
-            s0 = fma((double)a0.z, u0.z, s0); s0 = fma((double)a0.w, u0.w, s0);
-            s1 = fma((double)a1.x, u1.x, s1); s1 = fma((double)a1.y, u1.y, s1);
-            s1 = fma((double)a1.z, u1.z, s1); s1 = fma((double)a1.w, u1.w, s1);
+    if (m < n2) {
+        const T* row = M + (size_t)m * n2 + off;
+        const double* x = src + off;
+        if constexpr (sizeof(T) == 4) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            typedef double d4v __attribute__((ext_vector_type(4)));
+            const f4v* a4 = reinterpret_cast<const f4v*>(row);
+            const d4v* x4 = reinterpret_cast<const d4v*>(x);
+            const int n4 = plen >> 2;
+            int c = lane;
+            for (; c + 192 < n4; c += 256) {
+                f4v a[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = __builtin_nontemporal_load(a4 + c + 64 * u);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    d4v xu = x4[c + 64 * u];
+                    s0 = fma((double)a[u].x, xu.x, s0); s0 = fma((double)a[u].y, xu.y, s0);
+                    s1 = fma((double)a[u].z, xu.z, s1); s1 = fma((double)a[u].w, xu.w, s1);
+                }
+            }
+            for (; c < n4; c += 64) {
+                f4v a0 = __builtin_nontemporal_load(a4 + c);
+                d4v u0 = x4[c];
+                s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
+                s1 = fma((double)a0.z, u0.z, s1); s1 = fma((double)a0.w, u0.w, s1);
+            }
+        } else {
+            row1(reinterpret_cast<const double*>(row), x, plen, lane, s0);
         }
-        for (; c < n4; c += 64) {
-            f4v a0 = __builtin_nontemporal_load(a4 + c);
-            d4v u0 = x4[c];
-            s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
-            s0 = fma((double)a0.z, u0.z, s0); s0 = fma((double)a0.w, u0.w, s0);
-        }
-    } else {
-        row1(reinterpret_cast<const double*>(row), src, n2, lane, s0);
     }
     double s = wave_sum(s0 + s1);
-    if (lane == 0) {
-        z[m] = sc * s;
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (lane == 0 && part == 0 && m < n2) {
+        double t = 0;
+        for (int p = 0; p < wpr; ++p) t += red[wv + p];
+        const double sc = gm->inv_h;
+        z[m] = sc * t;
         vj[m] = sc * src[m];
     }
 }
@@ -363,7 +454,7 @@ __global__ __launch_bounds__(256) void k_gm_residual(int n2, const double* __res
         flag->done = conv;
         flag->total = gm->total;
         __threadfence_system();
-        flag->seq = flag->seq + 1;
+        flag->seq = ++gm->seq;
     }
 }
 
@@ -486,7 +577,7 @@ __global__ __launch_bounds__(256) void k_gm_orth(int n2, const double* __restric
     flag->done = gm->done;
     flag->total = gm->total;
     __threadfence_system();
-    flag->seq = flag->seq + 1;
+    flag->seq = ++gm->seq;
 }
 
 // Single-workgroup variants used when a good preconditioner keeps the Krylov
@@ -510,10 +601,12 @@ __device__ __forceinline__ double block_sum_sw(double v, double* sh) {
 // r = y - t (t = Q0 x0, or nothing for x0 = 0); beta, bnorm; start a cycle.
 __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restrict__ b,
                                                     double* __restrict__ r, int have_t, GmState* gm,
-                                                    GmFlag* flag, double tol, int first) {
+                                                    GmFlag* flag, double tol, int first,
+                                                    double* __restrict__ xzero) {
     __shared__ double sh[kSW / 64];
     double s1 = 0, s2 = 0;
     for (int i = threadIdx.x; i < n2; i += kSW) {
+        if (xzero) xzero[i] = 0.0;      // cold start x0 = 0
         double bi = b[i];
         double ri = have_t ? bi - r[i] : bi;
         r[i] = ri;
@@ -524,7 +617,7 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
     s2 = block_sum_sw(s2, sh);
     if (threadIdx.x == 0) {
         double beta = sqrt(s1);
-        if (first) { gm->bnorm = sqrt(s2); gm->total = 0; }
+        if (first) { gm->bnorm = sqrt(s2); gm->total = 0; gm->seq = 0; }
         gm->beta = beta;
         gm->g[0] = beta;
         gm->j = 0;
@@ -541,53 +634,65 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
         flag->done = conv;
         flag->total = gm->total;
         __threadfence_system();
-        flag->seq = flag->seq + 1;
+        flag->seq = ++gm->seq;
     }
 }
 
-__device__ void givens_finish(GmState* gm, GmFlag* flag, double* col, double hn, int j, int M, double tol) {
-    col[j + 1] = hn;
+__device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, double* col, double hn, int j,
+                              int M, double tol) {
+    // values kept in registers; global state written once at the end
+    double cl[MOT_MAXM + 1];
+    for (int l = 0; l <= j; ++l) cl[l] = hvals[l];
+    cl[j + 1] = hn;
     for (int l = 0; l < j; ++l) {
-        double a = col[l], b = col[l + 1];
-        col[l] = gm->cs[l] * a + gm->sn[l] * b;
-        col[l + 1] = -gm->sn[l] * a + gm->cs[l] * b;
+        double cs = gm->cs[l], sn = gm->sn[l];
+        double a = cl[l], b = cl[l + 1];
+        cl[l] = cs * a + sn * b;
+        cl[l + 1] = -sn * a + cs * b;
     }
-    double a = col[j], b = col[j + 1];
+    double a = cl[j], b = cl[j + 1];
     double r = hypot(a, b);
     double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
+    cl[j] = r;
+    cl[j + 1] = 0.0;
+    const double gj = gm->g[j], bnorm = gm->bnorm, beta = gm->beta;
+    const int total = gm->total + 1;
+    const double gnew = -sn * gj;
+    const int jj = j + 1;
+    const double rel = bnorm > 0 ? fabs(gnew) / bnorm : 0.0;
+    const int conv = rel <= tol;
+    const int brk = !(hn > 1e-300 * (beta + 1e-300));
+    const int done = conv || brk || jj >= M;
+    const int seq = gm->seq + 1;
+    // publish the progress word first (host-visible), then the device state
+    flag->relres = rel;
+    flag->converged = conv || brk;
+    flag->done = done;
+    flag->total = total;
+    for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
     gm->cs[j] = cs;
     gm->sn[j] = sn;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    double gj = gm->g[j];
     gm->g[j] = cs * gj;
-    gm->g[j + 1] = -sn * gj;
-    int jj = j + 1;
+    gm->g[jj] = gnew;
     gm->j = jj;
     gm->cycle_iters = jj;
-    gm->total += 1;
-    double rel = gm->bnorm > 0 ? fabs(gm->g[jj]) / gm->bnorm : 0.0;
+    gm->total = total;
     gm->relres = rel;
-    int conv = rel <= tol;
-    int brk = !(hn > 1e-300 * (gm->beta + 1e-300));
     gm->breakdown = brk;
     gm->converged = conv || brk;
-    gm->done = conv || brk || jj >= M;
+    gm->done = done;
     gm->inv_h = hn > 0 ? 1.0 / hn : 0.0;
-    if (gm->done) {
+    gm->seq = seq;
+    if (done) {
         for (int i = jj - 1; i >= 0; --i) {
             double s = gm->g[i];
             for (int l = i + 1; l < jj; ++l) s -= gm->H[(size_t)l * (M + 1) + i] * gm->y[l];
-            double d = gm->H[(size_t)i * (M + 1) + i];
+            double d = (i == j) ? r : gm->H[(size_t)i * (M + 1) + i];
             gm->y[i] = d != 0 ? s / d : 0.0;
         }
     }
-    flag->relres = rel;
-    flag->converged = gm->converged;
-    flag->done = gm->done;
-    flag->total = gm->total;
     __threadfence_system();
-    flag->seq = flag->seq + 1;
+    flag->seq = seq;
 }
 
 // CGS2 of w against V[0..j], norm, Givens: one workgroup.
@@ -602,7 +707,7 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
             flag->done = 1;
             flag->total = gm->total;
             __threadfence_system();
-            flag->seq = flag->seq + 1;
+            flag->seq = ++gm->seq;
         }
         return;
     }
@@ -645,11 +750,7 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
         if (e < ne_t && i < n2) w[i] = wv[e];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double* col = gm->H + (size_t)j * (M + 1);
-        for (int l = 0; l <= j; ++l) col[l] = hc[l];
-        givens_finish(gm, flag, col, sqrt(nn), j, M, tol);
-    }
+    if (threadIdx.x == 0) givens_finish(gm, flag, hc, gm->H + (size_t)j * (M + 1), sqrt(nn), j, M, tol);
 }
 
 // When the cycle is done: x += sum_l y_l Z_l ; when converged (or forced) also
@@ -785,13 +886,19 @@ void rhs_batch(mot_handle* h, int k0, double* rb) {
 }
 
 void history(mot_handle* h) {
-    hipLaunchKernelGGL(k_history, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, h->Q, h->ring, h->rb, h->B, h->y);
+    if (h->hist_variant == 1) {
+        hipLaunchKernelGGL(k_history_co, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
+                           h->nh, h->Q, h->ring, h->rb, h->B, h->y);
+        return;
+    }
+    const int rpb = 4 / h->wpr;
+    hipLaunchKernelGGL(k_history, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
+                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr);
 }
 
-void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first) {
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero) {
     hipLaunchKernelGGL(k_gm_start1, dim3(1), dim3(kSW), 0, h->stream, h->n2, b, r, have_t, h->gm, h->dflag,
-                       h->opt.gmres_tol, first);
+                       h->opt.gmres_tol, first, xzero);
 }
 
 void gm_orth1(mot_handle* h, double* w) {
@@ -805,16 +912,18 @@ void gm_finish(mot_handle* h, const double* basis, int force) {
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
-    hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
-                       src, vout, y, h->gm, check_done, use_inv);
+    const int rpb = 4 / h->wpr;
+    hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
+                       src, vout, y, h->gm, check_done, use_inv, h->wpr);
 }
 
 void precond(mot_handle* h, const double* src, double* vj, double* z) {
-    dim3 grid((h->n2 + 3) / 4);
+    const int rpb = 4 / h->wpr;
+    dim3 grid((h->n2 + rpb - 1) / rpb);
     if (h->M32)
-        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm);
+        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm, h->wpr);
     else
-        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm);
+        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm, h->wpr);
 }
 
 void dense_q0(mot_handle* h, double* D) {

@@ -126,3 +126,18 @@ def test_preconditioner_variants(pc):
     if pc:
         assert its < 6
     s.close()
+
+
+@pytest.mark.parametrize("opts", [dict(history_order=2), dict(stream_split=2), dict(stream_split=4),
+                                  dict(history_order=2, precond=1), dict(history_order=2, stream_split=2)])
+def test_kernel_variants(opts):
+    """Loop-order and row-split variants of the streaming kernels give the oracle's march."""
+    print("variant", opts, flush=True)
+    O = oracle("sphere_480")
+    ref = O.run(100)
+    s = _solver("sphere_480", **opts)
+    out = s.run(100)
+    assert _rel(out["w"], ref["W"]) < 1e-10
+    assert _rel(out["loop"], ref["loop"]) < 1e-10
+    assert _rel(out["star"], ref["star"]) < 1e-10
+    s.close()
