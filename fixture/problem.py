@@ -45,6 +45,9 @@ CONFIGS = {
     "tiny_box": dict(mesh=("box", 2, 2, 2), eps_r=5.0, mu_r=1.0, dt=0.5, nsteps=40, nrhs=2, sigma=1.0, nq=12, seeded=True),
     # sphere, 320 triangles / 480 edges: plain FP64, 1 RHS
     "sphere_480": dict(mesh=("icosphere", 4), eps_r=2.0, mu_r=1.0, dt=0.25, nsteps=200, nrhs=1, sigma=1.0, nq=7),
+    "sphere_480_r16": dict(mesh=("icosphere", 4), eps_r=2.0, mu_r=1.0, dt=0.25, nsteps=120, nrhs=16, sigma=1.0, nq=7, seeded=True),
+    # sphere, 1280 triangles / 1920 edges, 16 seeded plane waves (multi-RHS benchmark size)
+    "sphere_1920_r16": dict(mesh=("icosphere", 8), eps_r=2.0, mu_r=1.0, dt=0.15, nsteps=400, nrhs=16, sigma=0.6, nq=7, seeded=True),
     # torus, 2048 triangles / 3072 edges, large timestep, 10^4 steps
     "torus_3072": dict(mesh=("torus", 1.0, 0.4, 64, 16), eps_r=4.0, mu_r=1.0, dt=2.0, nsteps=10000, nrhs=1, sigma=8.0, nq=7),
     # sphere, 5120 triangles / 7680 edges, 64 RHS

@@ -33,6 +33,16 @@ void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, doubl
 void pack(mot_handle* h, int ns, const double* src, double* dst);
 }  // namespace motk_step
 
+namespace motk_multi {
+size_t part_doubles(const mot_handle* h);
+void history(mot_handle* h);
+void q0_product(mot_handle* h, const double* X, double* out);
+void precond(mot_handle* h, const double* src, double* vj, double* z);
+void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero);
+void orth(mot_handle* h, double* w);
+void finish(mot_handle* h, int force);
+}  // namespace motk_multi
+
 static std::string g_create_err;
 
 int mot_fail(mot_handle* h, int code, const std::string& msg) {
@@ -524,6 +534,67 @@ int gmres_solve_pc(mot_handle* h) {
     return h->last_conv ? MOT_OK : MOT_ENOCONV;
 }
 
+// R > 1: one right-preconditioned GMRES per column, products shared as
+// tall-skinny GEMMs; cold start; the finisher is queued after the first Arnoldi
+// step and pushes w_k only once every column has converged.
+int gmres_solve_mr(mot_handle* h) {
+    namespace mm = motk_multi;
+    const int M = h->M;
+    const int maxit = h->opt.gmres_maxit;
+    h->hflag->seq = 0;
+    int prc;
+    const size_t vs = (size_t)h->n2 * h->Rp;
+    mm::start(h, h->y, h->wA, 0, 1, h->x);
+    int seq = 1, iters = 0;
+    bool first_cycle = true;
+    for (;;) {
+        double* src = h->wA;
+        double* dst = h->wB;
+        int j = 0;
+        bool done = false;
+        for (; j < M && iters + j < maxit; ++j) {
+            double* vj = h->V + (size_t)j * vs;
+            double* zj = h->Z + (size_t)j * vs;
+            mm::precond(h, src, vj, zj);
+            if ((prc = ev_begin(h, h->ev_q0))) return prc;
+            mm::q0_product(h, zj, dst);
+            if ((prc = ev_end(h, h->ev_q0))) return prc;
+            mm::orth(h, dst);
+            if (j == 0 && first_cycle) mm::finish(h, 0);
+            std::swap(src, dst);
+            if ((prc = wait_flag(h, seq + j + 1))) return prc;
+            if (h->hflag->done) { done = true; ++j; break; }
+        }
+        iters += j;
+        seq += j;
+        bool conv = done && h->hflag->converged;
+        if (!(done && j == 1 && first_cycle)) mm::finish(h, (!done && iters >= maxit) ? 1 : 0);
+        if (conv || iters >= maxit) {
+            h->iters_total += iters;
+            h->last_iters = iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = conv;
+            break;
+        }
+        first_cycle = false;
+        if ((prc = ev_begin(h, h->ev_q0))) return prc;
+        mm::q0_product(h, h->x, h->wA);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
+        mm::start(h, h->y, h->wA, 1, 0, nullptr);
+        seq += 1;
+        if ((prc = wait_flag(h, seq))) return prc;
+        if (h->hflag->done) {
+            mm::finish(h, 1);
+            h->iters_total += iters;
+            h->last_iters = iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = h->hflag->converged;
+            break;
+        }
+    }
+    return h->last_conv ? MOT_OK : MOT_ENOCONV;
+}
+
 // Single right-hand-side GMRES on Q0 x = y (x holds the warm start).
 int gmres_solve(mot_handle* h) {
     using namespace motk_step;
@@ -674,7 +745,9 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     const int nv = mesh->nv, nf = mesh->nf, ne = mesh->ne;
     if (nv < 4 || nf < 4 || ne < 6 || 2 * ne != 3 * nf)
         return mot_fail(nullptr, MOT_EINVAL, "mesh sizes are not those of a closed triangulation");
-    if (nrhs != 1) return mot_fail(nullptr, MOT_EINVAL, "this build marches one right-hand side per handle");
+    if (nrhs < 1 || nrhs > 64) return mot_fail(nullptr, MOT_EINVAL, "nrhs must be in 1..64");
+    if (nrhs > 1 && opt && opt->precond == 0)
+        return mot_fail(nullptr, MOT_EINVAL, "several right-hand sides need the Q_0 preconditioner (precond 1 or 2)");
     // ---- mesh validation (host, integers) ----
     const int32_t* E = mesh->edges;
     const int32_t* F = mesh->tris;
@@ -724,6 +797,9 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     if (!(h->opt.gmres_tol > 0)) h->opt.gmres_tol = 1e-13;
     h->stream = (hipStream_t)stream;
     h->nv = nv; h->nf = nf; h->ne = ne; h->R = nrhs;
+    h->Rp = 1;
+    if (nrhs > 1) { h->Rp = 4; while (h->Rp < nrhs) h->Rp *= 2; }
+    h->B = std::max(8, std::min(128, 4096 / h->Rp));
     h->hs = (ne + 7) & ~7;
     h->n2 = 2 * h->hs;
     {
@@ -873,13 +949,17 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     if ((rc = dalloc(h, &h->Q, (size_t)h->nlags * 3 * blk)) || (rc = dalloc(h, &h->tmp, 3 * blk, false)) ||
         (rc = dalloc(h, &h->raw, blk)))
         return bail(rc);
-    const int n2 = h->n2;
+    // every march vector holds all Rp columns: [n2][Rp]
+    const size_t n2 = (size_t)h->n2 * h->Rp;
+    const size_t NB = (size_t)h->B * h->Rp;
     h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
     if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
-        (rc = dalloc(h, &h->ebar, (size_t)2 * h->hs * h->B)) || (rc = dalloc(h, &h->Ebar, (size_t)2 * h->hs * h->B)) ||
-        (rc = dalloc(h, &h->rb, (size_t)2 * h->ne * h->B)) || (rc = dalloc(h, &h->y, n2)) ||
+        (rc = dalloc(h, &h->ebar, (size_t)2 * h->hs * NB)) || (rc = dalloc(h, &h->Ebar, (size_t)2 * h->hs * NB)) ||
+        (rc = dalloc(h, &h->rb, (size_t)2 * h->ne * NB)) || (rc = dalloc(h, &h->y, n2)) ||
         (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
         (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
+        return bail(rc);
+    if (h->Rp > 1 && ((rc = dalloc(h, &h->gms, h->Rp)) || (rc = dalloc(h, &h->mr_part, motk_multi::part_doubles(h)))))
         return bail(rc);
     if (h->hist_cap && (rc = dalloc(h, &h->hist, (size_t)h->hist_cap * n2))) return bail(rc);
     if (hipHostMalloc((void**)&h->hflag, sizeof(GmFlag), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -942,7 +1022,7 @@ int mot_reset(mot_handle* h) {
     h->ev_hist.ms = h->ev_q0.ms = 0;
     h->ev_hist.n = h->ev_q0.n = 0;
     HIPCHK(h, hipMemsetAsync(h->d_k, 0, sizeof(int), h->stream));
-    HIPCHK(h, hipMemsetAsync(h->ring, 0, (size_t)h->nh * h->n2 * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ring, 0, (size_t)h->nh * h->n2 * h->Rp * sizeof(double), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MOT_OK;
 }
@@ -956,10 +1036,15 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
     int prc = ev_begin(h, h->ev_hist);
     if (prc) return prc;
-    history(h);
+    if (h->Rp > 1 && (!h->gms || !h->mr_part)) return mot_fail(h, MOT_ESTATE, "multi-RHS buffers missing");
+    if (h->Rp > 1) motk_multi::history(h); else history(h);
     if ((prc = ev_end(h, h->ev_hist))) return prc;
     int rc;
-    if ((h->M32 || h->M64) && h->n2 <= 32768) {
+    if (h->Rp > 1) {
+        if (!h->gms || !h->mr_part) return mot_fail(h, MOT_ESTATE, "multi-RHS buffers missing");
+        rc = gmres_solve_mr(h);
+        if (rc && rc != MOT_ENOCONV) return rc;
+    } else if ((h->M32 || h->M64) && h->n2 <= 32768) {
         rc = gmres_solve_pc(h);           // pushes w_k itself
         if (rc && rc != MOT_ENOCONV) return rc;
     } else {
@@ -1004,7 +1089,7 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
     int rc;
     if (w_out) {
         if (out_on_device) dw = w_out; else if ((rc = dalloc(h, &dw, tot, false))) return rc;
-        motk_step::pack(h, nsteps, h->hist + (size_t)s0 * h->n2 * h->R, dw);
+        motk_step::pack(h, nsteps, h->hist + (size_t)s0 * h->n2 * h->Rp, dw);
     }
     if (loop_out) { if (out_on_device) dl = loop_out; else if ((rc = dalloc(h, &dl, tot, false))) return rc; }
     if (star_out) { if (out_on_device) ds = star_out; else if ((rc = dalloc(h, &ds, tot, false))) return rc; }
@@ -1067,13 +1152,18 @@ int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
         // r_lag = C1 ebar + C2 Ebar / T_max of step 'lag' (Section V-C)
         if (lag < 1) return mot_fail(h, MOT_EINVAL, "step >= 1");
         double* rb2;
-        if ((rc = dalloc(h, &rb2, (size_t)2 * ne * h->B))) return rc;
+        const size_t NB = (size_t)h->B * h->Rp;
+        if ((rc = dalloc(h, &rb2, (size_t)2 * ne * NB))) return rc;
         motk_step::rhs_batch(h, lag, rb2);
-        std::vector<double> tmp((size_t)2 * ne * h->B);
+        std::vector<double> tmp((size_t)2 * ne * NB);
         HIPCHK(h, hipMemcpyAsync(tmp.data(), rb2, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
         dfree(h, rb2);    // only the field temporaries were reused; the current batch r is intact
-        for (int i = 0; i < ne; ++i) { out[i] = tmp[(size_t)i * h->B]; out[ne + i] = tmp[(size_t)(ne + i) * h->B]; }
+        for (int i = 0; i < ne; ++i)
+            for (int r = 0; r < h->R; ++r) {
+                out[(size_t)i * h->R + r] = tmp[(size_t)i * NB + r];
+                out[(size_t)(ne + i) * h->R + r] = tmp[(size_t)(ne + i) * NB + r];
+            }
         return MOT_OK;
     }
     return mot_fail(h, MOT_EINVAL, "unknown matrix id");

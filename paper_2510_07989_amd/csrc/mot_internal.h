@@ -96,6 +96,7 @@ struct mot_handle {
     std::string err;
     mot_options opt;
     int nv = 0, nf = 0, ne = 0, hs = 0, n2 = 0, R = 1;
+    int Rp = 1;                      // internal column count (R rounded up to a power of two >= 4, or 1)
     double eps_r = 1, mu_r = 1, dt = 1, D = 0, Tmax = 0;
     double c = 1, eta = 1, cp = 1, etap = 1;
     int kmax = 0, nlags = 0, nh = 0, genus = 0;
@@ -145,7 +146,9 @@ struct mot_handle {
     double ns_resid = 0;             // ||I - M Q_0||_F reached
     double* wA = nullptr;
     double* wB = nullptr;
-    GmState* gm = nullptr;
+    GmState* gm = nullptr;           // single-RHS state, aggregate state when R > 1
+    GmState* gms = nullptr;          // [Rp] per-column states (R > 1)
+    double* mr_part = nullptr;       // split-K partial products (R > 1)
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;
     int M = 40;

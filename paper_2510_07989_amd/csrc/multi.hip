@@ -1,0 +1,485 @@
+// Multi-right-hand-side march: the R plane waves of one scatterer share every
+// lag matrix, so the history convolution and the Q_0 products become
+// tall-skinny GEMMs [ne x hs] x [hs x RP] (RP = R rounded up to a power of two).
+// Vectors are [n2][RP] (column index fastest).  FP64 throughout.
+#include "mot_internal.h"
+
+namespace {
+
+constexpr int TM = 64;    // rows per workgroup tile
+constexpr int TK = 32;    // K slice staged in LDS
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Structured product for one row tile, one lag j and one K chunk:
+//   Yu = q1_j Wu - qk_j Wv,   Yv = qk_j Wu + q2_j Wv     (Q_j = [[q1, -qk], [qk, q2]])
+// W is the history vector w_{k-j} from the ring (history) or a given vector X
+// (Q_0 product).  Partial results part[(jj * KC + kc)][2][ne][RP].
+template <int RP>
+__global__ __launch_bounds__(256) void k_struct_gemm(int ne, int hs, const int* __restrict__ dk, int nh,
+                                                     int q0_mode, const double* __restrict__ Q,
+                                                     const double* __restrict__ ring,
+                                                     const double* __restrict__ X, int KC,
+                                                     double* __restrict__ part) {
+    const int k = *dk;
+    const int jj = blockIdx.y;                       // 0-based lag slot
+    const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
+    if (jj >= nact) return;
+    const int j = q0_mode ? 0 : jj + 1;
+    const int n2 = 2 * hs;
+    const size_t blk = (size_t)ne * hs;
+    const double* q1 = Q + (size_t)j * 3 * blk;
+    const double* qk = q1 + blk;
+    const double* q2 = q1 + 2 * blk;
+    const double* W = q0_mode ? X : ring + (size_t)((k - j) % nh) * n2 * RP;
+    const int m0 = blockIdx.x * TM;
+    const int kc = blockIdx.z;
+    const int KL = ((hs + KC - 1) / KC + TK - 1) / TK * TK;
+    const int kb = kc * KL, ke = min(hs, kb + KL);
+
+    __shared__ double A1[TK][TM + 1], Ak[TK][TM + 1], A2[TK][TM + 1];
+    __shared__ double Wu[TK][RP], Wv[TK][RP];
+    constexpr int RPT = TM * RP / 256;               // rows per thread
+    constexpr int RG = 256 / RP;                     // row groups
+    const int t = threadIdx.x;
+    const int c = t % RP, rg = t / RP;
+    double au[RPT], av[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) au[i] = av[i] = 0.0;
+
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+#pragma unroll
+        for (int q = 0; q < TM * TK / 256; ++q) {
+            int e = t + 256 * q;
+            int row = e / TK, col = e % TK;
+            int gm = m0 + row, gk = k0 + col;
+            bool ok = gm < ne && gk < ke;
+            size_t o = (size_t)gm * hs + gk;
+            A1[col][row] = ok ? __builtin_nontemporal_load(q1 + o) : 0.0;
+            Ak[col][row] = ok ? __builtin_nontemporal_load(qk + o) : 0.0;
+            A2[col][row] = ok ? __builtin_nontemporal_load(q2 + o) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < (TK * RP + 255) / 256; ++q) {
+            int e = t + 256 * q;
+            if (e < TK * RP) {
+                int kk = e / RP, cc = e % RP;
+                int gk = k0 + kk;
+                bool ok = gk < ke;
+                Wu[kk][cc] = ok ? W[(size_t)gk * RP + cc] : 0.0;
+                Wv[kk][cc] = ok ? W[(size_t)(hs + gk) * RP + cc] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < TK; ++kk) {
+            const double wu = Wu[kk][c], wv = Wv[kk][c];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int row = rg + i * RG;
+                const double a1 = A1[kk][row], ak = Ak[kk][row], a2 = A2[kk][row];
+                au[i] = fma(a1, wu, fma(-ak, wv, au[i]));
+                av[i] = fma(ak, wu, fma(a2, wv, av[i]));
+            }
+        }
+        __syncthreads();
+    }
+    double* P = part + ((size_t)jj * KC + kc) * 2 * ne * RP;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int gm = m0 + rg + i * RG;
+        if (gm < ne) {
+            P[(size_t)gm * RP + c] = au[i];
+            P[(size_t)(ne + gm) * RP + c] = av[i];
+        }
+    }
+}
+
+// y = rb(step) - sum of history partials     (hist = 1)
+// y = sum of partials                         (hist = 0, Q_0 product)
+template <int RP>
+__global__ void k_struct_reduce(int ne, int hs, const int* __restrict__ dk, int nh, int q0_mode, int KC,
+                                const double* __restrict__ part, const double* __restrict__ rb, int B,
+                                double* __restrict__ y) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * RP) return;
+    const int m = t / RP, c = t % RP;
+    const int k = *dk;
+    const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
+    double su = 0, sv = 0;
+    for (int p = 0; p < nact * KC; ++p) {
+        const double* P = part + (size_t)p * 2 * ne * RP;
+        su += P[(size_t)m * RP + c];
+        sv += P[(size_t)(ne + m) * RP + c];
+    }
+    if (q0_mode) {
+        y[(size_t)m * RP + c] = su;
+        y[(size_t)(hs + m) * RP + c] = sv;
+    } else {
+        const int sc = (k - 1) % B;
+        const size_t ld = (size_t)B * RP;
+        y[(size_t)m * RP + c] = rb[(size_t)m * ld + (size_t)sc * RP + c] - su;
+        y[(size_t)(hs + m) * RP + c] = rb[(size_t)ne * ld + (size_t)m * ld + (size_t)sc * RP + c] - sv;
+    }
+}
+
+// Plain product for one row tile and K chunk: part[kc][n][RP] = A[rows][K] X[K][RP]
+// (A in FP64 or FP32; the approximate inverse of Q_0).
+template <int RP, typename T>
+__global__ __launch_bounds__(256) void k_plain_gemm(int n, const T* __restrict__ A, const double* __restrict__ X,
+                                                    int KC, double* __restrict__ part,
+                                                    const GmState* __restrict__ agg) {
+    if (agg->done) return;
+    const int m0 = blockIdx.x * TM;
+    const int kc = blockIdx.z;
+    const int KL = ((n + KC - 1) / KC + TK - 1) / TK * TK;
+    const int kb = kc * KL, ke = min(n, kb + KL);
+    __shared__ double As[TK][TM + 1];
+    __shared__ double Ws[TK][RP];
+    constexpr int RPT = TM * RP / 256;
+    constexpr int RG = 256 / RP;
+    const int t = threadIdx.x;
+    const int c = t % RP, rg = t / RP;
+    double acc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] = 0.0;
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+#pragma unroll
+        for (int q = 0; q < TM * TK / 256; ++q) {
+            int e = t + 256 * q;
+            int row = e / TK, col = e % TK;
+            int gm = m0 + row, gk = k0 + col;
+            As[col][row] = (gm < n && gk < ke) ? (double)__builtin_nontemporal_load(A + (size_t)gm * n + gk) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < (TK * RP + 255) / 256; ++q) {
+            int e = t + 256 * q;
+            if (e < TK * RP) {
+                int kk = e / RP, cc = e % RP;
+                int gk = k0 + kk;
+                Ws[kk][cc] = gk < ke ? X[(size_t)gk * RP + cc] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < TK; ++kk) {
+            const double w = Ws[kk][c];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) acc[i] = fma(As[kk][rg + i * RG], w, acc[i]);
+        }
+        __syncthreads();
+    }
+    double* P = part + (size_t)kc * n * RP;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int gm = m0 + rg + i * RG;
+        if (gm < n) P[(size_t)gm * RP + c] = acc[i];
+    }
+}
+
+// z = (sum of partials) * inv_h[c] ; vj = src * inv_h[c]
+template <int RP>
+__global__ void k_plain_reduce(int n, int KC, const double* __restrict__ part, const double* __restrict__ src,
+                               const GmState* __restrict__ gms, const GmState* __restrict__ agg,
+                               double* __restrict__ z, double* __restrict__ vj) {
+    if (agg->done) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * RP) return;
+    const int m = t / RP, c = t % RP;
+    double s = 0;
+    for (int p = 0; p < KC; ++p) s += part[(size_t)p * n * RP + (size_t)m * RP + c];
+    const double sc = gms[c].inv_h;
+    z[t] = sc * s;
+    vj[t] = sc * src[t];
+}
+
+__device__ __forceinline__ double bsum(double v, double* sh) {
+    v = wsum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// Combine the column states into the aggregate state and publish one word.
+__device__ void aggregate(int RP, int R, GmState* gms, GmState* agg, GmFlag* flag) {
+    int done = 1, conv = 1, total = 0;
+    double rel = 0;
+    for (int c = 0; c < RP; ++c) {
+        done &= gms[c].done;
+        conv &= gms[c].converged;
+        if (c < R) { total = max(total, gms[c].total); rel = fmax(rel, gms[c].relres); }
+    }
+    agg->done = done;
+    agg->converged = done && conv;
+    agg->total = total;
+    agg->relres = rel;
+    agg->counter = 0;
+    const int seq = agg->seq + 1;
+    agg->seq = seq;
+    flag->relres = rel;
+    flag->converged = done && conv;
+    flag->done = done;
+    flag->total = total;
+    __threadfence_system();
+    flag->seq = seq;
+}
+
+__device__ __forceinline__ bool last_of_grid(unsigned int* counter) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// one workgroup per column: r = y - t (or y), beta, bnorm; x = 0 when cold
+__global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, const double* __restrict__ y,
+                                                   double* __restrict__ r, int have_t, GmState* gms,
+                                                   GmState* agg, GmFlag* flag, double tol, int first,
+                                                   double* __restrict__ xzero) {
+    __shared__ double sh[4];
+    const int c = blockIdx.x;
+    double s1 = 0, s2 = 0;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const size_t o = (size_t)i * RP + c;
+        if (xzero) xzero[o] = 0.0;
+        double bi = y[o];
+        double ri = have_t ? bi - r[o] : bi;
+        r[o] = ri;
+        s1 = fma(ri, ri, s1);
+        s2 = fma(bi, bi, s2);
+    }
+    s1 = bsum(s1, sh);
+    s2 = bsum(s2, sh);
+    if (threadIdx.x == 0) {
+        GmState* g = gms + c;
+        double beta = sqrt(s1);
+        if (first) { g->bnorm = sqrt(s2); g->total = 0; }
+        g->beta = beta;
+        g->g[0] = beta;
+        g->j = 0;
+        g->cycle_iters = 0;
+        double bn = g->bnorm;
+        g->relres = bn > 0 ? beta / bn : 0.0;
+        int conv = (bn == 0.0) || (beta <= tol * bn);
+        g->converged = conv;
+        g->done = conv;
+        g->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+    }
+    if (first && blockIdx.x == 0 && threadIdx.x == 0) agg->seq = 0;
+    if (!last_of_grid(&agg->counter)) return;
+    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag);
+}
+
+// one workgroup per column: CGS2 of w[:, c] against V[0..j][:, c], norm, Givens
+__global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const double* __restrict__ V,
+                                                  double* __restrict__ w, GmState* gms, GmState* agg,
+                                                  GmFlag* flag, double tol, int M) {
+    __shared__ double sh[4];
+    __shared__ double hc[MOT_MAXM + 1];
+    const int c = blockIdx.x;
+    GmState* g = gms + c;
+    const bool active = !g->done && !agg->done;
+    if (active) {
+        const int j = g->j;
+        if (threadIdx.x <= j) hc[threadIdx.x] = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l = 0; l <= j; ++l) {
+                const double* v = V + (size_t)l * n2 * RP;
+                double s = 0;
+                for (int i = threadIdx.x; i < n2; i += blockDim.x) s = fma(v[(size_t)i * RP + c], w[(size_t)i * RP + c], s);
+                s = bsum(s, sh);
+                for (int i = threadIdx.x; i < n2; i += blockDim.x)
+                    w[(size_t)i * RP + c] = fma(-s, v[(size_t)i * RP + c], w[(size_t)i * RP + c]);
+                if (threadIdx.x == 0) hc[l] += s;
+                __syncthreads();
+            }
+        }
+        double nn = 0;
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) nn = fma(w[(size_t)i * RP + c], w[(size_t)i * RP + c], nn);
+        nn = bsum(nn, sh);
+        if (threadIdx.x == 0) {
+            const double hn = sqrt(nn);
+            double* col = g->H + (size_t)j * (M + 1);
+            double cl[MOT_MAXM + 1];
+            for (int l = 0; l <= j; ++l) cl[l] = hc[l];
+            cl[j + 1] = hn;
+            for (int l = 0; l < j; ++l) {
+                double a = cl[l], b = cl[l + 1];
+                cl[l] = g->cs[l] * a + g->sn[l] * b;
+                cl[l + 1] = -g->sn[l] * a + g->cs[l] * b;
+            }
+            double a = cl[j], b = cl[j + 1];
+            double r = hypot(a, b);
+            double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
+            cl[j] = r;
+            cl[j + 1] = 0.0;
+            for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
+            g->cs[j] = cs;
+            g->sn[j] = sn;
+            double gj = g->g[j];
+            g->g[j] = cs * gj;
+            g->g[j + 1] = -sn * gj;
+            const int jn = j + 1;
+            g->j = jn;
+            g->cycle_iters = jn;
+            g->total += 1;
+            double rel = g->bnorm > 0 ? fabs(g->g[jn]) / g->bnorm : 0.0;
+            g->relres = rel;
+            int conv = rel <= tol;
+            int brk = !(hn > 1e-300 * (g->beta + 1e-300));
+            g->converged = conv || brk;
+            g->done = conv || brk || jn >= M;
+            g->inv_h = hn > 0 ? 1.0 / hn : 0.0;
+            if (g->done) {
+                for (int i = jn - 1; i >= 0; --i) {
+                    double s = g->g[i];
+                    for (int l = i + 1; l < jn; ++l) s -= g->H[(size_t)l * (M + 1) + i] * g->y[l];
+                    double d = g->H[(size_t)i * (M + 1) + i];
+                    g->y[i] = d != 0 ? s / d : 0.0;
+                }
+            }
+        }
+    }
+    if (!last_of_grid(&agg->counter)) return;
+    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag);
+}
+
+// x[:, c] += sum_l y_l(c) Z_l[:, c] for columns whose cycle is done (once per
+// cycle: cycle_iters is consumed); push x into the ring and history when every
+// column converged, or when forced.
+__global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmState* gms,
+                             const GmState* __restrict__ agg, double* __restrict__ x,
+                             const int* __restrict__ dk, int nh, double* __restrict__ ring,
+                             double* __restrict__ hist, int hist_cap, int force) {
+    const int k = *dk;
+    const int push = agg->converged || force;
+    double* slot = ring + (size_t)(k % nh) * n2 * RP;
+    double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 * RP : nullptr;
+    const size_t total = (size_t)n2 * RP;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t % RP);
+        const GmState* g = gms + c;
+        double s = x[t];
+        if (g->done)
+            for (int l = 0; l < g->cycle_iters; ++l) s = fma(g->y[l], Z[(size_t)l * total + t], s);
+        x[t] = s;
+        if (push) {
+            slot[t] = s;
+            if (hs) hs[t] = s;
+        }
+    }
+}
+
+// after a finish: mark consumed cycles (so a restart does not add them twice)
+__global__ void k_gmb_consume(int RP, GmState* gms) {
+    int c = threadIdx.x;
+    if (c < RP && gms[c].done) gms[c].cycle_iters = 0;
+}
+
+int pick_kc(int tiles, int groups, int K) {
+    int want = (1024 + tiles * groups - 1) / (tiles * groups);
+    int maxkc = K / (4 * TK);
+    if (maxkc < 1) maxkc = 1;
+    return want < 1 ? 1 : (want > maxkc ? maxkc : want);
+}
+
+template <int RP>
+void struct_product(mot_handle* h, int q0_mode, const double* X, double* out, int hist) {
+    const int tiles = (h->ne + TM - 1) / TM;
+    const int groups = q0_mode ? 1 : h->nh;
+    const int KC = pick_kc(tiles, groups, h->hs);
+    dim3 grid(tiles, groups, KC);
+    hipLaunchKernelGGL(k_struct_gemm<RP>, grid, dim3(256), 0, h->stream, h->ne, h->hs, h->d_k, h->nh, q0_mode, h->Q,
+                       h->ring, X, KC, h->mr_part);
+    const int n = h->ne * RP;
+    hipLaunchKernelGGL(k_struct_reduce<RP>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
+                       h->nh, q0_mode, KC, h->mr_part, h->rb, h->B, out);
+    (void)hist;
+}
+
+template <int RP>
+void plain_product(mot_handle* h, const double* src, double* vj, double* z) {
+    const int n = h->n2;
+    const int tiles = (n + TM - 1) / TM;
+    const int KC = pick_kc(tiles, 1, n);
+    dim3 grid(tiles, 1, KC);
+    if (h->M32)
+        hipLaunchKernelGGL((k_plain_gemm<RP, float>), grid, dim3(256), 0, h->stream, n, h->M32, src, KC, h->mr_part, h->gm);
+    else
+        hipLaunchKernelGGL((k_plain_gemm<RP, double>), grid, dim3(256), 0, h->stream, n, h->M64, src, KC, h->mr_part, h->gm);
+    hipLaunchKernelGGL(k_plain_reduce<RP>, dim3((n * RP + 255) / 256), dim3(256), 0, h->stream, n, KC, h->mr_part, src,
+                       h->gms, h->gm, z, vj);
+}
+
+}  // namespace
+
+namespace motk_multi {
+
+size_t part_doubles(const mot_handle* h) {
+    const int tiles = (h->ne + TM - 1) / TM;
+    size_t a = (size_t)h->nh * pick_kc(tiles, h->nh, h->hs) * 2 * h->ne * h->Rp;
+    size_t b = (size_t)pick_kc(tiles, 1, h->hs) * 2 * h->ne * h->Rp;
+    const int t2 = (h->n2 + TM - 1) / TM;
+    size_t c = (size_t)pick_kc(t2, 1, h->n2) * h->n2 * h->Rp;
+    return std::max(a, std::max(b, c));
+}
+
+#define MOT_RP_SWITCH(RPV, CALL)                                         \
+    switch (RPV) {                                                       \
+        case 4: CALL(4); break;                                          \
+        case 8: CALL(8); break;                                          \
+        case 16: CALL(16); break;                                        \
+        case 32: CALL(32); break;                                        \
+        case 64: CALL(64); break;                                        \
+        default: break;                                                  \
+    }
+
+void history(mot_handle* h) {
+#define C_(R_) struct_product<R_>(h, 0, nullptr, h->y, 1)
+    MOT_RP_SWITCH(h->Rp, C_)
+#undef C_
+}
+
+void q0_product(mot_handle* h, const double* X, double* out) {
+#define C_(R_) struct_product<R_>(h, 1, X, out, 0)
+    MOT_RP_SWITCH(h->Rp, C_)
+#undef C_
+}
+
+void precond(mot_handle* h, const double* src, double* vj, double* z) {
+#define C_(R_) plain_product<R_>(h, src, vj, z)
+    MOT_RP_SWITCH(h->Rp, C_)
+#undef C_
+}
+
+void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero) {
+    hipLaunchKernelGGL(k_gmb_start, dim3(h->Rp), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, y, r, have_t, h->gms,
+                       h->gm, h->dflag, h->opt.gmres_tol, first, xzero);
+}
+
+void orth(mot_handle* h, double* w) {
+    hipLaunchKernelGGL(k_gmb_orth, dim3(h->Rp), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->V, w, h->gms, h->gm,
+                       h->dflag, h->opt.gmres_tol, h->M);
+}
+
+void finish(mot_handle* h, int force) {
+    size_t total = (size_t)h->n2 * h->Rp;
+    int nb = (int)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_gmb_finish, dim3(nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->Z, h->gms, h->gm, h->x,
+                       h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force);
+    hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms);
+}
+
+}  // namespace motk_multi

@@ -21,16 +21,24 @@ __device__ __forceinline__ double erf_diff(double s1, double s0) {
     return erf(s1) - erf(s0);
 }
 
-__global__ void k_rhs_fields(int ne, int hs, int k0, int B, double dt,
+__global__ void k_rhs_fields(int ne, int hs, int k0, int B, int R, int Rp, double dt,
                              const double* __restrict__ X, const double* __restrict__ Fw,
                              const double* __restrict__ waves, const double* __restrict__ tcut,
                              double* __restrict__ ebar, double* __restrict__ Ebar) {
-    // thread per (edge m, batch column s); step k = k0 + s; outputs [half][hs][B]
+    // thread per (edge m, batch column sc, wave r); step k = k0 + sc;
+    // outputs [half][hs][B * Rp], column sc * Rp + r (zero for padding waves r >= R)
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * B) return;
-    int m = t / B, sc = t % B;
+    if (t >= ne * B * Rp) return;
+    const int r = t % Rp, sc = (t / Rp) % B, m = t / (Rp * B);
+    const size_t ld = (size_t)B * Rp;
+    const size_t hb = (size_t)hs * ld;
+    const size_t o = (size_t)m * ld + (size_t)sc * Rp + r;
+    if (r >= R) {
+        ebar[o] = 0; ebar[hb + o] = 0; Ebar[o] = 0; Ebar[hb + o] = 0;
+        return;
+    }
     const int k = k0 + sc;
-    const double* wv = waves;
+    const double* wv = waves + 9 * r;
     const double amp = wv[0], w = wv[7], t0 = wv[8];
     const double px = wv[1], py = wv[2], pz = wv[3];
     const double kx = wv[4], ky = wv[5], kz = wv[6];
@@ -38,7 +46,7 @@ __global__ void k_rhs_fields(int ne, int hs, int k0, int B, double dt,
     const double hx = ky * pz - kz * py, hy = kz * px - kx * pz, hz = kx * py - ky * px;
     const double c4 = 4.0 / w;
     const double tk = k * dt, tk1 = (k - 1) * dt;
-    const bool star_on = tk <= tcut[0];
+    const bool star_on = tk <= tcut[r];
     double ee = 0, eh = 0, Ee = 0, Eh = 0;
     for (int q = 0; q < 14; ++q) {
         const double* x = X + ((size_t)m * 14 + q) * 3;
@@ -53,11 +61,10 @@ __global__ void k_rhs_fields(int ne, int hs, int k0, int B, double dt,
         Ee += tE * fp; Eh += tE * fh;
     }
     const double a = -0.5 * amp;   // -(A / (2c)), the minus from n x f testing
-    const size_t hb = (size_t)hs * B;
-    ebar[(size_t)m * B + sc] = a * ee;
-    ebar[hb + (size_t)m * B + sc] = a * eh;
-    Ebar[(size_t)m * B + sc] = a * Ee;
-    Ebar[hb + (size_t)m * B + sc] = a * Eh;
+    ebar[o] = a * ee;
+    ebar[hb + o] = a * eh;
+    Ebar[o] = a * Ee;
+    Ebar[hb + o] = a * Eh;
 }
 
 // ------------------------------------------------ streamed row products ---
@@ -819,7 +826,7 @@ __global__ void k_inc_step(int* dk) { *dk += 1; }
 
 // recovery gather: columns (step s in [s0, s1), half h, kind t, rhs r) of
 // X[ne][ncol], kind 0 = u_k, kind 1 = u_k - u_{k-1} (u_0 = 0)
-__global__ void k_rec_gather(int ne, int hs, int n2, int R, int s0, int ns,
+__global__ void k_rec_gather(int ne, int hs, int n2, int R, int Rp, int s0, int ns,
                              const double* __restrict__ hist, double* __restrict__ X) {
     const int ncol = ns * 4 * R;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -827,9 +834,9 @@ __global__ void k_rec_gather(int ne, int hs, int n2, int R, int s0, int ns,
     if (c >= ncol) return;
     int r = c % R, t = (c / R) % 2, hh = (c / (2 * R)) % 2, s = c / (4 * R);
     int step = s0 + s;     // 0-based index into hist
-    size_t off = (size_t)(hh * hs + m) * R + r;
-    double v = hist[(size_t)step * n2 * R + off];
-    if (t == 1 && step > 0) v -= hist[(size_t)(step - 1) * n2 * R + off];
+    size_t off = (size_t)(hh * hs + m) * Rp + r;
+    double v = hist[(size_t)step * n2 * Rp + off];
+    if (t == 1 && step > 0) v -= hist[(size_t)(step - 1) * n2 * Rp + off];
     X[(size_t)m * ncol + c] = v;
 }
 
@@ -852,7 +859,7 @@ __global__ void k_rec_scatter(int ne, int R, int ns, const double* __restrict__ 
 }
 
 // pack w from the internal padded layout [n2][R] to [n][R]
-__global__ void k_pack(int ne, int hs, int R, int ns, const double* __restrict__ src,
+__global__ void k_pack(int ne, int hs, int R, int Rp, int ns, const double* __restrict__ src,
                        double* __restrict__ dst) {
     size_t total = (size_t)ns * 2 * ne * R;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
@@ -861,7 +868,7 @@ __global__ void k_pack(int ne, int hs, int R, int ns, const double* __restrict__
         int i = (int)(q % (2 * ne));
         size_t s = q / (2 * ne);
         int row = i < ne ? i : hs + (i - ne);
-        dst[t] = src[(s * 2 * hs + row) * R + r];
+        dst[t] = src[(s * 2 * hs + row) * Rp + r];
     }
 }
 
@@ -872,16 +879,17 @@ namespace motk_step {
 
 // RHS of steps k0 .. k0+B-1: fields, then r = C1 ebar + C2 Ebar / T_max per half
 void rhs_batch(mot_handle* h, int k0, double* rb) {
-    const int ne = h->ne, hs = h->hs, B = h->B;
-    int tot = ne * B;
-    hipLaunchKernelGGL(k_rhs_fields, dim3((tot + 255) / 256), dim3(256), 0, h->stream, ne, hs, k0, B, h->dt,
-                       h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
+    const int ne = h->ne, hs = h->hs, B = h->B, Rp = h->Rp;
+    const int N = B * Rp;
+    size_t tot = (size_t)ne * N;
+    hipLaunchKernelGGL(k_rhs_fields, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, ne, hs, k0, B,
+                       h->R, Rp, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
     for (int half = 0; half < 2; ++half) {
-        const double* eb = h->ebar + (size_t)half * hs * B;
-        const double* Eb = h->Ebar + (size_t)half * hs * B;
-        double* out = rb + (size_t)half * ne * B;
-        motk::gemm(h->stream, ne, B, ne, 1.0, h->C1, hs, eb, B, 0.0, out, B);
-        motk::gemm(h->stream, ne, B, ne, 1.0 / h->Tmax, h->C2, hs, Eb, B, 1.0, out, B);
+        const double* eb = h->ebar + (size_t)half * hs * N;
+        const double* Eb = h->Ebar + (size_t)half * hs * N;
+        double* out = rb + (size_t)half * ne * N;
+        motk::gemm(h->stream, ne, N, ne, 1.0, h->C1, hs, eb, N, 0.0, out, N);
+        motk::gemm(h->stream, ne, N, ne, 1.0 / h->Tmax, h->C2, hs, Eb, N, 1.0, out, N);
     }
 }
 
@@ -980,7 +988,7 @@ void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 
 void rec_gather(mot_handle* h, int s0, int ns, double* X) {
     int ncol = ns * 4 * h->R;
     dim3 grid((ncol + 255) / 256, h->ne);
-    hipLaunchKernelGGL(k_rec_gather, grid, dim3(256), 0, h->stream, h->ne, h->hs, h->n2, h->R, s0, ns,
+    hipLaunchKernelGGL(k_rec_gather, grid, dim3(256), 0, h->stream, h->ne, h->hs, h->n2, h->R, h->Rp, s0, ns,
                        h->hist, X);
 }
 
@@ -995,7 +1003,7 @@ void pack(mot_handle* h, int ns, const double* src, double* dst) {
     size_t total = (size_t)ns * 2 * h->ne * h->R;
     int nb = (int)((total + 255) / 256);
     if (nb > 65535 * 8) nb = 65535 * 8;
-    hipLaunchKernelGGL(k_pack, dim3(nb), dim3(256), 0, h->stream, h->ne, h->hs, h->R, ns, src, dst);
+    hipLaunchKernelGGL(k_pack, dim3(nb), dim3(256), 0, h->stream, h->ne, h->hs, h->R, h->Rp, ns, src, dst);
 }
 
 }  // namespace motk_step

@@ -141,3 +141,36 @@ def test_kernel_variants(opts):
     assert _rel(out["loop"], ref["loop"]) < 1e-10
     assert _rel(out["star"], ref["star"]) < 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("tiny_box", 40), ("sphere_480_r16", 100)])
+def test_multi_rhs_parity(name, nsteps):
+    """R plane waves marched together (tall-skinny GEMM history and Q_0 products,
+    one GMRES per column) against the oracle."""
+    print("case", name, flush=True)
+    O = oracle(name)
+    ref = O.run(nsteps)
+    s = _solver(name, precond=2)
+    out = s.run(nsteps)
+    assert out["rc"] == 0
+    e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+    print("errors", e, flush=True)
+    assert max(e) < 1e-10
+    s.close()
+
+
+def test_multi_rhs_column_equals_alone():
+    """Column r of a batched march equals the march of wave r alone."""
+    import paper_2510_07989_amd as p
+    prob = problem("sphere_480_r16")
+    s = _solver("sphere_480_r16", precond=2)
+    out = s.run(60)
+    s.close()
+    for r in (0, 7, 15):
+        o = p.default_options(precond=2)
+        s1 = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                      prob["T0s"], prob["T0h"], prob["G"], [prob["waves"][r]], options=o)
+        s1.load_raw(prob["raw"], prob["kmax"])
+        one = s1.run(60)
+        s1.close()
+        assert _rel(out["w"][:, :, r], one["w"][:, :, 0]) < 1e-12
