@@ -190,6 +190,8 @@ def tested_fields(V, F, E, waves, dt, k):
     with [e(t)]_m = <n x f_m, e_in x n> = -<f_m, e_in> and likewise h with
     h_in = k x e_in / eta.  The Gaussian time integral is closed-form:
     int_{-inf}^t e_in = A/(2c) p (1 + erf s),  s = (4/w)(c (t - t0) - k.x).
+    The spatial integral over the two triangles of each RWG uses the 7-point
+    rule; all edges are evaluated at once (numpy), one wave at a time.
     Returns ebar, Ebar of shape (2 ne, R); Ebar is zeroed after star_cut.
     """
     V = np.asarray(V, dtype=np.float64)
@@ -200,30 +202,31 @@ def tested_fields(V, F, E, waves, dt, k):
     R = len(waves)
     ebar = np.zeros((2 * ne, R))
     Ebar = np.zeros((2 * ne, R))
-    for m in range(ne):
-        for side, sgn in ((2, 1.0), (3, -1.0)):
-            f = E[m, side]
-            tv = V[F[f]]
-            area = 0.5 * np.linalg.norm(np.cross(tv[1] - tv[0], tv[2] - tv[0]))
-            opp = [v for v in F[f] if v != E[m, 0] and v != E[m, 1]][0]
-            X = L @ tv                                     # quadrature points
-            fm = sgn * (X - V[opp]) / (2 * area)           # RWG values (Section II)
-            for r, wv in enumerate(waves):
-                c = 1.0
-                s1 = (4 / wv.width) * (c * (k * dt - wv.t0) - X @ wv.dir)
-                s0 = (4 / wv.width) * (c * ((k - 1) * dt - wv.t0) - X @ wv.dir)
-                amp = wv.amp / (2 * c)
-                ep = wv.pol
-                hp = np.cross(wv.dir, wv.pol)             # eta = 1
-                te = amp * _erf_diff(s1, s0) / dt          # time average over the step
-                tE = amp * erfc(-s1)                       # running integral
-                if k * dt > star_cut(V, wv):
-                    tE = np.zeros_like(tE)
-                wq = W * area
-                ebar[m, r] += -np.sum(wq * te * (fm @ ep))
-                ebar[ne + m, r] += -np.sum(wq * te * (fm @ hp))
-                Ebar[m, r] += -np.sum(wq * tE * (fm @ ep))
-                Ebar[ne + m, r] += -np.sum(wq * tE * (fm @ hp))
+    c = 1.0
+    for side, sgn in ((2, 1.0), (3, -1.0)):
+        f = E[:, side]
+        tv = V[F[f]]                                        # (ne, 3, 3)
+        area = 0.5 * np.linalg.norm(np.cross(tv[:, 1] - tv[:, 0], tv[:, 2] - tv[:, 0]), axis=1)
+        fv = F[f]
+        opp = np.where((fv != E[:, [0]]) & (fv != E[:, [1]]), fv, -1).max(axis=1)
+        X = np.einsum("qk,mkd->mqd", L, tv)                 # (ne, 7, 3) quadrature points
+        fm = sgn * (X - V[opp][:, None, :]) / (2 * area)[:, None, None]   # RWG values (Section II)
+        wq = W[None, :] * area[:, None]
+        for r, wv in enumerate(waves):
+            s1 = (4 / wv.width) * (c * (k * dt - wv.t0) - X @ wv.dir)
+            s0 = (4 / wv.width) * (c * ((k - 1) * dt - wv.t0) - X @ wv.dir)
+            amp = wv.amp / (2 * c)
+            hp = np.cross(wv.dir, wv.pol)                   # eta = 1
+            te = amp * _erf_diff(s1.ravel(), s0.ravel()).reshape(s1.shape) / dt
+            tE = amp * erfc(-s1)
+            if k * dt > star_cut(V, wv):
+                tE = np.zeros_like(tE)
+            fp = fm @ wv.pol
+            fh = fm @ hp
+            ebar[:ne, r] += -np.sum(wq * te * fp, axis=1)
+            ebar[ne:, r] += -np.sum(wq * te * fh, axis=1)
+            Ebar[:ne, r] += -np.sum(wq * tE * fp, axis=1)
+            Ebar[ne:, r] += -np.sum(wq * tE * fh, axis=1)
     return ebar, Ebar
 
 
