@@ -26,6 +26,8 @@ WORKLOADS = {
                   "dt=2.0, 1 Gaussian plane wave, plain FP64",
     "sphere_480": "sphere r=1, 320 triangles / 480 edges -> 960 unknowns, eps_r=2, dt=0.25, "
                   "1 Gaussian plane wave, plain FP64",
+    "sphere_1920_r16": "sphere r=1, 1280 triangles / 1920 edges -> 3840 unknowns, eps_r=2, dt=0.15, "
+                       "16 seeded Gaussian plane waves marched together",
 }
 
 
@@ -74,6 +76,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64 history, 1 mixed FP32/MFMA history")
+    ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with split hi/lo products (-1: none)")
+    ap.add_argument("--mix-group", type=int, default=4, help="mixed: summation indices per FP32 accumulator (4, 16, 64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the MOT march of one problem runs on one device "
@@ -95,7 +100,8 @@ def main():
     t_fixture = time.perf_counter() - t
     log("inputs assembled on the host in %.1f s" % t_fixture)
 
-    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond, stream_split=args.split)
+    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond, stream_split=args.split,
+                               precision=args.precision, hilo_lags=args.hilo, mix_group=args.mix_group)
     t = time.perf_counter()
     s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
                    prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
@@ -120,13 +126,15 @@ def main():
     el = t1 - t0
     steps_s = K / el
     ne, n = s.ne, s.n
+    R = s.nrhs
     L = b["nlags"]
+    qb = 4 if args.precision == 1 else 8
     iters = (b["gmres_iters_total"] - a["gmres_iters_total"]) / K
     # algorithmic bytes (FP64): the Q_0 product reads q1, qk, q2 (3 ne^2) and the
     # input vector, writes n; the history kernel reads the (L-1) 3 ne^2 entries
     # of Q_1..Q_{L-1}, the L-1 history vectors and r_k, writes n.
-    q0_bytes = 8.0 * (3 * ne * ne + 2 * n)
-    hist_bytes = 8.0 * ((L - 1) * 3 * ne * ne + (L - 1) * n + 2 * n)
+    q0_bytes = 8.0 * (3 * ne * ne + 2 * n * R)
+    hist_bytes = qb * (L - 1) * 3 * ne * ne + 8.0 * ((L - 1) * n * R + 2 * n * R)
     q0_ms = (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
     hist_ms = (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
     q0_tot = b["q0_ms"] - a["q0_ms"]
@@ -141,10 +149,12 @@ def main():
         "history %.1f us (%.0f GB/s); recovery %.1f ms"
         % (K, el, steps_s, iters, q0_ms * 1e3, q0_gbs, hist_ms * 1e3, hist_gbs, b["recover_ms"]))
 
+    prec = "fp64" if args.precision == 0 else "mixed fp32-mfma history"
     result = {
-        "metric": "MOT steps/s (plain FP64, 1 RHS)",
+        "metric": "MOT steps/s (%s, %d RHS)" % ("plain FP64" if args.precision == 0 else "mixed precision", R),
         "value": round(steps_s, 3),
         "unit": "steps/s",
+        "rhs_steps_per_s": round(steps_s * R, 2),
         "n_gpus": 1,
         "steps": K,
         "warmup": W_,
@@ -154,8 +164,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "nrhs": 1,
-                   "unknowns": n, "lags": L, "kmax": b["kmax"], "precision": "fp64",
+        "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "nrhs": R,
+                   "unknowns": n, "lags": L, "kmax": b["kmax"], "precision": prec,
                    "q0_preconditioner": ["none", "fp32 approximate inverse", "fp64 approximate inverse"][args.precond]},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),

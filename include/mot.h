@@ -72,7 +72,11 @@ typedef struct {
 } mot_planewave;
 
 typedef struct {
-    int32_t precision;       /* MOT_FP64 (default) or MOT_MIXED              */
+    int32_t precision;       /* MOT_FP64 (default) or MOT_MIXED: Q_1..Q_{L-1}
+                                stored in FP32 and multiplied on FP32 MFMA
+                                with FP64 accumulation across K slices and
+                                lags (needs nrhs > 1); Q_0, GMRES, projectors
+                                and recovery stay FP64                        */
     double gmres_tol;        /* relative residual of each Q_0 solve (1e-13)  */
     int32_t gmres_restart;   /* Krylov dimension m (40)                      */
     int32_t gmres_maxit;     /* total iterations per step (400)              */
@@ -94,7 +98,12 @@ typedef struct {
     int32_t history_order;   /* history kernel loop order: 1 (or 0) column
                                 slices across all blocks, 2 whole rows of one
                                 block at a time                               */
-    int32_t reserved[4];
+    int32_t hilo_lags;       /* MOT_MIXED: lags 1..hilo_lags use split
+                                hi/lo FP32 products (default 2, -1: none)     */
+    int32_t mix_group;       /* MOT_MIXED: summation indices per half that one
+                                FP32 MFMA accumulator sums before it is added
+                                into the FP64 total: 4 (default), 16 or 64    */
+    int32_t reserved[2];
 } mot_options;
 
 typedef struct {

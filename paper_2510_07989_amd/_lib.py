@@ -28,7 +28,8 @@ class MotOptions(ctypes.Structure):
     _fields_ = [("precision", _I), ("gmres_tol", _D), ("gmres_restart", _I), ("gmres_maxit", _I),
                 ("cg_tol", _D), ("cg_maxit", _I), ("diameter", _D), ("keep_history", _I),
                 ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
-                ("precond", _I), ("stream_split", _I), ("history_order", _I), ("reserved", _I * 4)]
+                ("precond", _I), ("stream_split", _I), ("history_order", _I),
+                ("hilo_lags", _I), ("mix_group", _I), ("reserved", _I * 2)]
 
 
 class MotStepInfo(ctypes.Structure):

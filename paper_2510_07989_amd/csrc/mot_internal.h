@@ -149,6 +149,10 @@ struct mot_handle {
     GmState* gm = nullptr;           // single-RHS state, aggregate state when R > 1
     GmState* gms = nullptr;          // [Rp] per-column states (R > 1)
     double* mr_part = nullptr;       // split-K partial products (R > 1)
+    float* Qf = nullptr;             // [nlags-1][3][ne][hs] FP32 Q_1.. (mixed precision)
+    float* Qlo = nullptr;            // [hilo][3][ne][hs] FP32 residual Q - Qf of the short lags
+    int hilo = 0;                    // lags with split hi/lo products
+    int mix_kc = 1;                  // K chunks of the mixed history kernel
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;
     int M = 40;

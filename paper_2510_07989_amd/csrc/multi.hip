@@ -388,6 +388,175 @@ __global__ void k_gmb_consume(int RP, GmState* gms) {
     if (c < RP && gms[c].done) gms[c].cycle_iters = 0;
 }
 
+// ---------------------------------------------------------------- mixed ---
+// History in mixed precision (FP32 storage of Q_1..Q_{L-1}, FP32 MFMA):
+//   Yu = q1 Wu - qk Wv,  Yv = qk Wu + q2 Wv   per lag, with
+//   Q W ~ Q_hi W_hi + Q_hi W_lo + Q_lo W_hi   on the first hilo lags.
+// v_mfma_f32_16x16x4f32 operand layout (one wavefront): A lane l = row l%16,
+// k l/16;  B lane l = col l%16, k l/16;  D lane l = col l%16, rows 4(l/16)..+3.
+// Each lane loads four consecutive k of its row; the summation index inside one
+// MFMA is permuted consistently for A and B, so the product is unchanged.
+// One FP32 accumulator sums 4*FL summation indices of each half (u and v), then
+// is added into the FP64 total: the history sums cancel strongly (row sums are
+// 10-100x smaller than the sums of magnitudes), so the FP32 partial sums are
+// kept short.  Slices of MTK indices are staged per block; FP64 across slices,
+// K chunks and lags.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int MTK = 64;       // K slice staged in LDS
+
+template <int CB, int FL>
+__global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const int* __restrict__ dk, int nh,
+                                                   int hilo, const float* __restrict__ Qf,
+                                                   const float* __restrict__ Qlo,
+                                                   const double* __restrict__ ring, int KC,
+                                                   double* __restrict__ part) {
+    const int k = *dk;
+    const int jj = blockIdx.y;
+    const int nact = k - 1 < nh ? k - 1 : nh;
+    if (jj >= nact) return;
+    const int j = jj + 1;
+    const bool hl = j <= hilo;
+    const int n2 = 2 * hs;
+    const size_t blk = (size_t)ne * hs;
+    const float* a1p = Qf + (size_t)(j - 1) * 3 * blk;
+    const float* akp = a1p + blk;
+    const float* a2p = a1p + 2 * blk;
+    const float* l1p = hl ? Qlo + (size_t)(j - 1) * 3 * blk : nullptr;
+    const float* lkp = hl ? l1p + blk : nullptr;
+    const float* l2p = hl ? l1p + 2 * blk : nullptr;
+    const double* W = ring + (size_t)((k - j) % nh) * n2 * Rp;
+    const int kc = blockIdx.z;
+    const int KL = ((hs + KC - 1) / KC + MTK - 1) / MTK * MTK;
+    const int kb = kc * KL, ke = min(hs, kb + KL);
+
+    // staged history vectors, transposed: [u/v][hi/lo][column][k]
+    __shared__ float Wt[2][2][CB * 16][MTK + 4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int row = blockIdx.x * 64 + wv * 16 + (lane & 15);
+    const bool rok = row < ne;
+    const int kq = 4 * (lane >> 4);
+    double Du[CB][4], Dv[CB][4];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Du[c][r] = Dv[c][r] = 0.0;
+
+    for (int s0 = kb; s0 < ke; s0 += MTK) {
+        // stage the slice of W (FP64) as hi/lo FP32
+        for (int e = t; e < CB * 16 * MTK; e += 256) {
+            const int col = e % (CB * 16), kk = e / (CB * 16);
+            const int gk = s0 + kk;
+            double wu = 0.0, wvv = 0.0;
+            if (col < Rp && gk < ke) {
+                wu = W[(size_t)gk * Rp + col];
+                wvv = W[(size_t)(hs + gk) * Rp + col];
+            }
+            const float uh = (float)wu, vh = (float)wvv;
+            Wt[0][0][col][kk] = uh;
+            Wt[0][1][col][kk] = (float)(wu - (double)uh);
+            Wt[1][0][col][kk] = vh;
+            Wt[1][1][col][kk] = (float)(wvv - (double)vh);
+        }
+        __syncthreads();
+        v4f Cu[CB], Cv[CB];
+        // unrolling the quarters lets the compiler keep more loads in flight,
+        // but with one-step groups it keeps every group's accumulator alive
+        constexpr int QUN = (FL == 1 && CB > 1) ? 1 : MTK / 16;
+#pragma unroll QUN
+        for (int ss = 0; ss < MTK / 16; ++ss) {
+            const int kl = ss * 16 + kq;          // k within the slice
+            const int gk = s0 + kl;
+            v4f a1 = {0.f, 0.f, 0.f, 0.f}, ak = a1, a2 = a1, b1 = a1, bk = a1, b2 = a1;
+            if (rok && gk < ke) {
+                const size_t o = (size_t)row * hs + gk;
+                a1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a1p + o));
+                ak = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(akp + o));
+                a2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a2p + o));
+                if (hl) {
+                    b1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l1p + o));
+                    bk = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lkp + o));
+                    b2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l2p + o));
+                }
+            }
+            v4f UH[CB], VH[CB], UL[CB], VL[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int col = c * 16 + (lane & 15);
+                UH[c] = *reinterpret_cast<const v4f*>(&Wt[0][0][col][kl]);
+                VH[c] = *reinterpret_cast<const v4f*>(&Wt[1][0][col][kl]);
+                if (hl) {
+                    UL[c] = *reinterpret_cast<const v4f*>(&Wt[0][1][col][kl]);
+                    VL[c] = *reinterpret_cast<const v4f*>(&Wt[1][1][col][kl]);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q = ss * 4 + e;         // 4-index step within the slice
+                if (q % FL == 0) {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) Cu[c] = Cv[c] = (v4f){0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const float uh = UH[c][e], vh = VH[c][e];
+                    Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], uh, Cu[c], 0, 0, 0);
+                    Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vh, Cu[c], 0, 0, 0);
+                    Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], uh, Cv[c], 0, 0, 0);
+                    Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vh, Cv[c], 0, 0, 0);
+                    if (hl) {
+                        const float ul = UL[c][e], vl = VL[c][e];
+                        // Q_hi W_lo
+                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], ul, Cu[c], 0, 0, 0);
+                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vl, Cu[c], 0, 0, 0);
+                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], ul, Cv[c], 0, 0, 0);
+                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vl, Cv[c], 0, 0, 0);
+                        // Q_lo W_hi
+                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1[e], uh, Cu[c], 0, 0, 0);
+                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bk[e], vh, Cu[c], 0, 0, 0);
+                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(bk[e], uh, Cv[c], 0, 0, 0);
+                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(b2[e], vh, Cv[c], 0, 0, 0);
+                    }
+                }
+                if (q % FL == FL - 1) {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            Du[c][r] += (double)Cu[c][r];
+                            Dv[c][r] += (double)Cv[c][r];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double* P = part + ((size_t)jj * KC + kc) * 2 * ne * Rp;
+    const int rbase = blockIdx.x * 64 + wv * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const int col = c * 16 + (lane & 15);
+        if (col >= Rp) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = rbase + r;
+            if (rr < ne) {
+                P[(size_t)rr * Rp + col] = Du[c][r];
+                P[(size_t)(ne + rr) * Rp + col] = Dv[c][r];
+            }
+        }
+    }
+}
+
+// Qf = fp32(Q), Qlo = fp32(Q - Qf) (lo only when requested), one lag (3 blocks)
+__global__ void k_split_f32(size_t n, const double* __restrict__ Q, float* __restrict__ hi, float* __restrict__ lo) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double v = Q[t];
+        const float h = (float)v;
+        hi[t] = h;
+        if (lo) lo[t] = (float)(v - (double)h);
+    }
+}
+
 int pick_kc(int tiles, int groups, int K) {
     int want = (1024 + tiles * groups - 1) / (tiles * groups);
     int maxkc = K / (4 * TK);
@@ -427,9 +596,11 @@ void plain_product(mot_handle* h, const double* src, double* vj, double* z) {
 
 namespace motk_multi {
 
+int mixed_kc(const mot_handle* h);
+
 size_t part_doubles(const mot_handle* h) {
     const int tiles = (h->ne + TM - 1) / TM;
-    size_t a = (size_t)h->nh * pick_kc(tiles, h->nh, h->hs) * 2 * h->ne * h->Rp;
+    size_t a = (size_t)h->nh * std::max(pick_kc(tiles, h->nh, h->hs), mixed_kc(h)) * 2 * h->ne * h->Rp;
     size_t b = (size_t)pick_kc(tiles, 1, h->hs) * 2 * h->ne * h->Rp;
     const int t2 = (h->n2 + TM - 1) / TM;
     size_t c = (size_t)pick_kc(t2, 1, h->n2) * h->n2 * h->Rp;
@@ -447,9 +618,57 @@ size_t part_doubles(const mot_handle* h) {
     }
 
 void history(mot_handle* h) {
+    if (h->Qf) {
+        const int tiles = (h->ne + 63) / 64;
+        const int KC = h->mix_kc;
+        dim3 grid(tiles, h->nh, KC);
+        const int CB = (h->Rp + 15) / 16;
+        const int FL = h->opt.mix_group == 64 ? 16 : (h->opt.mix_group == 16 ? 4 : 1);
+#define L_(CB_, FL_) hipLaunchKernelGGL((k_hist_mfma<CB_, FL_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->Rp, \
+                                        h->d_k, h->nh, h->hilo, h->Qf, h->Qlo, h->ring, KC, h->mr_part)
+#define F_(CB_)              \
+    do {                     \
+        if (FL == 16)        \
+            L_(CB_, 16);     \
+        else if (FL == 4)    \
+            L_(CB_, 4);      \
+        else                 \
+            L_(CB_, 1);      \
+    } while (0)
+        if (CB == 1)
+            F_(1);
+        else if (CB == 2)
+            F_(2);
+        else
+            F_(4);
+#undef F_
+#undef L_
+        const int n = h->ne * h->Rp;
+#define C_(R_) hipLaunchKernelGGL(k_struct_reduce<R_>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, \
+                                  h->d_k, h->nh, 0, KC, h->mr_part, h->rb, h->B, h->y)
+        MOT_RP_SWITCH(h->Rp, C_)
+#undef C_
+        return;
+    }
 #define C_(R_) struct_product<R_>(h, 0, nullptr, h->y, 1)
     MOT_RP_SWITCH(h->Rp, C_)
 #undef C_
+}
+
+int mixed_kc(const mot_handle* h) {
+    const int tiles = (h->ne + 63) / 64;
+    int want = (1024 + tiles * h->nh - 1) / (tiles * h->nh);
+    int maxkc = h->hs / (4 * MTK);
+    if (maxkc < 1) maxkc = 1;
+    return want < 1 ? 1 : (want > maxkc ? maxkc : want);
+}
+
+void split_lag(mot_handle* h, int lag) {
+    const size_t blk3 = (size_t)3 * h->ne * h->hs;
+    const double* src = h->Q + (size_t)lag * blk3;
+    float* hi = h->Qf + (size_t)(lag - 1) * blk3;
+    float* lo = lag <= h->hilo ? h->Qlo + (size_t)(lag - 1) * blk3 : nullptr;
+    hipLaunchKernelGGL(k_split_f32, dim3(4096), dim3(256), 0, h->stream, blk3, src, hi, lo);
 }
 
 void q0_product(mot_handle* h, const double* X, double* out) {

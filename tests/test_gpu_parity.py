@@ -174,3 +174,42 @@ def test_multi_rhs_column_equals_alone():
         one = s1.run(60)
         s1.close()
         assert _rel(out["w"][:, :, r], one["w"][:, :, 0]) < 1e-12
+
+
+@pytest.mark.parametrize("name,nsteps,hilo,group,bound_w,bound_star", [
+    ("tiny_box", 60, 2, 4, 1e-6, 1e-5),
+    ("sphere_480_r16", 200, 2, 4, 1e-6, 3e-5),
+    ("sphere_480_r16", 200, -1, 4, 1e-6, 3e-5),
+    ("sphere_480_r16", 200, 2, 64, 6e-6, 1e-4),
+])
+def test_mixed_precision(name, nsteps, hilo, group, bound_w, bound_star):
+    """FP32-MFMA history, Q_0, GMRES, projectors and recovery in FP64.
+
+    Stated bounds, relative L2 over all steps against the FP64 oracle: the
+    currents w and their loop parts <= 1e-6 with FP32 accumulators of 4
+    summation indices per half; the star parts, which are (T_max/dt) times a
+    first difference of the unknowns, <= 3e-5.  A 64-index FP32 accumulator is
+    a few times less accurate.  No late-time growth in either case."""
+    print("case", name, nsteps, hilo, group, flush=True)
+    O = oracle(name)
+    ref = O.run(nsteps)
+    s = _solver(name, precond=2, precision=1, hilo_lags=hilo, mix_group=group)
+    out = s.run(nsteps)
+    e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+    print("mixed errors (hilo %d, group %d): w %.3e loop %.3e star %.3e" % (hilo, group, *e), flush=True)
+    assert e[0] < bound_w and e[1] < bound_w and e[2] < bound_star
+    nrm = np.linalg.norm(out["w"].reshape(nsteps, -1), axis=1)
+    late = np.log10(nrm[-nsteps // 4:] + 1e-300)
+    assert np.polyfit(np.arange(late.size), late, 1)[0] <= 0.0     # no late-time growth
+    s.close()
+
+
+def test_mixed_option_errors():
+    """Invalid accumulator length and single-RHS mixed precision are refused at create."""
+    import paper_2510_07989_amd as p
+    prob = problem("tiny_box")
+    with pytest.raises(p.MotError):
+        _solver("tiny_box", precond=2, precision=1, mix_group=8)
+    with pytest.raises(p.MotError):
+        p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                 prob["T0h"], prob["G"], prob["waves"][:1], options=p.default_options(precision=1))
