@@ -43,7 +43,7 @@ enum {
     MOT_ESTATE = -5    /* call out of order (e.g. a required lag missing)   */
 };
 
-enum { MOT_FP64 = 0, MOT_MIXED = 1 };                 /* history precision      */
+enum { MOT_FP64 = 0, MOT_MIXED = 1, MOT_MIXED32 = 2 }; /* history precision     */
 enum { MOT_FAM_H = 0, MOT_FAM_HAT = 1, MOT_FAM_TILDE = 2 };
 enum { MOT_EXT = 0, MOT_INT = 1 };
 enum { MOT_OP_T = 0, MOT_OP_K = 1 };
@@ -72,11 +72,15 @@ typedef struct {
 } mot_planewave;
 
 typedef struct {
-    int32_t precision;       /* MOT_FP64 (default) or MOT_MIXED: Q_1..Q_{L-1}
-                                stored in FP32 and multiplied on FP32 MFMA
-                                with FP64 accumulation across K slices and
-                                lags (needs nrhs > 1); Q_0, GMRES, projectors
-                                and recovery stay FP64                        */
+    int32_t precision;       /* history precision (Q_0, GMRES, projectors and
+                                recovery are FP64 in every mode):
+                                MOT_FP64 (default);
+                                MOT_MIXED: Q_1..Q_{L-1} stored in FP32 (plus an
+                                FP32 low part on lags 1..hilo_lags), every
+                                product and sum on FP64 MFMA;
+                                MOT_MIXED32: the same storage multiplied on
+                                FP32 MFMA, short FP32 sums added in FP64.
+                                Both mixed modes need nrhs > 1.               */
     double gmres_tol;        /* relative residual of each Q_0 solve (1e-13)  */
     int32_t gmres_restart;   /* Krylov dimension m (40)                      */
     int32_t gmres_maxit;     /* total iterations per step (400)              */
@@ -98,9 +102,11 @@ typedef struct {
     int32_t history_order;   /* history kernel loop order: 1 (or 0) column
                                 slices across all blocks, 2 whole rows of one
                                 block at a time                               */
-    int32_t hilo_lags;       /* MOT_MIXED: lags 1..hilo_lags use split
-                                hi/lo FP32 products (default 2, -1: none)     */
-    int32_t mix_group;       /* MOT_MIXED: summation indices per half that one
+    int32_t hilo_lags;       /* mixed modes: lags 1..hilo_lags keep the FP32
+                                low part fl(Q - fl(Q)) (default 2, -1: none);
+                                MOT_MIXED32 multiplies it as split hi/lo
+                                products                                      */
+    int32_t mix_group;       /* MOT_MIXED32: summation indices per half that one
                                 FP32 MFMA accumulator sums before it is added
                                 into the FP64 total: 4 (default), 16 or 64    */
     int32_t reserved[2];

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmot.so")
 
 MOT_OK, MOT_EINVAL, MOT_ENOMEM, MOT_ENOCONV, MOT_EHIP, MOT_ESTATE = 0, -1, -2, -3, -4, -5
-MOT_FP64, MOT_MIXED = 0, 1
+MOT_FP64, MOT_MIXED, MOT_MIXED32 = 0, 1, 2
 FAM_H, FAM_HAT, FAM_TILDE = 0, 1, 2
 MED_EXT, MED_INT = 0, 1
 OP_T, OP_K = 0, 1

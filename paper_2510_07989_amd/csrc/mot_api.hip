@@ -41,8 +41,9 @@ void precond(mot_handle* h, const double* src, double* vj, double* z);
 void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero);
 void orth(mot_handle* h, double* w);
 void finish(mot_handle* h, int force);
-int mixed_kc(const mot_handle* h);
-void split_lag(mot_handle* h, int lag);
+void plan_tiles(mot_handle* h);
+size_t tile_elems(const mot_handle* h);
+void pack_lag(mot_handle* h, int lag);
 }  // namespace motk_multi
 
 static std::string g_create_err;
@@ -344,8 +345,8 @@ int fold_lag(mot_handle* h, int lag) {
         if (Zf[f]) dfree(h, Zf[f]);
         h->stage[(size_t)lag * 3 + f] = nullptr;
     }
-    if (lag >= 1 && h->Qf) {
-        motk_multi::split_lag(h, lag);
+    if (h->Rp > 1) {
+        motk_multi::pack_lag(h, lag);
         HIPCHK(h, hipStreamSynchronize(s));
     }
     h->lag_done[lag] = 1;
@@ -756,10 +757,10 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     if (nrhs < 1 || nrhs > 64) return mot_fail(nullptr, MOT_EINVAL, "nrhs must be in 1..64");
     if (nrhs > 1 && opt && opt->precond == 0)
         return mot_fail(nullptr, MOT_EINVAL, "several right-hand sides need the Q_0 preconditioner (precond 1 or 2)");
-    if (opt && opt->precision == MOT_MIXED && nrhs < 2)
+    if (opt && opt->precision != MOT_FP64 && opt->precision != MOT_MIXED && opt->precision != MOT_MIXED32)
+        return mot_fail(nullptr, MOT_EINVAL, "precision must be MOT_FP64, MOT_MIXED or MOT_MIXED32");
+    if (opt && opt->precision != MOT_FP64 && nrhs < 2)
         return mot_fail(nullptr, MOT_EINVAL, "the mixed-precision history multiplies several right-hand sides (nrhs >= 2)");
-    if (opt && opt->precision != MOT_FP64 && opt->precision != MOT_MIXED)
-        return mot_fail(nullptr, MOT_EINVAL, "precision must be MOT_FP64 or MOT_MIXED");
     if (opt && opt->mix_group != 0 && opt->mix_group != 4 && opt->mix_group != 16 && opt->mix_group != 64)
         return mot_fail(nullptr, MOT_EINVAL, "mix_group must be 4, 16 or 64 (0: 4)");
     // ---- mesh validation (host, integers) ----
@@ -973,13 +974,18 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
         (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
         (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
         return bail(rc);
-    if (h->opt.precision == MOT_MIXED) {
-        h->hilo = h->opt.hilo_lags < 0 ? 0 : std::min(h->opt.hilo_lags, h->nh);
-        h->mix_kc = motk_multi::mixed_kc(h);
-        const size_t blk3 = (size_t)3 * h->ne * h->hs;
-        if ((rc = dalloc(h, &h->Qf, (size_t)h->nh * blk3)) ||
-            (h->hilo && (rc = dalloc(h, &h->Qlo, (size_t)h->hilo * blk3))))
-            return bail(rc);
+    if (h->Rp > 1) {
+        // tile-major copies of the lags for the multi-RHS products
+        motk_multi::plan_tiles(h);
+        const size_t tsz3 = 3 * motk_multi::tile_elems(h);
+        if (h->opt.precision == MOT_FP64) {
+            if ((rc = dalloc(h, &h->Qt, (size_t)h->nlags * tsz3))) return bail(rc);
+        } else {
+            h->hilo = h->opt.hilo_lags < 0 ? 0 : std::min(h->opt.hilo_lags, h->nh);
+            if ((rc = dalloc(h, &h->Qt, tsz3)) || (rc = dalloc(h, &h->QtF, (size_t)h->nh * tsz3)) ||
+                (h->hilo && (rc = dalloc(h, &h->QtL, (size_t)h->hilo * tsz3))))
+                return bail(rc);
+        }
     }
     if (h->Rp > 1 && ((rc = dalloc(h, &h->gms, h->Rp)) || (rc = dalloc(h, &h->mr_part, motk_multi::part_doubles(h)))))
         return bail(rc);

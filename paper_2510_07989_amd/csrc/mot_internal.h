@@ -149,10 +149,13 @@ struct mot_handle {
     GmState* gm = nullptr;           // single-RHS state, aggregate state when R > 1
     GmState* gms = nullptr;          // [Rp] per-column states (R > 1)
     double* mr_part = nullptr;       // split-K partial products (R > 1)
-    float* Qf = nullptr;             // [nlags-1][3][ne][hs] FP32 Q_1.. (mixed precision)
-    float* Qlo = nullptr;            // [hilo][3][ne][hs] FP32 residual Q - Qf of the short lags
-    int hilo = 0;                    // lags with split hi/lo products
-    int mix_kc = 1;                  // K chunks of the mixed history kernel
+    // multi-RHS tile-major lag storage (16 x 16 tiles, see multi.hip)
+    int G16 = 0, KT = 0;             // row groups and summation tiles per block
+    double* Qt = nullptr;            // FP64 tiles: lags 0..nh (FP64 path) or lag 0 (mixed)
+    float* QtF = nullptr;            // FP32 tiles of lags 1..nh (mixed paths)
+    float* QtL = nullptr;            // FP32 low parts fl(Q - fl(Q)) of lags 1..hilo
+    int hilo = 0;                    // lags with a low part
+    int hist_kc = 1, q0_kc = 1;      // K chunks of the tile products
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;
     int M = 40;

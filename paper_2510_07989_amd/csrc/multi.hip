@@ -1,7 +1,23 @@
 // Multi-right-hand-side march: the R plane waves of one scatterer share every
 // lag matrix, so the history convolution and the Q_0 products become
 // tall-skinny GEMMs [ne x hs] x [hs x RP] (RP = R rounded up to a power of two).
-// Vectors are [n2][RP] (column index fastest).  FP64 throughout.
+// Vectors are [n2][RP] (column index fastest).
+//
+// Tile-major lag storage.  Each ne x hs block of Q_j (q1, qk, q2, with
+// Q_j = [[q1, -qk], [qk, q2]]) is cut into 16 x 16 tiles; tile (g, c) holds rows
+// 16g..16g+15 and summation indices 16c..16c+15, tiles stored g-major
+// (index g * KT + c), 256 entries each, zero beyond ne.  Inside a tile, lane l
+// of a wavefront owns row 16g + l%16 and indices 16c + 4(l/16) + e, e = 0..3:
+//   FP32 entry (l, e) at l*4 + e                 (one 16-byte load per lane)
+//   FP64 entry (l, e) at (e/2)*128 + l*2 + e%2   (two 16-byte loads per lane)
+// so one wavefront reads each tile as contiguous 1 KB pieces.  The 16x16x4
+// MFMAs take A as lane l = row l%16, summation slot l/16; slot l/16 of MFMA e is
+// index 4(l/16) + e here, and the B operand (the history vector, from LDS) is
+// read with the same permutation, so the product is unchanged.
+// Operand layout, measured on gfx950: B lane l = column l%16, slot l/16 for
+// both MFMAs; result register r of lane l holds column l%16 and row
+//   4(l/16) + r   for v_mfma_f32_16x16x4f32,
+//   l/16 + 4r     for v_mfma_f64_16x16x4f64.
 #include "mot_internal.h"
 
 namespace {
@@ -13,90 +29,6 @@ __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
-}
-
-// Structured product for one row tile, one lag j and one K chunk:
-//   Yu = q1_j Wu - qk_j Wv,   Yv = qk_j Wu + q2_j Wv     (Q_j = [[q1, -qk], [qk, q2]])
-// W is the history vector w_{k-j} from the ring (history) or a given vector X
-// (Q_0 product).  Partial results part[(jj * KC + kc)][2][ne][RP].
-template <int RP>
-__global__ __launch_bounds__(256) void k_struct_gemm(int ne, int hs, const int* __restrict__ dk, int nh,
-                                                     int q0_mode, const double* __restrict__ Q,
-                                                     const double* __restrict__ ring,
-                                                     const double* __restrict__ X, int KC,
-                                                     double* __restrict__ part) {
-    const int k = *dk;
-    const int jj = blockIdx.y;                       // 0-based lag slot
-    const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
-    if (jj >= nact) return;
-    const int j = q0_mode ? 0 : jj + 1;
-    const int n2 = 2 * hs;
-    const size_t blk = (size_t)ne * hs;
-    const double* q1 = Q + (size_t)j * 3 * blk;
-    const double* qk = q1 + blk;
-    const double* q2 = q1 + 2 * blk;
-    const double* W = q0_mode ? X : ring + (size_t)((k - j) % nh) * n2 * RP;
-    const int m0 = blockIdx.x * TM;
-    const int kc = blockIdx.z;
-    const int KL = ((hs + KC - 1) / KC + TK - 1) / TK * TK;
-    const int kb = kc * KL, ke = min(hs, kb + KL);
-
-    __shared__ double A1[TK][TM + 1], Ak[TK][TM + 1], A2[TK][TM + 1];
-    __shared__ double Wu[TK][RP], Wv[TK][RP];
-    constexpr int RPT = TM * RP / 256;               // rows per thread
-    constexpr int RG = 256 / RP;                     // row groups
-    const int t = threadIdx.x;
-    const int c = t % RP, rg = t / RP;
-    double au[RPT], av[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) au[i] = av[i] = 0.0;
-
-    for (int k0 = kb; k0 < ke; k0 += TK) {
-#pragma unroll
-        for (int q = 0; q < TM * TK / 256; ++q) {
-            int e = t + 256 * q;
-            int row = e / TK, col = e % TK;
-            int gm = m0 + row, gk = k0 + col;
-            bool ok = gm < ne && gk < ke;
-            size_t o = (size_t)gm * hs + gk;
-            A1[col][row] = ok ? __builtin_nontemporal_load(q1 + o) : 0.0;
-            Ak[col][row] = ok ? __builtin_nontemporal_load(qk + o) : 0.0;
-            A2[col][row] = ok ? __builtin_nontemporal_load(q2 + o) : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < (TK * RP + 255) / 256; ++q) {
-            int e = t + 256 * q;
-            if (e < TK * RP) {
-                int kk = e / RP, cc = e % RP;
-                int gk = k0 + kk;
-                bool ok = gk < ke;
-                Wu[kk][cc] = ok ? W[(size_t)gk * RP + cc] : 0.0;
-                Wv[kk][cc] = ok ? W[(size_t)(hs + gk) * RP + cc] : 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            const double wu = Wu[kk][c], wv = Wv[kk][c];
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int row = rg + i * RG;
-                const double a1 = A1[kk][row], ak = Ak[kk][row], a2 = A2[kk][row];
-                au[i] = fma(a1, wu, fma(-ak, wv, au[i]));
-                av[i] = fma(ak, wu, fma(a2, wv, av[i]));
-            }
-        }
-        __syncthreads();
-    }
-    double* P = part + ((size_t)jj * KC + kc) * 2 * ne * RP;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int gm = m0 + rg + i * RG;
-        if (gm < ne) {
-            P[(size_t)gm * RP + c] = au[i];
-            P[(size_t)(ne + gm) * RP + c] = av[i];
-        }
-    }
 }
 
 // y = rb(step) - sum of history partials     (hist = 1)
@@ -388,26 +320,191 @@ __global__ void k_gmb_consume(int RP, GmState* gms) {
     if (c < RP && gms[c].done) gms[c].cycle_iters = 0;
 }
 
-// ---------------------------------------------------------------- mixed ---
-// History in mixed precision (FP32 storage of Q_1..Q_{L-1}, FP32 MFMA):
-//   Yu = q1 Wu - qk Wv,  Yv = qk Wu + q2 Wv   per lag, with
-//   Q W ~ Q_hi W_hi + Q_hi W_lo + Q_lo W_hi   on the first hilo lags.
-// v_mfma_f32_16x16x4f32 operand layout (one wavefront): A lane l = row l%16,
-// k l/16;  B lane l = col l%16, k l/16;  D lane l = col l%16, rows 4(l/16)..+3.
-// Each lane loads four consecutive k of its row; the summation index inside one
-// MFMA is permuted consistently for A and B, so the product is unchanged.
+// ---------------------------------------------------------------- tiles ---
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__host__ __device__ inline size_t tile_pos64(int lane, int e) { return (size_t)(e >> 1) * 128 + lane * 2 + (e & 1); }
+__host__ __device__ inline size_t tile_pos32(int lane, int e) { return (size_t)lane * 4 + e; }
+
+// Pack one ne x hs row-major block into tiles: FP64 (hi64), or FP32 hi = fl(v)
+// and, when lo is given, lo = fl(v - hi).
+__global__ void k_pack_tiles(int ne, int hs, int G16, int KT, const double* __restrict__ src,
+                             double* __restrict__ hi64, float* __restrict__ hi32, float* __restrict__ lo32) {
+    const size_t total = (size_t)G16 * KT * 256;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
+        const size_t tile = p / 256;
+        const int in = (int)(p % 256);
+        const int g = (int)(tile / KT), c = (int)(tile % KT);
+        int lane, e;
+        if (hi64) { lane = (in & 127) >> 1; e = ((in >> 7) << 1) | (in & 1); }
+        else { lane = in >> 2; e = in & 3; }
+        const int row = g * 16 + (lane & 15), kk = c * 16 + 4 * (lane >> 4) + e;
+        const double v = (row < ne && kk < ne) ? src[(size_t)row * hs + kk] : 0.0;
+        if (hi64) {
+            hi64[p] = v;
+        } else {
+            const float h = (float)v;
+            hi32[p] = h;
+            if (lo32) lo32[p] = (float)(v - (double)h);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_tile(const double* __restrict__ t, int lane, double a[4]) {
+    const v2d x = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(t) + lane);
+    const v2d y = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(t + 128) + lane);
+    a[0] = x[0]; a[1] = x[1]; a[2] = y[0]; a[3] = y[1];
+}
+__device__ __forceinline__ void load_tile(const float* __restrict__ t, int lane, double a[4]) {
+    const v4f x = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(t) + lane);
+    a[0] = x[0]; a[1] = x[1]; a[2] = x[2]; a[3] = x[3];
+}
+
+// Structured product on FP64 MFMA for one 64-row block (4 wavefronts x 16
+// rows), one lag and one K chunk:
+//   Yu = q1 Wu - qk Wv,   Yv = qk Wu + q2 Wv
+// Tiles in FP64 (plain path) or FP32 (mixed path, with an FP32 low part added
+// in registers on lags 1..hilo); every product and sum in FP64, so the mixed
+// path differs from FP64 only by the rounding of the stored entries.
+// History (q0_mode 0): lag j = blockIdx.y + 1, At = tiles of lag 1, W = ring
+// slot of w_{k-j}.  Q_0 (q0_mode 1): At = tiles of lag 0, W = X.
+// Partial results part[(blockIdx.y * KC + kc)][2][ne][Rp].
+template <typename T, int CB>
+__global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int KT, int Rp,
+                                                   const int* __restrict__ dk, int nh, int q0_mode,
+                                                   const T* __restrict__ At, const float* __restrict__ Alo,
+                                                   int hilo, const double* __restrict__ ring,
+                                                   const double* __restrict__ X, int KC,
+                                                   double* __restrict__ part) {
+    const int k = *dk;
+    const int jj = blockIdx.y;
+    const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
+    if (jj >= nact) return;
+    const int j = q0_mode ? 0 : jj + 1;
+    const size_t tsz = (size_t)G16 * KT * 256;
+    const T* a1p = At + (size_t)(q0_mode ? 0 : j - 1) * 3 * tsz;
+    const T* akp = a1p + tsz;
+    const T* a2p = a1p + 2 * tsz;
+    const bool hl = Alo != nullptr && !q0_mode && j <= hilo;
+    const float* l1p = hl ? Alo + (size_t)(j - 1) * 3 * tsz : nullptr;
+    const double* W = q0_mode ? X : ring + (size_t)((k - j) % nh) * 2 * hs * Rp;
+    const int kc = blockIdx.z;
+    const int CT = (KT + KC - 1) / KC;
+    const int c0 = kc * CT, c1 = min(KT, c0 + CT);
+
+    constexpr int NC = CB * 16;                // columns staged
+    constexpr int ST = CB >= 4 ? 2 : 4;        // tiles per staged slice
+    __shared__ double Ws[2][ST * 16][NC + 2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int g = blockIdx.x * 4 + wv;
+    const bool gok = g < G16;
+    const int kq = 4 * (lane >> 4), cl = lane & 15;
+
+    // two accumulator sets (even / odd e) give a single column block independent
+    // MFMA chains; several column blocks already do
+    constexpr int NS = CB == 1 ? 2 : 1;
+    v4d Cu[CB][NS], Cv[CB][NS];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) Cu[cb][s2] = Cv[cb][s2] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    double n1[4], nk[4], n2v[4];
+    auto fetch = [&](int c) {
+        const size_t o = ((size_t)g * KT + c) * 256;
+        load_tile(a1p + o, lane, n1);
+        load_tile(akp + o, lane, nk);
+        load_tile(a2p + o, lane, n2v);
+        if (hl) {
+            double l[4];
+            load_tile(l1p + o, lane, l);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) n1[e] += l[e];
+            load_tile(l1p + tsz + o, lane, l);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) nk[e] += l[e];
+            load_tile(l1p + 2 * tsz + o, lane, l);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) n2v[e] += l[e];
+        }
+    };
+    if (gok && c0 < c1) fetch(c0);
+
+    for (int cs = c0; cs < c1; cs += ST) {
+        const int nst = min(ST, c1 - cs);
+        for (int e = t; e < ST * 16 * NC; e += 256) {
+            const int col = e % NC, kk = e / NC;
+            const int gk = cs * 16 + kk;
+            double wu = 0.0, wvv = 0.0;
+            if (col < Rp && kk < nst * 16 && gk < hs) {
+                wu = W[(size_t)gk * Rp + col];
+                wvv = W[(size_t)(hs + gk) * Rp + col];
+            }
+            Ws[0][kk][col] = wu;
+            Ws[1][kk][col] = wvv;
+        }
+        __syncthreads();
+        for (int ci = 0; ci < nst; ++ci) {
+            double a1[4], ak[4], a2[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { a1[e] = n1[e]; ak[e] = nk[e]; a2[e] = n2v[e]; }
+            if (gok && cs + ci + 1 < c1) fetch(cs + ci + 1);
+            if (gok) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int kk = ci * 16 + kq + e;
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const double wu = Ws[0][kk][cb * 16 + cl];
+                        const double wvv = Ws[1][kk][cb * 16 + cl];
+                        v4d& u = Cu[cb][e % NS];
+                        v4d& v = Cv[cb][e % NS];
+                        u = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], wu, u, 0, 0, 0);
+                        u = __builtin_amdgcn_mfma_f64_16x16x4f64(-ak[e], wvv, u, 0, 0, 0);
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[e], wu, v, 0, 0, 0);
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[e], wvv, v, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!gok) return;
+    double* P = part + ((size_t)jj * KC + kc) * 2 * ne * Rp;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = cb * 16 + cl;
+        if (col >= Rp) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = g * 16 + (lane >> 4) + 4 * r;
+            if (row < ne) {
+                double su = 0.0, sv = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) { su += Cu[cb][s2][r]; sv += Cv[cb][s2][r]; }
+                P[(size_t)row * Rp + col] = su;
+                P[(size_t)(ne + row) * Rp + col] = sv;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ FP32 MFMA history ---
+// History with FP32 products (v_mfma_f32_16x16x4f32) on the FP32 tiles:
+//   Q W ~ Q_hi W_hi + Q_hi W_lo + Q_lo W_hi   on lags 1..hilo, Q_hi W_hi beyond.
 // One FP32 accumulator sums 4*FL summation indices of each half (u and v), then
 // is added into the FP64 total: the history sums cancel strongly (row sums are
-// 10-100x smaller than the sums of magnitudes), so the FP32 partial sums are
-// kept short.  Slices of MTK indices are staged per block; FP64 across slices,
-// K chunks and lags.
-typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int MTK = 64;       // K slice staged in LDS
+// 10-100x below the sums of magnitudes), so FP32 partial sums are kept short.
+// Slices of MTK indices are staged per block; FP64 across slices, K chunks and
+// lags.
+constexpr int MTK = 64;       // K slice staged in LDS (4 tiles)
 
 template <int CB, int FL>
-__global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const int* __restrict__ dk, int nh,
-                                                   int hilo, const float* __restrict__ Qf,
-                                                   const float* __restrict__ Qlo,
+__global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int G16, int KT, int Rp,
+                                                   const int* __restrict__ dk, int nh, int hilo,
+                                                   const float* __restrict__ Qf, const float* __restrict__ Qlo,
                                                    const double* __restrict__ ring, int KC,
                                                    double* __restrict__ part) {
     const int k = *dk;
@@ -415,15 +512,15 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const
     const int nact = k - 1 < nh ? k - 1 : nh;
     if (jj >= nact) return;
     const int j = jj + 1;
-    const bool hl = j <= hilo;
+    const bool hl = Qlo != nullptr && j <= hilo;
     const int n2 = 2 * hs;
-    const size_t blk = (size_t)ne * hs;
-    const float* a1p = Qf + (size_t)(j - 1) * 3 * blk;
-    const float* akp = a1p + blk;
-    const float* a2p = a1p + 2 * blk;
-    const float* l1p = hl ? Qlo + (size_t)(j - 1) * 3 * blk : nullptr;
-    const float* lkp = hl ? l1p + blk : nullptr;
-    const float* l2p = hl ? l1p + 2 * blk : nullptr;
+    const size_t tsz = (size_t)G16 * KT * 256;
+    const float* a1p = Qf + (size_t)(j - 1) * 3 * tsz;
+    const float* akp = a1p + tsz;
+    const float* a2p = a1p + 2 * tsz;
+    const float* l1p = hl ? Qlo + (size_t)(j - 1) * 3 * tsz : nullptr;
+    const float* lkp = hl ? l1p + tsz : nullptr;
+    const float* l2p = hl ? l1p + 2 * tsz : nullptr;
     const double* W = ring + (size_t)((k - j) % nh) * n2 * Rp;
     const int kc = blockIdx.z;
     const int KL = ((hs + KC - 1) / KC + MTK - 1) / MTK * MTK;
@@ -432,8 +529,8 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const
     // staged history vectors, transposed: [u/v][hi/lo][column][k]
     __shared__ float Wt[2][2][CB * 16][MTK + 4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int row = blockIdx.x * 64 + wv * 16 + (lane & 15);
-    const bool rok = row < ne;
+    const int g = blockIdx.x * 4 + wv;
+    const bool gok = g < G16;
     const int kq = 4 * (lane >> 4);
     double Du[CB][4], Dv[CB][4];
 #pragma unroll
@@ -465,28 +562,28 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const
 #pragma unroll QUN
         for (int ss = 0; ss < MTK / 16; ++ss) {
             const int kl = ss * 16 + kq;          // k within the slice
-            const int gk = s0 + kl;
+            const int c = (s0 >> 4) + ss;         // tile column
             v4f a1 = {0.f, 0.f, 0.f, 0.f}, ak = a1, a2 = a1, b1 = a1, bk = a1, b2 = a1;
-            if (rok && gk < ke) {
-                const size_t o = (size_t)row * hs + gk;
-                a1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a1p + o));
-                ak = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(akp + o));
-                a2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a2p + o));
+            if (gok && s0 + ss * 16 < ke) {
+                const size_t o = ((size_t)g * KT + c) * 256;
+                a1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a1p + o) + lane);
+                ak = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(akp + o) + lane);
+                a2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a2p + o) + lane);
                 if (hl) {
-                    b1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l1p + o));
-                    bk = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lkp + o));
-                    b2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l2p + o));
+                    b1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l1p + o) + lane);
+                    bk = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lkp + o) + lane);
+                    b2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(l2p + o) + lane);
                 }
             }
             v4f UH[CB], VH[CB], UL[CB], VL[CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int col = c * 16 + (lane & 15);
-                UH[c] = *reinterpret_cast<const v4f*>(&Wt[0][0][col][kl]);
-                VH[c] = *reinterpret_cast<const v4f*>(&Wt[1][0][col][kl]);
+            for (int cb = 0; cb < CB; ++cb) {
+                const int col = cb * 16 + (lane & 15);
+                UH[cb] = *reinterpret_cast<const v4f*>(&Wt[0][0][col][kl]);
+                VH[cb] = *reinterpret_cast<const v4f*>(&Wt[1][0][col][kl]);
                 if (hl) {
-                    UL[c] = *reinterpret_cast<const v4f*>(&Wt[0][1][col][kl]);
-                    VL[c] = *reinterpret_cast<const v4f*>(&Wt[1][1][col][kl]);
+                    UL[cb] = *reinterpret_cast<const v4f*>(&Wt[0][1][col][kl]);
+                    VL[cb] = *reinterpret_cast<const v4f*>(&Wt[1][1][col][kl]);
                 }
             }
 #pragma unroll
@@ -494,66 +591,57 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int Rp, const
                 const int q = ss * 4 + e;         // 4-index step within the slice
                 if (q % FL == 0) {
 #pragma unroll
-                    for (int c = 0; c < CB; ++c) Cu[c] = Cv[c] = (v4f){0.f, 0.f, 0.f, 0.f};
+                    for (int cb = 0; cb < CB; ++cb) Cu[cb] = Cv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
                 }
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const float uh = UH[c][e], vh = VH[c][e];
-                    Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], uh, Cu[c], 0, 0, 0);
-                    Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vh, Cu[c], 0, 0, 0);
-                    Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], uh, Cv[c], 0, 0, 0);
-                    Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vh, Cv[c], 0, 0, 0);
+                for (int cb = 0; cb < CB; ++cb) {
+                    const float uh = UH[cb][e], vh = VH[cb][e];
+                    Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], uh, Cu[cb], 0, 0, 0);
+                    Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vh, Cu[cb], 0, 0, 0);
+                    Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], uh, Cv[cb], 0, 0, 0);
+                    Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vh, Cv[cb], 0, 0, 0);
                     if (hl) {
-                        const float ul = UL[c][e], vl = VL[c][e];
+                        const float ul = UL[cb][e], vl = VL[cb][e];
                         // Q_hi W_lo
-                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], ul, Cu[c], 0, 0, 0);
-                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vl, Cu[c], 0, 0, 0);
-                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], ul, Cv[c], 0, 0, 0);
-                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vl, Cv[c], 0, 0, 0);
+                        Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], ul, Cu[cb], 0, 0, 0);
+                        Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vl, Cu[cb], 0, 0, 0);
+                        Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], ul, Cv[cb], 0, 0, 0);
+                        Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vl, Cv[cb], 0, 0, 0);
                         // Q_lo W_hi
-                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1[e], uh, Cu[c], 0, 0, 0);
-                        Cu[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bk[e], vh, Cu[c], 0, 0, 0);
-                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(bk[e], uh, Cv[c], 0, 0, 0);
-                        Cv[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(b2[e], vh, Cv[c], 0, 0, 0);
+                        Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1[e], uh, Cu[cb], 0, 0, 0);
+                        Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bk[e], vh, Cu[cb], 0, 0, 0);
+                        Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bk[e], uh, Cv[cb], 0, 0, 0);
+                        Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b2[e], vh, Cv[cb], 0, 0, 0);
                     }
                 }
                 if (q % FL == FL - 1) {
 #pragma unroll
-                    for (int c = 0; c < CB; ++c)
+                    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            Du[c][r] += (double)Cu[c][r];
-                            Dv[c][r] += (double)Cv[c][r];
+                            Du[cb][r] += (double)Cu[cb][r];
+                            Dv[cb][r] += (double)Cv[cb][r];
                         }
                 }
             }
         }
         __syncthreads();
     }
+    if (!gok) return;
     double* P = part + ((size_t)jj * KC + kc) * 2 * ne * Rp;
-    const int rbase = blockIdx.x * 64 + wv * 16 + 4 * (lane >> 4);
+    const int rbase = g * 16 + kq;
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        const int col = c * 16 + (lane & 15);
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = cb * 16 + (lane & 15);
         if (col >= Rp) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int rr = rbase + r;
             if (rr < ne) {
-                P[(size_t)rr * Rp + col] = Du[c][r];
-                P[(size_t)(ne + rr) * Rp + col] = Dv[c][r];
+                P[(size_t)rr * Rp + col] = Du[cb][r];
+                P[(size_t)(ne + rr) * Rp + col] = Dv[cb][r];
             }
         }
-    }
-}
-
-// Qf = fp32(Q), Qlo = fp32(Q - Qf) (lo only when requested), one lag (3 blocks)
-__global__ void k_split_f32(size_t n, const double* __restrict__ Q, float* __restrict__ hi, float* __restrict__ lo) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-        const double v = Q[t];
-        const float h = (float)v;
-        hi[t] = h;
-        if (lo) lo[t] = (float)(v - (double)h);
     }
 }
 
@@ -562,20 +650,6 @@ int pick_kc(int tiles, int groups, int K) {
     int maxkc = K / (4 * TK);
     if (maxkc < 1) maxkc = 1;
     return want < 1 ? 1 : (want > maxkc ? maxkc : want);
-}
-
-template <int RP>
-void struct_product(mot_handle* h, int q0_mode, const double* X, double* out, int hist) {
-    const int tiles = (h->ne + TM - 1) / TM;
-    const int groups = q0_mode ? 1 : h->nh;
-    const int KC = pick_kc(tiles, groups, h->hs);
-    dim3 grid(tiles, groups, KC);
-    hipLaunchKernelGGL(k_struct_gemm<RP>, grid, dim3(256), 0, h->stream, h->ne, h->hs, h->d_k, h->nh, q0_mode, h->Q,
-                       h->ring, X, KC, h->mr_part);
-    const int n = h->ne * RP;
-    hipLaunchKernelGGL(k_struct_reduce<RP>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, q0_mode, KC, h->mr_part, h->rb, h->B, out);
-    (void)hist;
 }
 
 template <int RP>
@@ -592,20 +666,24 @@ void plain_product(mot_handle* h, const double* src, double* vj, double* z) {
                        h->gms, h->gm, z, vj);
 }
 
+template <typename T>
+void tile_launch(mot_handle* h, int q0_mode, const T* At, const float* Alo, const double* X, int KC, int groups) {
+    dim3 grid((h->G16 + 3) / 4, groups, KC);
+    const int CB = (h->Rp + 15) / 16;
+#define L_(CB_) hipLaunchKernelGGL((k_tile_gemm<T, CB_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->G16, h->KT, \
+                                   h->Rp, h->d_k, h->nh, q0_mode, At, Alo, h->hilo, h->ring, X, KC, h->mr_part)
+    if (CB == 1)
+        L_(1);
+    else if (CB == 2)
+        L_(2);
+    else
+        L_(4);
+#undef L_
+}
+
 }  // namespace
 
 namespace motk_multi {
-
-int mixed_kc(const mot_handle* h);
-
-size_t part_doubles(const mot_handle* h) {
-    const int tiles = (h->ne + TM - 1) / TM;
-    size_t a = (size_t)h->nh * std::max(pick_kc(tiles, h->nh, h->hs), mixed_kc(h)) * 2 * h->ne * h->Rp;
-    size_t b = (size_t)pick_kc(tiles, 1, h->hs) * 2 * h->ne * h->Rp;
-    const int t2 = (h->n2 + TM - 1) / TM;
-    size_t c = (size_t)pick_kc(t2, 1, h->n2) * h->n2 * h->Rp;
-    return std::max(a, std::max(b, c));
-}
 
 #define MOT_RP_SWITCH(RPV, CALL)                                         \
     switch (RPV) {                                                       \
@@ -617,15 +695,49 @@ size_t part_doubles(const mot_handle* h) {
         default: break;                                                  \
     }
 
+// K chunks so that one launch has about 2048 workgroups, each chunk at least
+// `unit` tiles long.
+static int tile_kc(int blocks, int KT, int unit) {
+    int want = (2048 + blocks - 1) / blocks;
+    int maxkc = KT / unit;
+    if (maxkc < 1) maxkc = 1;
+    return want < 1 ? 1 : (want > maxkc ? maxkc : want);
+}
+
+void plan_tiles(mot_handle* h) {
+    h->G16 = (h->ne + 15) / 16;
+    h->KT = (h->hs + 15) / 16;
+    const int gx = (h->G16 + 3) / 4;
+    h->hist_kc = tile_kc(gx * h->nh, h->KT, MTK / 16);
+    h->q0_kc = tile_kc(gx, h->KT, 4);
+}
+
+size_t tile_elems(const mot_handle* h) { return (size_t)h->G16 * h->KT * 256; }
+
+size_t part_doubles(const mot_handle* h) {
+    size_t a = (size_t)h->nh * h->hist_kc * 2 * h->ne * h->Rp;
+    size_t b = (size_t)h->q0_kc * 2 * h->ne * h->Rp;
+    const int t2 = (h->n2 + TM - 1) / TM;
+    size_t c = (size_t)pick_kc(t2, 1, h->n2) * h->n2 * h->Rp;
+    return std::max(a, std::max(b, c));
+}
+
+static void reduce(mot_handle* h, int q0_mode, int KC, double* out) {
+    const int n = h->ne * h->Rp;
+#define C_(R_) hipLaunchKernelGGL(k_struct_reduce<R_>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, \
+                                  h->d_k, h->nh, q0_mode, KC, h->mr_part, h->rb, h->B, out)
+    MOT_RP_SWITCH(h->Rp, C_)
+#undef C_
+}
+
 void history(mot_handle* h) {
-    if (h->Qf) {
-        const int tiles = (h->ne + 63) / 64;
-        const int KC = h->mix_kc;
-        dim3 grid(tiles, h->nh, KC);
+    const int KC = h->hist_kc;
+    if (h->opt.precision == MOT_MIXED32) {
+        dim3 grid((h->G16 + 3) / 4, h->nh, KC);
         const int CB = (h->Rp + 15) / 16;
         const int FL = h->opt.mix_group == 64 ? 16 : (h->opt.mix_group == 16 ? 4 : 1);
-#define L_(CB_, FL_) hipLaunchKernelGGL((k_hist_mfma<CB_, FL_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->Rp, \
-                                        h->d_k, h->nh, h->hilo, h->Qf, h->Qlo, h->ring, KC, h->mr_part)
+#define L_(CB_, FL_) hipLaunchKernelGGL((k_hist_mfma<CB_, FL_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->G16, \
+                                        h->KT, h->Rp, h->d_k, h->nh, h->hilo, h->QtF, h->QtL, h->ring, KC, h->mr_part)
 #define F_(CB_)              \
     do {                     \
         if (FL == 16)        \
@@ -643,38 +755,37 @@ void history(mot_handle* h) {
             F_(4);
 #undef F_
 #undef L_
-        const int n = h->ne * h->Rp;
-#define C_(R_) hipLaunchKernelGGL(k_struct_reduce<R_>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, \
-                                  h->d_k, h->nh, 0, KC, h->mr_part, h->rb, h->B, h->y)
-        MOT_RP_SWITCH(h->Rp, C_)
-#undef C_
-        return;
+    } else if (h->QtF) {
+        tile_launch<float>(h, 0, h->QtF, h->QtL, nullptr, KC, h->nh);
+    } else {
+        tile_launch<double>(h, 0, h->Qt + 3 * tile_elems(h), nullptr, nullptr, KC, h->nh);
     }
-#define C_(R_) struct_product<R_>(h, 0, nullptr, h->y, 1)
-    MOT_RP_SWITCH(h->Rp, C_)
-#undef C_
+    reduce(h, 0, KC, h->y);
 }
 
-int mixed_kc(const mot_handle* h) {
-    const int tiles = (h->ne + 63) / 64;
-    int want = (1024 + tiles * h->nh - 1) / (tiles * h->nh);
-    int maxkc = h->hs / (4 * MTK);
-    if (maxkc < 1) maxkc = 1;
-    return want < 1 ? 1 : (want > maxkc ? maxkc : want);
-}
-
-void split_lag(mot_handle* h, int lag) {
-    const size_t blk3 = (size_t)3 * h->ne * h->hs;
-    const double* src = h->Q + (size_t)lag * blk3;
-    float* hi = h->Qf + (size_t)(lag - 1) * blk3;
-    float* lo = lag <= h->hilo ? h->Qlo + (size_t)(lag - 1) * blk3 : nullptr;
-    hipLaunchKernelGGL(k_split_f32, dim3(4096), dim3(256), 0, h->stream, blk3, src, hi, lo);
+// After the fold of one lag: its tiles (FP64 for lag 0 and the plain path,
+// FP32 hi and, on lags 1..hilo, lo for the mixed paths).
+void pack_lag(mot_handle* h, int lag) {
+    const size_t blk = (size_t)h->ne * h->hs;
+    const size_t tsz = tile_elems(h);
+    for (int x = 0; x < 3; ++x) {
+        const double* src = h->Q + ((size_t)lag * 3 + x) * blk;
+        double* t64 = nullptr;
+        float *t32 = nullptr, *lo = nullptr;
+        if (lag == 0 || !h->QtF) {
+            t64 = h->Qt + ((size_t)lag * 3 + x) * tsz;
+        } else {
+            t32 = h->QtF + ((size_t)(lag - 1) * 3 + x) * tsz;
+            if (lag <= h->hilo) lo = h->QtL + ((size_t)(lag - 1) * 3 + x) * tsz;
+        }
+        hipLaunchKernelGGL(k_pack_tiles, dim3(4096), dim3(256), 0, h->stream, h->ne, h->hs, h->G16, h->KT, src, t64, t32,
+                           lo);
+    }
 }
 
 void q0_product(mot_handle* h, const double* X, double* out) {
-#define C_(R_) struct_product<R_>(h, 1, X, out, 0)
-    MOT_RP_SWITCH(h->Rp, C_)
-#undef C_
+    tile_launch<double>(h, 1, h->Qt, nullptr, X, h->q0_kc, 1);
+    reduce(h, 1, h->q0_kc, out);
 }
 
 void precond(mot_handle* h, const double* src, double* vj, double* z) {

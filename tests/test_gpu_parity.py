@@ -176,27 +176,60 @@ def test_multi_rhs_column_equals_alone():
         assert _rel(out["w"][:, :, r], one["w"][:, :, 0]) < 1e-12
 
 
-@pytest.mark.parametrize("name,nsteps,hilo,group,bound_w,bound_star", [
-    ("tiny_box", 60, 2, 4, 1e-6, 1e-5),
-    ("sphere_480_r16", 200, 2, 4, 1e-6, 3e-5),
-    ("sphere_480_r16", 200, -1, 4, 1e-6, 3e-5),
-    ("sphere_480_r16", 200, 2, 64, 6e-6, 1e-4),
-])
-def test_mixed_precision(name, nsteps, hilo, group, bound_w, bound_star):
-    """FP32-MFMA history, Q_0, GMRES, projectors and recovery in FP64.
+def _waves_problem(name, R):
+    """The named problem with R seeded plane waves instead of its own."""
+    from fixture.problem import CONFIGS, make_waves
+    prob = dict(problem(name))
+    prob["waves"] = make_waves(R, CONFIGS[name]["sigma"], True)
+    return prob
 
-    Stated bounds, relative L2 over all steps against the FP64 oracle: the
-    currents w and their loop parts <= 1e-6 with FP32 accumulators of 4
-    summation indices per half; the star parts, which are (T_max/dt) times a
-    first difference of the unknowns, <= 3e-5.  A 64-index FP32 accumulator is
-    a few times less accurate.  No late-time growth in either case."""
-    print("case", name, nsteps, hilo, group, flush=True)
+
+@pytest.mark.parametrize("R,precision", [(24, 0), (40, 0), (40, 1)])
+def test_multi_rhs_wide(R, precision):
+    """24 and 40 waves (2 and 4 column blocks of 16, the last partly masked) on
+    the 960-unknown sphere, FP64 and mixed, against the oracle."""
+    import paper_2510_07989_amd as p
+    from oracle.mot_oracle import Oracle
+    print("case sphere_480 R", R, "precision", precision, flush=True)
+    prob = _waves_problem("sphere_480", R)
+    ref = Oracle(prob).run(80)
+    s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                 prob["T0h"], prob["G"], prob["waves"], options=p.default_options(precond=2, precision=precision))
+    s.load_raw(prob["raw"], prob["kmax"])
+    out = s.run(80)
+    s.close()
+    e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+    print("errors", e, flush=True)
+    assert max(e) < (1e-10 if precision == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("name,nsteps,precision,hilo,group,bound_w,bound_star", [
+    ("tiny_box", 60, 1, 2, 4, 1e-6, 1e-5),
+    ("sphere_480_r16", 200, 1, 2, 4, 1e-6, 1e-5),
+    ("sphere_480_r16", 200, 1, -1, 4, 1e-6, 1e-5),
+    ("sphere_480_r16", 200, 2, 2, 4, 1e-6, 3e-5),
+    ("sphere_480_r16", 200, 2, 2, 64, 6e-6, 1e-4),
+])
+def test_mixed_precision(name, nsteps, precision, hilo, group, bound_w, bound_star):
+    """FP32 storage of Q_1..Q_{L-1}; Q_0, GMRES, projectors and recovery in FP64.
+
+    Stated bounds, relative L2 over all steps against the FP64 oracle, for the
+    currents w and their loop parts, and for the star parts, which are
+    (T_max/dt) times a first difference of the unknowns:
+      MOT_MIXED (FP64 MFMA products of the FP32-stored entries): w <= 1e-6,
+        star <= 1e-5;
+      MOT_MIXED32 (FP32 MFMA, FP32 sums of 4 indices per half added in FP64):
+        w <= 1e-6, star <= 3e-5 on this mesh; 64-index sums are a few times
+        less accurate.
+    No late-time growth in any case."""
+    print("case", name, nsteps, precision, hilo, group, flush=True)
     O = oracle(name)
     ref = O.run(nsteps)
-    s = _solver(name, precond=2, precision=1, hilo_lags=hilo, mix_group=group)
+    s = _solver(name, precond=2, precision=precision, hilo_lags=hilo, mix_group=group)
     out = s.run(nsteps)
     e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
-    print("mixed errors (hilo %d, group %d): w %.3e loop %.3e star %.3e" % (hilo, group, *e), flush=True)
+    print("mixed errors (precision %d, hilo %d, group %d): w %.3e loop %.3e star %.3e"
+          % (precision, hilo, group, *e), flush=True)
     assert e[0] < bound_w and e[1] < bound_w and e[2] < bound_star
     nrm = np.linalg.norm(out["w"].reshape(nsteps, -1), axis=1)
     late = np.log10(nrm[-nsteps // 4:] + 1e-300)
@@ -209,7 +242,10 @@ def test_mixed_option_errors():
     import paper_2510_07989_amd as p
     prob = problem("tiny_box")
     with pytest.raises(p.MotError):
-        _solver("tiny_box", precond=2, precision=1, mix_group=8)
+        _solver("tiny_box", precond=2, precision=2, mix_group=8)
+    for prec in (1, 2):
+        with pytest.raises(p.MotError):
+            p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                     prob["T0h"], prob["G"], prob["waves"][:1], options=p.default_options(precision=prec))
     with pytest.raises(p.MotError):
-        p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
-                 prob["T0h"], prob["G"], prob["waves"][:1], options=p.default_options(precision=1))
+        _solver("tiny_box", precond=2, precision=3)
