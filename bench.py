@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """MOT throughput on one MI355X: steps/s of the qHP TD-PMCHWT march.
 
-Workload (default): torus R = 1, r = 0.4, 2048 triangles / 3072 edges ->
-6144 unknowns, eps_r = 4, mu_r = 1, dt = 2.0 (c dt comparable to the
-diameter), one Gaussian plane wave, plain FP64.  A step is the whole hot
+Headline workload: torus R = 1, r = 0.4, 2048 triangles / 3072 edges -> 6144
+unknowns, eps_r = 4, mu_r = 1, dt = 2.0 (c dt comparable to the diameter),
+one Gaussian plane wave, plain FP64, 10,000 steps.  A step is the whole hot
 path: tested incident fields, preconditioned RHS, history convolution over
 Q_1..Q_{L-1}, GMRES on Q_0, ring update, and the loop/star current recovery
 of the timed steps.  Inputs are assembled on the host and resident on the
 device before the timed region.
 
+The `batched` object compares, on one sphere mesh (1280 triangles / 1920
+edges -> 3840 unknowns, eps_r = 2, dt = 0.15): plain FP64 with one wave, FP64
+with 16 seeded waves marched together, and the mixed path (FP32-stored lags,
+FP64 MFMA products) with the same 16 waves, whose error is stated against the
+FP64 run.
+
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,14 +28,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 WORKLOADS = {
     "torus_3072": "torus R=1 r=0.4, 2048 triangles / 3072 edges -> 6144 unknowns, eps_r=4, mu_r=1, "
-                  "dt=2.0, 1 Gaussian plane wave, plain FP64",
+                  "dt=2.0, 1 Gaussian plane wave",
     "sphere_480": "sphere r=1, 320 triangles / 480 edges -> 960 unknowns, eps_r=2, dt=0.25, "
-                  "1 Gaussian plane wave, plain FP64",
+                  "1 Gaussian plane wave",
     "sphere_1920_r16": "sphere r=1, 1280 triangles / 1920 edges -> 3840 unknowns, eps_r=2, dt=0.15, "
                        "16 seeded Gaussian plane waves marched together",
 }
+PRECISION = {0: "fp64", 1: "mixed: fp32-stored lags, fp64 mfma products",
+             2: "mixed32: fp32-stored lags, fp32 mfma products"}
+# committed PMC summary of the dominant kernels (HBM bytes per dispatch)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
@@ -45,14 +57,35 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
+def source_digest(rel):
+    try:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per dispatch from the committed counter runs, if they were taken
+    on the same workload and the kernel's source file is unchanged since; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for e in t.get("kernels", []):
+        if (e.get("kernel") == kernel and e.get("workload") == workload
+                and e.get("source_sha256_16") == source_digest(e.get("source", ""))):
+            return e.get("bytes_per_dispatch")
+    return None
+
+
 def cpu_baseline(prob, budget_s, nmax):
     """The oracle, as it stands, on the first steps of the same problem."""
-    import numpy as np
     from oracle.mot_oracle import Oracle, march, recover
     t = time.perf_counter()
     O = Oracle(prob)
     prep = time.perf_counter() - t
-    # one step to size the sample
     t = time.perf_counter()
     r1 = O.rhs_all(1)
     march(O.Q, r1)
@@ -66,19 +99,121 @@ def cpu_baseline(prob, budget_s, nmax):
     return dict(steps=ns, seconds=el, prep_s=prep, W=W, loop=loop, star=star)
 
 
+def history_model(ne, n, L, R, precision, hilo):
+    """Algorithmic bytes and flops of one history launch (all lags of one step):
+    the (L-1) lag matrices, 3 ne^2 stored entries each ([[q1, -qk], [qk, q2]]),
+    at 8 B (FP64) or 4 B (FP32, plus 4 B on the lags with a low part); the L-1
+    ring vectors and the RHS slice read once, the result written once.
+    flops: 4 ne^2 products per lag and column (qk acts twice), 2 flops each;
+    the split hi/lo FP32 products triple them on the low-part lags."""
+    ent = 3.0 * ne * ne
+    nl = L - 1
+    lo = min(max(hilo, 0), nl) if precision else 0
+    qbytes = ent * nl * 8.0 if precision == 0 else ent * (nl + lo) * 4.0
+    vbytes = 8.0 * (nl * n * R + 2 * n * R)
+    flops = 2.0 * 4 * ne * ne * R * (nl + (2 * lo if precision == 2 else 0))
+    return qbytes + vbytes, flops
+
+
+def roofline(kernel, nbytes, flops, us, dtype, mfma, traffic):
+    """Bound by the larger of bytes/HBM peak and flops/MFMA peak (MFMA kernels)."""
+    t = us * 1e-6
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_mma = flops / (MFMA_PEAK_TFLOPS[dtype] * 1e12) if mfma else 0.0
+    if t_mma > t_hbm:
+        ach = flops / t / 1e12
+        return {"bound": "mfma", "kernel": kernel, "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS[dtype], 4), "traffic": traffic,
+                "flops_per_launch": flops, "bytes_per_launch": nbytes, "avg_launch_us": round(us, 2),
+                "hbm_gbs": round(nbytes / t / 1e9, 1)}
+    ach = nbytes / t / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "bytes_per_launch": nbytes,
+            "avg_launch_us": round(us, 2)}
+
+
+def col_blocks(R):
+    rp = 1 if R == 1 else max(4, 1 << (R - 1).bit_length())
+    return min(4, (rp + 15) // 16)
+
+
+def history_kernel_name(R, precision, mix_group):
+    if R == 1:
+        return "k_history_co"
+    if precision == 2:
+        fl = {64: 16, 16: 4}.get(mix_group, 1)
+        return "k_hist_mfma<%d, %d>" % (col_blocks(R), fl)
+    return "k_tile_gemm<%s, %d>" % ("double" if precision == 0 else "float", col_blocks(R))
+
+
+def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, outputs=True):
+    """Set up one problem on the device, march W_ warm-up steps (kept as the
+    parity sample), then time K steps with device-resident outputs."""
+    import torch
+    R = len(prob["waves"])
+    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=precond, stream_split=split,
+                               precision=precision, hilo_lags=hilo, mix_group=mix_group)
+    t = time.perf_counter()
+    s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                   prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
+                   stream=torch.cuda.current_stream().cuda_stream)
+    s.load_raw(prob["raw"], prob["kmax"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    inf0 = s.info()
+    log("[%s R=%d %s] device setup %.2f s (preconditioner %.0f ms, fold %.0f ms), %d lags, %.2f GB on device"
+        % (name, R, PRECISION[precision], t_setup, inf0["setup_ms"], inf0["fold_ms"], inf0["nlags"],
+           inf0["device_bytes"] / 1e9))
+    warm = s.run(W_, w=True, loop=True, star=True, device=False)
+    torch.cuda.synchronize()
+    a = s.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(K, w=outputs, loop=outputs, star=outputs, device=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b = s.info()
+    s.close()
+    ne, n, L = prob["E"].shape[0], 2 * prob["E"].shape[0], b["nlags"]
+    hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
+    q0_us = 1e3 * (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
+    hb, hf = history_model(ne, n, L, R, precision, hilo)
+    kname = history_kernel_name(R, precision, mix_group)
+    dtype = "f32" if precision == 2 else "f64"
+    hist = roofline(kname, hb, hf, hist_us, dtype, R > 1, measured_traffic(kname, name))
+    q0b = 8.0 * (3 * ne * ne + 2 * n * R)
+    q0name = "k_q0_matvec" if R == 1 else "k_tile_gemm<double, %d>" % col_blocks(R)
+    q0 = roofline(q0name, q0b, 2.0 * 4 * ne * ne * R, q0_us, "f64", R > 1,
+                  measured_traffic(q0name if R == 1 else q0name + " (Q_0)", name))
+    hist_tot = b["hist_ms"] - a["hist_ms"]
+    q0_tot = b["q0_ms"] - a["q0_ms"]
+    out = dict(steps_s=K / el, el=el, K=K, W=W_, R=R, n=n, L=L, kmax=b["kmax"], setup_s=t_setup,
+               iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
+               q0_launches=(b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
+               dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
+               device_gb=inf0["device_bytes"] / 1e9)
+    log("[%s R=%d] timed %d steps in %.3f s: %.1f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
+        "history %.1f us (%s %.4g %s), Q0 product %.1f us"
+        % (name, R, K, el, K / el, R * K / el, out["iters"], hist_us, hist["bound"], hist["achieved"],
+           hist["unit"], q0_us))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="torus_3072", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched/mixed comparison")
+    ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
-    ap.add_argument("--precision", type=int, default=0, help="0 FP64 history, 1 mixed FP32/MFMA history")
-    ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with split hi/lo products (-1: none)")
-    ap.add_argument("--mix-group", type=int, default=4, help="mixed: summation indices per FP32 accumulator (4, 16, 64)")
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed (FP64 MFMA), 2 mixed (FP32 MFMA)")
+    ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with an FP32 low part (-1: none)")
+    ap.add_argument("--mix-group", type=int, default=4, help="precision 2: summation indices per FP32 sum")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the MOT march of one problem runs on one device "
@@ -99,89 +234,39 @@ def main():
     prob = build_problem(args.workload, nsteps=W_ + K, verbose=True)
     t_fixture = time.perf_counter() - t
     log("inputs assembled on the host in %.1f s" % t_fixture)
-
-    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=args.precond, stream_split=args.split,
-                               precision=args.precision, hilo_lags=args.hilo, mix_group=args.mix_group)
-    t = time.perf_counter()
-    s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
-                   prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
-                   stream=torch.cuda.current_stream().cuda_stream)
-    s.load_raw(prob["raw"], prob["kmax"])
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t
-    inf0 = s.info()
-    log("device setup %.2f s (preconditioner %.0f ms, fold %.0f ms), %d lags, %.2f GB on device"
-        % (t_setup, inf0["setup_ms"], inf0["fold_ms"], inf0["nlags"], inf0["device_bytes"] / 1e9))
-
-    # warm-up steps (their outputs are also the parity sample)
-    warm = s.run(W_, w=True, loop=True, star=True, device=False)
-    torch.cuda.synchronize()
-    a = s.info()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = s.run(K, w=True, loop=True, star=True, device=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    b = s.info()
-    el = t1 - t0
-    steps_s = K / el
-    ne, n = s.ne, s.n
-    R = s.nrhs
-    L = b["nlags"]
-    qb = 4 if args.precision == 1 else 8
-    iters = (b["gmres_iters_total"] - a["gmres_iters_total"]) / K
-    # algorithmic bytes (FP64): the Q_0 product reads q1, qk, q2 (3 ne^2) and the
-    # input vector, writes n; the history kernel reads the (L-1) 3 ne^2 entries
-    # of Q_1..Q_{L-1}, the L-1 history vectors and r_k, writes n.
-    q0_bytes = 8.0 * (3 * ne * ne + 2 * n * R)
-    hist_bytes = qb * (L - 1) * 3 * ne * ne + 8.0 * ((L - 1) * n * R + 2 * n * R)
-    q0_ms = (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
-    hist_ms = (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
-    q0_tot = b["q0_ms"] - a["q0_ms"]
-    hist_tot = b["hist_ms"] - a["hist_ms"]
-    q0_gbs = q0_bytes / (q0_ms * 1e-3) / 1e9
-    hist_gbs = hist_bytes / (hist_ms * 1e-3) / 1e9
-    if q0_tot >= hist_tot:
-        dom = dict(kernel="k_q0_matvec (GMRES Q_0 product)", bytes=q0_bytes, ms=q0_ms, gbs=q0_gbs)
-    else:
-        dom = dict(kernel="k_history (history convolution)", bytes=hist_bytes, ms=hist_ms, gbs=hist_gbs)
-    log("timed %d steps in %.3f s: %.1f steps/s, %.2f GMRES its/step; Q0 product %.1f us (%.0f GB/s), "
-        "history %.1f us (%.0f GB/s); recovery %.1f ms"
-        % (K, el, steps_s, iters, q0_ms * 1e3, q0_gbs, hist_ms * 1e3, hist_gbs, b["recover_ms"]))
-
-    prec = "fp64" if args.precision == 0 else "mixed fp32-mfma history"
+    m = measure(mot, prob, args.workload, args.precision, K, W_, args.precond, args.split, args.hilo,
+                args.mix_group)
+    R = m["R"]
     result = {
         "metric": "MOT steps/s (%s, %d RHS)" % ("plain FP64" if args.precision == 0 else "mixed precision", R),
-        "value": round(steps_s, 3),
+        "value": round(m["steps_s"], 3),
         "unit": "steps/s",
-        "rhs_steps_per_s": round(steps_s * R, 2),
+        "rhs_steps_per_s": round(m["steps_s"] * R, 2),
         "n_gpus": 1,
         "steps": K,
         "warmup": W_,
-        "ms_per_step": round(1e3 * el / K, 4),
+        "ms_per_step": round(1e3 * m["el"] / K, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f32 storage, f64 arithmetic" if args.precision == 1 else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "nrhs": R,
-                   "unknowns": n, "lags": L, "kmax": b["kmax"], "precision": prec,
+                   "unknowns": m["n"], "lags": m["L"], "kmax": m["kmax"], "precision": PRECISION[args.precision],
                    "q0_preconditioner": ["none", "fp32 approximate inverse", "fp64 approximate inverse"][args.precond]},
-        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": dom["bytes"], "avg_launch_us": round(dom["ms"] * 1e3, 2)},
-        "history_kernel": {"achieved_gbs": round(hist_gbs, 1), "avg_launch_us": round(hist_ms * 1e3, 2),
-                           "bytes_per_launch": hist_bytes},
-        "q0_product": {"achieved_gbs": round(q0_gbs, 1), "avg_launch_us": round(q0_ms * 1e3, 2),
-                       "bytes_per_launch": q0_bytes, "launches_per_step": round((b["q0_launches"] - a["q0_launches"]) / K, 2)},
-        "gmres_iters_per_step": round(iters, 2),
-        "setup_s": round(t_setup, 3),
+        "roofline": m["dominant"],
+        "history_kernel": m["hist"],
+        "q0_product": dict(m["q0"], launches_per_step=round(m["q0_launches"], 2)),
+        "gmres_iters_per_step": round(m["iters"], 2),
+        "setup_s": round(m["setup_s"], 3),
         "fixture_s": round(t_fixture, 1),
+        "device_gb": round(m["device_gb"], 2),
     }
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.cpu_budget, min(W_, 400))
         ns = cb["steps"]
+        warm = m["warm"]
         e_w = float(np.linalg.norm(warm["w"][:ns] - cb["W"]) / np.linalg.norm(cb["W"]))
         e_l = float(np.linalg.norm(warm["loop"][:ns] - cb["loop"]) / np.linalg.norm(cb["loop"]))
         e_s = float(np.linalg.norm(warm["star"][:ns] - cb["star"]) / max(np.linalg.norm(cb["star"]), 1e-300))
@@ -191,7 +276,44 @@ def main():
                                             "recovery), oracle setup %.1f s not timed" % (ns, cb["prep_s"])}
         result["err_vs_oracle"] = {"steps": ns, "w": e_w, "loop": e_l, "star": e_s}
         log("oracle: %d steps in %.1f s; GPU vs oracle: w %.2e loop %.2e star %.2e" % (ns, cb["seconds"], e_w, e_l, e_s))
-    s.close()
+
+    if not args.no_batched:
+        name = "sphere_1920_r16"
+        Kb, Wb = args.batched_steps, 300
+        t = time.perf_counter()
+        pb = build_problem(name, nsteps=Wb + Kb, verbose=True)
+        log("batched inputs assembled on the host in %.1f s" % (time.perf_counter() - t))
+        one = dict(pb, waves=pb["waves"][:1])
+        r1 = measure(mot, one, name, 0, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
+        r16 = measure(mot, pb, name, 0, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
+        rmx = measure(mot, pb, name, 1, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+        err = {k: rel(rmx["warm"][k], r16["warm"][k]) for k in ("w", "loop", "star")}
+        nrm = np.linalg.norm(rmx["warm"]["w"].reshape(Wb, -1), axis=1)
+        tail = np.log10(nrm[-Wb // 4:] + 1e-300)
+        growth = float(np.polyfit(np.arange(tail.size), tail, 1)[0])
+
+        def brief(r):
+            return {"steps_s": round(r["steps_s"], 2), "rhs_steps_per_s": round(r["steps_s"] * r["R"], 1),
+                    "ms_per_step": round(1e3 * r["el"] / r["K"], 4), "gmres_iters_per_step": round(r["iters"], 2),
+                    "history_kernel": r["hist"], "device_gb": round(r["device_gb"], 2)}
+
+        result["batched"] = {
+            "workload": name + ": " + WORKLOADS[name],
+            "steps": Kb, "warmup": Wb,
+            "fp64_1rhs": brief(r1),
+            "fp64_16rhs": brief(r16),
+            "mixed_16rhs": dict(brief(rmx), precision=PRECISION[1], hilo_lags=args.hilo,
+                                err_vs_fp64_16rhs={"steps": Wb, **err},
+                                late_log10_growth_per_step=growth),
+            "mixed_vs_fp64_1rhs_steps_ratio": round(rmx["steps_s"] / r1["steps_s"], 3),
+            "mixed_vs_fp64_1rhs_rhs_steps_ratio": round(rmx["steps_s"] * rmx["R"] / r1["steps_s"], 2),
+        }
+        log("batched: FP64 1 RHS %.1f steps/s; FP64 16 RHS %.1f; mixed 16 RHS %.1f (err w %.2e star %.2e vs FP64)"
+            % (r1["steps_s"], r16["steps_s"], rmx["steps_s"], err["w"], err["star"]))
     print(json.dumps(result), flush=True)
 
 

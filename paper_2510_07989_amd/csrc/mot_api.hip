@@ -35,8 +35,10 @@ void pack(mot_handle* h, int ns, const double* src, double* dst);
 
 namespace motk_multi {
 size_t part_doubles(const mot_handle* h);
-void history(mot_handle* h);
-void q0_product(mot_handle* h, const double* X, double* out);
+void history_gemm(mot_handle* h);
+void history_reduce(mot_handle* h);
+void q0_gemm(mot_handle* h, const double* X);
+void q0_reduce(mot_handle* h, double* out);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero);
 void orth(mot_handle* h, double* w);
@@ -564,8 +566,9 @@ int gmres_solve_mr(mot_handle* h) {
             double* zj = h->Z + (size_t)j * vs;
             mm::precond(h, src, vj, zj);
             if ((prc = ev_begin(h, h->ev_q0))) return prc;
-            mm::q0_product(h, zj, dst);
+            mm::q0_gemm(h, zj);
             if ((prc = ev_end(h, h->ev_q0))) return prc;
+            mm::q0_reduce(h, dst);
             mm::orth(h, dst);
             if (j == 0 && first_cycle) mm::finish(h, 0);
             std::swap(src, dst);
@@ -585,8 +588,9 @@ int gmres_solve_mr(mot_handle* h) {
         }
         first_cycle = false;
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
-        mm::q0_product(h, h->x, h->wA);
+        mm::q0_gemm(h, h->x);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
+        mm::q0_reduce(h, h->wA);
         mm::start(h, h->y, h->wA, 1, 0, nullptr);
         seq += 1;
         if ((prc = wait_flag(h, seq))) return prc;
@@ -1062,11 +1066,14 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     inc_step(h);
     h->k += 1;
     if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
+    if (h->Rp > 1 && (!h->gms || !h->mr_part)) return mot_fail(h, MOT_ESTATE, "multi-RHS buffers missing");
+    // the events bracket the streaming kernel alone (the multi-RHS partial
+    // reduction follows it)
     int prc = ev_begin(h, h->ev_hist);
     if (prc) return prc;
-    if (h->Rp > 1 && (!h->gms || !h->mr_part)) return mot_fail(h, MOT_ESTATE, "multi-RHS buffers missing");
-    if (h->Rp > 1) motk_multi::history(h); else history(h);
+    if (h->Rp > 1) motk_multi::history_gemm(h); else history(h);
     if ((prc = ev_end(h, h->ev_hist))) return prc;
+    if (h->Rp > 1) motk_multi::history_reduce(h);
     int rc;
     if (h->Rp > 1) {
         if (!h->gms || !h->mr_part) return mot_fail(h, MOT_ESTATE, "multi-RHS buffers missing");

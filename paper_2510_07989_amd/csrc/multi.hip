@@ -730,7 +730,7 @@ static void reduce(mot_handle* h, int q0_mode, int KC, double* out) {
 #undef C_
 }
 
-void history(mot_handle* h) {
+void history_gemm(mot_handle* h) {
     const int KC = h->hist_kc;
     if (h->opt.precision == MOT_MIXED32) {
         dim3 grid((h->G16 + 3) / 4, h->nh, KC);
@@ -760,8 +760,9 @@ void history(mot_handle* h) {
     } else {
         tile_launch<double>(h, 0, h->Qt + 3 * tile_elems(h), nullptr, nullptr, KC, h->nh);
     }
-    reduce(h, 0, KC, h->y);
 }
+
+void history_reduce(mot_handle* h) { reduce(h, 0, h->hist_kc, h->y); }
 
 // After the fold of one lag: its tiles (FP64 for lag 0 and the plain path,
 // FP32 hi and, on lags 1..hilo, lo for the mixed paths).
@@ -783,10 +784,9 @@ void pack_lag(mot_handle* h, int lag) {
     }
 }
 
-void q0_product(mot_handle* h, const double* X, double* out) {
-    tile_launch<double>(h, 1, h->Qt, nullptr, X, h->q0_kc, 1);
-    reduce(h, 1, h->q0_kc, out);
-}
+void q0_gemm(mot_handle* h, const double* X) { tile_launch<double>(h, 1, h->Qt, nullptr, X, h->q0_kc, 1); }
+
+void q0_reduce(mot_handle* h, double* out) { reduce(h, 1, h->q0_kc, out); }
 
 void precond(mot_handle* h, const double* src, double* vj, double* z) {
 #define C_(R_) plain_product<R_>(h, src, vj, z)
