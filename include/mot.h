@@ -109,7 +109,11 @@ typedef struct {
     int32_t mix_group;       /* MOT_MIXED32: summation indices per half that one
                                 FP32 MFMA accumulator sums before it is added
                                 into the FP64 total: 4 (default), 16 or 64    */
-    int32_t reserved[2];
+    int32_t spec_window;     /* mot_run with one RHS and a preconditioner:
+                                steps queued per host check of the device halt
+                                word (0: one RHS batch, 128; -1: wait for every
+                                step's GMRES on the host)                     */
+    int32_t reserved[1];
 } mot_options;
 
 typedef struct {
@@ -138,6 +142,7 @@ typedef struct {
     double recover_ms;       /* wall time of the last recovery (host clock)  */
     int32_t precond_iters;   /* Newton-Schulz iterations of the preconditioner */
     double precond_resid;    /* ||I - M Q_0||_F of the stored preconditioner  */
+    uint64_t peak_bytes;     /* high-water mark of device_bytes so far        */
 } mot_info;
 
 typedef struct mot_handle mot_handle;
@@ -203,6 +208,21 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out,
 int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out);
 
 int mot_get_info(const mot_handle* h, mot_info* info);
+
+/* Device memory a solve will need, before creating it: for admission by memory
+ * footprint when several solves share one GPU.  The arguments are those of
+ * mot_create (gram_nnz: nonzeros of G); nothing is allocated.
+ *   resident_bytes: held from the end of setup until mot_destroy (lag
+ *                   matrices Q_0..Q_{k_max+1} of Section V-B, projectors and
+ *                   factors of Sections III-IV, ring and kept history of the
+ *                   march of eq. (MOT), Krylov space, preconditioner);
+ *   peak_bytes:     resident plus the largest transient phase (setup solves,
+ *                   one lag staged for its fold, recovery batches).
+ * Both match what mot_create and mot_run allocate under the same options.
+ * MOT_EINVAL on a bad argument. */
+int mot_footprint(const mot_mesh* mesh, double eps_r, double mu_r, double dt, int32_t nrhs,
+                  int64_t gram_nnz, const mot_options* opt, uint64_t* resident_bytes,
+                  uint64_t* peak_bytes);
 
 /* Restart the march at step 0 (keeps every operator). */
 int mot_reset(mot_handle* h);

@@ -29,7 +29,8 @@ class MotOptions(ctypes.Structure):
                 ("cg_tol", _D), ("cg_maxit", _I), ("diameter", _D), ("keep_history", _I),
                 ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
                 ("precond", _I), ("stream_split", _I), ("history_order", _I),
-                ("hilo_lags", _I), ("mix_group", _I), ("reserved", _I * 2)]
+                ("hilo_lags", _I), ("mix_group", _I), ("spec_window", _I),
+                ("reserved", _I * 1)]
 
 
 class MotStepInfo(ctypes.Structure):
@@ -42,12 +43,12 @@ class MotInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64), ("setup_ms", _D), ("fold_ms", _D),
                 ("gmres_iters_total", ctypes.c_int64), ("hist_ms", _D), ("hist_launches", ctypes.c_int64),
                 ("q0_ms", _D), ("q0_launches", ctypes.c_int64), ("recover_ms", _D),
-                ("precond_iters", _I), ("precond_resid", _D)]
+                ("precond_iters", _I), ("precond_resid", _D), ("peak_bytes", ctypes.c_uint64)]
 
 
 EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr", "mot_step",
            "mot_run", "mot_get_matrix", "mot_get_info", "mot_reset", "mot_destroy",
-           "mot_last_error"]
+           "mot_last_error", "mot_footprint"]
 
 _lib = None
 
@@ -60,6 +61,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libmot.so is not built (run __graft_entry__.build() or "
                            "python paper_2510_07989_amd/build.py)")
+    # PyTorch ships its own HIP runtime with the same soname as the system one.
+    # Loading torch first makes libmot bind to that runtime, so the process has
+    # one HIP runtime and torch's streams and device tensors are valid handles
+    # for the library (loaded the other way round, two runtimes would coexist).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     lib.mot_default_options.argtypes = [ctypes.POINTER(MotOptions)]
     lib.mot_default_options.restype = None
@@ -85,5 +91,9 @@ def load():
     lib.mot_destroy.restype = None
     lib.mot_last_error.argtypes = [_P]
     lib.mot_last_error.restype = ctypes.c_char_p
+    lib.mot_footprint.argtypes = [ctypes.POINTER(MotMesh), _D, _D, _D, _I, ctypes.c_int64,
+                                  ctypes.POINTER(MotOptions), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    lib.mot_footprint.restype = _I
     _lib = lib
     return lib

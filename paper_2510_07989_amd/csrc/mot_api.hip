@@ -13,7 +13,7 @@ void rhs_batch(mot_handle* h, int k0, double* rb);
 void history(mot_handle* h);
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero);
 void gm_orth1(mot_handle* h, double* w);
-void gm_finish(mot_handle* h, const double* basis, int force);
+void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void dense_q0(mot_handle* h, double* D);
@@ -28,6 +28,7 @@ void gm_update_x(mot_handle* h, const double* basis, double* x);
 void warm_start(mot_handle* h);
 void push(mot_handle* h);
 void inc_step(mot_handle* h);
+void clear_halt(mot_handle* h);
 void rec_gather(mot_handle* h, int s0, int ns, double* X);
 void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, double* loop, double* star);
 void pack(mot_handle* h, int ns, const double* src, double* dst);
@@ -48,7 +49,7 @@ size_t tile_elems(const mot_handle* h);
 void pack_lag(mot_handle* h, int lag);
 }  // namespace motk_multi
 
-static std::string g_create_err;
+static thread_local std::string g_create_err;   // create errors, per host thread
 
 int mot_fail(mot_handle* h, int code, const std::string& msg) {
     if (h) h->err = msg; else g_create_err = msg;
@@ -68,6 +69,9 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Device memory comes from the stream-ordered pool on the handle's stream: a
+// free does not synchronise the device, so solves sharing one GPU keep running
+// while another sets up, recovers or is destroyed.
 template <class T>
 int dalloc(mot_handle* h, T** p, size_t count, bool zero = true) {
     size_t bytes = count * sizeof(T);
@@ -75,15 +79,16 @@ int dalloc(mot_handle* h, T** p, size_t count, bool zero = true) {
     if (h->opt.mem_cap_bytes && h->bytes + bytes > h->opt.mem_cap_bytes)
         return mot_fail(h, MOT_ENOMEM, "device memory cap exceeded");
     void* q = nullptr;
-    if (hipMalloc(&q, bytes) != hipSuccess) {
+    if (hipMallocAsync(&q, bytes, h->stream) != hipSuccess) {
         (void)hipGetLastError();
-        return mot_fail(h, MOT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return mot_fail(h, MOT_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
     if (zero && hipMemsetAsync(q, 0, bytes, h->stream) != hipSuccess)
         return mot_fail(h, MOT_EHIP, "hipMemsetAsync failed");
     h->allocs.push_back(q);
     h->sizes.push_back(bytes);
     h->bytes += bytes;
+    h->peak_bytes = std::max(h->peak_bytes, h->bytes);
     *p = static_cast<T*>(q);
     return MOT_OK;
 }
@@ -97,7 +102,7 @@ void dfree(mot_handle* h, void* p) {
         h->allocs.erase(it);
         h->sizes.erase(h->sizes.begin() + i);
     }
-    (void)hipFree(p);
+    (void)hipFreeAsync(p, h->stream);
 }
 
 template <class T>
@@ -708,6 +713,93 @@ int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
     return worst;
 }
 
+// Every size-determining field of a handle, from the mesh, media, dt, nrhs and
+// options alone (mot_create and mot_footprint share it).
+void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V, double eps_r, double mu_r,
+               double dt) {
+    if (h->opt.gmres_restart < 2 || h->opt.gmres_restart > MOT_MAXM) h->opt.gmres_restart = 40;
+    if (h->opt.precond < 0 || h->opt.precond > 2) h->opt.precond = 1;
+    h->M = h->opt.gmres_restart;
+    if (h->opt.gmres_maxit <= 0) h->opt.gmres_maxit = 400;
+    if (h->opt.cg_maxit <= 0) h->opt.cg_maxit = 20000;
+    if (!(h->opt.cg_tol > 0)) h->opt.cg_tol = 1e-13;
+    if (!(h->opt.gmres_tol > 0)) h->opt.gmres_tol = 1e-13;
+    h->nv = nv; h->nf = nf; h->ne = ne; h->R = nrhs;
+    h->Rp = 1;
+    if (nrhs > 1) { h->Rp = 4; while (h->Rp < nrhs) h->Rp *= 2; }
+    h->B = std::max(8, std::min(128, 4096 / h->Rp));
+    h->hs = (ne + 7) & ~7;
+    h->n2 = 2 * h->hs;
+    {
+        int sp = h->opt.stream_split;
+        if (sp != 1 && sp != 2 && sp != 4) sp = 1;
+        h->wpr = sp;
+        h->hist_variant = h->opt.history_order == 2 ? 0 : 1;
+    }
+    h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
+    h->c = 1.0; h->eta = 1.0;
+    h->cp = 1.0 / std::sqrt(eps_r * mu_r);
+    h->etap = std::sqrt(mu_r / eps_r);
+    // D, T_max, k_max (eq. alpha; Section V-B)
+    double D = h->opt.diameter;
+    if (!(D > 0)) {
+        D = 0;
+        for (int a = 0; a < nv; ++a)
+            for (int b = a + 1; b < nv; ++b) {
+                double dx = V[3 * a] - V[3 * b], dy = V[3 * a + 1] - V[3 * b + 1], dz = V[3 * a + 2] - V[3 * b + 2];
+                D = std::max(D, dx * dx + dy * dy + dz * dz);
+            }
+        D = std::sqrt(D);
+    }
+    h->D = D;
+    h->Tmax = D / std::min(h->c, h->cp);
+    h->kmax = (int)std::ceil(h->Tmax / dt - 1e-12);
+    h->nlags = h->kmax + 2;
+    h->nh = h->nlags - 1;
+    h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
+    if (h->opt.precision != MOT_FP64) h->hilo = h->opt.hilo_lags < 0 ? 0 : std::min(h->opt.hilo_lags, h->nh);
+    if (h->Rp > 1) motk_multi::plan_tiles(h);
+}
+
+// Device bytes of a planned handle: the allocations that live from create to
+// destroy (resident), and resident plus the largest transient phase (peak):
+// projector and Gram solves, the static products, one lag staged for its fold,
+// the Newton-Schulz build, and recovery batches.  Mirrors mot_create, the
+// fold, build_precond and recover.
+void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* peak) {
+    const double ne = h->ne, nf = h->nf, nv = h->nv, hs = h->hs, R = h->R;
+    const double blk = ne * hs;
+    const double n2r = (double)h->n2 * h->Rp, NB = (double)h->B * h->Rp, M = h->M;
+    double b = 0;
+    for (double nn : {nf, nv}) b += 4.0 * (ne + ne + (nn + 1) + 2 * ne + (nn + 1) + 2 * ne) + 8.0 * 2 * ne;  // graphs
+    b += 2 * (4.0 * (ne + 1) + 4.0 * gnnz + 8.0 * gnnz);                          // G, G^T (CSR)
+    b += 8.0 * (2 * ne * 42 + 9 * R + R);                                         // RHS quadrature, waves
+    b += 8.0 * 5 * blk;                                                           // PS, BL, G^-1, C1, C2
+    b += 8.0 * ((double)h->nlags * 3 + 4) * blk;                                  // Q, fold scratch, raw block
+    b += 4.0 + 8.0 * (h->nh * n2r + 4 * hs * NB + 4 * ne * NB + 4 * n2r + 2 * (M + 1) * n2r) + sizeof(GmState);
+    if (h->Rp > 1) {
+        const double t3 = 3.0 * motk_multi::tile_elems(h);
+        if (h->opt.precision == MOT_FP64) b += 8.0 * h->nlags * t3;
+        else b += 8.0 * t3 + 4.0 * h->nh * t3 + 4.0 * h->hilo * t3;
+        b += (double)sizeof(GmState) * h->Rp + 8.0 * motk_multi::part_doubles(h);
+    }
+    b += 8.0 * h->hist_cap * n2r;                                                 // kept history
+    const double nn2 = (double)h->n2 * h->n2;
+    if (h->opt.precond) b += (h->opt.precond == 2 ? 8.0 : 4.0) * nn2;            // approximate inverse
+    const double chunk = std::min(ne, 4096.0);
+    const double cgx = MOT_CG_CHUNKS + 8;                                         // per-column CG scalars
+    double t = 0;
+    t = std::max(t, 8.0 * ((2 * ne + 5 * std::max(nf, nv)) * chunk + cgx * chunk)); // projectors
+    t = std::max(t, 8.0 * (6 * ne * chunk + cgx * chunk));                         // G^-1
+    t = std::max(t, 8.0 * 3 * blk);                                                 // C1, C2
+    t = std::max(t, 8.0 * 9 * blk);                                                 // one lag staged
+    if (h->opt.precond) t = std::max(t, 8.0 * 4 * nn2 + 16.0 * h->n2);              // Newton-Schulz
+    const double per = 4 * R, bs = std::max(1.0, std::floor(8192 / per)), nc = bs * per;
+    t = std::max(t, 8.0 * ((2 * ne + 5 * nf) * nc + cgx * nc));                     // recovery batch
+    *resident = (uint64_t)b;
+    *peak = (uint64_t)(b + t);
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -731,6 +823,19 @@ void mot_default_options(mot_options* o) {
     o->mix_group = 4;
 }
 
+int mot_footprint(const mot_mesh* mesh, double eps_r, double mu_r, double dt, int32_t nrhs, int64_t gram_nnz,
+                  const mot_options* opt, uint64_t* resident_bytes, uint64_t* peak_bytes) {
+    if (!mesh || !mesh->verts || !resident_bytes || !peak_bytes) return mot_fail(nullptr, MOT_EINVAL, "null argument");
+    if (mesh->nv <= 0 || mesh->nf <= 0 || mesh->ne <= 0 || nrhs < 1 || nrhs > 64 || gram_nnz < 0)
+        return mot_fail(nullptr, MOT_EINVAL, "bad sizes");
+    if (!(dt > 0) || !(eps_r > 0) || !(mu_r > 0)) return mot_fail(nullptr, MOT_EINVAL, "dt, eps_r and mu_r must be > 0");
+    mot_handle h;
+    if (opt) h.opt = *opt; else mot_default_options(&h.opt);
+    plan_dims(&h, mesh->nv, mesh->nf, mesh->ne, nrhs, mesh->verts, eps_r, mu_r, dt);
+    footprint(&h, gram_nnz, resident_bytes, peak_bytes);
+    return MOT_OK;
+}
+
 const char* mot_last_error(const mot_handle* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 void mot_destroy(mot_handle* h) {
@@ -738,7 +843,8 @@ void mot_destroy(mot_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     ev_destroy(h->ev_hist);
     ev_destroy(h->ev_q0);
-    for (void* p : h->allocs) (void)hipFree(p);
+    for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
+    (void)hipStreamSynchronize(h->stream);
     if (h->hflag) (void)hipHostFree(h->hflag);
     delete h;
 }
@@ -807,48 +913,9 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
 
     mot_handle* h = new mot_handle();
     if (opt) h->opt = *opt; else mot_default_options(&h->opt);
-    if (h->opt.gmres_restart < 2 || h->opt.gmres_restart > MOT_MAXM) h->opt.gmres_restart = 40;
-    if (h->opt.precond < 0 || h->opt.precond > 2) h->opt.precond = 1;
-    h->M = h->opt.gmres_restart;
-    if (h->opt.gmres_maxit <= 0) h->opt.gmres_maxit = 400;
-    if (h->opt.cg_maxit <= 0) h->opt.cg_maxit = 20000;
-    if (!(h->opt.cg_tol > 0)) h->opt.cg_tol = 1e-13;
-    if (!(h->opt.gmres_tol > 0)) h->opt.gmres_tol = 1e-13;
+    plan_dims(h, nv, nf, ne, nrhs, mesh->verts, eps_r, mu_r, dt);
     h->stream = (hipStream_t)stream;
-    h->nv = nv; h->nf = nf; h->ne = ne; h->R = nrhs;
-    h->Rp = 1;
-    if (nrhs > 1) { h->Rp = 4; while (h->Rp < nrhs) h->Rp *= 2; }
-    h->B = std::max(8, std::min(128, 4096 / h->Rp));
-    h->hs = (ne + 7) & ~7;
-    h->n2 = 2 * h->hs;
-    {
-        int sp = h->opt.stream_split;
-        if (sp != 1 && sp != 2 && sp != 4) sp = 1;
-        h->wpr = sp;
-        h->hist_variant = h->opt.history_order == 2 ? 0 : 1;
-    }
     h->genus = (2 - chi) / 2;
-    h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
-    h->c = 1.0; h->eta = 1.0;
-    h->cp = 1.0 / std::sqrt(eps_r * mu_r);
-    h->etap = std::sqrt(mu_r / eps_r);
-    // D, T_max, k_max (eq. alpha; Section V-B)
-    double D = h->opt.diameter;
-    if (!(D > 0)) {
-        D = 0;
-        const double* V = mesh->verts;
-        for (int a = 0; a < nv; ++a)
-            for (int b = a + 1; b < nv; ++b) {
-                double dx = V[3 * a] - V[3 * b], dy = V[3 * a + 1] - V[3 * b + 1], dz = V[3 * a + 2] - V[3 * b + 2];
-                D = std::max(D, dx * dx + dy * dy + dz * dz);
-            }
-        D = std::sqrt(D);
-    }
-    h->D = D;
-    h->Tmax = D / std::min(h->c, h->cp);
-    h->kmax = (int)std::ceil(h->Tmax / dt - 1e-12);
-    h->nlags = h->kmax + 2;
-    h->nh = h->nlags - 1;
     double t_start = now_ms();
     int rc = MOT_OK;
     auto bail = [&](int code) { g_create_err = h->err; mot_destroy(h); return code; };
@@ -971,21 +1038,18 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     // every march vector holds all Rp columns: [n2][Rp]
     const size_t n2 = (size_t)h->n2 * h->Rp;
     const size_t NB = (size_t)h->B * h->Rp;
-    h->hist_cap = h->opt.keep_history ? (h->opt.max_steps > 0 ? h->opt.max_steps : 20000) : 0;
     if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
         (rc = dalloc(h, &h->ebar, (size_t)2 * h->hs * NB)) || (rc = dalloc(h, &h->Ebar, (size_t)2 * h->hs * NB)) ||
-        (rc = dalloc(h, &h->rb, (size_t)2 * h->ne * NB)) || (rc = dalloc(h, &h->y, n2)) ||
+        (rc = dalloc(h, &h->rb, (size_t)4 * h->ne * NB)) || (rc = dalloc(h, &h->y, n2)) ||
         (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
         (rc = dalloc(h, &h->wA, n2)) || (rc = dalloc(h, &h->wB, n2)) || (rc = dalloc(h, &h->gm, 1)))
         return bail(rc);
     if (h->Rp > 1) {
         // tile-major copies of the lags for the multi-RHS products
-        motk_multi::plan_tiles(h);
         const size_t tsz3 = 3 * motk_multi::tile_elems(h);
         if (h->opt.precision == MOT_FP64) {
             if ((rc = dalloc(h, &h->Qt, (size_t)h->nlags * tsz3))) return bail(rc);
         } else {
-            h->hilo = h->opt.hilo_lags < 0 ? 0 : std::min(h->opt.hilo_lags, h->nh);
             if ((rc = dalloc(h, &h->Qt, tsz3)) || (rc = dalloc(h, &h->QtF, (size_t)h->nh * tsz3)) ||
                 (h->hilo && (rc = dalloc(h, &h->QtL, (size_t)h->hilo * tsz3))))
                 return bail(rc);
@@ -1055,6 +1119,7 @@ int mot_reset(mot_handle* h) {
     h->ev_hist.n = h->ev_q0.n = 0;
     HIPCHK(h, hipMemsetAsync(h->d_k, 0, sizeof(int), h->stream));
     HIPCHK(h, hipMemsetAsync(h->ring, 0, (size_t)h->nh * h->n2 * h->Rp * sizeof(double), h->stream));
+    motk_step::clear_halt(h);
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MOT_OK;
 }
@@ -1099,6 +1164,105 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     return rc;
 }
 
+// Speculative stepping (one RHS, preconditioned GMRES): steps are queued back
+// to back with no host wait.  Each runs a fixed number of Arnoldi steps (one
+// with the FP64 approximate inverse) and a finisher that pushes w_k only if the
+// solve converged; otherwise it raises the halt word, which turns every later
+// queued step kernel into a no-op.  The host reads the halt word once per
+// window (at most one RHS batch long, so a batch computed ahead for a later
+// window never overwrites the one a halted step needs) and finishes a halted
+// step with the host-driven solve, then queues again from the next step.
+struct SpecWord { int halt, halt_k, iters_all; };
+
+static bool spec_ok(const mot_handle* h) {
+    return h->opt.spec_window >= 0 && h->Rp == 1 && (h->M32 || h->M64) && h->n2 <= 32768;
+}
+
+static int queue_spec_step(mot_handle* h) {
+    using namespace motk_step;
+    inc_step(h);
+    h->k += 1;
+    if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
+    int prc;
+    if ((prc = ev_begin(h, h->ev_hist))) return prc;
+    history(h);
+    if ((prc = ev_end(h, h->ev_hist))) return prc;
+    if (h->M32) {
+        warm_start(h);
+        if ((prc = ev_begin(h, h->ev_q0))) return prc;
+        q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
+        gm_start1(h, h->y, h->wA, 1, 1, nullptr);
+    } else {
+        gm_start1(h, h->y, h->wA, 0, 1, h->x);
+    }
+    double* src = h->wA;
+    double* dst = h->wB;
+    for (int j = 0; j < h->spec_iters; ++j) {
+        precond(h, src, h->V + (size_t)j * h->n2, h->Z + (size_t)j * h->n2);
+        if ((prc = ev_begin(h, h->ev_q0))) return prc;
+        q0_matvec(h, h->Z + (size_t)j * h->n2, nullptr, dst, 1, 0);
+        if ((prc = ev_end(h, h->ev_q0))) return prc;
+        gm_orth1(h, dst);
+        std::swap(src, dst);
+    }
+    gm_finish(h, h->Z, 0, 1);
+    return MOT_OK;
+}
+
+static int read_spec(mot_handle* h, SpecWord* w) {
+    HIPCHK(h, hipMemcpyAsync(w, &h->gm->halt, sizeof(SpecWord), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MOT_OK;
+}
+
+static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
+    const int win = std::max(1, std::min(h->opt.spec_window > 0 ? h->opt.spec_window : h->B, h->B));
+    SpecWord w0{};
+    int rc = read_spec(h, &w0);
+    if (rc) return rc;
+    int done = 0;
+    while (done < nsteps) {
+        const int nw = std::min(win, nsteps - done);
+        const int k0 = h->k;
+        for (int i = 0; i < nw; ++i)
+            if ((rc = queue_spec_step(h))) return rc;
+        HIPCHK(h, hipGetLastError());
+        SpecWord w{};
+        if ((rc = read_spec(h, &w))) return rc;
+        h->iters_total += w.iters_all - w0.iters_all;
+        w0 = w;
+        if (!w.halt) {
+            done += nw;
+            h->last_iters = h->spec_iters;
+            h->last_relres = h->hflag->relres;
+            h->last_conv = 1;
+            continue;
+        }
+        // steps k0+1 .. halt_k-1 are complete; halt_k has its history in y
+        if (w.halt_k <= k0 || w.halt_k > h->k) return mot_fail(h, MOT_EHIP, "speculative halt word out of range");
+        h->k = w.halt_k;
+        motk_step::clear_halt(h);
+        int src = gmres_solve_pc(h);
+        if (src && src != MOT_ENOCONV) return src;
+        if (src) *worst = src;
+        if ((rc = read_spec(h, &w0))) return rc;
+        h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
+        done += w.halt_k - k0;
+    }
+    return MOT_OK;
+}
+
+// an error return never leaves the halt word raised behind it
+static int run_spec(mot_handle* h, int nsteps, int* worst) {
+    int rc = run_spec_windows(h, nsteps, worst);
+    if (rc) {
+        motk_step::clear_halt(h);
+        (void)hipStreamSynchronize(h->stream);
+    }
+    return rc;
+}
+
 int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, double* star_out,
             int32_t out_on_device, mot_step_info* last) {
     if (!h) return MOT_EINVAL;
@@ -1108,10 +1272,20 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
     int s0 = h->k;
     int worst = MOT_OK;
     mot_step_info inf{};
-    for (int i = 0; i < nsteps; ++i) {
-        int rc = mot_step(h, &inf);
-        if (rc && rc != MOT_ENOCONV) return rc;
-        if (rc) worst = rc;
+    if (nsteps > 0 && spec_ok(h)) {
+        if (!all_folded(h)) return mot_fail(h, MOT_ESTATE, "lag matrices missing: upload every block first");
+        int rc = run_spec(h, nsteps, &worst);
+        if (rc) return rc;
+        inf.step = h->k;
+        inf.gmres_iters = h->last_iters;
+        inf.gmres_relres = h->last_relres;
+        inf.converged = h->last_conv;
+    } else {
+        for (int i = 0; i < nsteps; ++i) {
+            int rc = mot_step(h, &inf);
+            if (rc && rc != MOT_ENOCONV) return rc;
+            if (rc) worst = rc;
+        }
     }
     if (last) *last = inf;
     if (!(w_out || loop_out || star_out) || nsteps == 0) {
@@ -1217,6 +1391,7 @@ int mot_get_info(const mot_handle* hc, mot_info* info) {
     info->folded = all_folded(h) ? 1 : 0;
     info->steps_done = h->k;
     info->device_bytes = h->bytes;
+    info->peak_bytes = h->peak_bytes;
     info->setup_ms = h->setup_ms;
     info->fold_ms = h->fold_ms;
     info->gmres_iters_total = h->iters_total;

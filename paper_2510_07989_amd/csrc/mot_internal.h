@@ -42,6 +42,10 @@ struct GmState {
     int j, done, converged, total, cycle_iters, breakdown;
     unsigned int counter;
     int seq;                                // progress words published so far
+    // speculative stepping: a finisher whose solve did not converge sets halt
+    // (and the step in halt_k); every step kernel returns at entry while it is
+    // set.  iters_all counts Arnoldi steps over the whole run.
+    int halt, halt_k, iters_all;
     double partial[(MOT_MAXM + 1) * MOT_GM_BLOCKS];
 };
 
@@ -102,6 +106,7 @@ struct mot_handle {
     int kmax = 0, nlags = 0, nh = 0, genus = 0;
     double setup_ms = 0, fold_ms = 0;
     uint64_t bytes = 0;
+    uint64_t peak_bytes = 0;         // high-water mark of bytes
     std::vector<void*> allocs;
     std::vector<size_t> sizes;
 
@@ -155,6 +160,7 @@ struct mot_handle {
     float* QtF = nullptr;            // FP32 tiles of lags 1..nh (mixed paths)
     float* QtL = nullptr;            // FP32 low parts fl(Q - fl(Q)) of lags 1..hilo
     int hilo = 0;                    // lags with a low part
+    int spec_iters = 1;              // Arnoldi steps queued per speculative step
     int hist_kc = 1, q0_kc = 1;      // K chunks of the tile products
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;

@@ -54,6 +54,7 @@ __global__ void k_struct_reduce(int ne, int hs, const int* __restrict__ dk, int 
     } else {
         const int sc = (k - 1) % B;
         const size_t ld = (size_t)B * RP;
+        rb += (size_t)(((k - 1) / B) & 1) * 2 * ne * ld;   // double-buffered batches
         y[(size_t)m * RP + c] = rb[(size_t)m * ld + (size_t)sc * RP + c] - su;
         y[(size_t)(hs + m) * RP + c] = rb[(size_t)ne * ld + (size_t)m * ld + (size_t)sc * RP + c] - sv;
     }

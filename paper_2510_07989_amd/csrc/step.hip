@@ -24,9 +24,11 @@ __device__ __forceinline__ double erf_diff(double s1, double s0) {
 __global__ void k_rhs_fields(int ne, int hs, int k0, int B, int R, int Rp, double dt,
                              const double* __restrict__ X, const double* __restrict__ Fw,
                              const double* __restrict__ waves, const double* __restrict__ tcut,
-                             double* __restrict__ ebar, double* __restrict__ Ebar) {
+                             double* __restrict__ ebar, double* __restrict__ Ebar,
+                             const GmState* __restrict__ gm) {
     // thread per (edge m, batch column sc, wave r); step k = k0 + sc;
     // outputs [half][hs][B * Rp], column sc * Rp + r (zero for padding waves r >= R)
+    if (gm->halt) return;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ne * B * Rp) return;
     const int r = t % Rp, sc = (t / Rp) % B, m = t / (Rp * B);
@@ -127,7 +129,9 @@ __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __re
                                                  const double* __restrict__ Q,
                                                  const double* __restrict__ ring,
                                                  const double* __restrict__ rb, int B,
-                                                 double* __restrict__ y, int wpr) {
+                                                 double* __restrict__ y, int wpr,
+                                                 const GmState* __restrict__ gm) {
+    if (gm->halt) return;
     // wpr wavefronts share one row, each streaming a contiguous 1/wpr of it
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = blockIdx.x * (4 / wpr) + wv / wpr;
@@ -161,8 +165,9 @@ __global__ __launch_bounds__(256) void k_history(int ne, int hs, const int* __re
         double su = 0, sv = 0;
         for (int p = 0; p < wpr; ++p) { su += red[wv + p][0]; sv += red[wv + p][1]; }
         const int sc = (k - 1) % B;
-        y[m] = rb[(size_t)m * B + sc] - su;
-        y[hs + m] = rb[(size_t)ne * B + (size_t)m * B + sc] - sv;
+        const double* r = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;   // double-buffered batches
+        y[m] = r[(size_t)m * B + sc] - su;
+        y[hs + m] = r[(size_t)ne * B + (size_t)m * B + sc] - sv;
     }
 }
 
@@ -173,7 +178,8 @@ __global__ __launch_bounds__(256) void k_history_co(int ne, int hs, const int* _
                                                     const double* __restrict__ Q,
                                                     const double* __restrict__ ring,
                                                     const double* __restrict__ rb, int B,
-                                                    double* __restrict__ y) {
+                                                    double* __restrict__ y, const GmState* __restrict__ gm) {
+    if (gm->halt) return;
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m >= ne) return;
@@ -222,8 +228,9 @@ __global__ __launch_bounds__(256) void k_history_co(int ne, int hs, const int* _
     hv = wave_sum(hv);
     if (lane == 0) {
         const int sc = (k - 1) % B;
-        y[m] = rb[(size_t)m * B + sc] - hu;
-        y[hs + m] = rb[(size_t)ne * B + (size_t)m * B + sc] - hv;
+        const double* r = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;   // double-buffered batches
+        y[m] = r[(size_t)m * B + sc] - hu;
+        y[hs + m] = r[(size_t)ne * B + (size_t)m * B + sc] - hv;
     }
 }
 
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double*
                                                    double* __restrict__ vout, double* __restrict__ y,
                                                    const GmState* __restrict__ gm, int check_done,
                                                    int use_inv, int wpr) {
-    if (check_done && gm->done) return;
+    if (gm->halt || (check_done && gm->done)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = blockIdx.x * (4 / wpr) + wv / wpr;
     const int part = wv % wpr;
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
                                                  const double* __restrict__ src, double* __restrict__ vj,
                                                  double* __restrict__ z, const GmState* __restrict__ gm,
                                                  int wpr) {
-    if (gm->done) return;
+    if (gm->done || gm->halt) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = blockIdx.x * (4 / wpr) + wv / wpr;
     const int part = wv % wpr;
@@ -610,6 +617,7 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
                                                     double* __restrict__ r, int have_t, GmState* gm,
                                                     GmFlag* flag, double tol, int first,
                                                     double* __restrict__ xzero) {
+    if (gm->halt) return;
     __shared__ double sh[kSW / 64];
     double s1 = 0, s2 = 0;
     for (int i = threadIdx.x; i < n2; i += kSW) {
@@ -684,6 +692,7 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
     gm->j = jj;
     gm->cycle_iters = jj;
     gm->total = total;
+    gm->iters_all += 1;
     gm->relres = rel;
     gm->breakdown = brk;
     gm->converged = conv || brk;
@@ -706,6 +715,7 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
 __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restrict__ V,
                                                    double* __restrict__ w, GmState* gm, GmFlag* flag,
                                                    double tol, int M) {
+    if (gm->halt) return;
     if (gm->done) {
         // nothing to do, but every launch publishes one progress word
         if (threadIdx.x == 0) {
@@ -762,9 +772,21 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
 
 // When the cycle is done: x += sum_l y_l Z_l ; when converged (or forced) also
 // push x into the ring and the kept history.
-__global__ void k_gm_finish(int n2, const double* __restrict__ Zb, const GmState* __restrict__ gm,
+// spec = 1 (speculative stepping): a solve that has not converged pushes
+// nothing and raises the halt word instead, so that the later queued steps do
+// nothing until the host has finished this one.
+__global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __restrict__ gm,
                             double* __restrict__ x, const int* __restrict__ dk, int nh,
-                            double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force) {
+                            double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force,
+                            int spec) {
+    if (gm->halt) return;
+    if (spec && !(gm->done && gm->converged)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            gm->halt_k = *dk;
+            gm->halt = 1;
+        }
+        return;
+    }
     if (!gm->done && !force) return;
     const int jj = gm->done ? gm->cycle_iters : 0;
     const int push = gm->converged || force;
@@ -796,7 +818,9 @@ __global__ void k_gm_update_x(int n2, const double* __restrict__ V, const GmStat
 // ------------------------------------------------------------ ring / misc ---
 // x0 = 2 w_{k-1} - w_{k-2} (or w_{k-1}, or 0) from the ring
 __global__ void k_warm_start(int n2, const int* __restrict__ dk, int nh,
-                             const double* __restrict__ ring, double* __restrict__ x) {
+                             const double* __restrict__ ring, double* __restrict__ x,
+                             const GmState* __restrict__ gm) {
+    if (gm->halt) return;
     const int k = *dk;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
         double v = 0.0;
@@ -822,7 +846,11 @@ __global__ void k_push(int n2, const int* __restrict__ dk, int nh, const double*
     }
 }
 
-__global__ void k_inc_step(int* dk) { *dk += 1; }
+__global__ void k_inc_step(int* dk, const GmState* __restrict__ gm) {
+    if (!gm->halt) *dk += 1;
+}
+
+__global__ void k_clear_halt(GmState* gm) { gm->halt = 0; }
 
 // recovery gather: columns (step s in [s0, s1), half h, kind t, rhs r) of
 // X[ne][ncol], kind 0 = u_k, kind 1 = u_k - u_{k-1} (u_0 = 0)
@@ -883,11 +911,14 @@ void rhs_batch(mot_handle* h, int k0, double* rb) {
     const int N = B * Rp;
     size_t tot = (size_t)ne * N;
     hipLaunchKernelGGL(k_rhs_fields, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, ne, hs, k0, B,
-                       h->R, Rp, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar);
+                       h->R, Rp, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar, h->gm);
+    // consecutive batches alternate between the two halves of rb, so a batch
+    // queued ahead of a halted step never overwrites the one it still needs
+    double* rbk = rb + (size_t)(((k0 - 1) / B) & 1) * 2 * ne * N;
     for (int half = 0; half < 2; ++half) {
         const double* eb = h->ebar + (size_t)half * hs * N;
         const double* Eb = h->Ebar + (size_t)half * hs * N;
-        double* out = rb + (size_t)half * ne * N;
+        double* out = rbk + (size_t)half * ne * N;
         motk::gemm(h->stream, ne, N, ne, 1.0, h->C1, hs, eb, N, 0.0, out, N);
         motk::gemm(h->stream, ne, N, ne, 1.0 / h->Tmax, h->C2, hs, Eb, N, 1.0, out, N);
     }
@@ -896,12 +927,12 @@ void rhs_batch(mot_handle* h, int k0, double* rb) {
 void history(mot_handle* h) {
     if (h->hist_variant == 1) {
         hipLaunchKernelGGL(k_history_co, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                           h->nh, h->Q, h->ring, h->rb, h->B, h->y);
+                           h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm);
         return;
     }
     const int rpb = 4 / h->wpr;
     hipLaunchKernelGGL(k_history, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr);
+                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr, h->gm);
 }
 
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero) {
@@ -914,9 +945,9 @@ void gm_orth1(mot_handle* h, double* w) {
                        h->opt.gmres_tol, h->M);
 }
 
-void gm_finish(mot_handle* h, const double* basis, int force) {
+void gm_finish(mot_handle* h, const double* basis, int force, int spec) {
     hipLaunchKernelGGL(k_gm_finish, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, basis, h->gm,
-                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force);
+                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec);
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
@@ -975,7 +1006,7 @@ void gm_update_x(mot_handle* h, const double* basis, double* x) {
 
 void warm_start(mot_handle* h) {
     hipLaunchKernelGGL(k_warm_start, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->d_k,
-                       h->nh, h->ring, h->x);
+                       h->nh, h->ring, h->x, h->gm);
 }
 
 void push(mot_handle* h) {
@@ -983,7 +1014,9 @@ void push(mot_handle* h) {
                        h->x, h->ring, h->hist, h->hist_cap);
 }
 
-void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 0, h->stream, h->d_k); }
+void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 0, h->stream, h->d_k, h->gm); }
+
+void clear_halt(mot_handle* h) { hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(1), 0, h->stream, h->gm); }
 
 void rec_gather(mot_handle* h, int s0, int ns, double* X) {
     int ncol = ns * 4 * h->R;

@@ -37,6 +37,24 @@ def _csr(G):
             np.ascontiguousarray(A.data, dtype=np.float64))
 
 
+def footprint(V, F, E, eps_r, mu_r, dt, nrhs, G, options=None):
+    """Device bytes (resident, peak) that a Solver with these arguments will
+    hold, from mot_footprint: nothing is allocated."""
+    lib = L.load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    E = np.ascontiguousarray(E, dtype=np.int32)
+    mesh = L.MotMesh(V.shape[0], F.shape[0], E.shape[0], _ptr(V), _ptr(F), _ptr(E))
+    nnz = len(_csr(G)[1])
+    opt = options if options is not None else default_options()
+    res, peak = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib.mot_footprint(ctypes.byref(mesh), float(eps_r), float(mu_r), float(dt), int(nrhs), int(nnz),
+                           ctypes.byref(opt), ctypes.byref(res), ctypes.byref(peak))
+    if rc:
+        raise MotError(rc, lib.mot_last_error(None).decode())
+    return int(res.value), int(peak.value)
+
+
 class Solver:
     """One scattering problem on the current HIP device.
 

@@ -31,3 +31,37 @@ def test_default_options_without_gpu():
     import paper_2510_07989_amd as p
     o = p.default_options()
     assert o.gmres_tol == 1e-13 and o.gmres_restart == 40 and o.keep_history == 1
+
+
+def test_footprint_without_gpu():
+    """mot_footprint plans sizes only (no device call): more waves, a longer
+    kept history and the FP64 preconditioner need more; FP32 lag storage less."""
+    import paper_2510_07989_amd as p
+    from tests._problems import problem
+    prob = problem("sphere_480")
+    args = (prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"])
+    r1, k1 = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=100))
+    r16, _ = p.footprint(*args, 16, prob["G"], p.default_options(max_steps=100, precond=2))
+    r16m, _ = p.footprint(*args, 16, prob["G"], p.default_options(max_steps=100, precond=2, precision=1))
+    rlong, _ = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=1000))
+    r64, _ = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=100, precond=2))
+    assert 0 < r1 < k1
+    assert r16 > r16m > r1
+    assert rlong - r1 == 900 * 960 * 8          # kept history: steps x n x 8 bytes
+    assert r64 - r1 == 960 * 960 * 4            # FP64 instead of FP32 approximate inverse
+
+
+def test_one_hip_runtime_in_the_process():
+    """After loading the library, one HIP runtime and one HSA runtime are mapped
+    (PyTorch's), so torch streams and tensors are valid handles for it."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2510_07989_amd import _lib\n"
+            "_lib.load()\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = sorted(set(l.split()[-1] for l in maps if 'amdhip64' in l or 'hsa-runtime64' in l))\n"
+            "print(len([l for l in libs if 'amdhip64' in l]), len([l for l in libs if 'hsa-runtime64' in l]))\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.stdout.split() == ["1", "1"], out.stdout + out.stderr

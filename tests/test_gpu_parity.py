@@ -128,6 +128,30 @@ def test_preconditioner_variants(pc):
     s.close()
 
 
+@pytest.mark.parametrize("precond,window", [(2, 0), (1, 0), (2, 5), (1, 3)])
+def test_speculative_stepping_matches_host_driven(precond, window):
+    """Steps queued without host waits (device halt word, host fallback for a
+    step whose solve did not converge in the queued iterations) give the
+    host-driven march bit for bit, also across run() calls and windows that
+    straddle RHS batches.  The FP32 preconditioner needs several iterations, so
+    its first steps exercise the halt and the fallback."""
+    print("precond", precond, "window", window, flush=True)
+    s0 = _solver("sphere_480", precond=precond, spec_window=-1)
+    ref = s0.run(300)
+    it0 = s0.info()["gmres_iters_total"]
+    s0.close()
+    s = _solver("sphere_480", precond=precond, spec_window=window)
+    a = s.run(130)
+    b = s.run(170)
+    it1 = s.info()["gmres_iters_total"]
+    s.close()
+    print("iterations host-driven %d, speculative %d" % (it0, it1), flush=True)
+    assert np.array_equal(np.concatenate([a["w"], b["w"]]), ref["w"])
+    # recovery solves per run() call: its CG stops on the call's columns together
+    for k in ("loop", "star"):
+        assert _rel(np.concatenate([a[k], b[k]]), ref[k]) < 1e-12, k
+
+
 @pytest.mark.parametrize("opts", [dict(history_order=2), dict(stream_split=2), dict(stream_split=4),
                                   dict(history_order=2, precond=1), dict(history_order=2, stream_split=2)])
 def test_kernel_variants(opts):
