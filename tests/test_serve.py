@@ -1,0 +1,94 @@
+"""Scheduling of the serving loop, on the host (a backend that only sleeps)."""
+import threading
+import time
+
+import pytest
+
+from paper_2510_07989_amd.serve import Request, Server, latency_stats
+
+
+class SleepBackend:
+    """Footprint from the request; 'execution' sleeps per step and records
+    how many requests were executing at once and the budget in use."""
+
+    def __init__(self, step_s=0.002):
+        self.step_s = step_s
+        self.lock = threading.Lock()
+        self.running = {}
+        self.max_running = 0
+        self.max_bytes = 0
+
+    def footprint(self, req):
+        return req.problem["bytes"]
+
+    def execute(self, req, window, clock, res):
+        with self.lock:
+            self.running[req.rid] = req.problem["bytes"]
+            self.max_running = max(self.max_running, len(self.running))
+            self.max_bytes = max(self.max_bytes, sum(self.running.values()))
+        res.t_ready = clock()
+        done = 0
+        while done < req.nsteps:
+            nw = min(window, req.nsteps - done)
+            t0 = clock()
+            time.sleep(self.step_s * nw)
+            res.step_latency.extend([(clock() - t0) / nw] * nw)
+            done += nw
+        with self.lock:
+            del self.running[req.rid]
+
+
+def _req(rid, nbytes, nsteps, arrival):
+    return Request(rid, {"bytes": nbytes, "waves": [None]}, nsteps, arrival)
+
+
+def test_budget_is_never_exceeded_and_all_finish():
+    be = SleepBackend()
+    reqs = [_req(i, 300 + 100 * (i % 3), 20 + 5 * i, 0.003 * i) for i in range(12)]
+    srv = Server(be, mem_budget=1000, max_active=8, window=8)
+    res, summ = srv.run(reqs)
+    assert summ["errors"] == 0 and all(r.t_done > 0 for r in res.values())
+    assert be.max_bytes <= 1000
+    assert summ["peak_budget_used"] <= 1000
+    assert be.max_running >= 2                     # requests overlapped
+    for r in res.values():
+        assert r.t_admit >= r.t_arrival and r.t_done >= r.t_admit
+        assert len(r.step_latency) == r.nsteps
+
+
+def test_late_arrival_admitted_while_others_run():
+    """Continuous batching: a request arriving during a long solve starts
+    before that solve ends when it fits."""
+    be = SleepBackend(step_s=0.004)
+    long = _req(0, 400, 100, 0.0)              # ~0.4 s
+    late = _req(1, 400, 10, 0.05)
+    res, _ = Server(be, mem_budget=1000, window=10).run([long, late])
+    assert res[1].t_admit < res[0].t_done
+    assert res[1].t_done < res[0].t_done
+
+
+def test_admission_waits_for_memory_in_arrival_order():
+    be = SleepBackend(step_s=0.003)
+    a = _req(0, 700, 30, 0.0)
+    b = _req(1, 600, 10, 0.01)                 # does not fit beside a
+    c = _req(2, 100, 10, 0.02)                 # would fit, but queues behind b
+    res, _ = Server(be, mem_budget=1000, window=5).run([a, b, c])
+    assert res[1].t_admit >= res[0].t_done - 1e-3
+    assert res[2].t_admit >= res[1].t_admit
+
+
+def test_slot_limit():
+    be = SleepBackend()
+    reqs = [_req(i, 10, 10, 0.0) for i in range(6)]
+    Server(be, mem_budget=10 ** 6, max_active=2, window=5).run(reqs)
+    assert be.max_running <= 2
+
+
+def test_request_larger_than_budget_is_refused():
+    with pytest.raises(ValueError):
+        Server(SleepBackend(), mem_budget=100).run([_req(0, 200, 5, 0.0)])
+
+
+def test_latency_stats():
+    s = latency_stats(range(1, 101))
+    assert s["n"] == 100 and abs(s["p50"] - 50.5) < 1e-12 and 99 < s["p99"] <= 100
