@@ -113,7 +113,11 @@ typedef struct {
                                 steps queued per host check of the device halt
                                 word (0: one RHS batch, 128; -1: wait for every
                                 step's GMRES on the host)                     */
-    int32_t reserved[1];
+    int32_t recovery;        /* P^Sigma in the current recovery of eq.
+                                (dis_jm): 0 (default) the dense projector
+                                formed at setup, one GEMM per batch of steps;
+                                1 incidence products and graph-Laplacian CG
+                                per batch (no dense ne^2 product)             */
 } mot_options;
 
 typedef struct {

@@ -4,67 +4,87 @@
 namespace {
 
 // ------------------------------------------------------------------ GEMM ---
-// C = alpha A B + beta C, row-major, FP64.  64x64 output tile per 256-thread
-// workgroup, 4x4 per thread, K staged through LDS in slices of 16.
-constexpr int TM = 64, TN = 64, TK = 16;
+// C = alpha A B + beta C, row-major, FP64, on v_mfma_f64_16x16x4f64.
+// A workgroup of four wavefronts computes a (2 WT) x (2 WT) tile of C, each
+// wavefront a WT x WT quarter as (WT/16)^2 MFMA tiles of 16 x 16.  K advances
+// in slices of 16: A is staged transposed (As[k][m]) and B as is (Bs[k][n]) in
+// LDS, and the next slice's global loads are issued before the current
+// slice's MFMAs.  Operand layout: A lane l = row l%16, summation slot l/16; B
+// lane l = column l%16, slot l/16; result register r of lane l = row
+// l/16 + 4r, column l%16.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int GK = 16;
 
+template <int WT>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
                                               const double* __restrict__ A, int lda,
                                               const double* __restrict__ B, int ldb, double beta,
                                               double* __restrict__ C, int ldc) {
-    __shared__ double As[TK][TM + 1];
-    __shared__ double Bs[TK][TN];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    double acc[4][4];
+    constexpr int BT = 2 * WT;               // block tile edge
+    constexpr int NT = WT / 16;              // MFMA tiles per wavefront edge
+    constexpr int PE = BT * GK / 256;        // staged elements per thread, per operand
+    __shared__ double As[GK][BT + 2];
+    __shared__ double Bs[GK][BT + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+    const int wm = (wv >> 1) * WT, wn = (wv & 1) * WT;
+    v4d acc[NT][NT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += TK) {
-        // A tile TM x TK: 1024 elements, 4 per thread
+        for (int j = 0; j < NT; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    double ra[PE], rb[PE];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int e = tid + r * 256;
-            int am = e / TK, ak = e % TK;
-            int gm = m0 + am, gk = k0 + ak;
-            As[ak][am] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+        for (int r = 0; r < PE; ++r) {
+            const int e = tid + 256 * r;
+            const int am = e / GK, ak = e % GK;            // A: 16 consecutive k per row
+            const int gm = m0 + am, gk = k0 + ak;
+            ra[r] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+            const int bk = e / BT, bn = e % BT;            // B: BT consecutive columns per k
+            const int gk2 = k0 + bk, gn = n0 + bn;
+            rb[r] = (gk2 < K && gn < N) ? B[(size_t)gk2 * ldb + gn] : 0.0;
         }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += GK) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int e = tid + r * 256;
-            int bk = e / TN, bn = e % TN;
-            int gk = k0 + bk, gn = n0 + bn;
-            Bs[bk][bn] = (gk < K && gn < N) ? B[(size_t)gk * ldb + gn] : 0.0;
+        for (int r = 0; r < PE; ++r) {
+            const int e = tid + 256 * r;
+            As[e % GK][e / GK] = ra[r];
+            Bs[e / BT][e % BT] = rb[r];
         }
         __syncthreads();
+        if (k0 + GK < K) fetch(k0 + GK);
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4];
+        for (int kk = 0; kk < GK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double a[NT], b[NT];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < NT; ++i) a[i] = As[kr][wm + 16 * i + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < NT; ++j) b[j] = Bs[kr][wn + 16 * j + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NT; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int gm = m0 + ty + 16 * i;
-        if (gm >= M) continue;
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int gn = n0 + tx + 16 * j;
-            if (gn >= N) continue;
-            double* c = C + (size_t)gm * ldc + gn;
-            *c = beta == 0.0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * *c;
-        }
-    }
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + (lane >> 4) + 4 * r;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm < M && gn < N) {
+                    double* c = C + (size_t)gm * ldc + gn;
+                    *c = beta == 0.0 ? alpha * acc[i][j][r] : alpha * acc[i][j][r] + beta * *c;
+                }
+            }
 }
 
 __global__ void k_axpby2d(int rows, int cols, double a, const double* __restrict__ X, int ldx,
@@ -258,8 +278,15 @@ namespace motk {
 void gemm(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc) {
     if (M <= 0 || N <= 0) return;
-    dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    // 128 x 128 tiles when they still give about four workgroups per CU
+    const long big = (long)((N + 127) / 128) * ((M + 127) / 128);
+    if (big >= 1024) {
+        dim3 grid((N + 127) / 128, (M + 127) / 128);
+        hipLaunchKernelGGL(k_gemm<64>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    } else {
+        dim3 grid((N + 63) / 64, (M + 63) / 64);
+        hipLaunchKernelGGL(k_gemm<32>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    }
 }
 
 void axpby2d(hipStream_t s, int rows, int cols, double a, const double* X, int ldx, double b,

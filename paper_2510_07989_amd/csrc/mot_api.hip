@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <algorithm>
+#include <thread>
 
 #include "mot_internal.h"
 
@@ -457,10 +458,16 @@ void ev_destroy(EvPool& p) {
 // failed kernel turns into MOT_EHIP instead of a hang).
 int wait_flag(mot_handle* h, int want) {
     if (h->hflag->seq >= want) return MOT_OK;
-    double t0 = now_ms();
+    double t0 = now_ms(), tq = t0;
     unsigned spins = 0;
     while (h->hflag->seq < want) {
         if ((++spins & 1023u) == 0) {
+            // several solves may wait at once from their own threads: give the
+            // core away between bursts and ask the runtime only every 0.2 ms
+            std::this_thread::yield();
+            const double t = now_ms();
+            if (t - tq < 0.2) continue;
+            tq = t;
             hipError_t e = hipStreamQuery(h->stream);
             if (e != hipSuccess && e != hipErrorNotReady)
                 return mot_fail(h, MOT_EHIP, std::string("stream error while waiting: ") + hipGetErrorString(e));
@@ -687,24 +694,32 @@ int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
     const int per = 4 * h->R;
     const int maxcol = 8192;
     int bs = std::max(1, maxcol / per);
-    double *X, *S, *Z, *PX;
+    double *X, *S = nullptr, *Z = nullptr, *PX;
     int rc;
+    const bool cg = h->opt.recovery == 1;
     int ncmax = std::min(ns, bs) * per;
-    if ((rc = dalloc(h, &X, (size_t)h->ne * ncmax, false)) || (rc = dalloc(h, &S, (size_t)h->nf * ncmax, false)) ||
-        (rc = dalloc(h, &Z, (size_t)h->nf * ncmax, false)) || (rc = dalloc(h, &PX, (size_t)h->ne * ncmax, false)))
+    if ((rc = dalloc(h, &X, (size_t)h->ne * ncmax, false)) || (rc = dalloc(h, &PX, (size_t)h->ne * ncmax, false)) ||
+        (cg && ((rc = dalloc(h, &S, (size_t)h->nf * ncmax, false)) || (rc = dalloc(h, &Z, (size_t)h->nf * ncmax, false)))))
         return rc;
     int worst = MOT_OK;
     for (int b0 = 0; b0 < ns; b0 += bs) {
         int nb = std::min(bs, ns - b0);
         int nc = nb * per;
         motk_step::rec_gather(h, s0 + b0, nb, X);
-        motk::inc_T(h->stream, h->gf, nc, X, nc, S);
-        motk::col_center(h->stream, h->nf, nc, S);
-        auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
-        rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
-        if (rc && rc != MOT_ENOCONV) return rc;
-        if (rc) worst = rc;
-        motk::inc_apply(h->stream, h->gf, nc, Z, PX, nc);
+        if (cg) {
+            // P^Sigma X = Sigma (Sigma^T Sigma)^+ Sigma^T X: incidence products and
+            // CG on the face graph Laplacian (Section IV-B)
+            motk::inc_T(h->stream, h->gf, nc, X, nc, S);
+            motk::col_center(h->stream, h->nf, nc, S);
+            auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
+            rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
+            if (rc && rc != MOT_ENOCONV) return rc;
+            if (rc) worst = rc;
+            motk::inc_apply(h->stream, h->gf, nc, Z, PX, nc);
+        } else {
+            // the dense P^Sigma formed at setup by the same incidence products and CG
+            motk::gemm(h->stream, h->ne, nc, h->ne, 1.0, h->PS, h->hs, X, nc, 0.0, PX, nc);
+        }
         size_t off = (size_t)b0 * 2 * h->ne * h->R;
         motk_step::rec_scatter(h, nb, X, PX, loop ? loop + off : nullptr, star ? star + off : nullptr);
     }
@@ -795,7 +810,8 @@ void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* 
     t = std::max(t, 8.0 * 9 * blk);                                                 // one lag staged
     if (h->opt.precond) t = std::max(t, 8.0 * 4 * nn2 + 16.0 * h->n2);              // Newton-Schulz
     const double per = 4 * R, bs = std::max(1.0, std::floor(8192 / per)), nc = bs * per;
-    t = std::max(t, 8.0 * ((2 * ne + 5 * nf) * nc + cgx * nc));                     // recovery batch
+    if (h->opt.recovery == 1) t = std::max(t, 8.0 * ((2 * ne + 5 * nf) * nc + cgx * nc));  // recovery batch
+    else t = std::max(t, 8.0 * 2 * ne * nc);
     *resident = (uint64_t)b;
     *peak = (uint64_t)(b + t);
 }
@@ -871,6 +887,8 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
         return mot_fail(nullptr, MOT_EINVAL, "precision must be MOT_FP64, MOT_MIXED or MOT_MIXED32");
     if (opt && opt->precision != MOT_FP64 && nrhs < 2)
         return mot_fail(nullptr, MOT_EINVAL, "the mixed-precision history multiplies several right-hand sides (nrhs >= 2)");
+    if (opt && opt->recovery != 0 && opt->recovery != 1)
+        return mot_fail(nullptr, MOT_EINVAL, "recovery must be 0 (dense projector) or 1 (graph-Laplacian CG)");
     if (opt && opt->mix_group != 0 && opt->mix_group != 4 && opt->mix_group != 16 && opt->mix_group != 64)
         return mot_fail(nullptr, MOT_EINVAL, "mix_group must be 4, 16 or 64 (0: 4)");
     // ---- mesh validation (host, integers) ----

@@ -139,12 +139,15 @@ class GpuBackend:
 class Server:
     """Admission by memory footprint and concurrent execution (see module doc)."""
 
-    def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 64, poll: float = 0.001):
+    def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 64, poll: float = 0.001,
+                 request_timeout: float = 600.0, log: Optional[Callable[[str], None]] = None):
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_active = int(max_active)
         self.window = int(window)
         self.poll = poll
+        self.request_timeout = float(request_timeout)
+        self.log = log
         self.trace: List[tuple] = []          # (time, event, rid, active, used bytes)
 
     def run(self, requests: List[Request]):
@@ -188,6 +191,20 @@ class Server:
                 active.pop(rid).join()
                 used -= fp[rid]
                 self.trace.append((clock(), "done", rid, len(active), used))
+                if self.log:
+                    r = results[rid]
+                    self.log("[serve %.2fs] request %d done (%d steps, %.3f s end to end%s); %d active"
+                             % (clock(), rid, r.nsteps, r.end_to_end, ", " + r.error if r.error else "", len(active)))
+            # a request past its time limit is reported and its slot and memory
+            # stay held (its thread cannot be stopped from here)
+            for rid in list(active):
+                r = results[rid]
+                if r.error is None and clock() - r.t_admit > self.request_timeout:
+                    r.error = "TimeoutError: still running after %.0f s" % self.request_timeout
+                    if self.log:
+                        self.log("[serve %.2fs] request %d exceeded %.0f s" % (clock(), rid, self.request_timeout))
+            if active and all(results[rid].error for rid in active) and not queue and not pending:
+                break
             # strict arrival order: the head waits until it fits
             while queue and len(active) < self.max_active and used + fp[queue[0].rid] <= self.mem_budget:
                 req = queue.pop(0)
@@ -196,6 +213,10 @@ class Server:
                 th = threading.Thread(target=worker, args=(req,), daemon=True)
                 active[req.rid] = th
                 self.trace.append((clock(), "admit", req.rid, len(active), used))
+                if self.log:
+                    self.log("[serve %.2fs] request %d admitted (%d steps, %d waves, %.1f MB); %d active"
+                             % (clock(), req.rid, req.nsteps, len(req.problem["waves"]), fp[req.rid] / 1e6,
+                                len(active)))
                 th.start()
             if not (pending or queue or active):
                 break

@@ -153,9 +153,11 @@ def test_speculative_stepping_matches_host_driven(precond, window):
 
 
 @pytest.mark.parametrize("opts", [dict(history_order=2), dict(stream_split=2), dict(stream_split=4),
-                                  dict(history_order=2, precond=1), dict(history_order=2, stream_split=2)])
+                                  dict(history_order=2, precond=1), dict(history_order=2, stream_split=2),
+                                  dict(recovery=1)])
 def test_kernel_variants(opts):
-    """Loop-order and row-split variants of the streaming kernels give the oracle's march."""
+    """Loop-order and row-split variants of the streaming kernels, and the
+    graph-Laplacian CG recovery, give the oracle's march."""
     print("variant", opts, flush=True)
     O = oracle("sphere_480")
     ref = O.run(100)

@@ -92,3 +92,15 @@ def test_request_larger_than_budget_is_refused():
 def test_latency_stats():
     s = latency_stats(range(1, 101))
     assert s["n"] == 100 and abs(s["p50"] - 50.5) < 1e-12 and 99 < s["p99"] <= 100
+
+
+def test_request_time_limit_is_reported():
+    """A request that runs past the server's limit is reported as an error and
+    does not keep the server waiting."""
+    be = SleepBackend(step_s=0.05)
+    lines = []
+    srv = Server(be, mem_budget=1000, window=2, request_timeout=0.1, log=lines.append)
+    res, summ = srv.run([_req(0, 100, 40, 0.0), _req(1, 100, 2, 0.0)])
+    assert res[0].error and "Timeout" in res[0].error
+    assert res[1].error is None
+    assert any("exceeded" in l for l in lines) and any("admitted" in l for l in lines)
