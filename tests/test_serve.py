@@ -99,8 +99,8 @@ def test_request_time_limit_is_reported():
     does not keep the server waiting."""
     be = SleepBackend(step_s=0.05)
     lines = []
-    srv = Server(be, mem_budget=1000, window=2, request_timeout=0.1, log=lines.append)
-    res, summ = srv.run([_req(0, 100, 40, 0.0), _req(1, 100, 2, 0.0)])
+    srv = Server(be, mem_budget=1000, window=2, request_timeout=0.3, log=lines.append)
+    res, summ = srv.run([_req(0, 100, 40, 0.0), _req(1, 100, 1, 0.0)])     # 2 s and 0.05 s of work
     assert res[0].error and "Timeout" in res[0].error
     assert res[1].error is None
     assert any("exceeded" in l for l in lines) and any("admitted" in l for l in lines)
