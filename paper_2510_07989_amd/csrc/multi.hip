@@ -433,20 +433,57 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
     };
     if (gok && c0 < c1) fetch(c0);
 
-    for (int cs = c0; cs < c1; cs += ST) {
+    // With one or two column blocks, the history slice of the next K step is
+    // loaded into registers while the current one is multiplied, and stored to
+    // LDS after the barrier; with four, the registers are worth more as
+    // occupancy and the slice is loaded between the barriers.
+    constexpr bool WPF = CB < 4;
+    constexpr int WE = ST * 16 * NC / 256;     // staged (u, v) pairs per thread
+    double pu[WPF ? WE : 1], pv[WPF ? WE : 1];
+    auto wfetch = [&](int cs) {
         const int nst = min(ST, c1 - cs);
-        for (int e = t; e < ST * 16 * NC; e += 256) {
+#pragma unroll
+        for (int q = 0; q < WE; ++q) {
+            const int e = t + 256 * q;
             const int col = e % NC, kk = e / NC;
             const int gk = cs * 16 + kk;
-            double wu = 0.0, wvv = 0.0;
+            pu[q] = pv[q] = 0.0;
             if (col < Rp && kk < nst * 16 && gk < hs) {
-                wu = W[(size_t)gk * Rp + col];
-                wvv = W[(size_t)(hs + gk) * Rp + col];
+                pu[q] = W[(size_t)gk * Rp + col];
+                pv[q] = W[(size_t)(hs + gk) * Rp + col];
             }
-            Ws[0][kk][col] = wu;
-            Ws[1][kk][col] = wvv;
+        }
+    };
+    if constexpr (WPF) {
+        if (c0 < c1) wfetch(c0);
+    }
+
+    for (int cs = c0; cs < c1; cs += ST) {
+        const int nst = min(ST, c1 - cs);
+        if constexpr (WPF) {
+#pragma unroll
+            for (int q = 0; q < WE; ++q) {
+                const int e = t + 256 * q;
+                Ws[0][e / NC][e % NC] = pu[q];
+                Ws[1][e / NC][e % NC] = pv[q];
+            }
+        } else {
+            for (int e = t; e < ST * 16 * NC; e += 256) {
+                const int col = e % NC, kk = e / NC;
+                const int gk = cs * 16 + kk;
+                double wu = 0.0, wvv = 0.0;
+                if (col < Rp && kk < nst * 16 && gk < hs) {
+                    wu = W[(size_t)gk * Rp + col];
+                    wvv = W[(size_t)(hs + gk) * Rp + col];
+                }
+                Ws[0][kk][col] = wu;
+                Ws[1][kk][col] = wvv;
+            }
         }
         __syncthreads();
+        if constexpr (WPF) {
+            if (cs + ST < c1) wfetch(cs + ST);
+        }
         for (int ci = 0; ci < nst; ++ci) {
             double a1[4], ak[4], a2[4];
 #pragma unroll
@@ -462,9 +499,10 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
                         const double wvv = Ws[1][kk][cb * 16 + cl];
                         v4d& u = Cu[cb][e % NS];
                         v4d& v = Cv[cb][e % NS];
+                        // u and v chains alternate (each keeps its own summation order)
                         u = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], wu, u, 0, 0, 0);
-                        u = __builtin_amdgcn_mfma_f64_16x16x4f64(-ak[e], wvv, u, 0, 0, 0);
                         v = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[e], wu, v, 0, 0, 0);
+                        u = __builtin_amdgcn_mfma_f64_16x16x4f64(-ak[e], wvv, u, 0, 0, 0);
                         v = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[e], wvv, v, 0, 0, 0);
                     }
                 }
@@ -598,8 +636,8 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int G16, int 
                 for (int cb = 0; cb < CB; ++cb) {
                     const float uh = UH[cb][e], vh = VH[cb][e];
                     Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], uh, Cu[cb], 0, 0, 0);
-                    Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vh, Cu[cb], 0, 0, 0);
                     Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[e], uh, Cv[cb], 0, 0, 0);
+                    Cu[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ak[e], vh, Cu[cb], 0, 0, 0);
                     Cv[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[e], vh, Cv[cb], 0, 0, 0);
                     if (hl) {
                         const float ul = UL[cb][e], vl = VL[cb][e];
