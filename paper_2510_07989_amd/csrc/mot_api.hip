@@ -44,7 +44,7 @@ void q0_reduce(mot_handle* h, double* out);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero);
 void orth(mot_handle* h, double* w);
-void finish(mot_handle* h, int force);
+void finish(mot_handle* h, int force, int spec = 0);
 void plan_tiles(mot_handle* h);
 size_t tile_elems(const mot_handle* h);
 void pack_lag(mot_handle* h, int lag);
@@ -1193,18 +1193,39 @@ int mot_step(mot_handle* h, mot_step_info* info) {
 struct SpecWord { int halt, halt_k, iters_all; };
 
 static bool spec_ok(const mot_handle* h) {
-    return h->opt.spec_window >= 0 && h->Rp == 1 && (h->M32 || h->M64) && h->n2 <= 32768;
+    if (h->opt.spec_window < 0 || !(h->M32 || h->M64)) return false;
+    return h->Rp > 1 ? (h->gms && h->mr_part) : h->n2 <= 32768;
 }
 
 static int queue_spec_step(mot_handle* h) {
     using namespace motk_step;
+    namespace mm = motk_multi;
     inc_step(h);
     h->k += 1;
     if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
     int prc;
     if ((prc = ev_begin(h, h->ev_hist))) return prc;
-    history(h);
+    if (h->Rp > 1) mm::history_gemm(h); else history(h);
     if ((prc = ev_end(h, h->ev_hist))) return prc;
+    if (h->Rp > 1) {
+        // R waves: one cold-started GMRES per column, products shared
+        const size_t vs = (size_t)h->n2 * h->Rp;
+        mm::history_reduce(h);
+        mm::start(h, h->y, h->wA, 0, 1, h->x);
+        double* src = h->wA;
+        double* dst = h->wB;
+        for (int j = 0; j < h->spec_iters; ++j) {
+            mm::precond(h, src, h->V + (size_t)j * vs, h->Z + (size_t)j * vs);
+            if ((prc = ev_begin(h, h->ev_q0))) return prc;
+            mm::q0_gemm(h, h->Z + (size_t)j * vs);
+            if ((prc = ev_end(h, h->ev_q0))) return prc;
+            mm::q0_reduce(h, dst);
+            mm::orth(h, dst);
+            std::swap(src, dst);
+        }
+        mm::finish(h, 0, 1);
+        return MOT_OK;
+    }
     if (h->M32) {
         warm_start(h);
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
@@ -1261,7 +1282,7 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
         if (w.halt_k <= k0 || w.halt_k > h->k) return mot_fail(h, MOT_EHIP, "speculative halt word out of range");
         h->k = w.halt_k;
         motk_step::clear_halt(h);
-        int src = gmres_solve_pc(h);
+        int src = h->Rp > 1 ? gmres_solve_mr(h) : gmres_solve_pc(h);
         if (src && src != MOT_ENOCONV) return src;
         if (src) *worst = src;
         if ((rc = read_spec(h, &w0))) return rc;

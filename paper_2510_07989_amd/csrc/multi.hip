@@ -36,7 +36,8 @@ __device__ __forceinline__ double wsum(double v) {
 template <int RP>
 __global__ void k_struct_reduce(int ne, int hs, const int* __restrict__ dk, int nh, int q0_mode, int KC,
                                 const double* __restrict__ part, const double* __restrict__ rb, int B,
-                                double* __restrict__ y) {
+                                double* __restrict__ y, const GmState* __restrict__ agg) {
+    if (agg->halt) return;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ne * RP) return;
     const int m = t / RP, c = t % RP;
@@ -66,7 +67,7 @@ template <int RP, typename T>
 __global__ __launch_bounds__(256) void k_plain_gemm(int n, const T* __restrict__ A, const double* __restrict__ X,
                                                     int KC, double* __restrict__ part,
                                                     const GmState* __restrict__ agg) {
-    if (agg->done) return;
+    if (agg->done || agg->halt) return;
     const int m0 = blockIdx.x * TM;
     const int kc = blockIdx.z;
     const int KL = ((n + KC - 1) / KC + TK - 1) / TK * TK;
@@ -119,7 +120,7 @@ template <int RP>
 __global__ void k_plain_reduce(int n, int KC, const double* __restrict__ part, const double* __restrict__ src,
                                const GmState* __restrict__ gms, const GmState* __restrict__ agg,
                                double* __restrict__ z, double* __restrict__ vj) {
-    if (agg->done) return;
+    if (agg->done || agg->halt) return;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * RP) return;
     const int m = t / RP, c = t % RP;
@@ -143,7 +144,8 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 }
 
 // Combine the column states into the aggregate state and publish one word.
-__device__ void aggregate(int RP, int R, GmState* gms, GmState* agg, GmFlag* flag) {
+__device__ void aggregate(int RP, int R, GmState* gms, GmState* agg, GmFlag* flag, int arnoldi) {
+    if (arnoldi) agg->iters_all += 1;
     int done = 1, conv = 1, total = 0;
     double rel = 0;
     for (int c = 0; c < RP; ++c) {
@@ -181,6 +183,7 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, const 
                                                    double* __restrict__ r, int have_t, GmState* gms,
                                                    GmState* agg, GmFlag* flag, double tol, int first,
                                                    double* __restrict__ xzero) {
+    if (agg->halt) return;
     __shared__ double sh[4];
     const int c = blockIdx.x;
     double s1 = 0, s2 = 0;
@@ -212,13 +215,14 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, const 
     }
     if (first && blockIdx.x == 0 && threadIdx.x == 0) agg->seq = 0;
     if (!last_of_grid(&agg->counter)) return;
-    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag);
+    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag, 0);
 }
 
 // one workgroup per column: CGS2 of w[:, c] against V[0..j][:, c], norm, Givens
 __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const double* __restrict__ V,
                                                   double* __restrict__ w, GmState* gms, GmState* agg,
                                                   GmFlag* flag, double tol, int M) {
+    if (agg->halt) return;
     __shared__ double sh[4];
     __shared__ double hc[MOT_MAXM + 1];
     const int c = blockIdx.x;
@@ -286,16 +290,26 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const d
         }
     }
     if (!last_of_grid(&agg->counter)) return;
-    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag);
+    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag, 1);
 }
 
 // x[:, c] += sum_l y_l(c) Z_l[:, c] for columns whose cycle is done (once per
 // cycle: cycle_iters is consumed); push x into the ring and history when every
 // column converged, or when forced.
+// spec = 1 (speculative stepping): unless every column has converged, push
+// nothing and raise the halt word, so that later queued steps do nothing.
 __global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmState* gms,
-                             const GmState* __restrict__ agg, double* __restrict__ x,
+                             GmState* __restrict__ agg, double* __restrict__ x,
                              const int* __restrict__ dk, int nh, double* __restrict__ ring,
-                             double* __restrict__ hist, int hist_cap, int force) {
+                             double* __restrict__ hist, int hist_cap, int force, int spec) {
+    if (agg->halt) return;
+    if (spec && !agg->converged) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            agg->halt_k = *dk;
+            agg->halt = 1;
+        }
+        return;
+    }
     const int k = *dk;
     const int push = agg->converged || force;
     double* slot = ring + (size_t)(k % nh) * n2 * RP;
@@ -316,7 +330,8 @@ __global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmSta
 }
 
 // after a finish: mark consumed cycles (so a restart does not add them twice)
-__global__ void k_gmb_consume(int RP, GmState* gms) {
+__global__ void k_gmb_consume(int RP, GmState* gms, const GmState* __restrict__ agg) {
+    if (agg->halt) return;
     int c = threadIdx.x;
     if (c < RP && gms[c].done) gms[c].cycle_iters = 0;
 }
@@ -378,7 +393,8 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
                                                    const T* __restrict__ At, const float* __restrict__ Alo,
                                                    int hilo, const double* __restrict__ ring,
                                                    const double* __restrict__ X, int KC,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const GmState* __restrict__ agg) {
+    if (agg->halt) return;
     const int k = *dk;
     const int jj = blockIdx.y;
     const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
@@ -545,7 +561,8 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int G16, int 
                                                    const int* __restrict__ dk, int nh, int hilo,
                                                    const float* __restrict__ Qf, const float* __restrict__ Qlo,
                                                    const double* __restrict__ ring, int KC,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const GmState* __restrict__ agg) {
+    if (agg->halt) return;
     const int k = *dk;
     const int jj = blockIdx.y;
     const int nact = k - 1 < nh ? k - 1 : nh;
@@ -710,7 +727,7 @@ void tile_launch(mot_handle* h, int q0_mode, const T* At, const float* Alo, cons
     dim3 grid((h->G16 + 3) / 4, groups, KC);
     const int CB = (h->Rp + 15) / 16;
 #define L_(CB_) hipLaunchKernelGGL((k_tile_gemm<T, CB_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->G16, h->KT, \
-                                   h->Rp, h->d_k, h->nh, q0_mode, At, Alo, h->hilo, h->ring, X, KC, h->mr_part)
+                                   h->Rp, h->d_k, h->nh, q0_mode, At, Alo, h->hilo, h->ring, X, KC, h->mr_part, h->gm)
     if (CB == 1)
         L_(1);
     else if (CB == 2)
@@ -764,7 +781,7 @@ size_t part_doubles(const mot_handle* h) {
 static void reduce(mot_handle* h, int q0_mode, int KC, double* out) {
     const int n = h->ne * h->Rp;
 #define C_(R_) hipLaunchKernelGGL(k_struct_reduce<R_>, dim3((n + 255) / 256), dim3(256), 0, h->stream, h->ne, h->hs, \
-                                  h->d_k, h->nh, q0_mode, KC, h->mr_part, h->rb, h->B, out)
+                                  h->d_k, h->nh, q0_mode, KC, h->mr_part, h->rb, h->B, out, h->gm)
     MOT_RP_SWITCH(h->Rp, C_)
 #undef C_
 }
@@ -776,7 +793,8 @@ void history_gemm(mot_handle* h) {
         const int CB = (h->Rp + 15) / 16;
         const int FL = h->opt.mix_group == 64 ? 16 : (h->opt.mix_group == 16 ? 4 : 1);
 #define L_(CB_, FL_) hipLaunchKernelGGL((k_hist_mfma<CB_, FL_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->G16, \
-                                        h->KT, h->Rp, h->d_k, h->nh, h->hilo, h->QtF, h->QtL, h->ring, KC, h->mr_part)
+                                        h->KT, h->Rp, h->d_k, h->nh, h->hilo, h->QtF, h->QtL, h->ring, KC, h->mr_part, \
+                                        h->gm)
 #define F_(CB_)              \
     do {                     \
         if (FL == 16)        \
@@ -843,12 +861,12 @@ void orth(mot_handle* h, double* w) {
                        h->dflag, h->opt.gmres_tol, h->M);
 }
 
-void finish(mot_handle* h, int force) {
+void finish(mot_handle* h, int force, int spec) {
     size_t total = (size_t)h->n2 * h->Rp;
     int nb = (int)std::min<size_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_gmb_finish, dim3(nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->Z, h->gms, h->gm, h->x,
-                       h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force);
-    hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms);
+                       h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec);
+    hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms, h->gm);
 }
 
 }  // namespace motk_multi

@@ -128,19 +128,23 @@ def test_preconditioner_variants(pc):
     s.close()
 
 
-@pytest.mark.parametrize("precond,window", [(2, 0), (1, 0), (2, 5), (1, 3)])
-def test_speculative_stepping_matches_host_driven(precond, window):
+@pytest.mark.parametrize("name,precond,window,precision", [("sphere_480", 2, 0, 0), ("sphere_480", 1, 0, 0),
+                                                           ("sphere_480", 2, 5, 0), ("sphere_480", 1, 3, 0),
+                                                           ("sphere_480_r16", 2, 0, 0), ("sphere_480_r16", 2, 7, 1),
+                                                           ("tiny_box", 1, 0, 0)])
+def test_speculative_stepping_matches_host_driven(name, precond, window, precision):
     """Steps queued without host waits (device halt word, host fallback for a
     step whose solve did not converge in the queued iterations) give the
-    host-driven march bit for bit, also across run() calls and windows that
-    straddle RHS batches.  The FP32 preconditioner needs several iterations, so
-    its first steps exercise the halt and the fallback."""
-    print("precond", precond, "window", window, flush=True)
-    s0 = _solver("sphere_480", precond=precond, spec_window=-1)
+    host-driven march bit for bit, for one wave and for several (one GMRES per
+    column), also across run() calls and windows that straddle RHS batches.
+    The FP32 preconditioner needs several iterations, so its first steps
+    exercise the halt and the fallback."""
+    print("case", name, "precond", precond, "window", window, "precision", precision, flush=True)
+    s0 = _solver(name, precond=precond, spec_window=-1, precision=precision)
     ref = s0.run(300)
     it0 = s0.info()["gmres_iters_total"]
     s0.close()
-    s = _solver("sphere_480", precond=precond, spec_window=window)
+    s = _solver(name, precond=precond, spec_window=window, precision=precision)
     a = s.run(130)
     b = s.run(170)
     it1 = s.info()["gmres_iters_total"]
