@@ -48,6 +48,8 @@ void finish(mot_handle* h, int force, int spec = 0);
 void plan_tiles(mot_handle* h);
 size_t tile_elems(const mot_handle* h);
 void pack_lag(mot_handle* h, int lag);
+void pack_square(mot_handle* h, const double* X, double* t64, float* t32);
+size_t orth_part_doubles(const mot_handle* h);
 }  // namespace motk_multi
 
 static thread_local std::string g_create_err;   // create errors, per host thread
@@ -300,12 +302,15 @@ int build_precond(mot_handle* h) {
     h->ns_iters = it;
     h->ns_resid = best;
     if (!(best < 0.5)) return mot_fail(h, MOT_ENOCONV, "Newton-Schulz did not converge");
+    // several waves: stored in 16 x 16 tiles for the MFMA products (same bytes)
     if (h->opt.precond == 2) {
         if ((rc = dalloc(h, &h->M64, nn, false))) return rc;
-        HIPCHK(h, hipMemcpyAsync(h->M64, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (h->Rp > 1) motk_multi::pack_square(h, X, h->M64, nullptr);
+        else HIPCHK(h, hipMemcpyAsync(h->M64, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
         if ((rc = dalloc(h, &h->M32, nn, false))) return rc;
-        motk_step::to_f32(h, nn, X, h->M32);
+        if (h->Rp > 1) motk_multi::pack_square(h, X, nullptr, h->M32);
+        else motk_step::to_f32(h, nn, X, h->M32);
     }
     HIPCHK(h, hipStreamSynchronize(s));
     dfree(h, Q0); dfree(h, X); dfree(h, T); dfree(h, Xn); dfree(h, rs); dfree(h, cs); dfree(h, acc);
@@ -796,7 +801,8 @@ void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* 
         const double t3 = 3.0 * motk_multi::tile_elems(h);
         if (h->opt.precision == MOT_FP64) b += 8.0 * h->nlags * t3;
         else b += 8.0 * t3 + 4.0 * h->nh * t3 + 4.0 * h->hilo * t3;
-        b += (double)sizeof(GmState) * h->Rp + 8.0 * motk_multi::part_doubles(h);
+        b += (double)sizeof(GmState) * h->Rp + 8.0 * motk_multi::part_doubles(h) +
+             8.0 * motk_multi::orth_part_doubles(h);
     }
     b += 8.0 * h->hist_cap * n2r;                                                 // kept history
     const double nn2 = (double)h->n2 * h->n2;
@@ -1073,7 +1079,8 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
                 return bail(rc);
         }
     }
-    if (h->Rp > 1 && ((rc = dalloc(h, &h->gms, h->Rp)) || (rc = dalloc(h, &h->mr_part, motk_multi::part_doubles(h)))))
+    if (h->Rp > 1 && ((rc = dalloc(h, &h->gms, h->Rp)) || (rc = dalloc(h, &h->mr_part, motk_multi::part_doubles(h))) ||
+                      (rc = dalloc(h, &h->orth_part, motk_multi::orth_part_doubles(h)))))
         return bail(rc);
     if (h->hist_cap && (rc = dalloc(h, &h->hist, (size_t)h->hist_cap * n2))) return bail(rc);
     if (hipHostMalloc((void**)&h->hflag, sizeof(GmFlag), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {

@@ -37,6 +37,7 @@ struct DevCSR {
 struct GmState {
     double H[(MOT_MAXM + 1) * MOT_MAXM];   // column j at H[j*(M+1) + i]
     double h1[MOT_MAXM + 1];
+    double h2[MOT_MAXM + 1];                // re-orthogonalisation coefficients
     double cs[MOT_MAXM], sn[MOT_MAXM], g[MOT_MAXM + 1], y[MOT_MAXM];
     double beta, bnorm, relres, inv_h;
     int j, done, converged, total, cycle_iters, breakdown;
@@ -145,8 +146,8 @@ struct mot_handle {
     // GMRES workspace (R = 1 path)
     double* V = nullptr;             // [M+1][n2]
     double* Z = nullptr;             // [M+1][n2]  preconditioned basis M v_j
-    float* M32 = nullptr;            // [n2][n2]   approximate Q_0^-1 (FP32)
-    double* M64 = nullptr;           // [n2][n2]   approximate Q_0^-1 (FP64)
+    float* M32 = nullptr;            // [n2][n2]   approximate Q_0^-1 (FP32); 16x16 tiles when Rp > 1
+    double* M64 = nullptr;           // [n2][n2]   approximate Q_0^-1 (FP64); 16x16 tiles when Rp > 1
     int ns_iters = 0;                // Newton-Schulz iterations used
     double ns_resid = 0;             // ||I - M Q_0||_F reached
     double* wA = nullptr;
@@ -162,6 +163,9 @@ struct mot_handle {
     int hilo = 0;                    // lags with a low part
     int spec_iters = 1;              // Arnoldi steps queued per speculative step
     int hist_kc = 1, q0_kc = 1;      // K chunks of the tile products
+    int plain_kc = 1;                // K chunks of the preconditioner product (Rp > 1)
+    int orth_nb = 1, orth_rb = 1;    // workgroups and rows of the multi-RHS Krylov sweeps
+    double* orth_part = nullptr;     // [orth_nb][MOT_MAXM + 1][Rp] per-workgroup column sums
     GmFlag* hflag = nullptr;         // pinned, device-mapped
     GmFlag* dflag = nullptr;
     int M = 40;

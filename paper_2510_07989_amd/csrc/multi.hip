@@ -22,8 +22,6 @@
 
 namespace {
 
-constexpr int TM = 64;    // rows per workgroup tile
-constexpr int TK = 32;    // K slice staged in LDS
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -61,61 +59,6 @@ __global__ void k_struct_reduce(int ne, int hs, const int* __restrict__ dk, int 
     }
 }
 
-// Plain product for one row tile and K chunk: part[kc][n][RP] = A[rows][K] X[K][RP]
-// (A in FP64 or FP32; the approximate inverse of Q_0).
-template <int RP, typename T>
-__global__ __launch_bounds__(256) void k_plain_gemm(int n, const T* __restrict__ A, const double* __restrict__ X,
-                                                    int KC, double* __restrict__ part,
-                                                    const GmState* __restrict__ agg) {
-    if (agg->done || agg->halt) return;
-    const int m0 = blockIdx.x * TM;
-    const int kc = blockIdx.z;
-    const int KL = ((n + KC - 1) / KC + TK - 1) / TK * TK;
-    const int kb = kc * KL, ke = min(n, kb + KL);
-    __shared__ double As[TK][TM + 1];
-    __shared__ double Ws[TK][RP];
-    constexpr int RPT = TM * RP / 256;
-    constexpr int RG = 256 / RP;
-    const int t = threadIdx.x;
-    const int c = t % RP, rg = t / RP;
-    double acc[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) acc[i] = 0.0;
-    for (int k0 = kb; k0 < ke; k0 += TK) {
-#pragma unroll
-        for (int q = 0; q < TM * TK / 256; ++q) {
-            int e = t + 256 * q;
-            int row = e / TK, col = e % TK;
-            int gm = m0 + row, gk = k0 + col;
-            As[col][row] = (gm < n && gk < ke) ? (double)__builtin_nontemporal_load(A + (size_t)gm * n + gk) : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < (TK * RP + 255) / 256; ++q) {
-            int e = t + 256 * q;
-            if (e < TK * RP) {
-                int kk = e / RP, cc = e % RP;
-                int gk = k0 + kk;
-                Ws[kk][cc] = gk < ke ? X[(size_t)gk * RP + cc] : 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            const double w = Ws[kk][c];
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) acc[i] = fma(As[kk][rg + i * RG], w, acc[i]);
-        }
-        __syncthreads();
-    }
-    double* P = part + (size_t)kc * n * RP;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int gm = m0 + rg + i * RG;
-        if (gm < n) P[(size_t)gm * RP + c] = acc[i];
-    }
-}
-
-// z = (sum of partials) * inv_h[c] ; vj = src * inv_h[c]
 template <int RP>
 __global__ void k_plain_reduce(int n, int KC, const double* __restrict__ part, const double* __restrict__ src,
                                const GmState* __restrict__ gms, const GmState* __restrict__ agg,
@@ -179,78 +122,151 @@ __device__ __forceinline__ bool last_of_grid(unsigned int* counter) {
 }
 
 // one workgroup per column: r = y - t (or y), beta, bnorm; x = 0 when cold
-__global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, const double* __restrict__ y,
+// Start and Arnoldi steps for all columns at once.  Workgroups own ranges of
+// RB rows and all RP columns (thread t: column t % RP, rows t / RP, t / RP +
+// 256 / RP, ...: consecutive threads read consecutive addresses); each sweep
+// writes per-workgroup column sums to part[block][l][c], and the last
+// workgroup of the grid adds them in block order (deterministic) and carries
+// the per-column state.
+__device__ __forceinline__ void col_sums(double s, int RP, double* red, double* out) {
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < RP) {
+        double a = 0.0;
+        for (int k = threadIdx.x; k < 256; k += RP) a += red[k];
+        out[threadIdx.x] = a;
+    }
+    __syncthreads();
+}
+
+// r = y - t (have_t) or y; x = 0 (xzero); beta = ||r||, ||y|| per column.
+__global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB, const double* __restrict__ y,
                                                    double* __restrict__ r, int have_t, GmState* gms,
                                                    GmState* agg, GmFlag* flag, double tol, int first,
-                                                   double* __restrict__ xzero) {
+                                                   double* __restrict__ xzero, double* __restrict__ part) {
     if (agg->halt) return;
-    __shared__ double sh[4];
-    const int c = blockIdx.x;
+    __shared__ double red[256];
+    const int c = threadIdx.x % RP, r0 = threadIdx.x / RP, stride = 256 / RP;
+    const int i0 = blockIdx.x * RB, i1 = min(n2, i0 + RB);
     double s1 = 0, s2 = 0;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    for (int i = i0 + r0; i < i1; i += stride) {
         const size_t o = (size_t)i * RP + c;
         if (xzero) xzero[o] = 0.0;
-        double bi = y[o];
-        double ri = have_t ? bi - r[o] : bi;
+        const double bi = y[o];
+        const double ri = have_t ? bi - r[o] : bi;
         r[o] = ri;
         s1 = fma(ri, ri, s1);
         s2 = fma(bi, bi, s2);
     }
-    s1 = bsum(s1, sh);
-    s2 = bsum(s2, sh);
-    if (threadIdx.x == 0) {
+    double* P = part + (size_t)blockIdx.x * (MOT_MAXM + 1) * RP;
+    col_sums(s1, RP, red, P);
+    col_sums(s2, RP, red, P + RP);
+    if (!last_of_grid(&agg->counter)) return;
+    if ((int)threadIdx.x < RP) {
+        double a1 = 0, a2 = 0;
+        for (int b = 0; b < (int)gridDim.x; ++b) {
+            const double* Pb = part + (size_t)b * (MOT_MAXM + 1) * RP;
+            a1 += Pb[c];
+            a2 += Pb[RP + c];
+        }
         GmState* g = gms + c;
-        double beta = sqrt(s1);
-        if (first) { g->bnorm = sqrt(s2); g->total = 0; }
+        const double beta = sqrt(a1);
+        if (first) { g->bnorm = sqrt(a2); g->total = 0; }
         g->beta = beta;
         g->g[0] = beta;
         g->j = 0;
         g->cycle_iters = 0;
-        double bn = g->bnorm;
+        const double bn = g->bnorm;
         g->relres = bn > 0 ? beta / bn : 0.0;
-        int conv = (bn == 0.0) || (beta <= tol * bn);
+        const int conv = (bn == 0.0) || (beta <= tol * bn);
         g->converged = conv;
         g->done = conv;
         g->inv_h = beta > 0 ? 1.0 / beta : 0.0;
     }
-    if (first && blockIdx.x == 0 && threadIdx.x == 0) agg->seq = 0;
-    if (!last_of_grid(&agg->counter)) return;
-    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (first) agg->seq = 0;
+        aggregate(RP, R, gms, agg, flag, 0);
+    }
 }
 
-// one workgroup per column: CGS2 of w[:, c] against V[0..j][:, c], norm, Givens
-__global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const double* __restrict__ V,
-                                                  double* __restrict__ w, GmState* gms, GmState* agg,
-                                                  GmFlag* flag, double tol, int M) {
+// Arnoldi step, classical Gram-Schmidt with one re-orthogonalisation, in three
+// sweeps over w (the new Krylov vector, in place) and the basis V_0..V_j:
+//   1: h1_l = <V_l, w>
+//   2: w -= sum_l h1_l V_l;  h2_l = <V_l, w>
+//   3: w -= sum_l h2_l V_l;  ||w||, then H column, Givens, residual estimate.
+// Columns whose cycle is done are left as they are.
+__global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB, int sweep,
+                                                  const double* __restrict__ V, double* __restrict__ w,
+                                                  GmState* gms, GmState* agg, GmFlag* flag, double tol, int M,
+                                                  double* __restrict__ part) {
+    // once every column is done the sweeps do no arithmetic, but the third
+    // still publishes a progress word (the host-driven solve waits for one
+    // word per Arnoldi step)
     if (agg->halt) return;
-    __shared__ double sh[4];
-    __shared__ double hc[MOT_MAXM + 1];
-    const int c = blockIdx.x;
+    __shared__ double red[256];
+    __shared__ int jmax_s;
+    const int c = threadIdx.x % RP, r0 = threadIdx.x / RP, stride = 256 / RP;
     GmState* g = gms + c;
-    const bool active = !g->done && !agg->done;
-    if (active) {
-        const int j = g->j;
-        if (threadIdx.x <= j) hc[threadIdx.x] = 0.0;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int l = 0; l <= j; ++l) {
-                const double* v = V + (size_t)l * n2 * RP;
-                double s = 0;
-                for (int i = threadIdx.x; i < n2; i += blockDim.x) s = fma(v[(size_t)i * RP + c], w[(size_t)i * RP + c], s);
-                s = bsum(s, sh);
-                for (int i = threadIdx.x; i < n2; i += blockDim.x)
-                    w[(size_t)i * RP + c] = fma(-s, v[(size_t)i * RP + c], w[(size_t)i * RP + c]);
-                if (threadIdx.x == 0) hc[l] += s;
-                __syncthreads();
-            }
+    const bool active = !agg->done && !g->done;
+    const int jc = active ? g->j : -1;
+    if (threadIdx.x == 0) {
+        int jm = -1;
+        if (!agg->done)
+            for (int q = 0; q < RP; ++q)
+                if (!gms[q].done) jm = max(jm, gms[q].j);
+        jmax_s = jm;
+    }
+    __syncthreads();
+    const int J = jmax_s;
+    const int i0 = blockIdx.x * RB, i1 = min(n2, i0 + RB);
+    const size_t vs = (size_t)n2 * RP;
+    double* P = part + (size_t)blockIdx.x * (MOT_MAXM + 1) * RP;
+    if (sweep > 1 && active) {
+        const double* h = sweep == 2 ? g->h1 : g->h2;
+        for (int i = i0 + r0; i < i1; i += stride) {
+            const size_t o = (size_t)i * RP + c;
+            double x = w[o];
+            for (int l = 0; l <= jc; ++l) x = fma(-h[l], V[l * vs + o], x);
+            w[o] = x;
         }
-        double nn = 0;
-        for (int i = threadIdx.x; i < n2; i += blockDim.x) nn = fma(w[(size_t)i * RP + c], w[(size_t)i * RP + c], nn);
-        nn = bsum(nn, sh);
-        if (threadIdx.x == 0) {
+    }
+    if (sweep < 3) {
+        for (int l = 0; l <= J; ++l) {
+            double s = 0;
+            if (active && l <= jc)
+                for (int i = i0 + r0; i < i1; i += stride) {
+                    const size_t o = (size_t)i * RP + c;
+                    s = fma(V[l * vs + o], w[o], s);
+                }
+            col_sums(s, RP, red, P + (size_t)l * RP);
+        }
+    } else {
+        double s = 0;
+        if (active)
+            for (int i = i0 + r0; i < i1; i += stride) {
+                const double x = w[(size_t)i * RP + c];
+                s = fma(x, x, s);
+            }
+        col_sums(s, RP, red, P);
+    }
+    if (!last_of_grid(&agg->counter)) return;
+    if ((int)threadIdx.x < RP && active) {
+        if (sweep < 3) {
+            double* h = sweep == 1 ? g->h1 : g->h2;
+            for (int l = 0; l <= jc; ++l) {
+                double a = 0;
+                for (int b = 0; b < (int)gridDim.x; ++b) a += part[((size_t)b * (MOT_MAXM + 1) + l) * RP + c];
+                h[l] = a;
+            }
+        } else {
+            double nn = 0;
+            for (int b = 0; b < (int)gridDim.x; ++b) nn += part[(size_t)b * (MOT_MAXM + 1) * RP + c];
+            const int j = jc;
             const double hn = sqrt(nn);
             double* col = g->H + (size_t)j * (M + 1);
             double cl[MOT_MAXM + 1];
-            for (int l = 0; l <= j; ++l) cl[l] = hc[l];
+            for (int l = 0; l <= j; ++l) cl[l] = g->h1[l] + g->h2[l];
             cl[j + 1] = hn;
             for (int l = 0; l < j; ++l) {
                 double a = cl[l], b = cl[l + 1];
@@ -258,9 +274,9 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const d
                 cl[l + 1] = -g->sn[l] * a + g->cs[l] * b;
             }
             double a = cl[j], b = cl[j + 1];
-            double r = hypot(a, b);
-            double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
-            cl[j] = r;
+            double rr = hypot(a, b);
+            double cs = rr > 0 ? a / rr : 1.0, sn = rr > 0 ? b / rr : 0.0;
+            cl[j] = rr;
             cl[j + 1] = 0.0;
             for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
             g->cs[j] = cs;
@@ -281,16 +297,19 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, const d
             g->inv_h = hn > 0 ? 1.0 / hn : 0.0;
             if (g->done) {
                 for (int i = jn - 1; i >= 0; --i) {
-                    double s = g->g[i];
-                    for (int l = i + 1; l < jn; ++l) s -= g->H[(size_t)l * (M + 1) + i] * g->y[l];
+                    double s2 = g->g[i];
+                    for (int l = i + 1; l < jn; ++l) s2 -= g->H[(size_t)l * (M + 1) + i] * g->y[l];
                     double d = g->H[(size_t)i * (M + 1) + i];
-                    g->y[i] = d != 0 ? s / d : 0.0;
+                    g->y[i] = d != 0 ? s2 / d : 0.0;
                 }
             }
         }
     }
-    if (!last_of_grid(&agg->counter)) return;
-    if (threadIdx.x == 0) aggregate(RP, R, gms, agg, flag, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sweep == 3) aggregate(RP, R, gms, agg, flag, 1);
+        else agg->counter = 0;
+    }
 }
 
 // x[:, c] += sum_l y_l(c) Z_l[:, c] for columns whose cycle is done (once per
@@ -546,6 +565,78 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
     }
 }
 
+// Plain product z = M x with the approximate inverse of Q_0 stored in tiles
+// (n x n, FP64 or FP32 entries, FP64 MFMA): one 64-row block and one K chunk
+// per workgroup, partial results part[kc][n][Rp] (summed and scaled by
+// k_plain_reduce).  Skipped once every column's GMRES is done.
+template <typename T, int CB>
+__global__ __launch_bounds__(256) void k_tile_plain(int n, int G16, int KT, int Rp, const T* __restrict__ At,
+                                                    const double* __restrict__ X, int KC,
+                                                    double* __restrict__ part, const GmState* __restrict__ agg) {
+    if (agg->done || agg->halt) return;
+    const int kc = blockIdx.z;
+    const int CT = (KT + KC - 1) / KC;
+    const int c0 = kc * CT, c1 = min(KT, c0 + CT);
+    constexpr int NC = CB * 16;
+    constexpr int ST = CB >= 4 ? 2 : 4;
+    __shared__ double Ws[ST * 16][NC + 2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int g = blockIdx.x * 4 + wv;
+    const bool gok = g < G16;
+    const int kq = 4 * (lane >> 4), cl = lane & 15;
+    constexpr int NS = CB == 1 ? 2 : 1;
+    v4d C[CB][NS];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) C[cb][s2] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double nx[4];
+    if (gok && c0 < c1) load_tile(At + ((size_t)g * KT + c0) * 256, lane, nx);
+    for (int cs = c0; cs < c1; cs += ST) {
+        const int nst = min(ST, c1 - cs);
+        for (int e = t; e < ST * 16 * NC; e += 256) {
+            const int col = e % NC, kk = e / NC;
+            const int gk = cs * 16 + kk;
+            Ws[kk][col] = (col < Rp && kk < nst * 16 && gk < n) ? X[(size_t)gk * Rp + col] : 0.0;
+        }
+        __syncthreads();
+        for (int ci = 0; ci < nst; ++ci) {
+            double a[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[e] = nx[e];
+            if (gok && cs + ci + 1 < c1) load_tile(At + ((size_t)g * KT + cs + ci + 1) * 256, lane, nx);
+            if (gok) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int kk = ci * 16 + kq + e;
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        C[cb][e % NS] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], Ws[kk][cb * 16 + cl], C[cb][e % NS],
+                                                                             0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!gok) return;
+    double* P = part + (size_t)kc * n * Rp;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = cb * 16 + cl;
+        if (col >= Rp) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = g * 16 + (lane >> 4) + 4 * r;
+            if (row < n) {
+                double sum = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) sum += C[cb][s2][r];
+                P[(size_t)row * Rp + col] = sum;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------ FP32 MFMA history ---
 // History with FP32 products (v_mfma_f32_16x16x4f32) on the FP32 tiles:
 //   Q W ~ Q_hi W_hi + Q_hi W_lo + Q_lo W_hi   on lags 1..hilo, Q_hi W_hi beyond.
@@ -701,23 +792,20 @@ __global__ __launch_bounds__(256) void k_hist_mfma(int ne, int hs, int G16, int 
     }
 }
 
-int pick_kc(int tiles, int groups, int K) {
-    int want = (1024 + tiles * groups - 1) / (tiles * groups);
-    int maxkc = K / (4 * TK);
-    if (maxkc < 1) maxkc = 1;
-    return want < 1 ? 1 : (want > maxkc ? maxkc : want);
-}
 
 template <int RP>
 void plain_product(mot_handle* h, const double* src, double* vj, double* z) {
     const int n = h->n2;
-    const int tiles = (n + TM - 1) / TM;
-    const int KC = pick_kc(tiles, 1, n);
-    dim3 grid(tiles, 1, KC);
+    const int KC = h->plain_kc;
+    const int G16 = n / 16, KT = n / 16;
+    dim3 grid((G16 + 3) / 4, 1, KC);
+    constexpr int CB = RP >= 64 ? 4 : (RP >= 32 ? 2 : 1);
     if (h->M32)
-        hipLaunchKernelGGL((k_plain_gemm<RP, float>), grid, dim3(256), 0, h->stream, n, h->M32, src, KC, h->mr_part, h->gm);
+        hipLaunchKernelGGL((k_tile_plain<float, CB>), grid, dim3(256), 0, h->stream, n, G16, KT, RP, h->M32, src, KC,
+                           h->mr_part, h->gm);
     else
-        hipLaunchKernelGGL((k_plain_gemm<RP, double>), grid, dim3(256), 0, h->stream, n, h->M64, src, KC, h->mr_part, h->gm);
+        hipLaunchKernelGGL((k_tile_plain<double, CB>), grid, dim3(256), 0, h->stream, n, G16, KT, RP, h->M64, src, KC,
+                           h->mr_part, h->gm);
     hipLaunchKernelGGL(k_plain_reduce<RP>, dim3((n * RP + 255) / 256), dim3(256), 0, h->stream, n, KC, h->mr_part, src,
                        h->gms, h->gm, z, vj);
 }
@@ -766,15 +854,24 @@ void plan_tiles(mot_handle* h) {
     const int gx = (h->G16 + 3) / 4;
     h->hist_kc = tile_kc(gx * h->nh, h->KT, MTK / 16);
     h->q0_kc = tile_kc(gx, h->KT, 4);
+    // the approximate inverse (n2 x n2 tiles): about 1024 workgroups
+    const int gp = (h->n2 / 16 + 3) / 4;
+    int want = (1024 + gp - 1) / gp, maxkc = std::max(1, h->n2 / 64);
+    h->plain_kc = std::max(1, std::min(want, maxkc));
+    // Krylov sweeps: about 1024 (row, column) entries per workgroup
+    h->orth_nb = std::max(1, std::min(480, (int)(((size_t)h->n2 * h->Rp + 1023) / 1024)));
+    h->orth_rb = (h->n2 + h->orth_nb - 1) / h->orth_nb;
+    h->orth_nb = (h->n2 + h->orth_rb - 1) / h->orth_rb;
 }
+
+size_t orth_part_doubles(const mot_handle* h) { return (size_t)h->orth_nb * (MOT_MAXM + 1) * h->Rp; }
 
 size_t tile_elems(const mot_handle* h) { return (size_t)h->G16 * h->KT * 256; }
 
 size_t part_doubles(const mot_handle* h) {
     size_t a = (size_t)h->nh * h->hist_kc * 2 * h->ne * h->Rp;
     size_t b = (size_t)h->q0_kc * 2 * h->ne * h->Rp;
-    const int t2 = (h->n2 + TM - 1) / TM;
-    size_t c = (size_t)pick_kc(t2, 1, h->n2) * h->n2 * h->Rp;
+    size_t c = (size_t)h->plain_kc * h->n2 * h->Rp;
     return std::max(a, std::max(b, c));
 }
 
@@ -841,6 +938,13 @@ void pack_lag(mot_handle* h, int lag) {
     }
 }
 
+// The approximate inverse (n2 x n2, row-major X) into tiles, FP64 or FP32.
+void pack_square(mot_handle* h, const double* X, double* t64, float* t32) {
+    const int n = h->n2;
+    hipLaunchKernelGGL(k_pack_tiles, dim3(4096), dim3(256), 0, h->stream, n, n, n / 16, n / 16, X, t64, t32,
+                       (float*)nullptr);
+}
+
 void q0_gemm(mot_handle* h, const double* X) { tile_launch<double>(h, 1, h->Qt, nullptr, X, h->q0_kc, 1); }
 
 void q0_reduce(mot_handle* h, double* out) { reduce(h, 1, h->q0_kc, out); }
@@ -852,13 +956,14 @@ void precond(mot_handle* h, const double* src, double* vj, double* z) {
 }
 
 void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero) {
-    hipLaunchKernelGGL(k_gmb_start, dim3(h->Rp), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, y, r, have_t, h->gms,
-                       h->gm, h->dflag, h->opt.gmres_tol, first, xzero);
+    hipLaunchKernelGGL(k_gmb_start, dim3(h->orth_nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->orth_rb, y, r,
+                       have_t, h->gms, h->gm, h->dflag, h->opt.gmres_tol, first, xzero, h->orth_part);
 }
 
 void orth(mot_handle* h, double* w) {
-    hipLaunchKernelGGL(k_gmb_orth, dim3(h->Rp), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->V, w, h->gms, h->gm,
-                       h->dflag, h->opt.gmres_tol, h->M);
+    for (int sweep = 1; sweep <= 3; ++sweep)
+        hipLaunchKernelGGL(k_gmb_orth, dim3(h->orth_nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->orth_rb,
+                           sweep, h->V, w, h->gms, h->gm, h->dflag, h->opt.gmres_tol, h->M, h->orth_part);
 }
 
 void finish(mot_handle* h, int force, int spec) {
