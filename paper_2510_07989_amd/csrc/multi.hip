@@ -41,12 +41,19 @@ __global__ void k_struct_reduce(int ne, int hs, const int* __restrict__ dk, int 
     const int m = t / RP, c = t % RP;
     const int k = *dk;
     const int nact = q0_mode ? 1 : (k - 1 < nh ? k - 1 : nh);
-    double su = 0, sv = 0;
-    for (int p = 0; p < nact * KC; ++p) {
-        const double* P = part + (size_t)p * 2 * ne * RP;
-        su += P[(size_t)m * RP + c];
-        sv += P[(size_t)(ne + m) * RP + c];
+    // four interleaved partial sums keep several loads in flight
+    double su4[4] = {0, 0, 0, 0}, sv4[4] = {0, 0, 0, 0};
+    const int np = nact * KC;
+    const size_t stride = (size_t)2 * ne * RP;
+    const double* Pu = part + (size_t)m * RP + c;
+    const double* Pv = part + (size_t)(ne + m) * RP + c;
+#pragma unroll 4
+    for (int p = 0; p < np; ++p) {
+        su4[p & 3] += Pu[(size_t)p * stride];
+        sv4[p & 3] += Pv[(size_t)p * stride];
     }
+    const double su = (su4[0] + su4[1]) + (su4[2] + su4[3]);
+    const double sv = (sv4[0] + sv4[1]) + (sv4[2] + sv4[3]);
     if (q0_mode) {
         y[(size_t)m * RP + c] = su;
         y[(size_t)(hs + m) * RP + c] = sv;
@@ -87,28 +94,44 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 }
 
 // Combine the column states into the aggregate state and publish one word.
+// Called by every thread of one workgroup: threads c < RP read column c (the
+// states are far apart in memory, so the reads go out together), thread 0
+// combines them from LDS.
 __device__ void aggregate(int RP, int R, GmState* gms, GmState* agg, GmFlag* flag, int arnoldi) {
-    if (arnoldi) agg->iters_all += 1;
-    int done = 1, conv = 1, total = 0;
-    double rel = 0;
-    for (int c = 0; c < RP; ++c) {
-        done &= gms[c].done;
-        conv &= gms[c].converged;
-        if (c < R) { total = max(total, gms[c].total); rel = fmax(rel, gms[c].relres); }
+    __shared__ int s_done[64], s_conv[64], s_total[64];
+    __shared__ double s_rel[64];
+    const int c = threadIdx.x;
+    if (c < RP) {
+        const GmState* g = gms + c;
+        s_done[c] = g->done;
+        s_conv[c] = g->converged;
+        s_total[c] = g->total;
+        s_rel[c] = g->relres;
     }
-    agg->done = done;
-    agg->converged = done && conv;
-    agg->total = total;
-    agg->relres = rel;
-    agg->counter = 0;
-    const int seq = agg->seq + 1;
-    agg->seq = seq;
-    flag->relres = rel;
-    flag->converged = done && conv;
-    flag->done = done;
-    flag->total = total;
-    __threadfence_system();
-    flag->seq = seq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int done = 1, conv = 1, total = 0;
+        double rel = 0;
+        for (int q = 0; q < RP; ++q) {
+            done &= s_done[q];
+            conv &= s_conv[q];
+            if (q < R) { total = max(total, s_total[q]); rel = fmax(rel, s_rel[q]); }
+        }
+        if (arnoldi) agg->iters_all += 1;
+        agg->done = done;
+        agg->converged = done && conv;
+        agg->total = total;
+        agg->relres = rel;
+        agg->counter = 0;
+        const int seq = agg->seq + 1;
+        agg->seq = seq;
+        flag->relres = rel;
+        flag->converged = done && conv;
+        flag->done = done;
+        flag->total = total;
+        __threadfence_system();
+        flag->seq = seq;
+    }
 }
 
 __device__ __forceinline__ bool last_of_grid(unsigned int* counter) {
@@ -139,6 +162,23 @@ __device__ __forceinline__ void col_sums(double s, int RP, double* red, double* 
     __syncthreads();
 }
 
+// In the last workgroup: the sum over workgroups b of part[b][l][c] for one l
+// and every column, spread over all 256 threads (256 / RP per column, then a
+// fixed-order sum in LDS); threads c < RP get column c's value.
+__device__ __forceinline__ double grid_col_sum(const double* __restrict__ part, int nb, int RP, int l,
+                                               double* red) {
+    const int c = threadIdx.x % RP, q = threadIdx.x / RP, nq = 256 / RP;
+    double a = 0.0;
+    for (int b = q; b < nb; b += nq) a += part[((size_t)b * (MOT_MAXM + 1) + l) * RP + c];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x < RP)
+        for (int k = 0; k < nq; ++k) s += red[threadIdx.x + k * RP];
+    __syncthreads();
+    return s;
+}
+
 // r = y - t (have_t) or y; x = 0 (xzero); beta = ||r||, ||y|| per column.
 __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB, const double* __restrict__ y,
                                                    double* __restrict__ r, int have_t, GmState* gms,
@@ -162,13 +202,10 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB
     col_sums(s1, RP, red, P);
     col_sums(s2, RP, red, P + RP);
     if (!last_of_grid(&agg->counter)) return;
+    // part[b][0][c] and part[b][RP + c] = part[b][1][c]
+    const double a1 = grid_col_sum(part, gridDim.x, RP, 0, red);
+    const double a2 = grid_col_sum(part, gridDim.x, RP, 1, red);
     if ((int)threadIdx.x < RP) {
-        double a1 = 0, a2 = 0;
-        for (int b = 0; b < (int)gridDim.x; ++b) {
-            const double* Pb = part + (size_t)b * (MOT_MAXM + 1) * RP;
-            a1 += Pb[c];
-            a2 += Pb[RP + c];
-        }
         GmState* g = gms + c;
         const double beta = sqrt(a1);
         if (first) { g->bnorm = sqrt(a2); g->total = 0; }
@@ -184,10 +221,9 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB
         g->inv_h = beta > 0 ? 1.0 / beta : 0.0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (first) agg->seq = 0;
-        aggregate(RP, R, gms, agg, flag, 0);
-    }
+    if (first && threadIdx.x == 0) agg->seq = 0;
+    __syncthreads();
+    aggregate(RP, R, gms, agg, flag, 0);
 }
 
 // Arnoldi step, classical Gram-Schmidt with one re-orthogonalisation, in three
@@ -210,11 +246,12 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB,
     GmState* g = gms + c;
     const bool active = !agg->done && !g->done;
     const int jc = active ? g->j : -1;
+    __shared__ int s_j[64];
+    if ((int)threadIdx.x < RP) s_j[threadIdx.x] = active ? jc : -1;
+    __syncthreads();
     if (threadIdx.x == 0) {
         int jm = -1;
-        if (!agg->done)
-            for (int q = 0; q < RP; ++q)
-                if (!gms[q].done) jm = max(jm, gms[q].j);
+        for (int q = 0; q < RP; ++q) jm = max(jm, s_j[q]);
         jmax_s = jm;
     }
     __syncthreads();
@@ -251,17 +288,15 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB,
         col_sums(s, RP, red, P);
     }
     if (!last_of_grid(&agg->counter)) return;
+    if (sweep < 3) {
+        for (int l = 0; l <= J; ++l) {
+            const double a = grid_col_sum(part, gridDim.x, RP, l, red);
+            if ((int)threadIdx.x < RP && active && l <= jc) (sweep == 1 ? g->h1 : g->h2)[l] = a;
+        }
+    }
+    const double nn = sweep == 3 ? grid_col_sum(part, gridDim.x, RP, 0, red) : 0.0;
     if ((int)threadIdx.x < RP && active) {
-        if (sweep < 3) {
-            double* h = sweep == 1 ? g->h1 : g->h2;
-            for (int l = 0; l <= jc; ++l) {
-                double a = 0;
-                for (int b = 0; b < (int)gridDim.x; ++b) a += part[((size_t)b * (MOT_MAXM + 1) + l) * RP + c];
-                h[l] = a;
-            }
-        } else {
-            double nn = 0;
-            for (int b = 0; b < (int)gridDim.x; ++b) nn += part[(size_t)b * (MOT_MAXM + 1) * RP + c];
+        if (sweep == 3) {
             const int j = jc;
             const double hn = sqrt(nn);
             double* col = g->H + (size_t)j * (M + 1);
@@ -306,10 +341,8 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB,
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (sweep == 3) aggregate(RP, R, gms, agg, flag, 1);
-        else agg->counter = 0;
-    }
+    if (sweep == 3) aggregate(RP, R, gms, agg, flag, 1);
+    else if (threadIdx.x == 0) agg->counter = 0;
 }
 
 // x[:, c] += sum_l y_l(c) Z_l[:, c] for columns whose cycle is done (once per
