@@ -12,8 +12,8 @@
 namespace motk_step {
 void rhs_batch(mot_handle* h, int k0, double* rb);
 void history(mot_handle* h);
-void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero);
-void gm_orth1(mot_handle* h, double* w);
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish = 1);
+void gm_orth1(mot_handle* h, double* w, int publish = 1);
 void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
@@ -42,8 +42,8 @@ void history_reduce(mot_handle* h);
 void q0_gemm(mot_handle* h, const double* X);
 void q0_reduce(mot_handle* h, double* out);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
-void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero);
-void orth(mot_handle* h, double* w);
+void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero, int publish = 1);
+void orth(mot_handle* h, double* w, int publish = 1);
 void finish(mot_handle* h, int force, int spec = 0);
 void plan_tiles(mot_handle* h);
 size_t tile_elems(const mot_handle* h);
@@ -1197,7 +1197,7 @@ int mot_step(mot_handle* h, mot_step_info* info) {
 // window (at most one RHS batch long, so a batch computed ahead for a later
 // window never overwrites the one a halted step needs) and finishes a halted
 // step with the host-driven solve, then queues again from the next step.
-struct SpecWord { int halt, halt_k, iters_all; };
+struct SpecWord { int halt, halt_k, iters_all; double relres; };
 
 static bool spec_ok(const mot_handle* h) {
     if (h->opt.spec_window < 0 || !(h->M32 || h->M64)) return false;
@@ -1218,7 +1218,7 @@ static int queue_spec_step(mot_handle* h) {
         // R waves: one cold-started GMRES per column, products shared
         const size_t vs = (size_t)h->n2 * h->Rp;
         mm::history_reduce(h);
-        mm::start(h, h->y, h->wA, 0, 1, h->x);
+        mm::start(h, h->y, h->wA, 0, 1, h->x, 0);
         double* src = h->wA;
         double* dst = h->wB;
         for (int j = 0; j < h->spec_iters; ++j) {
@@ -1227,7 +1227,7 @@ static int queue_spec_step(mot_handle* h) {
             mm::q0_gemm(h, h->Z + (size_t)j * vs);
             if ((prc = ev_end(h, h->ev_q0))) return prc;
             mm::q0_reduce(h, dst);
-            mm::orth(h, dst);
+            mm::orth(h, dst, 0);
             std::swap(src, dst);
         }
         mm::finish(h, 0, 1);
@@ -1238,9 +1238,9 @@ static int queue_spec_step(mot_handle* h) {
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
-        gm_start1(h, h->y, h->wA, 1, 1, nullptr);
+        gm_start1(h, h->y, h->wA, 1, 1, nullptr, 0);
     } else {
-        gm_start1(h, h->y, h->wA, 0, 1, h->x);
+        gm_start1(h, h->y, h->wA, 0, 1, h->x, 0);
     }
     double* src = h->wA;
     double* dst = h->wB;
@@ -1249,7 +1249,7 @@ static int queue_spec_step(mot_handle* h) {
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->Z + (size_t)j * h->n2, nullptr, dst, 1, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
-        gm_orth1(h, dst);
+        gm_orth1(h, dst, 0);
         std::swap(src, dst);
     }
     gm_finish(h, h->Z, 0, 1);
@@ -1257,7 +1257,8 @@ static int queue_spec_step(mot_handle* h) {
 }
 
 static int read_spec(mot_handle* h, SpecWord* w) {
-    HIPCHK(h, hipMemcpyAsync(w, &h->gm->halt, sizeof(SpecWord), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(w, &h->gm->halt, 3 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&w->relres, &h->gm->relres, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MOT_OK;
 }
@@ -1281,7 +1282,7 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
         if (!w.halt) {
             done += nw;
             h->last_iters = h->spec_iters;
-            h->last_relres = h->hflag->relres;
+            h->last_relres = w.relres;
             h->last_conv = 1;
             continue;
         }

@@ -125,12 +125,14 @@ __device__ void aggregate(int RP, int R, GmState* gms, GmState* agg, GmFlag* fla
         agg->counter = 0;
         const int seq = agg->seq + 1;
         agg->seq = seq;
-        flag->relres = rel;
-        flag->converged = done && conv;
-        flag->done = done;
-        flag->total = total;
-        __threadfence_system();
-        flag->seq = seq;
+        if (flag) {               // null: queued steps, nobody waits on the host
+            flag->relres = rel;
+            flag->converged = done && conv;
+            flag->done = done;
+            flag->total = total;
+            __threadfence_system();
+            flag->seq = seq;
+        }
     }
 }
 
@@ -988,15 +990,17 @@ void precond(mot_handle* h, const double* src, double* vj, double* z) {
 #undef C_
 }
 
-void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero) {
+void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero, int publish) {
     hipLaunchKernelGGL(k_gmb_start, dim3(h->orth_nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->orth_rb, y, r,
-                       have_t, h->gms, h->gm, h->dflag, h->opt.gmres_tol, first, xzero, h->orth_part);
+                       have_t, h->gms, h->gm, publish ? h->dflag : nullptr, h->opt.gmres_tol, first, xzero,
+                       h->orth_part);
 }
 
-void orth(mot_handle* h, double* w) {
+void orth(mot_handle* h, double* w, int publish) {
     for (int sweep = 1; sweep <= 3; ++sweep)
         hipLaunchKernelGGL(k_gmb_orth, dim3(h->orth_nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->R, h->orth_rb,
-                           sweep, h->V, w, h->gms, h->gm, h->dflag, h->opt.gmres_tol, h->M, h->orth_part);
+                           sweep, h->V, w, h->gms, h->gm, publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M,
+                           h->orth_part);
 }
 
 void finish(mot_handle* h, int force, int spec) {

@@ -644,12 +644,15 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
         gm->converged = conv;
         gm->done = conv;
         gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
-        flag->relres = gm->relres;
-        flag->converged = conv;
-        flag->done = conv;
-        flag->total = gm->total;
-        __threadfence_system();
-        flag->seq = ++gm->seq;
+        ++gm->seq;
+        if (flag) {               // null: queued steps, nobody waits on the host
+            flag->relres = gm->relres;
+            flag->converged = conv;
+            flag->done = conv;
+            flag->total = gm->total;
+            __threadfence_system();
+            flag->seq = gm->seq;
+        }
     }
 }
 
@@ -680,10 +683,12 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
     const int done = conv || brk || jj >= M;
     const int seq = gm->seq + 1;
     // publish the progress word first (host-visible), then the device state
-    flag->relres = rel;
-    flag->converged = conv || brk;
-    flag->done = done;
-    flag->total = total;
+    if (flag) {
+        flag->relres = rel;
+        flag->converged = conv || brk;
+        flag->done = done;
+        flag->total = total;
+    }
     for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
     gm->cs[j] = cs;
     gm->sn[j] = sn;
@@ -707,8 +712,10 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
             gm->y[i] = d != 0 ? s / d : 0.0;
         }
     }
-    __threadfence_system();
-    flag->seq = seq;
+    if (flag) {
+        __threadfence_system();
+        flag->seq = seq;
+    }
 }
 
 // CGS2 of w against V[0..j], norm, Givens: one workgroup.
@@ -719,12 +726,15 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
     if (gm->done) {
         // nothing to do, but every launch publishes one progress word
         if (threadIdx.x == 0) {
-            flag->relres = gm->relres;
-            flag->converged = gm->converged;
-            flag->done = 1;
-            flag->total = gm->total;
-            __threadfence_system();
-            flag->seq = ++gm->seq;
+            ++gm->seq;
+            if (flag) {
+                flag->relres = gm->relres;
+                flag->converged = gm->converged;
+                flag->done = 1;
+                flag->total = gm->total;
+                __threadfence_system();
+                flag->seq = gm->seq;
+            }
         }
         return;
     }
@@ -935,14 +945,14 @@ void history(mot_handle* h) {
                        h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr, h->gm);
 }
 
-void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero) {
-    hipLaunchKernelGGL(k_gm_start1, dim3(1), dim3(kSW), 0, h->stream, h->n2, b, r, have_t, h->gm, h->dflag,
-                       h->opt.gmres_tol, first, xzero);
+void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish) {
+    hipLaunchKernelGGL(k_gm_start1, dim3(1), dim3(kSW), 0, h->stream, h->n2, b, r, have_t, h->gm,
+                       publish ? h->dflag : nullptr, h->opt.gmres_tol, first, xzero);
 }
 
-void gm_orth1(mot_handle* h, double* w) {
-    hipLaunchKernelGGL(k_gm_orth1, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm, h->dflag,
-                       h->opt.gmres_tol, h->M);
+void gm_orth1(mot_handle* h, double* w, int publish) {
+    hipLaunchKernelGGL(k_gm_orth1, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm,
+                       publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M);
 }
 
 void gm_finish(mot_handle* h, const double* basis, int force, int spec) {
