@@ -14,7 +14,7 @@ void rhs_batch(mot_handle* h, int k0, double* rb);
 void history(mot_handle* h);
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish = 1);
 void gm_orth1(mot_handle* h, double* w, int publish = 1);
-void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0);
+void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0, int kq = 0);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void dense_q0(mot_handle* h, double* D);
@@ -30,6 +30,7 @@ void warm_start(mot_handle* h);
 void push(mot_handle* h);
 void inc_step(mot_handle* h);
 void clear_halt(mot_handle* h);
+void set_step(mot_handle* h, int k);
 void rec_gather(mot_handle* h, int s0, int ns, double* X);
 void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, double* loop, double* star);
 void pack(mot_handle* h, int ns, const double* src, double* dst);
@@ -44,7 +45,7 @@ void q0_reduce(mot_handle* h, double* out);
 void precond(mot_handle* h, const double* src, double* vj, double* z);
 void start(mot_handle* h, const double* y, double* r, int have_t, int first, double* xzero, int publish = 1);
 void orth(mot_handle* h, double* w, int publish = 1);
-void finish(mot_handle* h, int force, int spec = 0);
+void finish(mot_handle* h, int force, int spec = 0, int kq = 0);
 void plan_tiles(mot_handle* h);
 size_t tile_elems(const mot_handle* h);
 void pack_lag(mot_handle* h, int lag);
@@ -1204,10 +1205,12 @@ static bool spec_ok(const mot_handle* h) {
     return h->Rp > 1 ? (h->gms && h->mr_part) : h->n2 <= 32768;
 }
 
-static int queue_spec_step(mot_handle* h) {
+// first: the window's first step advances the device step counter; later
+// steps find it set by the previous step's finisher
+static int queue_spec_step(mot_handle* h, bool first) {
     using namespace motk_step;
     namespace mm = motk_multi;
-    inc_step(h);
+    if (first) inc_step(h);
     h->k += 1;
     if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
     int prc;
@@ -1230,7 +1233,7 @@ static int queue_spec_step(mot_handle* h) {
             mm::orth(h, dst, 0);
             std::swap(src, dst);
         }
-        mm::finish(h, 0, 1);
+        mm::finish(h, 0, 1, h->k);
         return MOT_OK;
     }
     if (h->M32) {
@@ -1252,7 +1255,7 @@ static int queue_spec_step(mot_handle* h) {
         gm_orth1(h, dst, 0);
         std::swap(src, dst);
     }
-    gm_finish(h, h->Z, 0, 1);
+    gm_finish(h, h->Z, 0, 1, h->k);
     return MOT_OK;
 }
 
@@ -1269,11 +1272,16 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
     int rc = read_spec(h, &w0);
     if (rc) return rc;
     int done = 0;
+    // the device step counter runs one ahead of h->k after a window in which
+    // every step pushed (the last finisher set it); a halted window leaves it at
+    // the halted step, which is then h->k
+    bool ahead = false;
     while (done < nsteps) {
         const int nw = std::min(win, nsteps - done);
         const int k0 = h->k;
         for (int i = 0; i < nw; ++i)
-            if ((rc = queue_spec_step(h))) return rc;
+            if ((rc = queue_spec_step(h, i == 0 && !ahead))) return rc;
+        ahead = true;
         HIPCHK(h, hipGetLastError());
         SpecWord w{};
         if ((rc = read_spec(h, &w))) return rc;
@@ -1289,6 +1297,7 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
         // steps k0+1 .. halt_k-1 are complete; halt_k has its history in y
         if (w.halt_k <= k0 || w.halt_k > h->k) return mot_fail(h, MOT_EHIP, "speculative halt word out of range");
         h->k = w.halt_k;
+        ahead = false;
         motk_step::clear_halt(h);
         int src = h->Rp > 1 ? gmres_solve_mr(h) : gmres_solve_pc(h);
         if (src && src != MOT_ENOCONV) return src;
@@ -1297,6 +1306,7 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
         h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
         done += w.halt_k - k0;
     }
+    if (ahead) motk_step::set_step(h, h->k);   // as the step-by-step march leaves it
     return MOT_OK;
 }
 
@@ -1305,6 +1315,7 @@ static int run_spec(mot_handle* h, int nsteps, int* worst) {
     int rc = run_spec_windows(h, nsteps, worst);
     if (rc) {
         motk_step::clear_halt(h);
+        motk_step::set_step(h, h->k);
         (void)hipStreamSynchronize(h->stream);
     }
     return rc;

@@ -354,18 +354,21 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB,
 // nothing and raise the halt word, so that later queued steps do nothing.
 __global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmState* gms,
                              GmState* __restrict__ agg, double* __restrict__ x,
-                             const int* __restrict__ dk, int nh, double* __restrict__ ring,
-                             double* __restrict__ hist, int hist_cap, int force, int spec) {
+                             int* __restrict__ dk, int nh, double* __restrict__ ring,
+                             double* __restrict__ hist, int hist_cap, int force, int spec, int kq) {
     if (agg->halt) return;
+    // kq > 0 (queued steps): host step index; the counter is set to kq + 1
+    // after a push (no block of this launch reads it)
+    const int k = kq > 0 ? kq : *dk;
     if (spec && !agg->converged) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            agg->halt_k = *dk;
+            agg->halt_k = k;
             agg->halt = 1;
         }
         return;
     }
-    const int k = *dk;
     const int push = agg->converged || force;
+    if (kq > 0 && push && blockIdx.x == 0 && threadIdx.x == 0) *dk = kq + 1;
     double* slot = ring + (size_t)(k % nh) * n2 * RP;
     double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 * RP : nullptr;
     const size_t total = (size_t)n2 * RP;
@@ -1003,11 +1006,11 @@ void orth(mot_handle* h, double* w, int publish) {
                            h->orth_part);
 }
 
-void finish(mot_handle* h, int force, int spec) {
+void finish(mot_handle* h, int force, int spec, int kq) {
     size_t total = (size_t)h->n2 * h->Rp;
     int nb = (int)std::min<size_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_gmb_finish, dim3(nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->Z, h->gms, h->gm, h->x,
-                       h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec);
+                       h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec, kq);
     hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms, h->gm);
 }
 

@@ -785,14 +785,18 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
 // spec = 1 (speculative stepping): a solve that has not converged pushes
 // nothing and raises the halt word instead, so that the later queued steps do
 // nothing until the host has finished this one.
+// kq > 0 (queued steps): the step index comes from the host, and after a push
+// the device step counter is set to kq + 1 for the next queued step (no block
+// of this launch reads the counter, so the write does not race).
 __global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __restrict__ gm,
-                            double* __restrict__ x, const int* __restrict__ dk, int nh,
+                            double* __restrict__ x, int* __restrict__ dk, int nh,
                             double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force,
-                            int spec) {
+                            int spec, int kq) {
     if (gm->halt) return;
+    const int k = kq > 0 ? kq : *dk;
     if (spec && !(gm->done && gm->converged)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            gm->halt_k = *dk;
+            gm->halt_k = k;
             gm->halt = 1;
         }
         return;
@@ -800,7 +804,7 @@ __global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __re
     if (!gm->done && !force) return;
     const int jj = gm->done ? gm->cycle_iters : 0;
     const int push = gm->converged || force;
-    const int k = *dk;
+    if (kq > 0 && push && blockIdx.x == 0 && threadIdx.x == 0) *dk = kq + 1;
     double* slot = ring + (size_t)(k % nh) * n2;
     double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 : nullptr;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
@@ -861,6 +865,8 @@ __global__ void k_inc_step(int* dk, const GmState* __restrict__ gm) {
 }
 
 __global__ void k_clear_halt(GmState* gm) { gm->halt = 0; }
+
+__global__ void k_set_step(int* dk, int k) { *dk = k; }
 
 // recovery gather: columns (step s in [s0, s1), half h, kind t, rhs r) of
 // X[ne][ncol], kind 0 = u_k, kind 1 = u_k - u_{k-1} (u_0 = 0)
@@ -955,9 +961,9 @@ void gm_orth1(mot_handle* h, double* w, int publish) {
                        publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M);
 }
 
-void gm_finish(mot_handle* h, const double* basis, int force, int spec) {
+void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) {
     hipLaunchKernelGGL(k_gm_finish, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, basis, h->gm,
-                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec);
+                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec, kq);
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
@@ -1027,6 +1033,8 @@ void push(mot_handle* h) {
 void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 0, h->stream, h->d_k, h->gm); }
 
 void clear_halt(mot_handle* h) { hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(1), 0, h->stream, h->gm); }
+
+void set_step(mot_handle* h, int k) { hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, h->stream, h->d_k, k); }
 
 void rec_gather(mot_handle* h, int s0, int ns, double* X) {
     int ncol = ns * 4 * h->R;
