@@ -137,9 +137,9 @@ def col_blocks(R):
     return min(4, (rp + 15) // 16)
 
 
-def history_kernel_name(R, precision, mix_group):
+def history_kernel_name(R, precision, mix_group, sched_hist=11):
     if R == 1:
-        return "k_history_co"
+        return "k_history_co" if sched_hist >= 10 else "k_history"
     if precision == 2:
         fl = {64: 16, 16: 4}.get(mix_group, 1)
         return "k_hist_mfma<%d, %d>" % (col_blocks(R), fl)
@@ -161,9 +161,10 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
     inf0 = s.info()
-    log("[%s R=%d %s] device setup %.2f s (preconditioner %.0f ms, fold %.0f ms), %d lags, %.2f GB on device"
+    log("[%s R=%d %s] device setup %.2f s (preconditioner %.0f ms, fold %.0f ms), %d lags, %.2f GB on device; "
+        "schedules history %d, Q0 %d, preconditioner %d (tuned in %.1f ms)"
         % (name, R, PRECISION[precision], t_setup, inf0["setup_ms"], inf0["fold_ms"], inf0["nlags"],
-           inf0["device_bytes"] / 1e9))
+           inf0["device_bytes"] / 1e9, inf0["sched_hist"], inf0["sched_q0"], inf0["sched_pc"], inf0["tune_ms"]))
     warm = s.run(W_, w=True, loop=True, star=True, device=False)
     torch.cuda.synchronize()
     a = s.info()
@@ -178,7 +179,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
     q0_us = 1e3 * (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
     hb, hf = history_model(ne, n, L, R, precision, hilo)
-    kname = history_kernel_name(R, precision, mix_group)
+    kname = history_kernel_name(R, precision, mix_group, inf0["sched_hist"])
     dtype = "f32" if precision == 2 else "f64"
     hist = roofline(kname, hb, hf, hist_us, dtype, R > 1, measured_traffic(kname, name))
     q0b = 8.0 * (3 * ne * ne + 2 * n * R)
@@ -191,7 +192,9 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
                iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
                q0_launches=(b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
                dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
-               device_gb=inf0["device_bytes"] / 1e9)
+               device_gb=inf0["device_bytes"] / 1e9,
+               schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
+                         "autotuned": bool(inf0["tuned"] and opts.autotune), "tune_ms": round(inf0["tune_ms"], 1)})
     log("[%s R=%d] timed %d steps in %.3f s: %.1f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
         "history %.1f us (%s %.4g %s), Q0 product %.1f us"
         % (name, R, K, el, K / el, R * K / el, out["iters"], hist_us, hist["bound"], hist["achieved"],
@@ -261,6 +264,7 @@ def main():
         "history_kernel": m["hist"],
         "q0_product": dict(m["q0"], launches_per_step=round(m["q0_launches"], 2)),
         "gmres_iters_per_step": round(m["iters"], 2),
+        "schedule": m["schedule"],
         "setup_s": round(m["setup_s"], 3),
         "fixture_s": round(t_fixture, 1),
         "device_gb": round(m["device_gb"], 2),
@@ -302,7 +306,7 @@ def main():
         def brief(r):
             return {"steps_s": round(r["steps_s"], 2), "rhs_steps_per_s": round(r["steps_s"] * r["R"], 1),
                     "ms_per_step": round(1e3 * r["el"] / r["K"], 4), "gmres_iters_per_step": round(r["iters"], 2),
-                    "history_kernel": r["hist"], "device_gb": round(r["device_gb"], 2)}
+                    "history_kernel": r["hist"], "schedule": r["schedule"], "device_gb": round(r["device_gb"], 2)}
 
         result["batched"] = {
             "workload": name + ": " + WORKLOADS[name],

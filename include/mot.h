@@ -118,6 +118,15 @@ typedef struct {
                                 formed at setup, one GEMM per batch of steps;
                                 1 incidence products and graph-Laplacian CG
                                 per batch (no dense ne^2 product)             */
+    int32_t autotune;        /* launch schedules of the per-step products
+                                (history convolution, Q_0 product, approximate
+                                inverse): 1 (default) time each candidate once
+                                on the device when the last lag is folded and
+                                keep the fastest (choices cached per process
+                                for the same sizes and options); 0 fixed size
+                                rules.  stream_split and history_order, when
+                                set, fix their part of the choice.  Schedules
+                                change only the order of summation.           */
 } mot_options;
 
 typedef struct {
@@ -147,6 +156,13 @@ typedef struct {
     int32_t precond_iters;   /* Newton-Schulz iterations of the preconditioner */
     double precond_resid;    /* ||I - M Q_0||_F of the stored preconditioner  */
     uint64_t peak_bytes;     /* high-water mark of device_bytes so far        */
+    int32_t tuned;           /* 1 once the schedules were timed (autotune)    */
+    int32_t sched_hist;      /* history schedule: one RHS 10*variant + wavefronts
+                                per row (variant 1 column slices, 0 rows);
+                                several RHS the K chunks of the tile product   */
+    int32_t sched_q0;        /* Q_0 product: wavefronts per row / K chunks    */
+    int32_t sched_pc;        /* approximate inverse: wavefronts per row / K chunks */
+    double tune_ms;          /* time spent timing candidates (0 on a cache hit) */
 } mot_info;
 
 typedef struct mot_handle mot_handle;

@@ -60,12 +60,6 @@ int mot_fail(mot_handle* h, int code, const std::string& msg) {
     return code;
 }
 
-#define HIPCHK(h, call)                                                                          \
-    do {                                                                                         \
-        hipError_t e_ = (call);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
-            return mot_fail(h, MOT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
-    } while (0)
 
 namespace {
 
@@ -318,6 +312,12 @@ int build_precond(mot_handle* h) {
     return MOT_OK;
 }
 
+bool all_folded(const mot_handle* h) {
+    for (int i = 0; i < h->nlags; ++i)
+        if (!h->lag_done[i]) return false;
+    return true;
+}
+
 // Section V-B fold of lag i:  with blocks X in {1 = eta T + eta' T', k = K + K', 2 = T/eta + T'/eta'}
 //   a_X = Zh_X + (Zhat_X - Zh_X) P^Sigma,  b_X = Ztil_X + (Zh_X - Ztil_X) P^Sigma
 //   q_X = C1 a_X + C2 b_X                 (Q_i = [[q_1, -q_k], [q_k, q_2]])
@@ -365,14 +365,12 @@ int fold_lag(mot_handle* h, int lag) {
     }
     h->lag_done[lag] = 1;
     h->fold_ms += now_ms() - t0;
-    if (lag == 0) return build_precond(h);
+    if (lag == 0) {
+        int rc = build_precond(h);
+        if (rc) return rc;
+    }
+    if (all_folded(h) && !h->tuned) return mot_autotune(h);
     return MOT_OK;
-}
-
-bool all_folded(const mot_handle* h) {
-    for (int i = 0; i < h->nlags; ++i)
-        if (!h->lag_done[i]) return false;
-    return true;
 }
 
 int stage_add(mot_handle* h, int family, int lag, int medium, int op, const double* dev_block) {
@@ -752,10 +750,15 @@ void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V,
     h->hs = (ne + 7) & ~7;
     h->n2 = 2 * h->hs;
     {
-        int sp = h->opt.stream_split;
-        if (sp != 1 && sp != 2 && sp != 4) sp = 1;
-        h->wpr = sp;
+        // an explicit stream_split or history_order fixes that part of the
+        // schedule; otherwise the autotuner picks it (or the defaults stay)
+        const int sp = h->opt.stream_split;
+        const bool sp_set = sp == 1 || sp == 2 || sp == 4;
+        const bool ho_set = h->opt.history_order == 1 || h->opt.history_order == 2;
+        h->wpr_hist = h->wpr_q0 = h->wpr_pc = sp_set ? sp : 1;
         h->hist_variant = h->opt.history_order == 2 ? 0 : 1;
+        h->tune_hist = h->opt.autotune && !sp_set && !ho_set;
+        h->tune_mv = h->opt.autotune && !sp_set;
     }
     h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
     h->c = 1.0; h->eta = 1.0;
@@ -844,6 +847,7 @@ void mot_default_options(mot_options* o) {
     o->precond = 1;
     o->hilo_lags = 2;
     o->mix_group = 4;
+    o->autotune = 1;
 }
 
 int mot_footprint(const mot_mesh* mesh, double eps_r, double mu_r, double dt, int32_t nrhs, int64_t gram_nnz,
@@ -1460,6 +1464,11 @@ int mot_get_info(const mot_handle* hc, mot_info* info) {
     info->recover_ms = h->recover_ms;
     info->precond_iters = h->ns_iters;
     info->precond_resid = h->ns_resid;
+    info->tuned = h->tuned;
+    info->sched_hist = h->Rp > 1 ? h->hist_kc : 10 * h->hist_variant + (h->hist_variant ? 1 : h->wpr_hist);
+    info->sched_q0 = h->Rp > 1 ? h->q0_kc : h->wpr_q0;
+    info->sched_pc = h->Rp > 1 ? h->plain_kc : h->wpr_pc;
+    info->tune_ms = h->tune_ms;
     return MOT_OK;
 }
 

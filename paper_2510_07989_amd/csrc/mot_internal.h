@@ -136,8 +136,14 @@ struct mot_handle {
     double* hist = nullptr;          // [max_steps][n2][R]
     int hist_cap = 0;
     int B = 128;                     // steps per RHS batch
-    int wpr = 1;                     // wavefronts per matrix row in the streaming kernels
+    // launch schedules (fixed by options or picked by the autotuner)
+    int wpr_hist = 1;                // wavefronts per matrix row: row-outer history kernel
+    int wpr_q0 = 1;                  //   Q_0 product (one RHS)
+    int wpr_pc = 1;                  //   approximate inverse product (one RHS)
     int hist_variant = 0;            // 0 row-outer, 1 column-outer history kernel
+    int tune_hist = 0, tune_mv = 0;  // 1: that part of the schedule is tuned
+    int tuned = 0;
+    double tune_ms = 0;
     double* ebar = nullptr;          // [2][hs][B] tested fields of a batch
     double* Ebar = nullptr;
     double* rb = nullptr;            // [2][ne][B] r_k = C1 ebar + C2 Ebar / T_max
@@ -164,6 +170,7 @@ struct mot_handle {
     int spec_iters = 1;              // Arnoldi steps queued per speculative step
     int hist_kc = 1, q0_kc = 1;      // K chunks of the tile products
     int plain_kc = 1;                // K chunks of the preconditioner product (Rp > 1)
+    std::vector<int> hist_kc_c, q0_kc_c, plain_kc_c;   // autotuner candidates (Rp > 1)
     int orth_nb = 1, orth_rb = 1;    // workgroups and rows of the multi-RHS Krylov sweeps
     double* orth_part = nullptr;     // [orth_nb][MOT_MAXM + 1][Rp] per-workgroup column sums
     GmFlag* hflag = nullptr;         // pinned, device-mapped
@@ -179,3 +186,16 @@ struct mot_handle {
 
 // host glue implemented in mot_api.hip
 int mot_fail(mot_handle* h, int code, const std::string& msg);
+
+// return MOT_EHIP (with the call's text) from the enclosing function on a HIP error
+#define HIPCHK(h, call)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return mot_fail(h, MOT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+// launch-schedule autotuner (tune.hip): times the candidates of every tuned
+// product on the handle's stream once all lags are folded; returns MOT_OK or
+// MOT_EHIP
+int mot_autotune(mot_handle* h);

@@ -20,6 +20,8 @@
 //   l/16 + 4r     for v_mfma_f64_16x16x4f64.
 #include "mot_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 
@@ -886,6 +888,17 @@ static int tile_kc(int blocks, int KT, int unit) {
     return want < 1 ? 1 : (want > maxkc ? maxkc : want);
 }
 
+// Autotuner candidates around the size rule's choice: base/4 .. 4 base, within
+// 1..maxkc (the partial buffer is sized for the largest).
+static std::vector<int> kc_candidates(int base, int maxkc) {
+    std::vector<int> c;
+    for (int v : {base / 4, base / 2, base, base * 2, base * 4}) {
+        v = std::max(1, std::min(v, maxkc));
+        if (std::find(c.begin(), c.end(), v) == c.end()) c.push_back(v);
+    }
+    return c;
+}
+
 void plan_tiles(mot_handle* h) {
     h->G16 = (h->ne + 15) / 16;
     h->KT = (h->hs + 15) / 16;
@@ -896,6 +909,14 @@ void plan_tiles(mot_handle* h) {
     const int gp = (h->n2 / 16 + 3) / 4;
     int want = (1024 + gp - 1) / gp, maxkc = std::max(1, h->n2 / 64);
     h->plain_kc = std::max(1, std::min(want, maxkc));
+    h->hist_kc_c.clear();
+    h->q0_kc_c.clear();
+    h->plain_kc_c.clear();
+    if (h->opt.autotune) {
+        h->hist_kc_c = kc_candidates(h->hist_kc, std::max(1, h->KT / (MTK / 16)));
+        h->q0_kc_c = kc_candidates(h->q0_kc, std::max(1, h->KT / 4));
+        if (h->opt.precond) h->plain_kc_c = kc_candidates(h->plain_kc, maxkc);
+    }
     // Krylov sweeps: about 1024 (row, column) entries per workgroup
     h->orth_nb = std::max(1, std::min(480, (int)(((size_t)h->n2 * h->Rp + 1023) / 1024)));
     h->orth_rb = (h->n2 + h->orth_nb - 1) / h->orth_nb;
@@ -907,9 +928,13 @@ size_t orth_part_doubles(const mot_handle* h) { return (size_t)h->orth_nb * (MOT
 size_t tile_elems(const mot_handle* h) { return (size_t)h->G16 * h->KT * 256; }
 
 size_t part_doubles(const mot_handle* h) {
-    size_t a = (size_t)h->nh * h->hist_kc * 2 * h->ne * h->Rp;
-    size_t b = (size_t)h->q0_kc * 2 * h->ne * h->Rp;
-    size_t c = (size_t)h->plain_kc * h->n2 * h->Rp;
+    auto top = [](int v, const std::vector<int>& c) {
+        for (int x : c) v = std::max(v, x);
+        return (size_t)v;
+    };
+    size_t a = (size_t)h->nh * top(h->hist_kc, h->hist_kc_c) * 2 * h->ne * h->Rp;
+    size_t b = top(h->q0_kc, h->q0_kc_c) * 2 * h->ne * h->Rp;
+    size_t c = top(h->plain_kc, h->plain_kc_c) * h->n2 * h->Rp;
     return std::max(a, std::max(b, c));
 }
 

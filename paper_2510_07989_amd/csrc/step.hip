@@ -946,9 +946,9 @@ void history(mot_handle* h) {
                            h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm);
         return;
     }
-    const int rpb = 4 / h->wpr;
+    const int rpb = 4 / h->wpr_hist;
     hipLaunchKernelGGL(k_history, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr, h->gm);
+                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr_hist, h->gm);
 }
 
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish) {
@@ -967,18 +967,20 @@ void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) 
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
-    const int rpb = 4 / h->wpr;
+    const int rpb = 4 / h->wpr_q0;
     hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
-                       src, vout, y, h->gm, check_done, use_inv, h->wpr);
+                       src, vout, y, h->gm, check_done, use_inv, h->wpr_q0);
 }
 
 void precond(mot_handle* h, const double* src, double* vj, double* z) {
-    const int rpb = 4 / h->wpr;
+    const int rpb = 4 / h->wpr_pc;
     dim3 grid((h->n2 + rpb - 1) / rpb);
     if (h->M32)
-        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm, h->wpr);
+        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm,
+                           h->wpr_pc);
     else
-        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm, h->wpr);
+        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm,
+                           h->wpr_pc);
 }
 
 void dense_q0(mot_handle* h, double* D) {

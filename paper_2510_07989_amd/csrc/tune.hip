@@ -1,0 +1,177 @@
+// Launch-schedule autotuner for the per-step products of the march.
+//
+// Every MOT step streams the lag matrices once (history convolution), and each
+// Arnoldi step applies the approximate inverse and Q_0 once.  How a launch cuts
+// that work into workgroups is a schedule:
+//   one RHS:      wavefronts per matrix row (1, 2 or 4) of the streaming
+//                 products, and for the history the loop order (column slices
+//                 across all lag blocks, or whole rows of one block);
+//   several RHS:  the number of K chunks of the tile products on MFMA (more
+//                 chunks: more workgroups in flight, more partial sums to add).
+// The fastest schedule depends on the sizes, the lag count and the chip, so it
+// is measured: once all lags are folded, each candidate runs on the real
+// operands a few times on the handle's stream, timed with HIP events, and the
+// fastest (smallest of its repetitions) is kept.  Choices are cached for the
+// process under a key of every size and option that shapes the launches, so
+// solves of the same shape (a serving stream) time nothing.  A schedule only
+// changes the order of summation, never what is summed.
+#include "mot_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace motk_step {
+void history(mot_handle* h);
+void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
+void precond(mot_handle* h, const double* src, double* vj, double* z);
+}  // namespace motk_step
+
+namespace motk_multi {
+void history_gemm(mot_handle* h);
+void q0_gemm(mot_handle* h, const double* X);
+void precond(mot_handle* h, const double* src, double* vj, double* z);
+}  // namespace motk_multi
+
+namespace {
+
+struct Schedule {
+    int hist_variant, wpr_hist, wpr_q0, wpr_pc;
+    int hist_kc, q0_kc, plain_kc;
+};
+
+typedef std::tuple<int, int, int, int, int, int, int, int, int, int> Key;
+
+std::mutex g_mu;
+std::map<Key, Schedule> g_cache;
+
+Key key_of(const mot_handle* h, int dev) {
+    return Key(dev, h->ne, h->nh, h->Rp, h->opt.precision, h->hilo, h->opt.precond,
+               h->opt.precision == MOT_MIXED32 ? h->opt.mix_group : 0, 2 * h->tune_hist + h->tune_mv,
+               h->tune_hist ? 0 : 10 * h->hist_variant + h->wpr_hist);
+}
+
+Schedule current(const mot_handle* h) {
+    return Schedule{h->hist_variant, h->wpr_hist, h->wpr_q0, h->wpr_pc, h->hist_kc, h->q0_kc, h->plain_kc};
+}
+
+void apply(mot_handle* h, const Schedule& s) {
+    h->hist_variant = s.hist_variant;
+    h->wpr_hist = s.wpr_hist;
+    h->wpr_q0 = s.wpr_q0;
+    h->wpr_pc = s.wpr_pc;
+    h->hist_kc = s.hist_kc;
+    h->q0_kc = s.q0_kc;
+    h->plain_kc = s.plain_kc;
+}
+
+// Smallest time (ms) of `reps` launches of f, after one untimed launch.
+template <class F>
+int best_time(mot_handle* h, F f, int reps, float* out) {
+    hipEvent_t a, b;
+    HIPCHK(h, hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return mot_fail(h, MOT_EHIP, "hipEventCreate failed");
+    }
+    float best = 3.4e38f;
+    int rc = MOT_OK;
+    f();
+    for (int r = 0; r < reps && rc == MOT_OK; ++r) {
+        float ms = 0;
+        if (hipEventRecord(a, h->stream) != hipSuccess) { rc = MOT_EHIP; break; }
+        f();
+        if (hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess)
+            rc = MOT_EHIP;
+        best = std::min(best, ms);
+    }
+    if (rc == MOT_OK && hipGetLastError() != hipSuccess) rc = MOT_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return mot_fail(h, rc, "autotune: a timed launch failed");
+    *out = best;
+    return MOT_OK;
+}
+
+// Pick the fastest value of one schedule field among cands.
+template <class Set, class F>
+int pick(mot_handle* h, const std::vector<int>& cands, Set set, F launch, int reps) {
+    if (cands.size() < 2) return MOT_OK;
+    int best_v = cands[0];
+    float best_t = 3.4e38f;
+    for (int v : cands) {
+        set(v);
+        float t;
+        int rc = best_time(h, launch, reps, &t);
+        if (rc) return rc;
+        if (t < best_t) { best_t = t; best_v = v; }
+    }
+    set(best_v);
+    return MOT_OK;
+}
+
+int tune(mot_handle* h) {
+    const int reps = 5;
+    // every lag active: the timed history launches stream all of Q_1..Q_{L-1}
+    const int kfull = h->nh + 1;
+    HIPCHK(h, hipMemcpyAsync(h->d_k, &kfull, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    int rc = MOT_OK;
+    if (h->Rp == 1) {
+        if (h->tune_hist) {
+            // 10 * variant + wavefronts per row
+            const std::vector<int> c = {11, 1, 2, 4};
+            rc = pick(h, c, [&](int v) { h->hist_variant = v / 10; h->wpr_hist = v % 10; },
+                      [&] { motk_step::history(h); }, reps);
+        }
+        if (!rc && h->tune_mv) {
+            const std::vector<int> c = {1, 2, 4};
+            rc = pick(h, c, [&](int v) { h->wpr_q0 = v; },
+                      [&] { motk_step::q0_matvec(h, h->x, nullptr, h->wA, 0, 0); }, reps);
+            if (!rc && (h->M32 || h->M64))
+                rc = pick(h, c, [&](int v) { h->wpr_pc = v; },
+                          [&] { motk_step::precond(h, h->wA, h->V, h->Z); }, reps);
+        }
+    } else {
+        rc = pick(h, h->hist_kc_c, [&](int v) { h->hist_kc = v; }, [&] { motk_multi::history_gemm(h); }, reps);
+        if (!rc) rc = pick(h, h->q0_kc_c, [&](int v) { h->q0_kc = v; }, [&] { motk_multi::q0_gemm(h, h->x); }, reps);
+        if (!rc && (h->M32 || h->M64))
+            rc = pick(h, h->plain_kc_c, [&](int v) { h->plain_kc = v; },
+                      [&] { motk_multi::precond(h, h->wA, h->V, h->Z); }, reps);
+    }
+    // the march starts from step 0 with clean scratch
+    const int zero = 0;
+    HIPCHK(h, hipMemcpyAsync(h->d_k, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+}  // namespace
+
+int mot_autotune(mot_handle* h) {
+    h->tuned = 1;
+    const bool any = h->Rp > 1 ? !h->hist_kc_c.empty() : (h->tune_hist || h->tune_mv);
+    if (!h->opt.autotune || !any) return MOT_OK;
+    int dev = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    const Key key = key_of(h, dev);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            apply(h, it->second);
+            return MOT_OK;
+        }
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = tune(h);
+    if (rc) return rc;
+    h->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // a concurrent tuner of the same key may have stored its choice first:
+    // every handle of one shape then runs the stored one
+    std::lock_guard<std::mutex> lk(g_mu);
+    apply(h, g_cache.emplace(key, current(h)).first->second);
+    return MOT_OK;
+}

@@ -31,6 +31,8 @@ def test_default_options_without_gpu():
     import paper_2510_07989_amd as p
     o = p.default_options()
     assert o.gmres_tol == 1e-13 and o.gmres_restart == 40 and o.keep_history == 1
+    # the last field: the ctypes layout reaches as far as the C struct
+    assert o.mix_group == 4 and o.autotune == 1
 
 
 def test_footprint_without_gpu():
@@ -49,6 +51,11 @@ def test_footprint_without_gpu():
     assert r16 > r16m > r1
     assert rlong - r1 == 900 * 960 * 8          # kept history: steps x n x 8 bytes
     assert r64 - r1 == 960 * 960 * 4            # FP64 instead of FP32 approximate inverse
+    # the autotuner's partial sums are sized for its largest K-chunk candidate
+    r16f, _ = p.footprint(*args, 16, prob["G"], p.default_options(max_steps=100, precond=2, autotune=0))
+    assert r16f <= r16
+    r1f, _ = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=100, autotune=0))
+    assert r1f == r1                            # one RHS: schedules need no memory
 
 
 def test_one_hip_runtime_in_the_process():

@@ -1,0 +1,69 @@
+"""Launch-schedule autotuner: the tuned march equals the untuned one and the
+oracle's, the choice lies among the candidates, and a second solve of the same
+shape reuses it without timing (MI355X only)."""
+import numpy as np
+import pytest
+
+from tests._problems import problem, oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(name, **opts):
+    import paper_2510_07989_amd as p
+    prob = problem(name)
+    s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                 prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=p.default_options(**opts))
+    s.load_raw(prob["raw"], prob["kmax"])
+    return s
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name,opts,nsteps", [("sphere_480", dict(precond=2), 120),
+                                              ("sphere_480", dict(precond=1), 120),
+                                              ("sphere_480_r16", dict(precond=2), 60),
+                                              ("sphere_480_r16", dict(precond=2, precision=1), 60)])
+def test_tuned_equals_untuned(name, opts, nsteps):
+    print("case", name, opts, flush=True)
+    s0 = _solver(name, autotune=0, **opts)
+    a = s0.run(nsteps)
+    i0 = s0.info()
+    s0.close()
+    s1 = _solver(name, autotune=1, **opts)
+    b = s1.run(nsteps)
+    i1 = s1.info()
+    s1.close()
+    print("untuned", {k: i0[k] for k in ("sched_hist", "sched_q0", "sched_pc")},
+          "tuned", {k: i1[k] for k in ("sched_hist", "sched_q0", "sched_pc", "tune_ms")}, flush=True)
+    assert i0["tuned"] == 1 and i1["tuned"] == 1
+    if i1["nrhs"] == 1:
+        assert i1["sched_hist"] in (11, 1, 2, 4)
+        assert i1["sched_q0"] in (1, 2, 4) and i1["sched_pc"] in (1, 2, 4)
+    else:
+        for k in ("sched_hist", "sched_q0", "sched_pc"):
+            assert i1[k] >= 1 and i0[k] // 4 <= i1[k] <= 4 * i0[k], k
+    tol = 1e-12 if opts.get("precision", 0) == 0 else 1e-9
+    for k in ("w", "loop", "star"):
+        assert _rel(b[k], a[k]) < tol, k
+    ref = oracle(name).run(nsteps)
+    assert _rel(b["w"], ref["W"]) < (1e-10 if tol == 1e-12 else 1e-6)
+    # same shape and options: the stored choice, nothing timed
+    s2 = _solver(name, autotune=1, **opts)
+    i2 = s2.info()
+    c = s2.run(nsteps)
+    s2.close()
+    assert i2["tune_ms"] == 0.0
+    assert all(i2[k] == i1[k] for k in ("sched_hist", "sched_q0", "sched_pc"))
+    for k in ("w", "loop", "star"):
+        assert _rel(c[k], b[k]) < tol, k
+
+
+def test_explicit_split_is_kept():
+    """stream_split and history_order fix their part of the schedule."""
+    s = _solver("sphere_480", precond=2, autotune=1, stream_split=2, history_order=2)
+    i = s.info()
+    s.close()
+    assert i["sched_hist"] == 2 and i["sched_q0"] == 2 and i["sched_pc"] == 2
