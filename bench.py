@@ -146,12 +146,18 @@ def history_kernel_name(R, precision, mix_group, sched_hist=11):
     return "k_tile_gemm<%s, %d>" % ("double" if precision == 0 else "float", col_blocks(R))
 
 
+# HIP events bracket every PROFILE_EVERY-th history and Q_0 launch of the timed
+# region: an event marker drains the queue, so bracketing every launch would
+# slow the march it measures (torus: 3600 instead of 3770 steps/s)
+PROFILE_EVERY = 16
+
+
 def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, outputs=True):
     """Set up one problem on the device, march W_ warm-up steps (kept as the
     parity sample), then time K steps with device-resident outputs."""
     import torch
     R = len(prob["waves"])
-    opts = mot.default_options(profile=1, max_steps=W_ + K + 8, precond=precond, stream_split=split,
+    opts = mot.default_options(profile=PROFILE_EVERY, max_steps=W_ + K + 8, precond=precond, stream_split=split,
                                precision=precision, hilo_lags=hilo, mix_group=mix_group)
     t = time.perf_counter()
     s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
@@ -190,7 +196,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     q0_tot = b["q0_ms"] - a["q0_ms"]
     out = dict(steps_s=K / el, el=el, K=K, W=W_, R=R, n=n, L=L, kmax=b["kmax"], setup_s=t_setup,
                iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
-               q0_launches=(b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
+               q0_launches=PROFILE_EVERY * (b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
                dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
                device_gb=inf0["device_bytes"] / 1e9,
                schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
@@ -199,6 +205,32 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
         "history %.1f us (%s %.4g %s), Q0 product %.1f us"
         % (name, R, K, el, K / el, R * K / el, out["iters"], hist_us, hist["bound"], hist["achieved"],
            hist["unit"], q0_us))
+    return out
+
+
+def graph_compare(mot, prob, K, W_, precond):
+    """The same march with its speculative windows queued launch by launch and
+    replayed from captured HIP graphs, on a stream of its own, no events."""
+    import torch
+    out = {}
+    for g in (0, 1):
+        st = torch.cuda.Stream()
+        opts = mot.default_options(max_steps=W_ + K + 8, precond=precond, graph=g)
+        s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                       prob["T0h"], prob["G"], prob["waves"], options=opts, stream=st.cuda_stream)
+        s.load_raw(prob["raw"], prob["kmax"])
+        with torch.cuda.stream(st):
+            s.run(W_, w=False, loop=False, star=False, device=True)
+            st.synchronize()
+            t0 = time.perf_counter()
+            s.run(K, w=True, loop=True, star=True, device=True)
+            st.synchronize()
+            el = time.perf_counter() - t0
+        inf = s.info()
+        s.close()
+        out["graph" if g else "launches"] = {"steps_s": round(K / el, 1), "graph_windows": inf["graph_windows"]}
+    log("window replay: launches %.1f steps/s, graphs %.1f steps/s (%d windows)"
+        % (out["launches"]["steps_s"], out["graph"]["steps_s"], out["graph"]["graph_windows"]))
     return out
 
 
@@ -211,6 +243,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched/mixed comparison")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
@@ -283,6 +316,10 @@ def main():
                                             "recovery), oracle setup %.1f s not timed" % (ns, cb["prep_s"])}
         result["err_vs_oracle"] = {"steps": ns, "w": e_w, "loop": e_l, "star": e_s}
         log("oracle: %d steps in %.1f s; GPU vs oracle: w %.2e loop %.2e star %.2e" % (ns, cb["seconds"], e_w, e_l, e_s))
+
+    if not args.no_graph:
+        result["graph_replay"] = dict(graph_compare(mot, prob, min(K, 5000), W_, args.precond),
+                                      steps=min(K, 5000), workload=args.workload)
 
     if not args.no_batched:
         name = "sphere_1920_r16"

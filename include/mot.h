@@ -90,9 +90,12 @@ typedef struct {
     int32_t keep_history;    /* keep every w_k on the device (1)             */
     int32_t max_steps;       /* capacity of the kept history (0: 20000)      */
     uint64_t mem_cap_bytes;  /* 0: no cap                                     */
-    int32_t profile;         /* 1: time the history kernel and every Q_0
-                                product with HIP events on the handle's stream
-                                (results in mot_info)                          */
+    int32_t profile;         /* N >= 1: time every N-th launch of the history
+                                kernel and of the Q_0 product with HIP events
+                                on the handle's stream (results in mot_info;
+                                each bracketed launch costs two event markers,
+                                so N > 1 keeps the march near its unprofiled
+                                rate); 0: off                                  */
     int32_t precond;         /* right preconditioner of the Q_0 GMRES: an
                                 approximate inverse of Q_0 built once on the
                                 device by Newton-Schulz iteration;
@@ -127,6 +130,17 @@ typedef struct {
                                 rules.  stream_split and history_order, when
                                 set, fix their part of the choice.  Schedules
                                 change only the order of summation.           */
+    int32_t graph;           /* mot_run with speculative stepping: 1 replays
+                                every full window of one RHS batch (B steps,
+                                B = max(8, min(128, 4096 / Rp)), Rp = nrhs
+                                rounded up to a power of two), aligned to a
+                                batch and spec_window 0, from a
+                                HIP graph captured once per batch parity (and
+                                again when the Arnoldi count per queued step
+                                grows); other windows, and handles on the
+                                legacy default stream, queue their launches
+                                one by one.  Ignored with profile = 1.
+                                Results are identical to graph = 0.           */
 } mot_options;
 
 typedef struct {
@@ -163,6 +177,7 @@ typedef struct {
     int32_t sched_q0;        /* Q_0 product: wavefronts per row / K chunks    */
     int32_t sched_pc;        /* approximate inverse: wavefronts per row / K chunks */
     double tune_ms;          /* time spent timing candidates (0 on a cache hit) */
+    int64_t graph_windows;   /* windows replayed from captured graphs          */
 } mot_info;
 
 typedef struct mot_handle mot_handle;

@@ -30,7 +30,7 @@ class MotOptions(ctypes.Structure):
                 ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
                 ("precond", _I), ("stream_split", _I), ("history_order", _I),
                 ("hilo_lags", _I), ("mix_group", _I), ("spec_window", _I),
-                ("recovery", _I), ("autotune", _I)]
+                ("recovery", _I), ("autotune", _I), ("graph", _I)]
 
 
 class MotStepInfo(ctypes.Structure):
@@ -44,7 +44,8 @@ class MotInfo(ctypes.Structure):
                 ("gmres_iters_total", ctypes.c_int64), ("hist_ms", _D), ("hist_launches", ctypes.c_int64),
                 ("q0_ms", _D), ("q0_launches", ctypes.c_int64), ("recover_ms", _D),
                 ("precond_iters", _I), ("precond_resid", _D), ("peak_bytes", ctypes.c_uint64),
-                ("tuned", _I), ("sched_hist", _I), ("sched_q0", _I), ("sched_pc", _I), ("tune_ms", _D)]
+                ("tuned", _I), ("sched_hist", _I), ("sched_q0", _I), ("sched_pc", _I), ("tune_ms", _D),
+                ("graph_windows", ctypes.c_int64)]
 
 
 EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr", "mot_step",

@@ -10,7 +10,7 @@
 #include "mot_internal.h"
 
 namespace motk_step {
-void rhs_batch(mot_handle* h, int k0, double* rb);
+void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase = nullptr);
 void history(mot_handle* h);
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish = 1);
 void gm_orth1(mot_handle* h, double* w, int publish = 1);
@@ -31,6 +31,7 @@ void push(mot_handle* h);
 void inc_step(mot_handle* h);
 void clear_halt(mot_handle* h);
 void set_step(mot_handle* h, int k);
+void set_base(mot_handle* h, int k);
 void rec_gather(mot_handle* h, int s0, int ns, double* X);
 void rec_scatter(mot_handle* h, int ns, const double* X, const double* PX, double* loop, double* star);
 void pack(mot_handle* h, int ns, const double* src, double* dst);
@@ -428,7 +429,10 @@ int ev_flush(mot_handle* h, EvPool& p) {
 }
 
 int ev_begin(mot_handle* h, EvPool& p) {
-    if (!h->opt.profile) return MOT_OK;
+    p.open = false;
+    if (h->opt.profile <= 0) return MOT_OK;
+    if (p.seen++ % h->opt.profile) return MOT_OK;      // sample every profile-th launch
+    p.open = true;
     if (p.a.empty()) {
         p.a.resize(kEvCap);
         p.b.resize(kEvCap);
@@ -446,7 +450,8 @@ int ev_begin(mot_handle* h, EvPool& p) {
 }
 
 int ev_end(mot_handle* h, EvPool& p) {
-    if (!h->opt.profile) return MOT_OK;
+    if (!p.open) return MOT_OK;
+    p.open = false;
     HIPCHK(h, hipEventRecord(p.b[p.used], h->stream));
     p.used++;
     return MOT_OK;
@@ -800,7 +805,7 @@ void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* 
     b += 8.0 * (2 * ne * 42 + 9 * R + R);                                         // RHS quadrature, waves
     b += 8.0 * 5 * blk;                                                           // PS, BL, G^-1, C1, C2
     b += 8.0 * ((double)h->nlags * 3 + 4) * blk;                                  // Q, fold scratch, raw block
-    b += 4.0 + 8.0 * (h->nh * n2r + 4 * hs * NB + 4 * ne * NB + 4 * n2r + 2 * (M + 1) * n2r) + sizeof(GmState);
+    b += 8.0 + 8.0 * (h->nh * n2r + 4 * hs * NB + 4 * ne * NB + 4 * n2r + 2 * (M + 1) * n2r) + sizeof(GmState);
     if (h->Rp > 1) {
         const double t3 = 3.0 * motk_multi::tile_elems(h);
         if (h->opt.precision == MOT_FP64) b += 8.0 * h->nlags * t3;
@@ -870,6 +875,8 @@ void mot_destroy(mot_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     ev_destroy(h->ev_hist);
     ev_destroy(h->ev_q0);
+    for (auto& g : h->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
     (void)hipStreamSynchronize(h->stream);
     if (h->hflag) (void)hipHostFree(h->hflag);
@@ -1067,7 +1074,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     // every march vector holds all Rp columns: [n2][Rp]
     const size_t n2 = (size_t)h->n2 * h->Rp;
     const size_t NB = (size_t)h->B * h->Rp;
-    if ((rc = dalloc(h, &h->d_k, 1)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
+    if ((rc = dalloc(h, &h->d_k, 2)) || (rc = dalloc(h, &h->ring, (size_t)h->nh * n2)) ||
         (rc = dalloc(h, &h->ebar, (size_t)2 * h->hs * NB)) || (rc = dalloc(h, &h->Ebar, (size_t)2 * h->hs * NB)) ||
         (rc = dalloc(h, &h->rb, (size_t)4 * h->ne * NB)) || (rc = dalloc(h, &h->y, n2)) ||
         (rc = dalloc(h, &h->x, n2)) || (rc = dalloc(h, &h->V, (size_t)(h->M + 1) * n2)) || (rc = dalloc(h, &h->Z, (size_t)(h->M + 1) * n2)) ||
@@ -1210,13 +1217,17 @@ static bool spec_ok(const mot_handle* h) {
 }
 
 // first: the window's first step advances the device step counter; later
-// steps find it set by the previous step's finisher
-static int queue_spec_step(mot_handle* h, bool first) {
+// steps find it set by the previous step's finisher.
+// goff >= 0: the launches are being captured into a graph as step goff of a
+// window; the step index then comes from the device (the window's first step
+// in d_k[1]), so one graph serves every window of its batch parity.
+static int queue_spec_step(mot_handle* h, bool first, int goff = -1) {
     using namespace motk_step;
     namespace mm = motk_multi;
     if (first) inc_step(h);
     h->k += 1;
-    if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb);
+    const int kq = goff >= 0 ? -(goff + 1) : h->k;
+    if ((h->k - 1) % h->B == 0) rhs_batch(h, h->k, h->rb, goff >= 0 ? h->d_k + 1 : nullptr);
     int prc;
     if ((prc = ev_begin(h, h->ev_hist))) return prc;
     if (h->Rp > 1) mm::history_gemm(h); else history(h);
@@ -1237,7 +1248,7 @@ static int queue_spec_step(mot_handle* h, bool first) {
             mm::orth(h, dst, 0);
             std::swap(src, dst);
         }
-        mm::finish(h, 0, 1, h->k);
+        mm::finish(h, 0, 1, kq);
         return MOT_OK;
     }
     if (h->M32) {
@@ -1259,7 +1270,59 @@ static int queue_spec_step(mot_handle* h, bool first) {
         gm_orth1(h, dst, 0);
         std::swap(src, dst);
     }
-    gm_finish(h, h->Z, 0, 1, h->k);
+    gm_finish(h, h->Z, 0, 1, kq);
+    return MOT_OK;
+}
+
+// Capture the B queued steps of a window whose batch has parity `parity` into
+// a graph (replayed with d_k[1] = the window's first step).  A capture that
+// the runtime refuses switches the handle to stream launches for good.
+static int capture_window(mot_handle* h, int parity) {
+    hipGraphExec_t& ex = h->gexec[parity];
+    if (ex) {
+        (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+    }
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_off = 1;
+        return MOT_OK;
+    }
+    const int k_save = h->k;
+    h->k = parity * h->B;                 // host bookkeeping only: selects the RHS half
+    int rc = MOT_OK;
+    for (int i = 0; i < h->B && rc == MOT_OK; ++i) rc = queue_spec_step(h, false, i);
+    h->k = k_save;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc == MOT_OK && e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ex = nullptr;
+        h->graph_off = 1;
+        return MOT_OK;
+    }
+    h->g_iters[parity] = h->spec_iters;
+    return MOT_OK;
+}
+
+// one full, batch-aligned window from the captured graph of its parity
+static int launch_window(mot_handle* h, bool ahead, bool* launched) {
+    *launched = false;
+    const int par = (h->k / h->B) & 1;
+    if (!h->gexec[par] || h->g_iters[par] != h->spec_iters) {
+        int rc = capture_window(h, par);
+        if (rc) return rc;
+        if (h->graph_off) return MOT_OK;
+    }
+    if (!ahead) motk_step::inc_step(h);                     // d_k[0] = first step
+    motk_step::set_base(h, h->k + 1);
+    HIPCHK(h, hipGraphLaunch(h->gexec[par], h->stream));
+    h->k += h->B;
+    h->graph_windows += 1;
+    *launched = true;
     return MOT_OK;
 }
 
@@ -1280,11 +1343,18 @@ static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
     // every step pushed (the last finisher set it); a halted window leaves it at
     // the halted step, which is then h->k
     bool ahead = false;
+    // graphs replay whole RHS batches: windows then end on batch boundaries
+    // (the legacy default stream cannot be captured)
+    const bool graphs = h->opt.graph && !h->opt.profile && win == h->B && h->stream != nullptr;
     while (done < nsteps) {
-        const int nw = std::min(win, nsteps - done);
+        int nw = std::min(win, nsteps - done);
         const int k0 = h->k;
-        for (int i = 0; i < nw; ++i)
-            if ((rc = queue_spec_step(h, i == 0 && !ahead))) return rc;
+        if (graphs && k0 % h->B) nw = std::min(nw, h->B - k0 % h->B);
+        bool launched = false;
+        if (graphs && !h->graph_off && nw == h->B && (rc = launch_window(h, ahead, &launched))) return rc;
+        if (!launched)
+            for (int i = 0; i < nw; ++i)
+                if ((rc = queue_spec_step(h, i == 0 && !ahead))) return rc;
         ahead = true;
         HIPCHK(h, hipGetLastError());
         SpecWord w{};
@@ -1469,6 +1539,7 @@ int mot_get_info(const mot_handle* hc, mot_info* info) {
     info->sched_q0 = h->Rp > 1 ? h->q0_kc : h->wpr_q0;
     info->sched_pc = h->Rp > 1 ? h->plain_kc : h->wpr_pc;
     info->tune_ms = h->tune_ms;
+    info->graph_windows = h->graph_windows;
     return MOT_OK;
 }
 

@@ -93,6 +93,8 @@ struct EvPool {
     int used = 0;
     double ms = 0;
     long long n = 0;
+    long long seen = 0;              // launches offered for timing (sampling)
+    bool open = false;               // the current launch is bracketed
 };
 
 // ------------------------------------------------------------ the handle ---
@@ -130,7 +132,7 @@ struct mot_handle {
     double* raw = nullptr;           // [ne][hs] upload buffer
 
     // march state
-    int* d_k = nullptr;              // current step (device)
+    int* d_k = nullptr;              // [0] current step, [1] first step of a graph-replayed window (device)
     int k = 0;
     double* ring = nullptr;          // [nh][n2][R]
     double* hist = nullptr;          // [max_steps][n2][R]
@@ -144,6 +146,12 @@ struct mot_handle {
     int tune_hist = 0, tune_mv = 0;  // 1: that part of the schedule is tuned
     int tuned = 0;
     double tune_ms = 0;
+    // speculative windows captured as HIP graphs, one per batch parity of the
+    // window's RHS half; captured with spec_iters Arnoldi steps per step
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_iters[2] = {0, 0};
+    int graph_off = 0;               // capture failed (e.g. the legacy default stream): stream launches
+    long long graph_windows = 0;
     double* ebar = nullptr;          // [2][hs][B] tested fields of a batch
     double* Ebar = nullptr;
     double* rb = nullptr;            // [2][ne][B] r_k = C1 ebar + C2 Ebar / T_max

@@ -359,9 +359,10 @@ __global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmSta
                              int* __restrict__ dk, int nh, double* __restrict__ ring,
                              double* __restrict__ hist, int hist_cap, int force, int spec, int kq) {
     if (agg->halt) return;
-    // kq > 0 (queued steps): host step index; the counter is set to kq + 1
+    // kq > 0 (queued steps): host step index; kq < 0 (graph replay): the
+    // window's first step dk[1] plus -kq - 1; the counter dk[0] is set to k + 1
     // after a push (no block of this launch reads it)
-    const int k = kq > 0 ? kq : *dk;
+    const int k = kq > 0 ? kq : (kq < 0 ? dk[1] - kq - 1 : dk[0]);
     if (spec && !agg->converged) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             agg->halt_k = k;
@@ -370,7 +371,7 @@ __global__ void k_gmb_finish(int n2, int RP, const double* __restrict__ Z, GmSta
         return;
     }
     const int push = agg->converged || force;
-    if (kq > 0 && push && blockIdx.x == 0 && threadIdx.x == 0) *dk = kq + 1;
+    if (kq != 0 && push && blockIdx.x == 0 && threadIdx.x == 0) dk[0] = k + 1;
     double* slot = ring + (size_t)(k % nh) * n2 * RP;
     double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 * RP : nullptr;
     const size_t total = (size_t)n2 * RP;

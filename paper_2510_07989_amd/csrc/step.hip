@@ -21,12 +21,13 @@ __device__ __forceinline__ double erf_diff(double s1, double s0) {
     return erf(s1) - erf(s0);
 }
 
-__global__ void k_rhs_fields(int ne, int hs, int k0, int B, int R, int Rp, double dt,
-                             const double* __restrict__ X, const double* __restrict__ Fw,
+__global__ void k_rhs_fields(int ne, int hs, int k0, const int* __restrict__ kbase, int B, int R, int Rp,
+                             double dt, const double* __restrict__ X, const double* __restrict__ Fw,
                              const double* __restrict__ waves, const double* __restrict__ tcut,
                              double* __restrict__ ebar, double* __restrict__ Ebar,
                              const GmState* __restrict__ gm) {
-    // thread per (edge m, batch column sc, wave r); step k = k0 + sc;
+    // thread per (edge m, batch column sc, wave r); step k = k0 + sc, with k0
+    // read from the device (kbase, graph replay) or passed by the host
     // outputs [half][hs][B * Rp], column sc * Rp + r (zero for padding waves r >= R)
     if (gm->halt) return;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,7 +40,7 @@ __global__ void k_rhs_fields(int ne, int hs, int k0, int B, int R, int Rp, doubl
         ebar[o] = 0; ebar[hb + o] = 0; Ebar[o] = 0; Ebar[hb + o] = 0;
         return;
     }
-    const int k = k0 + sc;
+    const int k = (kbase ? *kbase : k0) + sc;
     const double* wv = waves + 9 * r;
     const double amp = wv[0], w = wv[7], t0 = wv[8];
     const double px = wv[1], py = wv[2], pz = wv[3];
@@ -785,15 +786,17 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
 // spec = 1 (speculative stepping): a solve that has not converged pushes
 // nothing and raises the halt word instead, so that the later queued steps do
 // nothing until the host has finished this one.
-// kq > 0 (queued steps): the step index comes from the host, and after a push
-// the device step counter is set to kq + 1 for the next queued step (no block
-// of this launch reads the counter, so the write does not race).
+// kq > 0 (queued steps): the step index comes from the host; kq < 0 (steps
+// replayed from a captured graph): it is the window's first step dk[1] plus
+// -kq - 1.  In both cases the device step counter dk[0] is set to k + 1 after
+// a push, for the next queued step (no block of this launch reads it, so the
+// write does not race).
 __global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __restrict__ gm,
                             double* __restrict__ x, int* __restrict__ dk, int nh,
                             double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force,
                             int spec, int kq) {
     if (gm->halt) return;
-    const int k = kq > 0 ? kq : *dk;
+    const int k = kq > 0 ? kq : (kq < 0 ? dk[1] - kq - 1 : dk[0]);
     if (spec && !(gm->done && gm->converged)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             gm->halt_k = k;
@@ -804,7 +807,7 @@ __global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __re
     if (!gm->done && !force) return;
     const int jj = gm->done ? gm->cycle_iters : 0;
     const int push = gm->converged || force;
-    if (kq > 0 && push && blockIdx.x == 0 && threadIdx.x == 0) *dk = kq + 1;
+    if (kq != 0 && push && blockIdx.x == 0 && threadIdx.x == 0) dk[0] = k + 1;
     double* slot = ring + (size_t)(k % nh) * n2;
     double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 : nullptr;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
@@ -921,13 +924,15 @@ __global__ void k_pack(int ne, int hs, int R, int Rp, int ns, const double* __re
 // ------------------------------------------------------------ launchers ---
 namespace motk_step {
 
-// RHS of steps k0 .. k0+B-1: fields, then r = C1 ebar + C2 Ebar / T_max per half
-void rhs_batch(mot_handle* h, int k0, double* rb) {
+// RHS of steps k0 .. k0+B-1: fields, then r = C1 ebar + C2 Ebar / T_max per half.
+// kbase: read k0 from the device when the launches are replayed from a graph
+// (k0 then only selects the half of rb, by its batch parity).
+void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase) {
     const int ne = h->ne, hs = h->hs, B = h->B, Rp = h->Rp;
     const int N = B * Rp;
     size_t tot = (size_t)ne * N;
-    hipLaunchKernelGGL(k_rhs_fields, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, ne, hs, k0, B,
-                       h->R, Rp, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar, h->gm);
+    hipLaunchKernelGGL(k_rhs_fields, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, ne, hs, k0, kbase,
+                       B, h->R, Rp, h->dt, h->rq_x, h->rq_f, h->waves, h->tcut, h->ebar, h->Ebar, h->gm);
     // consecutive batches alternate between the two halves of rb, so a batch
     // queued ahead of a halted step never overwrites the one it still needs
     double* rbk = rb + (size_t)(((k0 - 1) / B) & 1) * 2 * ne * N;
@@ -1037,6 +1042,11 @@ void inc_step(mot_handle* h) { hipLaunchKernelGGL(k_inc_step, dim3(1), dim3(1), 
 void clear_halt(mot_handle* h) { hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(1), 0, h->stream, h->gm); }
 
 void set_step(mot_handle* h, int k) { hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, h->stream, h->d_k, k); }
+
+// first step of a window replayed from a graph
+void set_base(mot_handle* h, int k) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, h->stream, h->d_k + 1, k);
+}
 
 void rec_gather(mot_handle* h, int s0, int ns, double* X) {
     int ncol = ns * 4 * h->R;
