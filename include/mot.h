@@ -100,8 +100,12 @@ typedef struct {
                                 approximate inverse of Q_0 built once on the
                                 device by Newton-Schulz iteration;
                                 0 none, 1 stored FP32 (default), 2 FP64       */
-    int32_t stream_split;    /* wavefronts sharing one matrix row in the
-                                streaming products: 1, 2 or 4 (0: 1)          */
+    int32_t stream_split;    /* schedule of the one-RHS streaming products:
+                                1, 2 or 4 wavefronts share one matrix row, or
+                                12, 14, 18: one wavefront owns 2, 4 or 8 rows
+                                (the history at most 4); 0: chosen by the
+                                autotuner (or 1).  The history follows it
+                                in the loop order of history_order.           */
     int32_t history_order;   /* history kernel loop order: 1 (or 0) column
                                 slices across all blocks, 2 whole rows of one
                                 block at a time                               */
@@ -171,11 +175,16 @@ typedef struct {
     double precond_resid;    /* ||I - M Q_0||_F of the stored preconditioner  */
     uint64_t peak_bytes;     /* high-water mark of device_bytes so far        */
     int32_t tuned;           /* 1 once the schedules were timed (autotune)    */
-    int32_t sched_hist;      /* history schedule: one RHS 10*variant + wavefronts
-                                per row (variant 1 column slices, 0 rows);
-                                several RHS the K chunks of the tile product   */
-    int32_t sched_q0;        /* Q_0 product: wavefronts per row / K chunks    */
-    int32_t sched_pc;        /* approximate inverse: wavefronts per row / K chunks */
+    int32_t sched_hist;      /* history schedule.  One RHS: 1, 2, 4 wavefronts
+                                share a matrix row (whole rows of one lag
+                                block at a time); 10 + r: one wavefront owns
+                                r rows (column slices across all lag blocks;
+                                11 in four-wavefront workgroups); 20 + w: w
+                                wavefronts share those slices.  Several
+                                RHS: K chunks of the tile product              */
+    int32_t sched_q0;        /* Q_0 product: 1, 2, 4 wavefronts per row or
+                                10 + r rows per wavefront / K chunks          */
+    int32_t sched_pc;        /* approximate inverse: as sched_q0 / K chunks   */
     double tune_ms;          /* time spent timing candidates (0 on a cache hit) */
     int64_t graph_windows;   /* windows replayed from captured graphs          */
 } mot_info;

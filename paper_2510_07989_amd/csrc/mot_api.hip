@@ -758,10 +758,12 @@ void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V,
         // an explicit stream_split or history_order fixes that part of the
         // schedule; otherwise the autotuner picks it (or the defaults stay)
         const int sp = h->opt.stream_split;
-        const bool sp_set = sp == 1 || sp == 2 || sp == 4;
+        const bool sp_set = sp == 1 || sp == 2 || sp == 4 || sp == 12 || sp == 14 || sp == 18;
         const bool ho_set = h->opt.history_order == 1 || h->opt.history_order == 2;
-        h->wpr_hist = h->wpr_q0 = h->wpr_pc = sp_set ? sp : 1;
-        h->hist_variant = h->opt.history_order == 2 ? 0 : 1;
+        h->sch_q0 = h->sch_pc = sp_set ? sp : 1;
+        if (h->opt.history_order == 2) h->sch_hist = sp_set && sp <= 4 ? sp : 1;
+        else if (!sp_set || sp == 1) h->sch_hist = 11;
+        else h->sch_hist = sp > 10 ? std::min(sp, 14) : 20 + sp;
         h->tune_hist = h->opt.autotune && !sp_set && !ho_set;
         h->tune_mv = h->opt.autotune && !sp_set;
     }
@@ -1535,9 +1537,9 @@ int mot_get_info(const mot_handle* hc, mot_info* info) {
     info->precond_iters = h->ns_iters;
     info->precond_resid = h->ns_resid;
     info->tuned = h->tuned;
-    info->sched_hist = h->Rp > 1 ? h->hist_kc : 10 * h->hist_variant + (h->hist_variant ? 1 : h->wpr_hist);
-    info->sched_q0 = h->Rp > 1 ? h->q0_kc : h->wpr_q0;
-    info->sched_pc = h->Rp > 1 ? h->plain_kc : h->wpr_pc;
+    info->sched_hist = h->Rp > 1 ? h->hist_kc : h->sch_hist;
+    info->sched_q0 = h->Rp > 1 ? h->q0_kc : h->sch_q0;
+    info->sched_pc = h->Rp > 1 ? h->plain_kc : h->sch_pc;
     info->tune_ms = h->tune_ms;
     info->graph_windows = h->graph_windows;
     return MOT_OK;

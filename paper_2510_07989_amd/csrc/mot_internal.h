@@ -138,11 +138,15 @@ struct mot_handle {
     double* hist = nullptr;          // [max_steps][n2][R]
     int hist_cap = 0;
     int B = 128;                     // steps per RHS batch
-    // launch schedules (fixed by options or picked by the autotuner)
-    int wpr_hist = 1;                // wavefronts per matrix row: row-outer history kernel
-    int wpr_q0 = 1;                  //   Q_0 product (one RHS)
-    int wpr_pc = 1;                  //   approximate inverse product (one RHS)
-    int hist_variant = 0;            // 0 row-outer, 1 column-outer history kernel
+    // launch schedules of the one-RHS streaming products (fixed by options or
+    // picked by the autotuner):  1, 2, 4: that many wavefronts share one
+    // matrix row (history: whole rows of one lag block at a time);  10 + r:
+    // one wavefront owns r rows (history: column slices across all lag blocks;
+    // 11 is the four-wavefront workgroup form);  history 22, 24: 2 or 4
+    // wavefronts share a row's column slices across all lag blocks
+    int sch_hist = 11;
+    int sch_q0 = 1;
+    int sch_pc = 1;
     int tune_hist = 0, tune_mv = 0;  // 1: that part of the schedule is tuned
     int tuned = 0;
     double tune_ms = 0;

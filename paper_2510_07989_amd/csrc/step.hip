@@ -179,59 +179,71 @@ __global__ __launch_bounds__(256) void k_history_co(int ne, int hs, const int* _
                                                     const double* __restrict__ Q,
                                                     const double* __restrict__ ring,
                                                     const double* __restrict__ rb, int B,
-                                                    double* __restrict__ y, const GmState* __restrict__ gm) {
+                                                    double* __restrict__ y, const GmState* __restrict__ gm,
+                                                    int wpr) {
+    // wpr wavefronts share one row, each taking a contiguous 1/wpr of its
+    // column slices (across all lag blocks)
     if (gm->halt) return;
-    const int lane = threadIdx.x & 63;
-    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= ne) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = blockIdx.x * (4 / wpr) + wv / wpr;
+    const int part = wv % wpr;
     const int k = *dk;
     const size_t blk = (size_t)ne * hs;
     const int n2 = 2 * hs;
     const int nact = k - 1 < nh ? k - 1 : nh;
     const int np = hs >> 1;
+    const int cpart = np / wpr;                 // hs is a multiple of 8: np of 4
+    const int cb = part * cpart, ce = cb + cpart;
+    __shared__ double red[4][2];
     double hu = 0, hv = 0;
-    for (int c = lane; c < np; c += 64) {
-        int j = 1;
-        for (; j + 1 <= nact; j += 2) {
-            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
-            const d2v* A1 = reinterpret_cast<const d2v*>(Q + (size_t)(j + 1) * 3 * blk + (size_t)m * hs);
-            const size_t b2 = blk >> 1;
-            d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
-                q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
-            d2v a1 = __builtin_nontemporal_load(A1 + c), k1 = __builtin_nontemporal_load(A1 + b2 + c),
-                q1 = __builtin_nontemporal_load(A1 + 2 * b2 + c);
-            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
-            const d2v* w1 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j - 1) % nh) * n2);
-            d2v u0 = w0[c], v0 = w0[(hs >> 1) + c], u1 = w1[c], v1 = w1[(hs >> 1) + c];
-            hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
-            hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
-            hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
-            hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
-            hu = fma(a1.x, u1.x, hu); hu = fma(a1.y, u1.y, hu);
-            hu = fma(-k1.x, v1.x, hu); hu = fma(-k1.y, v1.y, hu);
-            hv = fma(k1.x, u1.x, hv); hv = fma(k1.y, u1.y, hv);
-            hv = fma(q1.x, v1.x, hv); hv = fma(q1.y, v1.y, hv);
-        }
-        for (; j <= nact; ++j) {
-            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
-            const size_t b2 = blk >> 1;
-            d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
-                q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
-            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
-            d2v u0 = w0[c], v0 = w0[(hs >> 1) + c];
-            hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
-            hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
-            hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
-            hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
+    if (m < ne) {
+        for (int c = cb + lane; c < ce; c += 64) {
+            int j = 1;
+            for (; j + 1 <= nact; j += 2) {
+                const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
+                const d2v* A1 = reinterpret_cast<const d2v*>(Q + (size_t)(j + 1) * 3 * blk + (size_t)m * hs);
+                const size_t b2 = blk >> 1;
+                d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
+                    q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
+                d2v a1 = __builtin_nontemporal_load(A1 + c), k1 = __builtin_nontemporal_load(A1 + b2 + c),
+                    q1 = __builtin_nontemporal_load(A1 + 2 * b2 + c);
+                const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+                const d2v* w1 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j - 1) % nh) * n2);
+                d2v u0 = w0[c], v0 = w0[(hs >> 1) + c], u1 = w1[c], v1 = w1[(hs >> 1) + c];
+                hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
+                hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
+                hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
+                hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
+                hu = fma(a1.x, u1.x, hu); hu = fma(a1.y, u1.y, hu);
+                hu = fma(-k1.x, v1.x, hu); hu = fma(-k1.y, v1.y, hu);
+                hv = fma(k1.x, u1.x, hv); hv = fma(k1.y, u1.y, hv);
+                hv = fma(q1.x, v1.x, hv); hv = fma(q1.y, v1.y, hv);
+            }
+            for (; j <= nact; ++j) {
+                const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk + (size_t)m * hs);
+                const size_t b2 = blk >> 1;
+                d2v a0 = __builtin_nontemporal_load(A0 + c), k0 = __builtin_nontemporal_load(A0 + b2 + c),
+                    q0 = __builtin_nontemporal_load(A0 + 2 * b2 + c);
+                const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+                d2v u0 = w0[c], v0 = w0[(hs >> 1) + c];
+                hu = fma(a0.x, u0.x, hu); hu = fma(a0.y, u0.y, hu);
+                hu = fma(-k0.x, v0.x, hu); hu = fma(-k0.y, v0.y, hu);
+                hv = fma(k0.x, u0.x, hv); hv = fma(k0.y, u0.y, hv);
+                hv = fma(q0.x, v0.x, hv); hv = fma(q0.y, v0.y, hv);
+            }
         }
     }
     hu = wave_sum(hu);
     hv = wave_sum(hv);
-    if (lane == 0) {
+    if (lane == 0) { red[wv][0] = hu; red[wv][1] = hv; }
+    __syncthreads();
+    if (lane == 0 && part == 0 && m < ne) {
+        double su = 0, sv = 0;
+        for (int p = 0; p < wpr; ++p) { su += red[wv + p][0]; sv += red[wv + p][1]; }
         const int sc = (k - 1) % B;
         const double* r = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;   // double-buffered batches
-        y[m] = r[(size_t)m * B + sc] - hu;
-        y[hs + m] = r[(size_t)ne * B + (size_t)m * B + sc] - hv;
+        y[m] = r[(size_t)m * B + sc] - su;
+        y[hs + m] = r[(size_t)ne * B + (size_t)m * B + sc] - sv;
     }
 }
 
@@ -343,6 +355,288 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
         const double sc = gm->inv_h;
         z[m] = sc * t;
         vj[m] = sc * src[m];
+    }
+}
+
+// ------------------------------------- several rows per wavefront (RPW) ---
+// One-wavefront workgroups, each owning RPW consecutive output rows: every
+// vector slice loaded from L2 serves RPW matrix rows, so a larger share of the
+// load instructions stream matrix entries from HBM.  Rows past the end are
+// clamped to the last row for loading (same addresses, results dropped).
+
+// history: column slices across all lag blocks, as k_history_co
+template <int RPW>
+__global__ __launch_bounds__(64) void k_history_rows(int ne, int hs, const int* __restrict__ dk, int nh,
+                                                      const double* __restrict__ Q,
+                                                      const double* __restrict__ ring,
+                                                      const double* __restrict__ rb, int B,
+                                                      double* __restrict__ y, const GmState* __restrict__ gm) {
+    if (gm->halt) return;
+    const int lane = threadIdx.x;
+    const int m0 = blockIdx.x * RPW;
+    if (m0 >= ne) return;
+    const int k = *dk;
+    const size_t blk = (size_t)ne * hs;
+    const size_t b2 = blk >> 1;                  // one block in 16-byte units
+    const int n2 = 2 * hs;
+    const int nact = k - 1 < nh ? k - 1 : nh;
+    const int np = hs >> 1;
+    size_t ro[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, ne - 1) * np;
+    double hu[RPW], hv[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) hu[r] = hv[r] = 0.0;
+    for (int c = lane; c < np; c += 64) {
+        int j = 1;
+        for (; j + 1 <= nact; j += 2) {
+            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk) + c;
+            const d2v* A1 = reinterpret_cast<const d2v*>(Q + (size_t)(j + 1) * 3 * blk) + c;
+            d2v a0[RPW], k0[RPW], q0[RPW], a1[RPW], k1[RPW], q1[RPW];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                a0[r] = __builtin_nontemporal_load(A0 + ro[r]);
+                k0[r] = __builtin_nontemporal_load(A0 + b2 + ro[r]);
+                q0[r] = __builtin_nontemporal_load(A0 + 2 * b2 + ro[r]);
+                a1[r] = __builtin_nontemporal_load(A1 + ro[r]);
+                k1[r] = __builtin_nontemporal_load(A1 + b2 + ro[r]);
+                q1[r] = __builtin_nontemporal_load(A1 + 2 * b2 + ro[r]);
+            }
+            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+            const d2v* w1 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j - 1) % nh) * n2);
+            const d2v u0 = w0[c], v0 = w0[np + c], u1 = w1[c], v1 = w1[np + c];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                double su = hu[r], sv = hv[r];
+                su = fma(a0[r].x, u0.x, su); su = fma(a0[r].y, u0.y, su);
+                su = fma(-k0[r].x, v0.x, su); su = fma(-k0[r].y, v0.y, su);
+                sv = fma(k0[r].x, u0.x, sv); sv = fma(k0[r].y, u0.y, sv);
+                sv = fma(q0[r].x, v0.x, sv); sv = fma(q0[r].y, v0.y, sv);
+                su = fma(a1[r].x, u1.x, su); su = fma(a1[r].y, u1.y, su);
+                su = fma(-k1[r].x, v1.x, su); su = fma(-k1[r].y, v1.y, su);
+                sv = fma(k1[r].x, u1.x, sv); sv = fma(k1[r].y, u1.y, sv);
+                sv = fma(q1[r].x, v1.x, sv); sv = fma(q1[r].y, v1.y, sv);
+                hu[r] = su; hv[r] = sv;
+            }
+        }
+        for (; j <= nact; ++j) {
+            const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk) + c;
+            d2v a0[RPW], k0[RPW], q0[RPW];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                a0[r] = __builtin_nontemporal_load(A0 + ro[r]);
+                k0[r] = __builtin_nontemporal_load(A0 + b2 + ro[r]);
+                q0[r] = __builtin_nontemporal_load(A0 + 2 * b2 + ro[r]);
+            }
+            const d2v* w0 = reinterpret_cast<const d2v*>(ring + (size_t)((k - j) % nh) * n2);
+            const d2v u0 = w0[c], v0 = w0[np + c];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                double su = hu[r], sv = hv[r];
+                su = fma(a0[r].x, u0.x, su); su = fma(a0[r].y, u0.y, su);
+                su = fma(-k0[r].x, v0.x, su); su = fma(-k0[r].y, v0.y, su);
+                sv = fma(k0[r].x, u0.x, sv); sv = fma(k0[r].y, u0.y, sv);
+                sv = fma(q0[r].x, v0.x, sv); sv = fma(q0[r].y, v0.y, sv);
+                hu[r] = su; hv[r] = sv;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        hu[r] = wave_sum(hu[r]);
+        hv[r] = wave_sum(hv[r]);
+    }
+    if (lane == 0) {
+        const int sc = (k - 1) % B;
+        const double* rr = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;   // double-buffered batches
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int m = m0 + r;
+            if (m < ne) {
+                y[m] = rr[(size_t)m * B + sc] - hu[r];
+                y[hs + m] = rr[(size_t)ne * B + (size_t)m * B + sc] - hv[r];
+            }
+        }
+    }
+}
+
+// y = Q0 (scale src), vout = scale src (when given), as k_q0_matvec
+template <int RPW>
+__global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __restrict__ Q0,
+                                                 const double* __restrict__ src, double* __restrict__ vout,
+                                                 double* __restrict__ y, const GmState* __restrict__ gm,
+                                                 int check_done, int use_inv) {
+    if (gm->halt || (check_done && gm->done)) return;
+    const int lane = threadIdx.x;
+    const int m0 = blockIdx.x * RPW;
+    if (m0 >= ne) return;
+    const int np = hs >> 1;
+    const size_t b2 = ((size_t)ne * hs) >> 1;
+    const d2v* A = reinterpret_cast<const d2v*>(Q0);
+    const d2v* xu = reinterpret_cast<const d2v*>(src);
+    const d2v* xv = reinterpret_cast<const d2v*>(src + hs);
+    size_t ro[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, ne - 1) * np;
+    double su[RPW], sv[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) su[r] = sv[r] = 0.0;
+    int c = lane;
+    for (; c + 64 < np; c += 128) {
+        d2v a[2][RPW], kk[2][RPW], q[2][RPW];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const size_t o = ro[r] + c + 64 * u;
+                a[u][r] = __builtin_nontemporal_load(A + o);
+                kk[u][r] = __builtin_nontemporal_load(A + b2 + o);
+                q[u][r] = __builtin_nontemporal_load(A + 2 * b2 + o);
+            }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const d2v uu = xu[c + 64 * u], vv = xv[c + 64 * u];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                double s1 = su[r], s2 = sv[r];
+                s1 = fma(a[u][r].x, uu.x, s1); s1 = fma(a[u][r].y, uu.y, s1);
+                s1 = fma(-kk[u][r].x, vv.x, s1); s1 = fma(-kk[u][r].y, vv.y, s1);
+                s2 = fma(kk[u][r].x, uu.x, s2); s2 = fma(kk[u][r].y, uu.y, s2);
+                s2 = fma(q[u][r].x, vv.x, s2); s2 = fma(q[u][r].y, vv.y, s2);
+                su[r] = s1; sv[r] = s2;
+            }
+        }
+    }
+    for (; c < np; c += 64) {
+        const d2v uu = xu[c], vv = xv[c];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const d2v a = __builtin_nontemporal_load(A + ro[r] + c);
+            const d2v kk = __builtin_nontemporal_load(A + b2 + ro[r] + c);
+            const d2v q = __builtin_nontemporal_load(A + 2 * b2 + ro[r] + c);
+            double s1 = su[r], s2 = sv[r];
+            s1 = fma(a.x, uu.x, s1); s1 = fma(a.y, uu.y, s1);
+            s1 = fma(-kk.x, vv.x, s1); s1 = fma(-kk.y, vv.y, s1);
+            s2 = fma(kk.x, uu.x, s2); s2 = fma(kk.y, uu.y, s2);
+            s2 = fma(q.x, vv.x, s2); s2 = fma(q.y, vv.y, s2);
+            su[r] = s1; sv[r] = s2;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        su[r] = wave_sum(su[r]);
+        sv[r] = wave_sum(sv[r]);
+    }
+    if (lane == 0) {
+        const double sc = use_inv ? gm->inv_h : 1.0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int m = m0 + r;
+            if (m < ne) {
+                y[m] = sc * su[r];
+                y[hs + m] = sc * sv[r];
+                if (vout) {
+                    vout[m] = sc * src[m];
+                    vout[hs + m] = sc * src[hs + m];
+                }
+            }
+        }
+    }
+}
+
+// z = M (inv_h src), V_j = inv_h src, as k_precond
+template <typename T, int RPW>
+__global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict__ M,
+                                                      const double* __restrict__ src, double* __restrict__ vj,
+                                                      double* __restrict__ z, const GmState* __restrict__ gm) {
+    if (gm->done || gm->halt) return;
+    const int lane = threadIdx.x;
+    const int m0 = blockIdx.x * RPW;
+    if (m0 >= n2) return;
+    double s[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) s[r] = 0.0;
+    if constexpr (sizeof(T) == 8) {
+        const int np = n2 >> 1;
+        const d2v* A = reinterpret_cast<const d2v*>(M);
+        const d2v* x2 = reinterpret_cast<const d2v*>(src);
+        size_t ro[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, n2 - 1) * np;
+        int c = lane;
+        for (; c + 192 < np; c += 256) {
+            d2v a[4][RPW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) a[u][r] = __builtin_nontemporal_load(A + ro[r] + c + 64 * u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const d2v xx = x2[c + 64 * u];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    s[r] = fma(a[u][r].x, xx.x, s[r]);
+                    s[r] = fma(a[u][r].y, xx.y, s[r]);
+                }
+            }
+        }
+        for (; c < np; c += 64) {
+            const d2v xx = x2[c];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const d2v a = __builtin_nontemporal_load(A + ro[r] + c);
+                s[r] = fma(a.x, xx.x, s[r]);
+                s[r] = fma(a.y, xx.y, s[r]);
+            }
+        }
+    } else {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        typedef double d4v __attribute__((ext_vector_type(4)));
+        const int nq = n2 >> 2;
+        const f4v* A = reinterpret_cast<const f4v*>(M);
+        const d4v* x4 = reinterpret_cast<const d4v*>(src);
+        size_t ro[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, n2 - 1) * nq;
+        int c = lane;
+        for (; c + 64 < nq; c += 128) {
+            f4v a[2][RPW];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) a[u][r] = __builtin_nontemporal_load(A + ro[r] + c + 64 * u);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const d4v xx = x4[c + 64 * u];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    s[r] = fma((double)a[u][r].x, xx.x, s[r]); s[r] = fma((double)a[u][r].y, xx.y, s[r]);
+                    s[r] = fma((double)a[u][r].z, xx.z, s[r]); s[r] = fma((double)a[u][r].w, xx.w, s[r]);
+                }
+            }
+        }
+        for (; c < nq; c += 64) {
+            const d4v xx = x4[c];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const f4v a = __builtin_nontemporal_load(A + ro[r] + c);
+                s[r] = fma((double)a.x, xx.x, s[r]); s[r] = fma((double)a.y, xx.y, s[r]);
+                s[r] = fma((double)a.z, xx.z, s[r]); s[r] = fma((double)a.w, xx.w, s[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) s[r] = wave_sum(s[r]);
+    if (lane == 0) {
+        const double sc = gm->inv_h;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int m = m0 + r;
+            if (m < n2) {
+                z[m] = sc * s[r];
+                vj[m] = sc * src[m];
+            }
+        }
     }
 }
 
@@ -946,14 +1240,24 @@ void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase) {
 }
 
 void history(mot_handle* h) {
-    if (h->hist_variant == 1) {
-        hipLaunchKernelGGL(k_history_co, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                           h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm);
+    const int sc = h->sch_hist;
+    if (sc == 11 || sc == 22 || sc == 24) {
+        const int w = sc == 11 ? 1 : sc - 20, rpb = 4 / w;
+        hipLaunchKernelGGL(k_history_co, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs,
+                           h->d_k, h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm, w);
         return;
     }
-    const int rpb = 4 / h->wpr_hist;
+    if (sc > 10) {
+        const int r = sc - 10;
+#define L_(R_) hipLaunchKernelGGL(k_history_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64), 0, h->stream, h->ne, \
+                                  h->hs, h->d_k, h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm)
+        if (r == 4) L_(4); else L_(2);
+#undef L_
+        return;
+    }
+    const int rpb = 4 / sc;
     hipLaunchKernelGGL(k_history, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->d_k,
-                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->wpr_hist, h->gm);
+                       h->nh, h->Q, h->ring, h->rb, h->B, h->y, sc, h->gm);
 }
 
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish) {
@@ -972,20 +1276,36 @@ void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) 
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
-    const int rpb = 4 / h->wpr_q0;
+    const int sc = h->sch_q0;
+    if (sc > 10) {
+#define L_(R_) hipLaunchKernelGGL(k_q0_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64), 0, h->stream, h->ne, h->hs, \
+                                  h->Q, src, vout, y, h->gm, check_done, use_inv)
+        if (sc == 18) L_(8); else if (sc == 14) L_(4); else L_(2);
+#undef L_
+        return;
+    }
+    const int rpb = 4 / sc;
     hipLaunchKernelGGL(k_q0_matvec, dim3((h->ne + rpb - 1) / rpb), dim3(256), 0, h->stream, h->ne, h->hs, h->Q,
-                       src, vout, y, h->gm, check_done, use_inv, h->wpr_q0);
+                       src, vout, y, h->gm, check_done, use_inv, sc);
 }
 
 void precond(mot_handle* h, const double* src, double* vj, double* z) {
-    const int rpb = 4 / h->wpr_pc;
+    const int sc = h->sch_pc;
+    if (sc > 10) {
+#define L_(T_, R_, M_) hipLaunchKernelGGL((k_precond_rows<T_, R_>), dim3((h->n2 + R_ - 1) / R_), dim3(64), 0, \
+                                          h->stream, h->n2, M_, src, vj, z, h->gm)
+#define P_(R_) do { if (h->M32) L_(float, R_, h->M32); else L_(double, R_, h->M64); } while (0)
+        if (sc == 18) P_(8); else if (sc == 14) P_(4); else P_(2);
+#undef P_
+#undef L_
+        return;
+    }
+    const int rpb = 4 / sc;
     dim3 grid((h->n2 + rpb - 1) / rpb);
     if (h->M32)
-        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm,
-                           h->wpr_pc);
+        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm, sc);
     else
-        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm,
-                           h->wpr_pc);
+        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm, sc);
 }
 
 void dense_q0(mot_handle* h, double* D) {

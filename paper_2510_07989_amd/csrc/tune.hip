@@ -3,9 +3,10 @@
 // Every MOT step streams the lag matrices once (history convolution), and each
 // Arnoldi step applies the approximate inverse and Q_0 once.  How a launch cuts
 // that work into workgroups is a schedule:
-//   one RHS:      wavefronts per matrix row (1, 2 or 4) of the streaming
-//                 products, and for the history the loop order (column slices
-//                 across all lag blocks, or whole rows of one block);
+//   one RHS:      wavefronts per matrix row (1, 2 or 4), or matrix rows per
+//                 wavefront (2, 4, 8), of the streaming products, and for the
+//                 history the loop order (column slices across all lag blocks,
+//                 or whole rows of one block);
 //   several RHS:  the number of K chunks of the tile products on MFMA (more
 //                 chunks: more workgroups in flight, more partial sums to add).
 // The fastest schedule depends on the sizes, the lag count and the chip, so it
@@ -19,6 +20,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -38,7 +41,7 @@ void precond(mot_handle* h, const double* src, double* vj, double* z);
 namespace {
 
 struct Schedule {
-    int hist_variant, wpr_hist, wpr_q0, wpr_pc;
+    int sch_hist, sch_q0, sch_pc;
     int hist_kc, q0_kc, plain_kc;
 };
 
@@ -50,18 +53,17 @@ std::map<Key, Schedule> g_cache;
 Key key_of(const mot_handle* h, int dev) {
     return Key(dev, h->ne, h->nh, h->Rp, h->opt.precision, h->hilo, h->opt.precond,
                h->opt.precision == MOT_MIXED32 ? h->opt.mix_group : 0, 2 * h->tune_hist + h->tune_mv,
-               h->tune_hist ? 0 : 10 * h->hist_variant + h->wpr_hist);
+               h->tune_hist ? 0 : h->sch_hist);
 }
 
 Schedule current(const mot_handle* h) {
-    return Schedule{h->hist_variant, h->wpr_hist, h->wpr_q0, h->wpr_pc, h->hist_kc, h->q0_kc, h->plain_kc};
+    return Schedule{h->sch_hist, h->sch_q0, h->sch_pc, h->hist_kc, h->q0_kc, h->plain_kc};
 }
 
 void apply(mot_handle* h, const Schedule& s) {
-    h->hist_variant = s.hist_variant;
-    h->wpr_hist = s.wpr_hist;
-    h->wpr_q0 = s.wpr_q0;
-    h->wpr_pc = s.wpr_pc;
+    h->sch_hist = s.sch_hist;
+    h->sch_q0 = s.sch_q0;
+    h->sch_pc = s.sch_pc;
     h->hist_kc = s.hist_kc;
     h->q0_kc = s.q0_kc;
     h->plain_kc = s.plain_kc;
@@ -96,10 +98,12 @@ int best_time(mot_handle* h, F f, int reps, float* out) {
     return MOT_OK;
 }
 
-// Pick the fastest value of one schedule field among cands.
+// Pick the fastest value of one schedule field among cands.  With MOT_TUNE_LOG
+// set in the environment every measurement is written to stderr.
 template <class Set, class F>
-int pick(mot_handle* h, const std::vector<int>& cands, Set set, F launch, int reps) {
+int pick(mot_handle* h, const char* what, const std::vector<int>& cands, Set set, F launch, int reps) {
     if (cands.size() < 2) return MOT_OK;
+    static const bool log = std::getenv("MOT_TUNE_LOG") != nullptr;
     int best_v = cands[0];
     float best_t = 3.4e38f;
     for (int v : cands) {
@@ -107,6 +111,8 @@ int pick(mot_handle* h, const std::vector<int>& cands, Set set, F launch, int re
         float t;
         int rc = best_time(h, launch, reps, &t);
         if (rc) return rc;
+        if (log) std::fprintf(stderr, "[mot autotune] ne %d R %d %s schedule %d: %.2f us\n", h->ne, h->R, what, v,
+                              1e3 * t);
         if (t < best_t) { best_t = t; best_v = v; }
     }
     set(best_v);
@@ -120,25 +126,24 @@ int tune(mot_handle* h) {
     HIPCHK(h, hipMemcpyAsync(h->d_k, &kfull, sizeof(int), hipMemcpyHostToDevice, h->stream));
     int rc = MOT_OK;
     if (h->Rp == 1) {
+        // codes: 1, 2, 4 wavefronts per row; 10 + r rows per wavefront
         if (h->tune_hist) {
-            // 10 * variant + wavefronts per row
-            const std::vector<int> c = {11, 1, 2, 4};
-            rc = pick(h, c, [&](int v) { h->hist_variant = v / 10; h->wpr_hist = v % 10; },
-                      [&] { motk_step::history(h); }, reps);
+            const std::vector<int> c = {11, 22, 24, 12, 14, 1, 2, 4};
+            rc = pick(h, "history", c, [&](int v) { h->sch_hist = v; }, [&] { motk_step::history(h); }, reps);
         }
         if (!rc && h->tune_mv) {
-            const std::vector<int> c = {1, 2, 4};
-            rc = pick(h, c, [&](int v) { h->wpr_q0 = v; },
+            const std::vector<int> c = {1, 2, 4, 12, 14, 18};
+            rc = pick(h, "Q_0 product", c, [&](int v) { h->sch_q0 = v; },
                       [&] { motk_step::q0_matvec(h, h->x, nullptr, h->wA, 0, 0); }, reps);
             if (!rc && (h->M32 || h->M64))
-                rc = pick(h, c, [&](int v) { h->wpr_pc = v; },
+                rc = pick(h, "approximate inverse", c, [&](int v) { h->sch_pc = v; },
                           [&] { motk_step::precond(h, h->wA, h->V, h->Z); }, reps);
         }
     } else {
-        rc = pick(h, h->hist_kc_c, [&](int v) { h->hist_kc = v; }, [&] { motk_multi::history_gemm(h); }, reps);
-        if (!rc) rc = pick(h, h->q0_kc_c, [&](int v) { h->q0_kc = v; }, [&] { motk_multi::q0_gemm(h, h->x); }, reps);
+        rc = pick(h, "history K chunks", h->hist_kc_c, [&](int v) { h->hist_kc = v; }, [&] { motk_multi::history_gemm(h); }, reps);
+        if (!rc) rc = pick(h, "Q_0 K chunks", h->q0_kc_c, [&](int v) { h->q0_kc = v; }, [&] { motk_multi::q0_gemm(h, h->x); }, reps);
         if (!rc && (h->M32 || h->M64))
-            rc = pick(h, h->plain_kc_c, [&](int v) { h->plain_kc = v; },
+            rc = pick(h, "approximate inverse K chunks", h->plain_kc_c, [&](int v) { h->plain_kc = v; },
                       [&] { motk_multi::precond(h, h->wA, h->V, h->Z); }, reps);
     }
     // the march starts from step 0 with clean scratch
