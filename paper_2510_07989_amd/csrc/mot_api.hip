@@ -16,7 +16,7 @@ void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first,
 void gm_orth1(mot_handle* h, double* w, int publish = 1);
 void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0, int kq = 0);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
-void precond(mot_handle* h, const double* src, double* vj, double* z);
+void precond(mot_handle* h, const double* src, double* vj, double* z, bool start = false);
 void dense_q0(mot_handle* h, double* D);
 void transpose_scale(mot_handle* h, int n, double alpha, const double* A, double* X);
 void abs_sums(mot_handle* h, int n, const double* A, double* rs, double* cs);
@@ -507,9 +507,9 @@ int gmres_solve_pc(mot_handle* h) {
         q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
         gm_start1(h, h->y, h->wA, 1, 1, nullptr);
-    } else {
-        gm_start1(h, h->y, h->wA, 0, 1, h->x);
     }
+    // cold start (FP64 approximate inverse): the first preconditioner launch
+    // takes r = y, forms beta and opens the cycle itself
     int seq = 1, iters = 0;
     bool first_cycle = true;
     for (;;) {
@@ -520,7 +520,8 @@ int gmres_solve_pc(mot_handle* h) {
         for (; j < M && iters + j < maxit; ++j) {
             double* vj = h->V + (size_t)j * h->n2;
             double* zj = h->Z + (size_t)j * h->n2;
-            precond(h, src, vj, zj);
+            const bool open = first_cycle && j == 0 && !warm;
+            precond(h, open ? h->y : src, vj, zj, open);
             if ((prc = ev_begin(h, h->ev_q0))) return prc;
             q0_matvec(h, zj, nullptr, dst, 1, 0);
             if ((prc = ev_end(h, h->ev_q0))) return prc;
@@ -1259,13 +1260,13 @@ static int queue_spec_step(mot_handle* h, bool first, int goff = -1) {
         q0_matvec(h, h->x, nullptr, h->wA, 0, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
         gm_start1(h, h->y, h->wA, 1, 1, nullptr, 0);
-    } else {
-        gm_start1(h, h->y, h->wA, 0, 1, h->x, 0);
     }
+    // cold start: the first preconditioner launch opens the cycle from r = y
     double* src = h->wA;
     double* dst = h->wB;
     for (int j = 0; j < h->spec_iters; ++j) {
-        precond(h, src, h->V + (size_t)j * h->n2, h->Z + (size_t)j * h->n2);
+        const bool open = j == 0 && !h->M32;
+        precond(h, open ? h->y : src, h->V + (size_t)j * h->n2, h->Z + (size_t)j * h->n2, open);
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->Z + (size_t)j * h->n2, nullptr, dst, 1, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;

@@ -304,20 +304,19 @@ __global__ __launch_bounds__(256) void k_gmb_orth(int n2, int RP, int R, int RB,
             const int j = jc;
             const double hn = sqrt(nn);
             double* col = g->H + (size_t)j * (M + 1);
-            double cl[MOT_MAXM + 1];
-            for (int l = 0; l <= j; ++l) cl[l] = g->h1[l] + g->h2[l];
-            cl[j + 1] = hn;
+            // rotation l touches entries l and l + 1: entry l is final after
+            // it, entry l + 1 is carried (no local array in scratch memory)
+            double carry = g->h1[0] + g->h2[0];
             for (int l = 0; l < j; ++l) {
-                double a = cl[l], b = cl[l + 1];
-                cl[l] = g->cs[l] * a + g->sn[l] * b;
-                cl[l + 1] = -g->sn[l] * a + g->cs[l] * b;
+                const double a = carry, b = g->h1[l + 1] + g->h2[l + 1];
+                col[l] = g->cs[l] * a + g->sn[l] * b;
+                carry = -g->sn[l] * a + g->cs[l] * b;
             }
-            double a = cl[j], b = cl[j + 1];
+            double a = carry, b = hn;
             double rr = hypot(a, b);
             double cs = rr > 0 ? a / rr : 1.0, sn = rr > 0 ? b / rr : 0.0;
-            cl[j] = rr;
-            cl[j + 1] = 0.0;
-            for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
+            col[j] = rr;
+            col[j + 1] = 0.0;
             g->cs[j] = cs;
             g->sn[j] = sn;
             double gj = g->g[j];

@@ -122,6 +122,50 @@ __device__ __forceinline__ void row1(const double* __restrict__ A, const double*
     }
 }
 
+// row1 that also adds the squares of the vector entries it reads into sq
+__device__ __forceinline__ void row1sq(const double* __restrict__ A, const double* __restrict__ xa,
+                                       int len, int lane, double& sa, double& sq) {
+    const d2v* a2 = reinterpret_cast<const d2v*>(A);
+    const d2v* x2 = reinterpret_cast<const d2v*>(xa);
+    const int n2 = len >> 1;
+    int c = lane;
+    for (; c + 448 < n2; c += 512) {
+        d2v a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(a2 + c + 64 * u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            d2v xu = x2[c + 64 * u];
+            sa = fma(a[u].x, xu.x, sa); sa = fma(a[u].y, xu.y, sa);
+            sq = fma(xu.x, xu.x, sq); sq = fma(xu.y, xu.y, sq);
+        }
+    }
+    for (; c < n2; c += 64) {
+        d2v a0 = __builtin_nontemporal_load(a2 + c);
+        d2v u0 = x2[c];
+        sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
+        sq = fma(u0.x, u0.x, sq); sq = fma(u0.y, u0.y, sq);
+    }
+}
+
+// Opening of a cold GMRES cycle (x0 = 0, r = b, ||b|| = beta), as k_gm_start1
+// with first = 1 leaves the state (written by one thread).
+__device__ __forceinline__ void open_cycle(GmState* gm, double beta, double tol) {
+    gm->bnorm = beta;
+    gm->total = 0;
+    gm->beta = beta;
+    gm->g[0] = beta;
+    gm->j = 0;
+    gm->cycle_iters = 0;
+    gm->breakdown = 0;
+    gm->relres = beta > 0 ? beta / beta : 0.0;
+    const int conv = (beta == 0.0) || (beta <= tol * beta);
+    gm->converged = conv;
+    gm->done = conv;
+    gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+    gm->seq = 1;
+}
+
 // y = r_k - sum_{j=1}^{min(k-1, nh)} Q_j w_{k-j}   (eq. MOT right-hand side).
 // r_k comes from the batched RHS [half][ne][B] (column (k-1) mod B).
 // Q_j = [[q1, -qk], [qk, q2]] in three [ne][hs] blocks; ring slot of w_{k-j}
@@ -303,26 +347,30 @@ __global__ __launch_bounds__(256) void k_q0_matvec(int ne, int hs, const double*
 
 // z = M (inv_h src), V_j = inv_h src : the right preconditioner of the Q_0 solve,
 // an approximate inverse of Q_0 stored dense [n2][n2] in FP32 or FP64.
+// start (FP64, cold start): src is the step's right-hand side r = y and this
+// launch also opens the GMRES cycle: every row group forms ||src|| from the
+// entries it streams anyway (same order in every group, so the same bits),
+// scales by its inverse, zeroes x, and row 0 writes the cycle state.
 template <typename T>
 __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M,
                                                  const double* __restrict__ src, double* __restrict__ vj,
-                                                 double* __restrict__ z, const GmState* __restrict__ gm,
-                                                 int wpr) {
-    if (gm->done || gm->halt) return;
+                                                 double* __restrict__ z, GmState* __restrict__ gm,
+                                                 int wpr, int start, double tol, double* __restrict__ x) {
+    if (gm->halt || (!start && gm->done)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = blockIdx.x * (4 / wpr) + wv / wpr;
     const int part = wv % wpr;
     const int plen = n2 / wpr, off = part * plen;
-    __shared__ double red[4];
-    double s0 = 0, s1 = 0;
+    __shared__ double red[4], rq[4];
+    double s0 = 0, s1 = 0, sq = 0;
     if (m < n2) {
         const T* row = M + (size_t)m * n2 + off;
-        const double* x = src + off;
+        const double* xs = src + off;
         if constexpr (sizeof(T) == 4) {
             typedef float f4v __attribute__((ext_vector_type(4)));
             typedef double d4v __attribute__((ext_vector_type(4)));
             const f4v* a4 = reinterpret_cast<const f4v*>(row);
-            const d4v* x4 = reinterpret_cast<const d4v*>(x);
+            const d4v* x4 = reinterpret_cast<const d4v*>(xs);
             const int n4 = plen >> 2;
             int c = lane;
             for (; c + 192 < n4; c += 256) {
@@ -342,17 +390,28 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
                 s0 = fma((double)a0.x, u0.x, s0); s0 = fma((double)a0.y, u0.y, s0);
                 s1 = fma((double)a0.z, u0.z, s1); s1 = fma((double)a0.w, u0.w, s1);
             }
+        } else if (start) {
+            row1sq(reinterpret_cast<const double*>(row), xs, plen, lane, s0, sq);
         } else {
-            row1(reinterpret_cast<const double*>(row), x, plen, lane, s0);
+            row1(reinterpret_cast<const double*>(row), xs, plen, lane, s0);
         }
     }
     double s = wave_sum(s0 + s1);
-    if (lane == 0) red[wv] = s;
+    if (start) sq = wave_sum(sq);
+    if (lane == 0) { red[wv] = s; rq[wv] = sq; }
     __syncthreads();
     if (lane == 0 && part == 0 && m < n2) {
         double t = 0;
         for (int p = 0; p < wpr; ++p) t += red[wv + p];
-        const double sc = gm->inv_h;
+        double sc = start ? 0.0 : gm->inv_h;
+        if (start) {
+            double q = 0;
+            for (int p = 0; p < wpr; ++p) q += rq[wv + p];
+            const double beta = sqrt(q);
+            sc = beta > 0 ? 1.0 / beta : 0.0;
+            x[m] = 0.0;
+            if (m == 0) open_cycle(gm, beta, tol);
+        }
         z[m] = sc * t;
         vj[m] = sc * src[m];
     }
@@ -544,18 +603,20 @@ __global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __
     }
 }
 
-// z = M (inv_h src), V_j = inv_h src, as k_precond
+// z = M (inv_h src), V_j = inv_h src, as k_precond (start likewise, FP64)
 template <typename T, int RPW>
 __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict__ M,
                                                       const double* __restrict__ src, double* __restrict__ vj,
-                                                      double* __restrict__ z, const GmState* __restrict__ gm) {
-    if (gm->done || gm->halt) return;
+                                                      double* __restrict__ z, GmState* __restrict__ gm,
+                                                      int start, double tol, double* __restrict__ x) {
+    if (gm->halt || (!start && gm->done)) return;
     const int lane = threadIdx.x;
     const int m0 = blockIdx.x * RPW;
     if (m0 >= n2) return;
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
+    double sq = 0.0;
     if constexpr (sizeof(T) == 8) {
         const int np = n2 >> 1;
         const d2v* A = reinterpret_cast<const d2v*>(M);
@@ -578,10 +639,12 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
                     s[r] = fma(a[u][r].x, xx.x, s[r]);
                     s[r] = fma(a[u][r].y, xx.y, s[r]);
                 }
+                if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
             }
         }
         for (; c < np; c += 64) {
             const d2v xx = x2[c];
+            if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
                 const d2v a = __builtin_nontemporal_load(A + ro[r] + c);
@@ -627,14 +690,20 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
     }
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = wave_sum(s[r]);
+    double sc = start ? 0.0 : gm->inv_h;
+    if (start) {
+        const double beta = sqrt(wave_sum(sq));
+        sc = beta > 0 ? 1.0 / beta : 0.0;
+        if (lane == 0 && m0 == 0) open_cycle(gm, beta, tol);
+    }
     if (lane == 0) {
-        const double sc = gm->inv_h;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int m = m0 + r;
             if (m < n2) {
                 z[m] = sc * s[r];
                 vj[m] = sc * src[m];
+                if (start) x[m] = 0.0;
             }
         }
     }
@@ -953,21 +1022,20 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
 
 __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, double* col, double hn, int j,
                               int M, double tol) {
-    // values kept in registers; global state written once at the end
-    double cl[MOT_MAXM + 1];
-    for (int l = 0; l <= j; ++l) cl[l] = hvals[l];
-    cl[j + 1] = hn;
+    // the earlier rotations sweep the new column from the top: rotation l
+    // touches entries l and l + 1 only, so entry l is final after it and is
+    // stored at once, and entry l + 1 is carried in a register (no local array,
+    // which would live in scratch memory)
+    double carry = hvals[0];
     for (int l = 0; l < j; ++l) {
-        double cs = gm->cs[l], sn = gm->sn[l];
-        double a = cl[l], b = cl[l + 1];
-        cl[l] = cs * a + sn * b;
-        cl[l + 1] = -sn * a + cs * b;
+        const double cs = gm->cs[l], sn = gm->sn[l];
+        const double a = carry, b = hvals[l + 1];
+        col[l] = cs * a + sn * b;
+        carry = -sn * a + cs * b;
     }
-    double a = cl[j], b = cl[j + 1];
+    double a = carry, b = hn;
     double r = hypot(a, b);
     double cs = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
-    cl[j] = r;
-    cl[j + 1] = 0.0;
     const double gj = gm->g[j], bnorm = gm->bnorm, beta = gm->beta;
     const int total = gm->total + 1;
     const double gnew = -sn * gj;
@@ -984,7 +1052,8 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
         flag->done = done;
         flag->total = total;
     }
-    for (int l = 0; l <= j + 1; ++l) col[l] = cl[l];
+    col[j] = r;
+    col[j + 1] = 0.0;
     gm->cs[j] = cs;
     gm->sn[j] = sn;
     gm->g[j] = cs * gj;
@@ -1013,7 +1082,9 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
     }
 }
 
-// CGS2 of w against V[0..j], norm, Givens: one workgroup.
+// CGS2 of w against V[0..j], norm, Givens: one workgroup; EPT elements of w
+// per thread stay in registers (EPT * 1024 >= n2).
+template <int EPT>
 __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restrict__ V,
                                                    double* __restrict__ w, GmState* gm, GmFlag* flag,
                                                    double tol, int M) {
@@ -1036,40 +1107,38 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
     __shared__ double sh[kSW / 64];
     __shared__ double hc[MOT_MAXM + 1];
     const int j = gm->j;
-    double wv[kSWE];
-    const int ne_t = (n2 + kSW - 1) / kSW;
+    double wv[EPT];
 #pragma unroll
-    for (int e = 0; e < kSWE; ++e) {
-        int i = threadIdx.x + e * kSW;
-        wv[e] = (e < ne_t && i < n2) ? w[i] : 0.0;
+    for (int e = 0; e < EPT; ++e) {
+        const int i = threadIdx.x + e * kSW;
+        wv[e] = i < n2 ? w[i] : 0.0;
     }
-    if (threadIdx.x <= j) hc[threadIdx.x] = 0.0;
+    if ((int)threadIdx.x <= j) hc[threadIdx.x] = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
         for (int l = 0; l <= j; ++l) {
             const double* v = V + (size_t)l * n2;
+            double vl[EPT];
             double s = 0;
 #pragma unroll
-            for (int e = 0; e < kSWE; ++e) {
-                int i = threadIdx.x + e * kSW;
-                if (e < ne_t && i < n2) s = fma(v[i], wv[e], s);
+            for (int e = 0; e < EPT; ++e) {
+                const int i = threadIdx.x + e * kSW;
+                vl[e] = i < n2 ? v[i] : 0.0;
+                s = fma(vl[e], wv[e], s);
             }
             s = block_sum_sw(s, sh);
 #pragma unroll
-            for (int e = 0; e < kSWE; ++e) {
-                int i = threadIdx.x + e * kSW;
-                if (e < ne_t && i < n2) wv[e] = fma(-s, v[i], wv[e]);
-            }
+            for (int e = 0; e < EPT; ++e) wv[e] = fma(-s, vl[e], wv[e]);
             if (threadIdx.x == 0) hc[l] += s;
         }
     }
     double nn = 0;
 #pragma unroll
-    for (int e = 0; e < kSWE; ++e) nn = fma(wv[e], wv[e], nn);
+    for (int e = 0; e < EPT; ++e) nn = fma(wv[e], wv[e], nn);
     nn = block_sum_sw(nn, sh);
 #pragma unroll
-    for (int e = 0; e < kSWE; ++e) {
-        int i = threadIdx.x + e * kSW;
-        if (e < ne_t && i < n2) w[i] = wv[e];
+    for (int e = 0; e < EPT; ++e) {
+        const int i = threadIdx.x + e * kSW;
+        if (i < n2) w[i] = wv[e];
     }
     __syncthreads();
     if (threadIdx.x == 0) givens_finish(gm, flag, hc, gm->H + (size_t)j * (M + 1), sqrt(nn), j, M, tol);
@@ -1266,8 +1335,15 @@ void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first,
 }
 
 void gm_orth1(mot_handle* h, double* w, int publish) {
-    hipLaunchKernelGGL(k_gm_orth1, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm,
-                       publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M);
+    const int ept = (h->n2 + kSW - 1) / kSW;
+#define L_(E_) hipLaunchKernelGGL(k_gm_orth1<E_>, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm, \
+                                  publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M)
+    if (ept <= 2) L_(2);
+    else if (ept <= 4) L_(4);
+    else if (ept <= 8) L_(8);
+    else if (ept <= 16) L_(16);
+    else L_(32);
+#undef L_
 }
 
 void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) {
@@ -1289,11 +1365,15 @@ void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int ch
                        src, vout, y, h->gm, check_done, use_inv, sc);
 }
 
-void precond(mot_handle* h, const double* src, double* vj, double* z) {
+// start: src is the step's right-hand side and the launch opens the cold
+// GMRES cycle (FP64 approximate inverse only)
+void precond(mot_handle* h, const double* src, double* vj, double* z, bool start) {
     const int sc = h->sch_pc;
+    const int st = start && !h->M32;
+    const double tol = h->opt.gmres_tol;
     if (sc > 10) {
 #define L_(T_, R_, M_) hipLaunchKernelGGL((k_precond_rows<T_, R_>), dim3((h->n2 + R_ - 1) / R_), dim3(64), 0, \
-                                          h->stream, h->n2, M_, src, vj, z, h->gm)
+                                          h->stream, h->n2, M_, src, vj, z, h->gm, st, tol, h->x)
 #define P_(R_) do { if (h->M32) L_(float, R_, h->M32); else L_(double, R_, h->M64); } while (0)
         if (sc == 18) P_(8); else if (sc == 14) P_(4); else P_(2);
 #undef P_
@@ -1303,9 +1383,11 @@ void precond(mot_handle* h, const double* src, double* vj, double* z) {
     const int rpb = 4 / sc;
     dim3 grid((h->n2 + rpb - 1) / rpb);
     if (h->M32)
-        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm, sc);
+        hipLaunchKernelGGL(k_precond<float>, grid, dim3(256), 0, h->stream, h->n2, h->M32, src, vj, z, h->gm, sc, 0,
+                           tol, h->x);
     else
-        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm, sc);
+        hipLaunchKernelGGL(k_precond<double>, grid, dim3(256), 0, h->stream, h->n2, h->M64, src, vj, z, h->gm, sc, st,
+                           tol, h->x);
 }
 
 void dense_q0(mot_handle* h, double* D) {

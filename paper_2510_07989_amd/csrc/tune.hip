@@ -29,7 +29,7 @@
 namespace motk_step {
 void history(mot_handle* h);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
-void precond(mot_handle* h, const double* src, double* vj, double* z);
+void precond(mot_handle* h, const double* src, double* vj, double* z, bool start = false);
 }  // namespace motk_step
 
 namespace motk_multi {
