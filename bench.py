@@ -139,7 +139,9 @@ def col_blocks(R):
 
 def history_kernel_name(R, precision, mix_group, sched_hist=11):
     if R == 1:
-        return "k_history_co" if sched_hist >= 10 else "k_history"
+        if sched_hist in (11, 22, 24):
+            return "k_history_co"
+        return "k_history_rows<%d>" % (sched_hist - 10) if sched_hist > 10 else "k_history"
     if precision == 2:
         fl = {64: 16, 16: 4}.get(mix_group, 1)
         return "k_hist_mfma<%d, %d>" % (col_blocks(R), fl)
@@ -189,7 +191,9 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     dtype = "f32" if precision == 2 else "f64"
     hist = roofline(kname, hb, hf, hist_us, dtype, R > 1, measured_traffic(kname, name))
     q0b = 8.0 * (3 * ne * ne + 2 * n * R)
-    q0name = "k_q0_matvec" if R == 1 else "k_tile_gemm<double, %d>" % col_blocks(R)
+    sq = inf0["sched_q0"]
+    q0name = (("k_q0_rows<%d>" % (sq - 10) if sq > 10 else "k_q0_matvec") if R == 1
+              else "k_tile_gemm<double, %d>" % col_blocks(R))
     q0 = roofline(q0name, q0b, 2.0 * 4 * ne * ne * R, q0_us, "f64", R > 1,
                   measured_traffic(q0name if R == 1 else q0name + " (Q_0)", name))
     hist_tot = b["hist_ms"] - a["hist_ms"]
@@ -244,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched/mixed comparison")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison")
+    ap.add_argument("--no-wide", action="store_true", help="skip the 64-wave batched runs")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
@@ -358,6 +363,32 @@ def main():
         }
         log("batched: FP64 1 RHS %.1f steps/s; FP64 16 RHS %.1f; mixed 16 RHS %.1f (err w %.2e star %.2e vs FP64)"
             % (r1["steps_s"], r16["steps_s"], rmx["steps_s"], err["w"], err["star"]))
+        if not args.no_wide:
+            # 64 waves on the same mesh (the lag blocks do not depend on the
+            # waves): the history products become MFMA-bound
+            from fixture.problem import CONFIGS, make_waves
+            cfg = CONFIGS[name]
+            p64 = dict(pb, waves=make_waves(64, cfg["sigma"], True))
+            K64, W64 = 300, 100
+            w64 = {}
+            for key, prec in (("fp64_64rhs", 0), ("mixed_64rhs", 1), ("mixed32_64rhs", 2)):
+                w64[key] = measure(mot, p64, name, prec, K64, W64, args.precond, args.split, args.hilo,
+                                   args.mix_group, outputs=False)
+            ref = w64["fp64_64rhs"]["warm"]
+            wide = {"workload": name + " with 64 seeded waves", "steps": K64, "warmup": W64}
+            for key, prec in (("fp64_64rhs", 0), ("mixed_64rhs", 1), ("mixed32_64rhs", 2)):
+                e = dict(brief(w64[key]), precision=PRECISION[prec])
+                if prec:
+                    e["err_vs_fp64_64rhs"] = {"steps": W64, **{k: rel(w64[key]["warm"][k], ref[k])
+                                                               for k in ("w", "loop", "star")}}
+                    if prec == 2:
+                        e["mix_group"] = args.mix_group
+                wide[key] = e
+            result["batched"]["wide"] = wide
+            log("batched, 64 waves: FP64 %.1f steps/s, mixed %.1f (err w %.2e), mixed32 %.1f (err w %.2e)"
+                % (w64["fp64_64rhs"]["steps_s"], w64["mixed_64rhs"]["steps_s"],
+                   wide["mixed_64rhs"]["err_vs_fp64_64rhs"]["w"], w64["mixed32_64rhs"]["steps_s"],
+                   wide["mixed32_64rhs"]["err_vs_fp64_64rhs"]["w"]))
     if args.serving:
         have = {args.workload: prob}
         if not args.no_batched:
