@@ -405,8 +405,9 @@ def serving(nreq, have=None, seed=251007990):
     each a random scatterer among the assembled ones (torus, box and sphere
     meshes of 432 to 6144 unknowns), 1 to 16 of its plane waves, 500 to 2000
     steps; admission by peak device footprint under a budget, at most 8 solves
-    at once, windows of 64 steps, every request from mot_create on (setup, the
-    upload and fold of its lag blocks, the march, outputs on the host)."""
+    at once, windows of 128 steps, every request from mot_create on (setup, the
+    upload and fold of its lag blocks, the march, outputs on the host); the
+    same stream once with launches and once with graph replay."""
     import numpy as np
     from fixture.problem import build_problem
     from paper_2510_07989_amd.serve import GpuBackend, Request, Server, latency_stats
@@ -427,19 +428,25 @@ def serving(nreq, have=None, seed=251007990):
         pr = dict(p, waves=p["waves"][:R])
         reqs.append(Request(i, pr, nsteps, float(arrivals[i]), dict(precond=2)))
         log("[serve] request %d: %s, %d waves, %d steps, arrives at %.3f s" % (i, m, R, nsteps, arrivals[i]))
-    be = GpuBackend(keep_outputs=True)
-    fps = sorted(be.footprint(r) for r in reqs)
+    out = {"requests": nreq, "arrival_rate_per_s": rate, "seed": seed, "meshes": SERVING_MESHES,
+           "max_active": 8, "window_steps": 128}
+    fps = sorted(GpuBackend().footprint(r) for r in reqs)
     budget = 3 * fps[-1]
-    srv = Server(be, mem_budget=budget, max_active=8, window=64, request_timeout=60.0, log=log)
-    res, summ = srv.run(reqs)
-    log("serving: %d requests in %.2f s, %.1f steps/s, step p50 %.1f us p99 %.1f us, end-to-end p50 %.3f s p99 %.3f s"
-        % (nreq, summ["wall_s"], summ["steps_per_s"], 1e6 * summ["step_latency_s"]["p50"],
-           1e6 * summ["step_latency_s"]["p99"], summ["end_to_end_s"]["p50"], summ["end_to_end_s"]["p99"]))
-    mix = {}
-    for r in reqs:
-        mix[r.problem["name"]] = mix.get(r.problem["name"], 0) + 1
-    return {"requests": nreq, "arrival_rate_per_s": rate, "seed": seed, "meshes": SERVING_MESHES,
-            "mem_budget_bytes": budget, "max_active": 8, "window_steps": 64,
+    out["mem_budget_bytes"] = budget
+    # the same stream twice: windows queued launch by launch, then replayed from
+    # captured graphs (128-step windows: one RHS batch, so every full window replays)
+    for label, graph in (("launches", 0), ("graphs", 1)):
+        be = GpuBackend(options={"graph": graph}, keep_outputs=True)
+        srv = Server(be, mem_budget=budget, max_active=8, window=128, request_timeout=60.0, log=log)
+        res, summ = srv.run(reqs)
+        log("serving (%s): %d requests in %.2f s, %.1f steps/s, step p50 %.1f us p99 %.1f us, end-to-end p50 "
+            "%.3f s p99 %.3f s" % (label, nreq, summ["wall_s"], summ["steps_per_s"],
+                                   1e6 * summ["step_latency_s"]["p50"], 1e6 * summ["step_latency_s"]["p99"],
+                                   summ["end_to_end_s"]["p50"], summ["end_to_end_s"]["p99"]))
+        mix = {}
+        for r in reqs:
+            mix[r.problem["name"]] = mix.get(r.problem["name"], 0) + 1
+        out[label] = {
             "wall_s": round(summ["wall_s"], 3), "steps_per_s": round(summ["steps_per_s"], 1),
             "rhs_steps_per_s": round(summ["rhs_steps_per_s"], 1),
             "step_latency_us": {k: round(1e6 * v, 2) if k != "n" else v for k, v in summ["step_latency_s"].items()},
@@ -449,10 +456,11 @@ def serving(nreq, have=None, seed=251007990):
                         for k, v in latency_stats(r.t_ready - r.t_admit for r in res.values()
                                                   if r.error is None).items()},
             "mix": mix,
-            "max_concurrent": summ["max_concurrent"], "errors": summ["errors"],
-            "note": "requests reuse the scatterers assembled for this run (host-side assembly of hundreds of "
-                    "distinct large meshes is out of reach of a bench run); each request still builds its "
-                    "solver, uploads and folds its lags on the device"}
+            "max_concurrent": summ["max_concurrent"], "errors": summ["errors"]}
+    out["note"] = ("requests reuse the scatterers assembled for this run (host-side assembly of hundreds of "
+                   "distinct large meshes is out of reach of a bench run); each request still builds its "
+                   "solver, uploads and folds its lags on the device")
+    return out
 
 
 if __name__ == "__main__":
