@@ -108,7 +108,9 @@ typedef struct {
                                 in the loop order of history_order.           */
     int32_t history_order;   /* history kernel loop order: 1 (or 0) column
                                 slices across all blocks, 2 whole rows of one
-                                block at a time                               */
+                                block at a time, 3 column slices with 2 (with
+                                stream_split 12) or 4 (otherwise) wavefronts
+                                sharing as many rows                          */
     int32_t hilo_lags;       /* mixed modes: lags 1..hilo_lags keep the FP32
                                 low part fl(Q - fl(Q)) (default 2, -1: none);
                                 MOT_MIXED32 multiplies it as split hi/lo
@@ -180,7 +182,8 @@ typedef struct {
                                 block at a time); 10 + r: one wavefront owns
                                 r rows (column slices across all lag blocks;
                                 11 in four-wavefront workgroups); 20 + w: w
-                                wavefronts share those slices.  Several
+                                wavefronts share those slices of one row;
+                                30 + r: r wavefronts share r rows.  Several
                                 RHS: K chunks of the tile product              */
     int32_t sched_q0;        /* Q_0 product: 1, 2, 4 wavefronts per row or
                                 10 + r rows per wavefront / K chunks          */

@@ -13,7 +13,7 @@ namespace motk_step {
 void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase = nullptr);
 void history(mot_handle* h);
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish = 1);
-void gm_orth1(mot_handle* h, double* w, int publish = 1);
+void gm_orth1(mot_handle* h, double* w, int publish = 1, int fin_kq = 0);
 void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0, int kq = 0);
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv);
 void precond(mot_handle* h, const double* src, double* vj, double* z, bool start = false);
@@ -760,9 +760,10 @@ void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V,
         // schedule; otherwise the autotuner picks it (or the defaults stay)
         const int sp = h->opt.stream_split;
         const bool sp_set = sp == 1 || sp == 2 || sp == 4 || sp == 12 || sp == 14 || sp == 18;
-        const bool ho_set = h->opt.history_order == 1 || h->opt.history_order == 2;
+        const bool ho_set = h->opt.history_order >= 1 && h->opt.history_order <= 3;
         h->sch_q0 = h->sch_pc = sp_set ? sp : 1;
         if (h->opt.history_order == 2) h->sch_hist = sp_set && sp <= 4 ? sp : 1;
+        else if (h->opt.history_order == 3) h->sch_hist = sp == 12 ? 32 : 34;
         else if (!sp_set || sp == 1) h->sch_hist = 11;
         else h->sch_hist = sp > 10 ? std::min(sp, 14) : 20 + sp;
         h->tune_hist = h->opt.autotune && !sp_set && !ho_set;
@@ -1270,10 +1271,10 @@ static int queue_spec_step(mot_handle* h, bool first, int goff = -1) {
         if ((prc = ev_begin(h, h->ev_q0))) return prc;
         q0_matvec(h, h->Z + (size_t)j * h->n2, nullptr, dst, 1, 0);
         if ((prc = ev_end(h, h->ev_q0))) return prc;
-        gm_orth1(h, dst, 0);
+        // the last queued Arnoldi step also runs the speculative finisher
+        gm_orth1(h, dst, 0, j + 1 == h->spec_iters ? kq : 0);
         std::swap(src, dst);
     }
-    gm_finish(h, h->Z, 0, 1, kq);
     return MOT_OK;
 }
 

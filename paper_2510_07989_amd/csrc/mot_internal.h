@@ -143,7 +143,8 @@ struct mot_handle {
     // matrix row (history: whole rows of one lag block at a time);  10 + r:
     // one wavefront owns r rows (history: column slices across all lag blocks;
     // 11 is the four-wavefront workgroup form);  history 22, 24: 2 or 4
-    // wavefronts share a row's column slices across all lag blocks
+    // wavefronts share a row's column slices across all lag blocks; 32, 34:
+    // 2 or 4 wavefronts share as many rows
     int sch_hist = 11;
     int sch_q0 = 1;
     int sch_pc = 1;

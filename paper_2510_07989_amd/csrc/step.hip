@@ -423,17 +423,20 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
 // load instructions stream matrix entries from HBM.  Rows past the end are
 // clamped to the last row for loading (same addresses, results dropped).
 
-// history: column slices across all lag blocks, as k_history_co
+// history: column slices across all lag blocks, as k_history_co.  cs
+// wavefronts (the workgroup) share the RPW rows, each taking a contiguous
+// 1/cs of the column slices: the ring slices a wavefront loads then serve RPW
+// rows while the launch keeps as many wavefronts as one row per wavefront.
 template <int RPW>
-__global__ __launch_bounds__(64) void k_history_rows(int ne, int hs, const int* __restrict__ dk, int nh,
-                                                      const double* __restrict__ Q,
-                                                      const double* __restrict__ ring,
-                                                      const double* __restrict__ rb, int B,
-                                                      double* __restrict__ y, const GmState* __restrict__ gm) {
+__global__ __launch_bounds__(256) void k_history_rows(int ne, int hs, const int* __restrict__ dk, int nh,
+                                                       const double* __restrict__ Q,
+                                                       const double* __restrict__ ring,
+                                                       const double* __restrict__ rb, int B,
+                                                       double* __restrict__ y, const GmState* __restrict__ gm,
+                                                       int cs) {
     if (gm->halt) return;
-    const int lane = threadIdx.x;
-    const int m0 = blockIdx.x * RPW;
-    if (m0 >= ne) return;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * RPW;             // < ne: the grid has ceil(ne / RPW) workgroups
     const int k = *dk;
     const size_t blk = (size_t)ne * hs;
     const size_t b2 = blk >> 1;                  // one block in 16-byte units
@@ -446,7 +449,8 @@ __global__ __launch_bounds__(64) void k_history_rows(int ne, int hs, const int* 
     double hu[RPW], hv[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) hu[r] = hv[r] = 0.0;
-    for (int c = lane; c < np; c += 64) {
+    const int cpart = np / cs;                   // hs is a multiple of 8: np of 4
+    for (int c = part * cpart + lane; c < (part + 1) * cpart; c += 64) {
         int j = 1;
         for (; j + 1 <= nact; j += 2) {
             const d2v* A0 = reinterpret_cast<const d2v*>(Q + (size_t)j * 3 * blk) + c;
@@ -500,20 +504,25 @@ __global__ __launch_bounds__(64) void k_history_rows(int ne, int hs, const int* 
             }
         }
     }
+    __shared__ double red[4][RPW][2];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         hu[r] = wave_sum(hu[r]);
         hv[r] = wave_sum(hv[r]);
+        if (lane == 0) { red[part][r][0] = hu[r]; red[part][r][1] = hv[r]; }
     }
-    if (lane == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const int sc = (k - 1) % B;
         const double* rr = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;   // double-buffered batches
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int m = m0 + r;
             if (m < ne) {
-                y[m] = rr[(size_t)m * B + sc] - hu[r];
-                y[hs + m] = rr[(size_t)ne * B + (size_t)m * B + sc] - hv[r];
+                double su = 0, sv = 0;
+                for (int p = 0; p < cs; ++p) { su += red[p][r][0]; sv += red[p][r][1]; }
+                y[m] = rr[(size_t)m * B + sc] - su;
+                y[hs + m] = rr[(size_t)ne * B + (size_t)m * B + sc] - sv;
             }
         }
     }
@@ -1082,12 +1091,69 @@ __device__ void givens_finish(GmState* gm, GmFlag* flag, const double* hvals, do
     }
 }
 
+// When the cycle is done: x += sum_l y_l Z_l ; when converged (or forced) also
+// push x into the ring and the kept history.
+// spec = 1 (speculative stepping): a solve that has not converged pushes
+// nothing and raises the halt word instead, so that the later queued steps do
+// nothing until the host has finished this one.
+// kq > 0 (queued steps): the step index comes from the host; kq < 0 (steps
+// replayed from a captured graph): it is the window's first step dk[1] plus
+// -kq - 1.  In both cases the device step counter dk[0] is set to k + 1 after
+// a push, for the next queued step (no thread of the launch reads it, so the
+// write does not race).
+struct FinArgs {
+    const double* Zb;
+    double* x;
+    int* dk;
+    int nh;
+    double* ring;
+    double* hist;
+    int hist_cap;
+    int kq;
+};
+
+// t0, nt: this thread's first element and the element stride of the launch;
+// lead: the one thread that writes the scalars
+__device__ __forceinline__ void finish_body(int n2, GmState* __restrict__ gm, const FinArgs& f, int force, int spec,
+                                            int t0, int nt, bool lead) {
+    const int k = f.kq > 0 ? f.kq : (f.kq < 0 ? f.dk[1] - f.kq - 1 : f.dk[0]);
+    if (spec && !(gm->done && gm->converged)) {
+        if (lead) {
+            gm->halt_k = k;
+            gm->halt = 1;
+        }
+        return;
+    }
+    if (!gm->done && !force) return;
+    const int jj = gm->done ? gm->cycle_iters : 0;
+    const int push = gm->converged || force;
+    if (f.kq != 0 && push && lead) f.dk[0] = k + 1;
+    double* slot = f.ring + (size_t)(k % f.nh) * n2;
+    double* hs = (f.hist && k - 1 < f.hist_cap) ? f.hist + (size_t)(k - 1) * n2 : nullptr;
+    for (int i = t0; i < n2; i += nt) {
+        double s = f.x[i];
+        for (int l = 0; l < jj; ++l) s = fma(gm->y[l], f.Zb[(size_t)l * n2 + i], s);
+        f.x[i] = s;
+        if (push) {
+            slot[i] = s;
+            if (hs) hs[i] = s;
+        }
+    }
+}
+
+__global__ void k_gm_finish(int n2, GmState* __restrict__ gm, FinArgs f, int force, int spec) {
+    if (gm->halt) return;
+    finish_body(n2, gm, f, force, spec, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                blockIdx.x == 0 && threadIdx.x == 0);
+}
+
 // CGS2 of w against V[0..j], norm, Givens: one workgroup; EPT elements of w
-// per thread stay in registers (EPT * 1024 >= n2).
+// per thread stay in registers (EPT * 1024 >= n2).  fin: the queued step's
+// speculative finisher (spec = 1) runs in the same workgroup afterwards.
 template <int EPT>
 __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restrict__ V,
                                                    double* __restrict__ w, GmState* gm, GmFlag* flag,
-                                                   double tol, int M) {
+                                                   double tol, int M, int fin, FinArgs fa) {
     if (gm->halt) return;
     if (gm->done) {
         // nothing to do, but every launch publishes one progress word
@@ -1102,6 +1168,7 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
                 flag->seq = gm->seq;
             }
         }
+        if (fin) finish_body(n2, gm, fa, 0, 1, threadIdx.x, kSW, threadIdx.x == 0);
         return;
     }
     __shared__ double sh[kSW / 64];
@@ -1142,45 +1209,9 @@ __global__ __launch_bounds__(kSW) void k_gm_orth1(int n2, const double* __restri
     }
     __syncthreads();
     if (threadIdx.x == 0) givens_finish(gm, flag, hc, gm->H + (size_t)j * (M + 1), sqrt(nn), j, M, tol);
-}
-
-// When the cycle is done: x += sum_l y_l Z_l ; when converged (or forced) also
-// push x into the ring and the kept history.
-// spec = 1 (speculative stepping): a solve that has not converged pushes
-// nothing and raises the halt word instead, so that the later queued steps do
-// nothing until the host has finished this one.
-// kq > 0 (queued steps): the step index comes from the host; kq < 0 (steps
-// replayed from a captured graph): it is the window's first step dk[1] plus
-// -kq - 1.  In both cases the device step counter dk[0] is set to k + 1 after
-// a push, for the next queued step (no block of this launch reads it, so the
-// write does not race).
-__global__ void k_gm_finish(int n2, const double* __restrict__ Zb, GmState* __restrict__ gm,
-                            double* __restrict__ x, int* __restrict__ dk, int nh,
-                            double* __restrict__ ring, double* __restrict__ hist, int hist_cap, int force,
-                            int spec, int kq) {
-    if (gm->halt) return;
-    const int k = kq > 0 ? kq : (kq < 0 ? dk[1] - kq - 1 : dk[0]);
-    if (spec && !(gm->done && gm->converged)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            gm->halt_k = k;
-            gm->halt = 1;
-        }
-        return;
-    }
-    if (!gm->done && !force) return;
-    const int jj = gm->done ? gm->cycle_iters : 0;
-    const int push = gm->converged || force;
-    if (kq != 0 && push && blockIdx.x == 0 && threadIdx.x == 0) dk[0] = k + 1;
-    double* slot = ring + (size_t)(k % nh) * n2;
-    double* hs = (hist && k - 1 < hist_cap) ? hist + (size_t)(k - 1) * n2 : nullptr;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
-        double s = x[i];
-        for (int l = 0; l < jj; ++l) s = fma(gm->y[l], Zb[(size_t)l * n2 + i], s);
-        x[i] = s;
-        if (push) {
-            slot[i] = s;
-            if (hs) hs[i] = s;
-        }
+    if (fin) {
+        __syncthreads();                  // the cycle state written by thread 0
+        finish_body(n2, gm, fa, 0, 1, threadIdx.x, kSW, threadIdx.x == 0);
     }
 }
 
@@ -1317,9 +1348,10 @@ void history(mot_handle* h) {
         return;
     }
     if (sc > 10) {
-        const int r = sc - 10;
-#define L_(R_) hipLaunchKernelGGL(k_history_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64), 0, h->stream, h->ne, \
-                                  h->hs, h->d_k, h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm)
+        // 12, 14: one wavefront per r rows; 32, 34: r wavefronts share r rows
+        const int r = sc % 10, cs = sc > 30 ? r : 1;
+#define L_(R_) hipLaunchKernelGGL(k_history_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64 * cs), 0, h->stream, \
+                                  h->ne, h->hs, h->d_k, h->nh, h->Q, h->ring, h->rb, h->B, h->y, h->gm, cs)
         if (r == 4) L_(4); else L_(2);
 #undef L_
         return;
@@ -1334,10 +1366,18 @@ void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first,
                        publish ? h->dflag : nullptr, h->opt.gmres_tol, first, xzero);
 }
 
-void gm_orth1(mot_handle* h, double* w, int publish) {
+static FinArgs fin_args(mot_handle* h, const double* basis, int kq) {
+    return FinArgs{basis, h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, kq};
+}
+
+// fin_kq != 0: also the speculative finisher of queued step fin_kq (as gm_finish
+// with spec = 1), in the same workgroup
+void gm_orth1(mot_handle* h, double* w, int publish, int fin_kq) {
     const int ept = (h->n2 + kSW - 1) / kSW;
+    const FinArgs fa = fin_args(h, h->Z, fin_kq);
+    const int fin = fin_kq != 0;
 #define L_(E_) hipLaunchKernelGGL(k_gm_orth1<E_>, dim3(1), dim3(kSW), 0, h->stream, h->n2, h->V, w, h->gm, \
-                                  publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M)
+                                  publish ? h->dflag : nullptr, h->opt.gmres_tol, h->M, fin, fa)
     if (ept <= 2) L_(2);
     else if (ept <= 4) L_(4);
     else if (ept <= 8) L_(8);
@@ -1347,8 +1387,8 @@ void gm_orth1(mot_handle* h, double* w, int publish) {
 }
 
 void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) {
-    hipLaunchKernelGGL(k_gm_finish, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, basis, h->gm,
-                       h->x, h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec, kq);
+    hipLaunchKernelGGL(k_gm_finish, dim3((h->n2 + 255) / 256), dim3(256), 0, h->stream, h->n2, h->gm,
+                       fin_args(h, basis, kq), force, spec);
 }
 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {

@@ -128,7 +128,7 @@ int tune(mot_handle* h) {
     if (h->Rp == 1) {
         // codes: 1, 2, 4 wavefronts per row; 10 + r rows per wavefront
         if (h->tune_hist) {
-            const std::vector<int> c = {11, 22, 24, 12, 14, 1, 2, 4};
+            const std::vector<int> c = {11, 22, 24, 12, 14, 32, 34, 1, 2, 4};
             rc = pick(h, "history", c, [&](int v) { h->sch_hist = v; }, [&] { motk_step::history(h); }, reps);
         }
         if (!rc && h->tune_mv) {

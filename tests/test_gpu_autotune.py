@@ -40,7 +40,7 @@ def test_tuned_equals_untuned(name, opts, nsteps):
           "tuned", {k: i1[k] for k in ("sched_hist", "sched_q0", "sched_pc", "tune_ms")}, flush=True)
     assert i0["tuned"] == 1 and i1["tuned"] == 1
     if i1["nrhs"] == 1:
-        assert i1["sched_hist"] in (11, 22, 24, 12, 14, 1, 2, 4)
+        assert i1["sched_hist"] in (11, 22, 24, 12, 14, 32, 34, 1, 2, 4)
         assert i1["sched_q0"] in (1, 2, 4, 12, 14, 18) and i1["sched_pc"] in (1, 2, 4, 12, 14, 18)
     else:
         for k in ("sched_hist", "sched_q0", "sched_pc"):
