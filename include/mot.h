@@ -103,9 +103,10 @@ typedef struct {
     int32_t stream_split;    /* schedule of the one-RHS streaming products:
                                 1, 2 or 4 wavefronts share one matrix row, or
                                 12, 14, 18: one wavefront owns 2, 4 or 8 rows
-                                (the history at most 4); 0: chosen by the
-                                autotuner (or 1).  The history follows it
-                                in the loop order of history_order.           */
+                                (the history at most 4); 32, 34: 2 or 4
+                                wavefronts share as many rows; 0: chosen by
+                                the autotuner (or 1).  The history follows
+                                it in the loop order of history_order.        */
     int32_t history_order;   /* history kernel loop order: 1 (or 0) column
                                 slices across all blocks, 2 whole rows of one
                                 block at a time, 3 column slices with 2 (with
@@ -185,8 +186,9 @@ typedef struct {
                                 wavefronts share those slices of one row;
                                 30 + r: r wavefronts share r rows.  Several
                                 RHS: K chunks of the tile product              */
-    int32_t sched_q0;        /* Q_0 product: 1, 2, 4 wavefronts per row or
-                                10 + r rows per wavefront / K chunks          */
+    int32_t sched_q0;        /* Q_0 product: 1, 2, 4 wavefronts per row,
+                                10 + r rows per wavefront, or 30 + r: r
+                                wavefronts share r rows / K chunks            */
     int32_t sched_pc;        /* approximate inverse: as sched_q0 / K chunks   */
     double tune_ms;          /* time spent timing candidates (0 on a cache hit) */
     int64_t graph_windows;   /* windows replayed from captured graphs          */

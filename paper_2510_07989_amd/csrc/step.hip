@@ -418,9 +418,10 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
 }
 
 // ------------------------------------- several rows per wavefront (RPW) ---
-// One-wavefront workgroups, each owning RPW consecutive output rows: every
-// vector slice loaded from L2 serves RPW matrix rows, so a larger share of the
-// load instructions stream matrix entries from HBM.  Rows past the end are
+// Workgroups of cs wavefronts, each owning RPW consecutive output rows, every
+// wavefront on 1/cs of the columns: every vector slice loaded from L2 serves
+// RPW matrix rows, so a larger share of the load instructions stream matrix
+// entries from HBM (cs = RPW keeps one wavefront per row).  Rows past the end are
 // clamped to the last row for loading (same addresses, results dropped).
 
 // history: column slices across all lag blocks, as k_history_co.  cs
@@ -528,17 +529,18 @@ __global__ __launch_bounds__(256) void k_history_rows(int ne, int hs, const int*
     }
 }
 
-// y = Q0 (scale src), vout = scale src (when given), as k_q0_matvec
+// y = Q0 (scale src), vout = scale src (when given), as k_q0_matvec; cs
+// wavefronts (the workgroup) share the RPW rows, each on 1/cs of the columns
 template <int RPW>
-__global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __restrict__ Q0,
-                                                 const double* __restrict__ src, double* __restrict__ vout,
-                                                 double* __restrict__ y, const GmState* __restrict__ gm,
-                                                 int check_done, int use_inv) {
+__global__ __launch_bounds__(256) void k_q0_rows(int ne, int hs, const double* __restrict__ Q0,
+                                                  const double* __restrict__ src, double* __restrict__ vout,
+                                                  double* __restrict__ y, const GmState* __restrict__ gm,
+                                                  int check_done, int use_inv, int cs) {
     if (gm->halt || (check_done && gm->done)) return;
-    const int lane = threadIdx.x;
-    const int m0 = blockIdx.x * RPW;
-    if (m0 >= ne) return;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * RPW;             // < ne: the grid has ceil(ne / RPW) workgroups
     const int np = hs >> 1;
+    const int cpart = np / cs, c1 = (part + 1) * cpart;
     const size_t b2 = ((size_t)ne * hs) >> 1;
     const d2v* A = reinterpret_cast<const d2v*>(Q0);
     const d2v* xu = reinterpret_cast<const d2v*>(src);
@@ -549,8 +551,8 @@ __global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __
     double su[RPW], sv[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) su[r] = sv[r] = 0.0;
-    int c = lane;
-    for (; c + 64 < np; c += 128) {
+    int c = part * cpart + lane;
+    for (; c + 64 < c1; c += 128) {
         d2v a[2][RPW], kk[2][RPW], q[2][RPW];
 #pragma unroll
         for (int u = 0; u < 2; ++u)
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __
             }
         }
     }
-    for (; c < np; c += 64) {
+    for (; c < c1; c += 64) {
         const d2v uu = xu[c], vv = xv[c];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
@@ -590,19 +592,24 @@ __global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __
             su[r] = s1; sv[r] = s2;
         }
     }
+    __shared__ double red[4][RPW][2];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         su[r] = wave_sum(su[r]);
         sv[r] = wave_sum(sv[r]);
+        if (lane == 0) { red[part][r][0] = su[r]; red[part][r][1] = sv[r]; }
     }
-    if (lane == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const double sc = use_inv ? gm->inv_h : 1.0;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int m = m0 + r;
             if (m < ne) {
-                y[m] = sc * su[r];
-                y[hs + m] = sc * sv[r];
+                double a = 0, b = 0;
+                for (int p = 0; p < cs; ++p) { a += red[p][r][0]; b += red[p][r][1]; }
+                y[m] = sc * a;
+                y[hs + m] = sc * b;
                 if (vout) {
                     vout[m] = sc * src[m];
                     vout[hs + m] = sc * src[hs + m];
@@ -612,16 +619,16 @@ __global__ __launch_bounds__(64) void k_q0_rows(int ne, int hs, const double* __
     }
 }
 
-// z = M (inv_h src), V_j = inv_h src, as k_precond (start likewise, FP64)
+// z = M (inv_h src), V_j = inv_h src, as k_precond (start likewise, FP64); cs
+// wavefronts (the workgroup) share the RPW rows, each on 1/cs of the columns
 template <typename T, int RPW>
-__global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict__ M,
-                                                      const double* __restrict__ src, double* __restrict__ vj,
-                                                      double* __restrict__ z, GmState* __restrict__ gm,
-                                                      int start, double tol, double* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_precond_rows(int n2, const T* __restrict__ M,
+                                                       const double* __restrict__ src, double* __restrict__ vj,
+                                                       double* __restrict__ z, GmState* __restrict__ gm,
+                                                       int start, double tol, double* __restrict__ x, int cs) {
     if (gm->halt || (!start && gm->done)) return;
-    const int lane = threadIdx.x;
-    const int m0 = blockIdx.x * RPW;
-    if (m0 >= n2) return;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * RPW;             // < n2: the grid has ceil(n2 / RPW) workgroups
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
@@ -633,8 +640,9 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
         size_t ro[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, n2 - 1) * np;
-        int c = lane;
-        for (; c + 192 < np; c += 256) {
+        const int cpart = np / cs, c1 = (part + 1) * cpart;
+        int c = part * cpart + lane;
+        for (; c + 192 < c1; c += 256) {
             d2v a[4][RPW];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -651,7 +659,7 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
                 if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
             }
         }
-        for (; c < np; c += 64) {
+        for (; c < c1; c += 64) {
             const d2v xx = x2[c];
             if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
 #pragma unroll
@@ -670,8 +678,9 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
         size_t ro[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) ro[r] = (size_t)min(m0 + r, n2 - 1) * nq;
-        int c = lane;
-        for (; c + 64 < nq; c += 128) {
+        const int cpart = nq / cs, c1 = (part + 1) * cpart;
+        int c = part * cpart + lane;
+        for (; c + 64 < c1; c += 128) {
             f4v a[2][RPW];
 #pragma unroll
             for (int u = 0; u < 2; ++u)
@@ -687,7 +696,7 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
                 }
             }
         }
-        for (; c < nq; c += 64) {
+        for (; c < c1; c += 64) {
             const d4v xx = x4[c];
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
@@ -697,20 +706,33 @@ __global__ __launch_bounds__(64) void k_precond_rows(int n2, const T* __restrict
             }
         }
     }
+    __shared__ double red[4][RPW + 1];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) s[r] = wave_sum(s[r]);
-    double sc = start ? 0.0 : gm->inv_h;
-    if (start) {
-        const double beta = sqrt(wave_sum(sq));
-        sc = beta > 0 ? 1.0 / beta : 0.0;
-        if (lane == 0 && m0 == 0) open_cycle(gm, beta, tol);
+    for (int r = 0; r < RPW; ++r) {
+        s[r] = wave_sum(s[r]);
+        if (lane == 0) red[part][r] = s[r];
     }
-    if (lane == 0) {
+    if (start) {
+        sq = wave_sum(sq);
+        if (lane == 0) red[part][RPW] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sc = start ? 0.0 : gm->inv_h;
+        if (start) {
+            double q = 0;
+            for (int p = 0; p < cs; ++p) q += red[p][RPW];
+            const double beta = sqrt(q);
+            sc = beta > 0 ? 1.0 / beta : 0.0;
+            if (m0 == 0) open_cycle(gm, beta, tol);
+        }
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int m = m0 + r;
             if (m < n2) {
-                z[m] = sc * s[r];
+                double t = 0;
+                for (int p = 0; p < cs; ++p) t += red[p][r];
+                z[m] = sc * t;
                 vj[m] = sc * src[m];
                 if (start) x[m] = 0.0;
             }
@@ -1394,9 +1416,11 @@ void gm_finish(mot_handle* h, const double* basis, int force, int spec, int kq) 
 void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int check_done, int use_inv) {
     const int sc = h->sch_q0;
     if (sc > 10) {
-#define L_(R_) hipLaunchKernelGGL(k_q0_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64), 0, h->stream, h->ne, h->hs, \
-                                  h->Q, src, vout, y, h->gm, check_done, use_inv)
-        if (sc == 18) L_(8); else if (sc == 14) L_(4); else L_(2);
+        // 12, 14, 18: one wavefront per r rows; 32, 34: r wavefronts share r rows
+        const int r = sc % 10, cs = sc > 30 ? r : 1;
+#define L_(R_) hipLaunchKernelGGL(k_q0_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64 * cs), 0, h->stream, h->ne, \
+                                  h->hs, h->Q, src, vout, y, h->gm, check_done, use_inv, cs)
+        if (r == 8) L_(8); else if (r == 4) L_(4); else L_(2);
 #undef L_
         return;
     }
@@ -1412,10 +1436,11 @@ void precond(mot_handle* h, const double* src, double* vj, double* z, bool start
     const int st = start && !h->M32;
     const double tol = h->opt.gmres_tol;
     if (sc > 10) {
-#define L_(T_, R_, M_) hipLaunchKernelGGL((k_precond_rows<T_, R_>), dim3((h->n2 + R_ - 1) / R_), dim3(64), 0, \
-                                          h->stream, h->n2, M_, src, vj, z, h->gm, st, tol, h->x)
+        const int r = sc % 10, cs = sc > 30 ? r : 1;
+#define L_(T_, R_, M_) hipLaunchKernelGGL((k_precond_rows<T_, R_>), dim3((h->n2 + R_ - 1) / R_), dim3(64 * cs), 0, \
+                                          h->stream, h->n2, M_, src, vj, z, h->gm, st, tol, h->x, cs)
 #define P_(R_) do { if (h->M32) L_(float, R_, h->M32); else L_(double, R_, h->M64); } while (0)
-        if (sc == 18) P_(8); else if (sc == 14) P_(4); else P_(2);
+        if (r == 8) P_(8); else if (r == 4) P_(4); else P_(2);
 #undef P_
 #undef L_
         return;
