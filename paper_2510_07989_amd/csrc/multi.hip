@@ -437,6 +437,63 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ t, int lane,
     a[0] = x[0]; a[1] = x[1]; a[2] = x[2]; a[3] = x[3];
 }
 
+// A tile triple (q1, qk, q2) as loaded, before any conversion: a prefetch into
+// these registers stays in flight until its tile is unpacked.
+template <typename T> struct RawTiles;
+template <> struct RawTiles<double> {
+    v2d x1, y1, xk, yk, x2, y2;
+};
+template <> struct RawTiles<float> {
+    v4f t1, tk, t2;                    // FP32 entries
+    v4f l1, lk, l2;                    // their FP32 low parts (lags with a low part)
+};
+
+__device__ __forceinline__ void fetch_raw(const double* __restrict__ a1, const double* __restrict__ ak,
+                                          const double* __restrict__ a2, const float*, size_t, bool, int lane,
+                                          RawTiles<double>& r) {
+    r.x1 = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(a1) + lane);
+    r.y1 = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(a1 + 128) + lane);
+    r.xk = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(ak) + lane);
+    r.yk = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(ak + 128) + lane);
+    r.x2 = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(a2) + lane);
+    r.y2 = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(a2 + 128) + lane);
+}
+
+// lo: the low-part tile of q1 (those of qk and q2 follow at +tsz, +2 tsz)
+__device__ __forceinline__ void fetch_raw(const float* __restrict__ a1, const float* __restrict__ ak,
+                                          const float* __restrict__ a2, const float* __restrict__ lo, size_t tsz,
+                                          bool hl, int lane, RawTiles<float>& r) {
+    r.t1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a1) + lane);
+    r.tk = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(ak) + lane);
+    r.t2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(a2) + lane);
+    if (hl) {
+        r.l1 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lo) + lane);
+        r.lk = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lo + tsz) + lane);
+        r.l2 = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(lo + 2 * tsz) + lane);
+    }
+}
+
+__device__ __forceinline__ void unpack(const RawTiles<double>& r, bool, double a1[4], double ak[4], double a2[4]) {
+    a1[0] = r.x1[0]; a1[1] = r.x1[1]; a1[2] = r.y1[0]; a1[3] = r.y1[1];
+    ak[0] = r.xk[0]; ak[1] = r.xk[1]; ak[2] = r.yk[0]; ak[3] = r.yk[1];
+    a2[0] = r.x2[0]; a2[1] = r.x2[1]; a2[2] = r.y2[0]; a2[3] = r.y2[1];
+}
+
+// entry = FP64(hi) + FP64(lo) on lags with a low part
+__device__ __forceinline__ void unpack(const RawTiles<float>& r, bool hl, double a1[4], double ak[4], double a2[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        a1[e] = r.t1[e];
+        ak[e] = r.tk[e];
+        a2[e] = r.t2[e];
+        if (hl) {
+            a1[e] += (double)r.l1[e];
+            ak[e] += (double)r.lk[e];
+            a2[e] += (double)r.l2[e];
+        }
+    }
+}
+
 // Structured product on FP64 MFMA for one 64-row block (4 wavefronts x 16
 // rows), one lag and one K chunk:
 //   Yu = q1 Wu - qk Wv,   Yv = qk Wu + q2 Wv
@@ -487,26 +544,16 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
 #pragma unroll
         for (int s2 = 0; s2 < NS; ++s2) Cu[cb][s2] = Cv[cb][s2] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    double n1[4], nk[4], n2v[4];
-    auto fetch = [&](int c) {
+    // two tile triples in flight: tile t of the chunk sits in raw set t % 2 and
+    // is converted only when it is multiplied, so its loads overlap the MFMAs
+    // of the tile before (ST is even, so the set of a tile is ci % 2)
+    RawTiles<T> rs[2];
+    auto fetch = [&](int c, RawTiles<T>& r) {
         const size_t o = ((size_t)g * KT + c) * 256;
-        load_tile(a1p + o, lane, n1);
-        load_tile(akp + o, lane, nk);
-        load_tile(a2p + o, lane, n2v);
-        if (hl) {
-            double l[4];
-            load_tile(l1p + o, lane, l);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) n1[e] += l[e];
-            load_tile(l1p + tsz + o, lane, l);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) nk[e] += l[e];
-            load_tile(l1p + 2 * tsz + o, lane, l);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) n2v[e] += l[e];
-        }
+        fetch_raw(a1p + o, akp + o, a2p + o, hl ? l1p + o : nullptr, tsz, hl, lane, r);
     };
-    if (gok && c0 < c1) fetch(c0);
+    if (gok && c0 < c1) fetch(c0, rs[0]);
+    if (gok && c0 + 1 < c1) fetch(c0 + 1, rs[1]);
 
     // With one or two column blocks, the history slice of the next K step is
     // loaded into registers while the current one is multiplied, and stored to
@@ -559,11 +606,12 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
         if constexpr (WPF) {
             if (cs + ST < c1) wfetch(cs + ST);
         }
-        for (int ci = 0; ci < nst; ++ci) {
-            double a1[4], ak[4], a2[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { a1[e] = n1[e]; ak[e] = nk[e]; a2[e] = n2v[e]; }
-            if (gok && cs + ci + 1 < c1) fetch(cs + ci + 1);
+        for (int ci = 0; ci < ST; ++ci) {
+            if (ci >= nst) break;
+            double a1[4], ak[4], a2[4];
+            unpack(rs[ci & 1], hl, a1, ak, a2);
+            if (gok && cs + ci + 2 < c1) fetch(cs + ci + 2, rs[ci & 1]);
             if (gok) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
