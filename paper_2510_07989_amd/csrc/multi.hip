@@ -1079,12 +1079,14 @@ void orth(mot_handle* h, double* w, int publish) {
                            h->orth_part);
 }
 
+// spec: a queued step; the next step's start resets every column's cycle, so
+// consumed cycles need no marking
 void finish(mot_handle* h, int force, int spec, int kq) {
     size_t total = (size_t)h->n2 * h->Rp;
     int nb = (int)std::min<size_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_gmb_finish, dim3(nb), dim3(256), 0, h->stream, h->n2, h->Rp, h->Z, h->gms, h->gm, h->x,
                        h->d_k, h->nh, h->ring, h->hist, h->hist_cap, force, spec, kq);
-    hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms, h->gm);
+    if (!spec) hipLaunchKernelGGL(k_gmb_consume, dim3(1), dim3(64), 0, h->stream, h->Rp, h->gms, h->gm);
 }
 
 }  // namespace motk_multi
