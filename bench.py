@@ -141,7 +141,7 @@ def history_kernel_name(R, precision, mix_group, sched_hist=11):
     if R == 1:
         if sched_hist in (11, 22, 24):
             return "k_history_co"
-        return "k_history_rows<%d>" % (sched_hist - 10) if sched_hist > 10 else "k_history"
+        return "k_history_rows<%d>" % (sched_hist % 10) if sched_hist > 10 else "k_history"
     if precision == 2:
         fl = {64: 16, 16: 4}.get(mix_group, 1)
         return "k_hist_mfma<%d, %d>" % (col_blocks(R), fl)
@@ -192,7 +192,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     hist = roofline(kname, hb, hf, hist_us, dtype, R > 1, measured_traffic(kname, name))
     q0b = 8.0 * (3 * ne * ne + 2 * n * R)
     sq = inf0["sched_q0"]
-    q0name = (("k_q0_rows<%d>" % (sq - 10) if sq > 10 else "k_q0_matvec") if R == 1
+    q0name = (("k_q0_rows<%d>" % (sq % 10) if sq > 10 else "k_q0_matvec") if R == 1
               else "k_tile_gemm<double, %d>" % col_blocks(R))
     q0 = roofline(q0name, q0b, 2.0 * 4 * ne * ne * R, q0_us, "f64", R > 1,
                   measured_traffic(q0name if R == 1 else q0name + " (Q_0)", name))
