@@ -169,3 +169,19 @@ def test_rhs_time_integral_and_star_tail():
     # after the cut the star part is exactly zero
     _, Eb2 = mo.tested_fields(V, F, E, [wv], prob["dt"], big)
     assert not Eb2.any()
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_box", "tiny_torus"])
+def test_q0_condition_flat_in_dt(name):
+    """Sec. VI (conditioning versus time step): the qHP Q_0 stays equally well
+    conditioned as c dt grows past the diameter, where the classical system
+    degrades like dt^2.  Here c dt runs from 2 D to 32 D (k_max = 1 or 2)."""
+    from fixture.problem import CONFIGS, build_problem
+    from oracle.mot_oracle import Oracle
+    conds = []
+    for dt in (4.0, 16.0, 64.0):
+        O = Oracle(build_problem(cfg=dict(CONFIGS[name], dt=dt), nsteps=4))
+        s = np.linalg.svd(O.Q[0], compute_uv=False)
+        conds.append(s[0] / s[-1])
+    print(name, ["%.3g" % c for c in conds])
+    assert max(conds) / min(conds) < 1.2, conds
