@@ -102,7 +102,8 @@ typedef struct {
                                 0 none, 1 stored FP32 (default), 2 FP64       */
     int32_t stream_split;    /* schedule of the one-RHS streaming products:
                                 1, 2 or 4 wavefronts share one matrix row, or
-                                12, 14, 18: one wavefront owns 2, 4 or 8 rows
+                                11, 12, 14, 18: one wavefront owns 1, 2, 4 or 8
+                                rows, column slices outermost
                                 (the history at most 4); 32, 34: 2 or 4
                                 wavefronts share as many rows; 0: chosen by
                                 the autotuner (or 1).  The history follows

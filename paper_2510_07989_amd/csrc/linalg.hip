@@ -15,11 +15,15 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int GK = 16;
 
+// blockIdx.z selects one of several products with the same A: B and C are
+// offset by z * sB and z * sC elements.
 template <int WT>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
                                               const double* __restrict__ A, int lda,
                                               const double* __restrict__ B, int ldb, double beta,
-                                              double* __restrict__ C, int ldc) {
+                                              double* __restrict__ C, int ldc, size_t sB, size_t sC) {
+    B += blockIdx.z * sB;
+    C += blockIdx.z * sC;
     constexpr int BT = 2 * WT;               // block tile edge
     constexpr int NT = WT / 16;              // MFMA tiles per wavefront edge
     constexpr int PE = BT * GK / 256;        // staged elements per thread, per operand
@@ -276,16 +280,18 @@ inline int nblk(size_t total, int bs = 256) {
 namespace motk {
 
 void gemm(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda,
-          const double* B, int ldb, double beta, double* C, int ldc) {
-    if (M <= 0 || N <= 0) return;
+          const double* B, int ldb, double beta, double* C, int ldc, int batch, size_t sB, size_t sC) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
     // 128 x 128 tiles when they still give about four workgroups per CU
-    const long big = (long)((N + 127) / 128) * ((M + 127) / 128);
+    const long big = (long)((N + 127) / 128) * ((M + 127) / 128) * batch;
     if (big >= 1024) {
-        dim3 grid((N + 127) / 128, (M + 127) / 128);
-        hipLaunchKernelGGL(k_gemm<64>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+        dim3 grid((N + 127) / 128, (M + 127) / 128, batch);
+        hipLaunchKernelGGL(k_gemm<64>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, sB,
+                           sC);
     } else {
-        dim3 grid((N + 63) / 64, (M + 63) / 64);
-        hipLaunchKernelGGL(k_gemm<32>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+        dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+        hipLaunchKernelGGL(k_gemm<32>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, sB,
+                           sC);
     }
 }
 

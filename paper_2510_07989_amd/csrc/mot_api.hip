@@ -759,8 +759,8 @@ void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V,
         // an explicit stream_split or history_order fixes that part of the
         // schedule; otherwise the autotuner picks it (or the defaults stay)
         const int sp = h->opt.stream_split;
-        const bool sp_set = sp == 1 || sp == 2 || sp == 4 || sp == 12 || sp == 14 || sp == 18 || sp == 32 ||
-                            sp == 34;
+        const bool sp_set = sp == 1 || sp == 2 || sp == 4 || sp == 11 || sp == 12 || sp == 14 || sp == 18 ||
+                            sp == 32 || sp == 34;
         const bool ho_set = h->opt.history_order >= 1 && h->opt.history_order <= 3;
         h->sch_q0 = h->sch_pc = sp_set ? sp : 1;
         if (h->opt.history_order == 2) h->sch_hist = sp_set && sp <= 4 ? sp : 1;

@@ -62,8 +62,10 @@ struct GmFlag {
 // --------------------------------------------------------- kernel entry ---
 namespace motk {
 // dense
+// C_z = alpha A B_z + beta C_z for z < batch, B_z = B + z sB, C_z = C + z sC
 void gemm(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda,
-          const double* B, int ldb, double beta, double* C, int ldc);
+          const double* B, int ldb, double beta, double* C, int ldc, int batch = 1, size_t sB = 0,
+          size_t sC = 0);
 void axpby2d(hipStream_t s, int rows, int cols, double a, const double* X, int ldx, double b,
              double* Y, int ldy);                       // Y = a X + b Y
 void fill2d(hipStream_t s, int rows, int cols, double v, double* Y, int ldy);

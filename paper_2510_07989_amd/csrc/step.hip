@@ -1352,13 +1352,10 @@ void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase) {
     // consecutive batches alternate between the two halves of rb, so a batch
     // queued ahead of a halted step never overwrites the one it still needs
     double* rbk = rb + (size_t)(((k0 - 1) / B) & 1) * 2 * ne * N;
-    for (int half = 0; half < 2; ++half) {
-        const double* eb = h->ebar + (size_t)half * hs * N;
-        const double* Eb = h->Ebar + (size_t)half * hs * N;
-        double* out = rbk + (size_t)half * ne * N;
-        motk::gemm(h->stream, ne, N, ne, 1.0, h->C1, hs, eb, N, 0.0, out, N);
-        motk::gemm(h->stream, ne, N, ne, 1.0 / h->Tmax, h->C2, hs, Eb, N, 1.0, out, N);
-    }
+    // both halves (u and v) in one launch per factor
+    motk::gemm(h->stream, ne, N, ne, 1.0, h->C1, hs, h->ebar, N, 0.0, rbk, N, 2, (size_t)hs * N, (size_t)ne * N);
+    motk::gemm(h->stream, ne, N, ne, 1.0 / h->Tmax, h->C2, hs, h->Ebar, N, 1.0, rbk, N, 2, (size_t)hs * N,
+               (size_t)ne * N);
 }
 
 void history(mot_handle* h) {
@@ -1420,7 +1417,7 @@ void q0_matvec(mot_handle* h, const double* src, double* vout, double* y, int ch
         const int r = sc % 10, cs = sc > 30 ? r : 1;
 #define L_(R_) hipLaunchKernelGGL(k_q0_rows<R_>, dim3((h->ne + R_ - 1) / R_), dim3(64 * cs), 0, h->stream, h->ne, \
                                   h->hs, h->Q, src, vout, y, h->gm, check_done, use_inv, cs)
-        if (r == 8) L_(8); else if (r == 4) L_(4); else L_(2);
+        if (r == 8) L_(8); else if (r == 4) L_(4); else if (r == 2) L_(2); else L_(1);
 #undef L_
         return;
     }
@@ -1440,7 +1437,7 @@ void precond(mot_handle* h, const double* src, double* vj, double* z, bool start
 #define L_(T_, R_, M_) hipLaunchKernelGGL((k_precond_rows<T_, R_>), dim3((h->n2 + R_ - 1) / R_), dim3(64 * cs), 0, \
                                           h->stream, h->n2, M_, src, vj, z, h->gm, st, tol, h->x, cs)
 #define P_(R_) do { if (h->M32) L_(float, R_, h->M32); else L_(double, R_, h->M64); } while (0)
-        if (r == 8) P_(8); else if (r == 4) P_(4); else P_(2);
+        if (r == 8) P_(8); else if (r == 4) P_(4); else if (r == 2) P_(2); else P_(1);
 #undef P_
 #undef L_
         return;

@@ -132,7 +132,7 @@ int tune(mot_handle* h) {
             rc = pick(h, "history", c, [&](int v) { h->sch_hist = v; }, [&] { motk_step::history(h); }, reps);
         }
         if (!rc && h->tune_mv) {
-            const std::vector<int> c = {1, 2, 4, 12, 14, 18, 32, 34};
+            const std::vector<int> c = {1, 2, 4, 11, 12, 14, 18, 32, 34};
             rc = pick(h, "Q_0 product", c, [&](int v) { h->sch_q0 = v; },
                       [&] { motk_step::q0_matvec(h, h->x, nullptr, h->wA, 0, 0); }, reps);
             if (!rc && (h->M32 || h->M64))

@@ -165,7 +165,8 @@ def test_speculative_stepping_matches_host_driven(name, precond, window, precisi
                                   dict(stream_split=12, precond=2, history_order=3),
                                   dict(stream_split=14, precond=2, history_order=3),
                                   dict(stream_split=32, precond=2), dict(stream_split=34, precond=2),
-                                  dict(stream_split=34, precond=1), dict(stream_split=32, precond=0)])
+                                  dict(stream_split=34, precond=1), dict(stream_split=32, precond=0),
+                                  dict(stream_split=11, precond=2), dict(stream_split=11, precond=1)])
 def test_kernel_variants(opts):
     """Loop-order and row-split variants of the streaming kernels, and the
     graph-Laplacian CG recovery, give the oracle's march."""
