@@ -251,6 +251,31 @@ int mot_step(mot_handle* h, mot_step_info* info);
 int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out,
             double* star_out, int32_t out_on_device, mot_step_info* last);
 
+/* Outputs of steps already taken, as mot_run returns them for its own steps
+ * (same layouts, [count][n][nrhs]; any pointer may be NULL): steps are counted
+ * from 0 since create or reset, and first .. first+count-1 must all be taken
+ * and kept (keep_history, max_steps).  The loop and star parts are the
+ * current recovery of eq. (dis_jm), recomputed on each call.  out_on_device:
+ * 1 if the pointers are device memory.  MOT_EINVAL for a range not taken or
+ * not kept. */
+int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, double* loop_out,
+                  double* star_out, int32_t out_on_device);
+
+/* nsteps MOT steps (eq. MOT) on each of n independent handles, for serving
+ * several scattering problems at once: the handles' windows of queued steps
+ * are interleaved across their streams, so small solves share the device
+ * instead of taking turns.  Every handle computes exactly what mot_run(h,
+ * nsteps, NULL, NULL, NULL, 0, NULL) would; mot_get_steps reads the outputs
+ * afterwards (keep_history).  Handles on distinct non-default streams
+ * overlap; handles sharing a stream
+ * run in turn.  hs: n distinct handles (host array); status: n codes out,
+ * each handle's worst step code (MOT_OK, MOT_ENOCONV) or its error, after
+ * which that handle stops at its last completed step while the others go on.
+ * Returns MOT_EINVAL for a bad argument or a repeated handle (nothing run),
+ * else the first error among the handles, else MOT_ENOCONV if any step hit
+ * its iteration cap, else MOT_OK. */
+int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* status);
+
 /* Copy internal operators to host memory (diagnostics and parity checks):
  *   which 0: Q_lag as dense [n][n]; 1: C1 [ne][ne]; 2: C2 [ne][ne];
  *   3: P^Sigma [ne][ne]; 4: PP^Lambda [ne][ne]; 5: G^-1 [ne][ne];

@@ -5,5 +5,5 @@ marshalling only; every step of the solver runs in HIP kernels.  PyTorch is
 used only for device buffers and the current stream when outputs are
 requested on the device.
 """
-from .solver import Solver, MotError, default_options, footprint  # noqa: F401
+from .solver import Solver, MotError, default_options, footprint, run_batch  # noqa: F401
 from . import _lib  # noqa: F401

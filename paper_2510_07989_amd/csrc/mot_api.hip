@@ -1339,67 +1339,113 @@ static int read_spec(mot_handle* h, SpecWord* w) {
     return MOT_OK;
 }
 
-static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
-    const int win = std::max(1, std::min(h->opt.spec_window > 0 ? h->opt.spec_window : h->B, h->B));
-    SpecWord w0{};
-    int rc = read_spec(h, &w0);
-    if (rc) return rc;
-    int done = 0;
+// One handle's speculative march, as a state machine: queue() puts one window
+// of steps on the handle's stream without waiting; settle() waits for it,
+// accounts for it and finishes a halted step on the host.  run_spec drives one
+// handle; mot_run_batch interleaves several, so their windows overlap on the
+// device.
+struct SpecRun {
+    mot_handle* h = nullptr;
+    int nsteps = 0, done = 0;
+    int win = 1;
+    bool graphs = false;
     // the device step counter runs one ahead of h->k after a window in which
-    // every step pushed (the last finisher set it); a halted window leaves it at
-    // the halted step, which is then h->k
+    // every step pushed (the last finisher set it); a halted window leaves it
+    // at the halted step, which is then h->k
     bool ahead = false;
+    SpecWord w0{};
+    int k0 = 0, nw = 0;       // the window in flight
+    int worst = MOT_OK;
+};
+
+static int spec_begin(SpecRun& r, mot_handle* h, int nsteps) {
+    r.h = h;
+    r.nsteps = nsteps;
+    r.win = std::max(1, std::min(h->opt.spec_window > 0 ? h->opt.spec_window : h->B, h->B));
     // graphs replay whole RHS batches: windows then end on batch boundaries
     // (the legacy default stream cannot be captured)
-    const bool graphs = h->opt.graph && !h->opt.profile && win == h->B && h->stream != nullptr;
-    while (done < nsteps) {
-        int nw = std::min(win, nsteps - done);
-        const int k0 = h->k;
-        if (graphs && k0 % h->B) nw = std::min(nw, h->B - k0 % h->B);
-        bool launched = false;
-        if (graphs && !h->graph_off && nw == h->B && (rc = launch_window(h, ahead, &launched))) return rc;
-        if (!launched)
-            for (int i = 0; i < nw; ++i)
-                if ((rc = queue_spec_step(h, i == 0 && !ahead))) return rc;
-        ahead = true;
-        HIPCHK(h, hipGetLastError());
-        SpecWord w{};
-        if ((rc = read_spec(h, &w))) return rc;
-        h->iters_total += w.iters_all - w0.iters_all;
-        w0 = w;
-        if (!w.halt) {
-            done += nw;
-            h->last_iters = h->spec_iters;
-            h->last_relres = w.relres;
-            h->last_conv = 1;
-            continue;
-        }
-        // steps k0+1 .. halt_k-1 are complete; halt_k has its history in y
-        if (w.halt_k <= k0 || w.halt_k > h->k) return mot_fail(h, MOT_EHIP, "speculative halt word out of range");
-        h->k = w.halt_k;
-        ahead = false;
-        motk_step::clear_halt(h);
-        int src = h->Rp > 1 ? gmres_solve_mr(h) : gmres_solve_pc(h);
-        if (src && src != MOT_ENOCONV) return src;
-        if (src) *worst = src;
-        if ((rc = read_spec(h, &w0))) return rc;
-        h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
-        done += w.halt_k - k0;
+    r.graphs = h->opt.graph && !h->opt.profile && r.win == h->B && h->stream != nullptr;
+    return read_spec(h, &r.w0);
+}
+
+static int spec_queue(SpecRun& r) {
+    mot_handle* h = r.h;
+    int nw = std::min(r.win, r.nsteps - r.done);
+    r.k0 = h->k;
+    if (r.graphs && r.k0 % h->B) nw = std::min(nw, h->B - r.k0 % h->B);
+    r.nw = nw;
+    int rc;
+    bool launched = false;
+    if (r.graphs && !h->graph_off && nw == h->B && (rc = launch_window(h, r.ahead, &launched))) return rc;
+    if (!launched)
+        for (int i = 0; i < nw; ++i)
+            if ((rc = queue_spec_step(h, i == 0 && !r.ahead))) return rc;
+    r.ahead = true;
+    HIPCHK(h, hipGetLastError());
+    return MOT_OK;
+}
+
+static int spec_settle(SpecRun& r) {
+    mot_handle* h = r.h;
+    SpecWord w{};
+    int rc;
+    if ((rc = read_spec(h, &w))) return rc;
+    h->iters_total += w.iters_all - r.w0.iters_all;
+    r.w0 = w;
+    if (!w.halt) {
+        r.done += r.nw;
+        h->last_iters = h->spec_iters;
+        h->last_relres = w.relres;
+        h->last_conv = 1;
+        return MOT_OK;
     }
-    if (ahead) motk_step::set_step(h, h->k);   // as the step-by-step march leaves it
+    // steps k0+1 .. halt_k-1 are complete; halt_k has its history in y
+    if (w.halt_k <= r.k0 || w.halt_k > h->k) return mot_fail(h, MOT_EHIP, "speculative halt word out of range");
+    h->k = w.halt_k;
+    r.ahead = false;
+    motk_step::clear_halt(h);
+    int src = h->Rp > 1 ? gmres_solve_mr(h) : gmres_solve_pc(h);
+    if (src && src != MOT_ENOCONV) return src;
+    if (src) r.worst = src;
+    if ((rc = read_spec(h, &r.w0))) return rc;
+    h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
+    r.done += w.halt_k - r.k0;
+    return MOT_OK;
+}
+
+static void spec_end(SpecRun& r) {
+    if (r.ahead) motk_step::set_step(r.h, r.h->k);   // as the step-by-step march leaves it
+}
+
+// after an error: no halt word left raised, the counter at the host's step
+static void spec_abort(mot_handle* h) {
+    motk_step::clear_halt(h);
+    motk_step::set_step(h, h->k);
+    (void)hipStreamSynchronize(h->stream);
+}
+
+static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
+    SpecRun r;
+    int rc = spec_begin(r, h, nsteps);
+    while (!rc && r.done < nsteps) {
+        rc = spec_queue(r);
+        if (!rc) rc = spec_settle(r);
+    }
+    if (rc) return rc;
+    spec_end(r);
+    if (r.worst) *worst = r.worst;
     return MOT_OK;
 }
 
 // an error return never leaves the halt word raised behind it
 static int run_spec(mot_handle* h, int nsteps, int* worst) {
     int rc = run_spec_windows(h, nsteps, worst);
-    if (rc) {
-        motk_step::clear_halt(h);
-        motk_step::set_step(h, h->k);
-        (void)hipStreamSynchronize(h->stream);
-    }
+    if (rc) spec_abort(h);
     return rc;
 }
+
+static int emit_steps(mot_handle* h, int s0, int nsteps, double* w_out, double* loop_out, double* star_out,
+                      int32_t out_on_device, int worst);
 
 int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, double* star_out,
             int32_t out_on_device, mot_step_info* last) {
@@ -1430,6 +1476,13 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
         HIPCHK(h, hipStreamSynchronize(h->stream));
         return worst;
     }
+    return emit_steps(h, s0, nsteps, w_out, loop_out, star_out, out_on_device, worst);
+}
+
+// outputs of the kept steps s0 .. s0+nsteps-1: the unknowns as computed and
+// the current recovery of eq. (dis_jm)
+static int emit_steps(mot_handle* h, int s0, int nsteps, double* w_out, double* loop_out, double* star_out,
+                      int32_t out_on_device, int worst) {
     const size_t per = (size_t)2 * h->ne * h->R;
     const size_t tot = per * nsteps;
     double *dw = nullptr, *dl = nullptr, *ds = nullptr;
@@ -1454,6 +1507,70 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (!out_on_device) { dfree(h, dw); dfree(h, dl); dfree(h, ds); }
+    return worst;
+}
+
+int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, double* loop_out,
+                  double* star_out, int32_t out_on_device) {
+    if (!h) return MOT_EINVAL;
+    if (first < 0 || count < 0 || first + count > h->k)
+        return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be read");
+    if (!h->hist || first + count > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (count == 0 || !(w_out || loop_out || star_out)) return MOT_OK;
+    return emit_steps(h, first, count, w_out, loop_out, star_out, out_on_device, MOT_OK);
+}
+
+// Several independent marches advanced together: every handle's speculative
+// window is queued on its own stream before the host waits on any of them, and
+// a handle is re-queued as soon as its window has settled, so windows of
+// different solves overlap on the device.  Each handle takes exactly the
+// kernels mot_run would queue for it, in the same order.
+int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* status) {
+    if (n < 0 || nsteps < 0 || (n > 0 && (!hs || !status))) return MOT_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i]) return MOT_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return mot_fail(hs[i], MOT_EINVAL, "handle listed twice in one batch");
+    }
+    std::vector<SpecRun> runs(n);
+    std::vector<int> live, plain;
+    for (int i = 0; i < n; ++i) {
+        mot_handle* h = hs[i];
+        status[i] = MOT_OK;
+        if (nsteps == 0) continue;
+        if (!spec_ok(h)) { plain.push_back(i); continue; }
+        if (!all_folded(h)) { status[i] = mot_fail(h, MOT_ESTATE, "lag matrices missing: upload every block first"); continue; }
+        int rc = spec_begin(runs[i], h, nsteps);
+        if (rc) { status[i] = rc; spec_abort(h); continue; }
+        live.push_back(i);
+    }
+    auto drop = [&](int i, int rc) { status[i] = rc; spec_abort(hs[i]); };
+    std::vector<int> next;
+    for (int i : live) {
+        int rc = spec_queue(runs[i]);
+        if (rc) drop(i, rc); else next.push_back(i);
+    }
+    live.swap(next);
+    while (!live.empty()) {
+        next.clear();
+        for (int i : live) {
+            SpecRun& r = runs[i];
+            int rc = spec_settle(r);
+            if (!rc && r.done < nsteps) rc = spec_queue(r);
+            if (rc) { drop(i, rc); continue; }
+            if (r.done < nsteps) { next.push_back(i); continue; }
+            spec_end(r);
+            hipError_t e = hipStreamSynchronize(r.h->stream);
+            status[i] = e != hipSuccess ? mot_fail(r.h, MOT_EHIP, hipGetErrorString(e)) : r.worst;
+        }
+        live.swap(next);
+    }
+    // handles that march step by step (no preconditioner, profiling, or a
+    // window of -1) run after the speculative ones, one after another
+    for (int i : plain) status[i] = mot_run(hs[i], nsteps, nullptr, nullptr, nullptr, 0, nullptr);
+    int worst = MOT_OK;
+    for (int i = 0; i < n; ++i)
+        if (status[i] && (worst == MOT_OK || worst == MOT_ENOCONV)) worst = status[i];
     return worst;
 }
 

@@ -128,8 +128,7 @@ class Solver:
         self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
         return dict(step=inf.step, iters=inf.gmres_iters, relres=inf.gmres_relres, converged=inf.converged)
 
-    def run(self, nsteps, w=True, loop=True, star=True, device=False):
-        """March nsteps; return arrays of shape (nsteps, n, nrhs) (numpy, or torch on device)."""
+    def _outputs(self, nsteps, w, loop, star, device):
         shape = (nsteps, self.n, self.nrhs)
         outs = {}
         ptrs = []
@@ -144,11 +143,23 @@ class Solver:
                 a = np.empty(shape) if want else None
                 outs[name] = a
                 ptrs.append(_ptr(a) if want else None)
+        return outs, ptrs
+
+    def run(self, nsteps, w=True, loop=True, star=True, device=False):
+        """March nsteps; return arrays of shape (nsteps, n, nrhs) (numpy, or torch on device)."""
+        outs, ptrs = self._outputs(nsteps, w, loop, star, device)
         inf = L.MotStepInfo()
         rc = self._lib.mot_run(self._h, int(nsteps), ptrs[0], ptrs[1], ptrs[2], 1 if device else 0, ctypes.byref(inf))
         self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
         outs["last"] = dict(step=inf.step, iters=inf.gmres_iters, relres=inf.gmres_relres, converged=inf.converged)
         outs["rc"] = rc
+        return outs
+
+    def steps(self, first, count, w=True, loop=True, star=True, device=False):
+        """Outputs of the kept steps first .. first+count-1 (counted from 0), as run returns them."""
+        outs, ptrs = self._outputs(count, w, loop, star, device)
+        self._check(self._lib.mot_get_steps(self._h, int(first), int(count), ptrs[0], ptrs[1], ptrs[2],
+                                            1 if device else 0))
         return outs
 
     def matrix(self, which, lag=0):
@@ -175,3 +186,20 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def run_batch(solvers, nsteps):
+    """March every solver nsteps with their windows interleaved on the device
+    (mot_run_batch); returns each solver's code (MOT_OK or MOT_ENOCONV) and
+    raises MotError for the first solver that failed."""
+    lib = L.load()
+    n = len(solvers)
+    hs = (ctypes.c_void_p * max(n, 1))(*[s._h.value for s in solvers])
+    st = (ctypes.c_int32 * max(n, 1))()
+    rc = lib.mot_run_batch(hs, n, int(nsteps), st)
+    if rc == L.MOT_EINVAL and not any(st[i] for i in range(n)):
+        raise MotError(rc, "mot_run_batch: bad argument")
+    for i, s in enumerate(solvers):
+        if st[i] not in (L.MOT_OK, L.MOT_ENOCONV):
+            raise MotError(st[i], lib.mot_last_error(s._h).decode())
+    return [st[i] for i in range(n)]
