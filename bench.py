@@ -253,6 +253,7 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--no-step-batch", action="store_true", help="skip the mot_run_batch comparison")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed (FP64 MFMA), 2 mixed (FP32 MFMA)")
@@ -389,6 +390,8 @@ def main():
                 % (w64["fp64_64rhs"]["steps_s"], w64["mixed_64rhs"]["steps_s"],
                    wide["mixed_64rhs"]["err_vs_fp64_64rhs"]["w"], w64["mixed32_64rhs"]["steps_s"],
                    wide["mixed32_64rhs"]["err_vs_fp64_64rhs"]["w"]))
+    if not args.no_step_batch:
+        result["step_batch"] = step_batch(mot)
     if args.serving:
         have = {args.workload: prob}
         if not args.no_batched:
@@ -398,6 +401,66 @@ def main():
 
 
 SERVING_MESHES = ["tiny_torus", "tiny_box", "sphere_480", "sphere_480_r16", "sphere_1920_r16", "torus_3072"]
+
+
+def step_batch(mot, nsteps=1024, copies=4):
+    """Several small solves on one GPU, each on its own stream: marched one
+    after another with mot_run, then together with mot_run_batch (windows of
+    all solves queued before the host waits on any).  Same kernels, same
+    results; the aggregate step rate shows what interleaving recovers on
+    meshes too small to fill the device."""
+    import numpy as np
+    import torch
+    from fixture.problem import build_problem
+    meshes = ["tiny_torus", "sphere_480"]
+    t = time.perf_counter()
+    probs = {m: build_problem(m, nsteps=nsteps) for m in meshes}
+    log("step-batch inputs assembled in %.1f s" % (time.perf_counter() - t))
+
+    def make():
+        out = []
+        for m in meshes:
+            p = probs[m]
+            for _ in range(copies):
+                st = torch.cuda.Stream()
+                s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"],
+                               p["G"], p["waves"], options=mot.default_options(precond=2, keep_history=1,
+                                                                              max_steps=2 * nsteps + 64),
+                               stream=st.cuda_stream)
+                s.load_raw(p["raw"], p["kmax"])
+                s._keep_stream = st
+                out.append(s)
+        return out
+
+    res = {"meshes": ["%d x %s" % (copies, m) for m in meshes], "steps_per_solve": nsteps}
+    ss = make()
+    for s in ss:                                   # warm-up: one window each, alone
+        s.run(128, w=False, loop=False, star=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s in ss:
+        s.run(nsteps, w=False, loop=False, star=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    ref = [s.steps(128, nsteps, loop=False, star=False)["w"] for s in ss]
+    for s in ss:
+        s.close()
+    ss = make()
+    mot.run_batch(ss, 128)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mot.run_batch(ss, nsteps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t
+    same = all(np.array_equal(s.steps(128, nsteps, loop=False, star=False)["w"], r) for s, r in zip(ss, ref))
+    for s in ss:
+        s.close()
+    tot = nsteps * len(ss)
+    res.update({"one_after_another_steps_per_s": round(tot / t_seq, 1), "batched_steps_per_s": round(tot / t_bat, 1),
+                "speedup": round(t_seq / t_bat, 3), "bitwise_equal": bool(same)})
+    log("step batch: %d solves x %d steps: one after another %.1f steps/s, mot_run_batch %.1f steps/s (x%.2f), "
+        "identical %s" % (len(ss), nsteps, tot / t_seq, tot / t_bat, t_seq / t_bat, same))
+    return res
 
 
 def serving(nreq, have=None, seed=251007990):
