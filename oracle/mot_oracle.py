@@ -17,6 +17,10 @@ Formulation"):
 * right-hand side, loop and star parts ..... Section V-C, eq. (rhs), (hin)
 * marching-on-in-time recurrence ........... Section V-A, eq. (MOT)
 * current recovery, loop/star kept apart ... Section V-A, eq. (dis_jm)
+* spectra of the loop and star currents at one frequency and the scattered
+  far field they radiate ...................... Section VI (far-field
+  computation) with eq. (dis_jm); the radiation integral itself is the
+  textbook one, which the paper does not print
 
 Dense linear algebra throughout: pseudo-inverses by numpy.linalg.pinv, G^-1
 and Q_0^-1 by LU (scipy.linalg), no blocking or fusion.
@@ -27,7 +31,14 @@ Readings where the paper is silent (also listed in the design notes):
 * the raw hat and tilde blocks arrive without their T_max, 1/T_max factors;
 * RWG testing of the incident field uses the 7-point degree-5 triangle rule;
 * the star part of the RHS is set to zero once the pulse has passed every
-  point of the surface: t > t0 + (max_x k.x + 1.6 w)/c (erfc(6.4) ~ 1e-19).
+  point of the surface: t > t0 + (max_x k.x + 1.6 w)/c (erfc(6.4) ~ 1e-19);
+* far field: exp(+i omega t) time convention, spectrum
+  J(f) = int j(t) exp(-i 2 pi f t) dt of j(t) = sum_i j_i p_i(t) with p_i the
+  unit pulse on ((i-1) dt, i dt); E_inf(rhat) = (i k / 4 pi)
+  [rhat x L + eta rhat x (rhat x N)] (the exp(-i k r)/r factor dropped),
+  N = int J exp(i k rhat.x) dS, L the same with M, eta = 1: the relative sign
+  is the one for which a scatterer with the exterior's own medium radiates no
+  scattered field.
 """
 from __future__ import annotations
 
@@ -40,6 +51,7 @@ __all__ = [
     "medium", "time_constants", "incidence", "projectors", "preconditioner",
     "media_sum", "lag_matrices", "tri_rule7", "tested_fields", "rhs",
     "march", "recover", "Oracle", "block_toeplitz_solve", "star_cut",
+    "rwg_at_rule_points", "current_spectrum", "radiation_vectors", "far_field",
 ]
 
 
@@ -281,6 +293,75 @@ def recover(P, Tmax, dt, W):
     return loop, star
 
 
+# -------------------------------------------------------------- far field ---
+def rwg_at_rule_points(V, F, E):
+    """Section II (RWG definition): the 7-point rule points of both triangles
+    of every edge, the RWG value there and the weight times area.
+    Returns X (ne, 2, 7, 3), f (ne, 2, 7, 3), w (ne, 2, 7)."""
+    V = np.asarray(V, dtype=np.float64)
+    F = np.asarray(F)
+    E = np.asarray(E)
+    L, W = tri_rule7()
+    Xs, fs, ws = [], [], []
+    for side, sgn in ((2, 1.0), (3, -1.0)):
+        f = E[:, side]
+        tv = V[F[f]]
+        area = 0.5 * np.linalg.norm(np.cross(tv[:, 1] - tv[:, 0], tv[:, 2] - tv[:, 0]), axis=1)
+        fv = F[f]
+        opp = np.where((fv != E[:, [0]]) & (fv != E[:, [1]]), fv, -1).max(axis=1)
+        X = np.einsum("qk,mkd->mqd", L, tv)
+        Xs.append(X)
+        fs.append(sgn * (X - V[opp][:, None, :]) / (2 * area)[:, None, None])
+        ws.append(W[None, :] * area[:, None])
+    return np.stack(Xs, 1), np.stack(fs, 1), np.stack(ws, 1)
+
+
+def current_spectrum(X, dt, freq, first=0):
+    """Section VI (far-field computation) on eq. (dis_jm): the Fourier
+    transform at freq of the current sum_i X_i p_i(t), where row s of X is
+    the coefficient of step first+s+1, whose pulse covers
+    ((first+s) dt, (first+s+1) dt):  sum_s X_s int_pulse exp(-i 2 pi f t) dt.
+    X: (count, n, R) real.  Returns (n, R) complex."""
+    s = first + np.arange(X.shape[0])
+    if freq == 0:
+        w = np.full(s.shape, dt, dtype=complex)
+    else:
+        om = 2 * np.pi * freq
+        w = (np.exp(-1j * om * s * dt) - np.exp(-1j * om * (s + 1) * dt)) / (1j * om)
+    return np.einsum("s,snr->nr", w, X)
+
+
+def radiation_vectors(V, F, E, k, dirs):
+    """int f_n(x) exp(i k rhat.x) dS for every RWG f_n and direction rhat
+    (7-point rule on both triangles).  dirs: (ndir, 3).  Returns
+    (ndir, ne, 3) complex."""
+    X, f, w = rwg_at_rule_points(V, F, E)
+    dirs = np.asarray(dirs, dtype=np.float64)
+    out = np.zeros((dirs.shape[0], E.shape[0], 3), complex)
+    for a, rh in enumerate(dirs):
+        ph = np.exp(1j * k * (X @ rh))                        # (ne, 2, 7)
+        out[a] = np.einsum("mtq,mtqd->md", w * ph, f)
+    return out
+
+
+def far_field(V, F, E, spec, freq, dirs, eta=1.0, c=1.0):
+    """Far field radiated by the spectra spec (2 ne, R) = (J; M) at freq:
+    E_inf(rhat) = (i k / 4 pi) [rhat x L + eta rhat x (rhat x N)],
+    N = sum_n J_n F_n(rhat), L = sum_n M_n F_n(rhat), k = 2 pi f / c.
+    Returns (ndir, R, 3) complex."""
+    ne = E.shape[0]
+    k = 2 * np.pi * freq / c
+    Fv = radiation_vectors(V, F, E, k, dirs)                  # (ndir, ne, 3)
+    dirs = np.asarray(dirs, dtype=np.float64)
+    out = np.zeros((dirs.shape[0], spec.shape[1], 3), complex)
+    for a, rh in enumerate(dirs):
+        Nv = np.einsum("nd,nr->rd", Fv[a], spec[:ne])
+        Lv = np.einsum("nd,nr->rd", Fv[a], spec[ne:])
+        rr = np.broadcast_to(rh, Nv.shape)
+        out[a] = (1j * k / (4 * np.pi)) * (np.cross(rr, Lv) + eta * np.cross(rr, np.cross(rr, Nv)))
+    return out
+
+
 # ------------------------------------------------------------ convenience ---
 class Oracle:
     """All oracle stages for one problem dict (see fixture.problem)."""
@@ -310,3 +391,15 @@ class Oracle:
         W = march(self.Q, r)
         loop, star = recover(self.P, self.Tmax, self.prob["dt"], W)
         return dict(r=r, W=W, loop=loop, star=star)
+
+    def far_field(self, res, freq, dirs, first=0, count=None):
+        """Spectra at freq of the loop and star currents of steps
+        first+1 .. first+count (res from run) and the far field each radiates,
+        kept apart (eq. (dis_jm) remark).  Returns dict(spec (2, n, R) complex:
+        loop, star; field (ndir, R, 2, 3) complex)."""
+        count = res["W"].shape[0] - first if count is None else count
+        p = self.prob
+        spec = np.stack([current_spectrum(res[part][first:first + count], p["dt"], freq, first)
+                         for part in ("loop", "star")])
+        field = np.stack([far_field(p["V"], p["F"], p["E"], spec[i], freq, dirs) for i in range(2)], axis=2)
+        return dict(spec=spec, field=field)

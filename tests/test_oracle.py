@@ -185,3 +185,105 @@ def test_q0_condition_flat_in_dt(name):
         conds.append(s[0] / s[-1])
     print(name, ["%.3g" % c for c in conds])
     assert max(conds) / min(conds) < 1.2, conds
+
+
+# ---------------------------------------------------------------- far field ---
+def test_spectrum_of_a_constant_current_is_one_long_pulse():
+    """Unit coefficients on steps first+1 .. first+N make one pulse over
+    (first dt, (first+N) dt); its transform is the closed-form integral of
+    exp(-i 2 pi f t) over that interval (and N dt at f = 0)."""
+    dt, first, N = 0.3, 7, 25
+    X = np.ones((N, 3, 2))
+    for f in (0.0, 0.013, 0.4, 2.9):
+        got = mo.current_spectrum(X, dt, f, first)
+        if f == 0:
+            ex = N * dt
+        else:
+            om = 2 * np.pi * f
+            ex = (np.exp(-1j * om * first * dt) - np.exp(-1j * om * (first + N) * dt)) / (1j * om)
+        assert np.allclose(got, ex, rtol=1e-12, atol=1e-14), f
+    # one coefficient alone: the pulse of step first+s+1, of width dt centred at (first+s+1/2) dt
+    X = np.zeros((N, 1, 1))
+    X[4] = 1.0
+    f = 0.21
+    om = 2 * np.pi * f
+    ex = dt * np.sinc(f * dt) * np.exp(-1j * om * (first + 4.5) * dt)
+    assert abs(mo.current_spectrum(X, dt, f, first)[0, 0] - ex) < 1e-14
+
+
+def _rwg_moments(V, F, E):
+    """Closed forms on each RWG: int f_n dS from centroids, and
+    int f_n (d.x) dS from int_T lam_i lam_j = A (1 + delta_ij) / 12."""
+    V = np.asarray(V)
+    ne = E.shape[0]
+    m0 = np.zeros((ne, 3))
+    m1 = np.zeros((ne, 3, 3))        # [n, component, d-axis]: int f_n x_d
+    for n in range(ne):
+        for side, sgn in ((2, 1.0), (3, -1.0)):
+            tri = F[E[n, side]]
+            P = V[tri]
+            A = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+            opp = [v for v in tri if v not in (E[n, 0], E[n, 1])][0]
+            g = sgn * (P - V[opp]) / (2 * A)          # RWG at the vertices (linear on the triangle)
+            m0[n] += A * g.mean(0)
+            for i in range(3):
+                for j in range(3):
+                    m1[n] += np.outer(g[i], P[j]) * A * (1 + (i == j)) / 12
+    return m0, m1
+
+
+def test_radiation_vectors_against_closed_moments():
+    """k = 0 gives int f_n dS; the odd part in k gives i k int f_n (rhat.x) dS."""
+    prob = problem("tiny")
+    V, F, E = prob["V"], prob["F"], prob["E"]
+    m0, m1 = _rwg_moments(V, F, E)
+    rng = np.random.default_rng(5)
+    dirs = rng.normal(size=(4, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    F0 = mo.radiation_vectors(V, F, E, 0.0, dirs)
+    for a in range(4):
+        assert np.allclose(F0[a], m0, atol=1e-13)
+    k = 1e-4
+    odd = (mo.radiation_vectors(V, F, E, k, dirs) - mo.radiation_vectors(V, F, E, -k, dirs)) / (2 * k)
+    for a, d in enumerate(dirs):
+        assert np.allclose(odd[a], 1j * (m1 @ d), atol=1e-8)
+
+
+def test_far_field_is_transverse():
+    prob = problem("tiny")
+    rng = np.random.default_rng(9)
+    spec = rng.normal(size=(2 * prob["E"].shape[0], 2)) + 1j * rng.normal(size=(2 * prob["E"].shape[0], 2))
+    dirs = rng.normal(size=(6, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    Ef = mo.far_field(prob["V"], prob["F"], prob["E"], spec, 0.3, dirs)
+    assert np.abs(np.einsum("ad,ard->ar", dirs, Ef)).max() < 1e-12 * np.abs(Ef).max()
+
+
+def _vacuum_ratio(eta):
+    """Largest far field of the vacuum-interior solution over the largest far
+    field of its electric current alone, at f = 0.1 (k a = 0.63)."""
+    prob = problem("sphere_vacuum")
+    O = oracle("sphere_vacuum")
+    res = O.run()
+    th = np.radians(np.arange(0, 181, 10))
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    spec = sum(mo.current_spectrum(res[p], prob["dt"], 0.1) for p in ("loop", "star"))
+    tot = mo.far_field(prob["V"], prob["F"], prob["E"], spec, 0.1, dirs, eta=eta)
+    ne = prob["E"].shape[0]
+    j_only = spec.copy()
+    j_only[ne:] = 0
+    ej = mo.far_field(prob["V"], prob["F"], prob["E"], j_only, 0.1, dirs, eta=eta)
+    return np.abs(tot).max() / np.abs(ej).max()
+
+
+def test_vacuum_interior_radiates_no_scattered_field():
+    """With the exterior's own medium inside there is no scatterer: the
+    electric and magnetic currents' far fields cancel (to discretisation
+    error), though each alone is of the incident field's size."""
+    assert _vacuum_ratio(1.0) < 0.03
+
+
+def test_vacuum_far_field_pin_catches_a_sign_error():
+    """Plant a sign error (the magnetic term against the electric one): the
+    cancellation pin must fail by a wide margin."""
+    assert _vacuum_ratio(-1.0) > 1.0
