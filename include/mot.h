@@ -261,6 +261,30 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out,
 int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, double* loop_out,
                   double* star_out, int32_t out_on_device);
 
+/* Spectra and far fields of the currents of kept steps (Section VI, far-field
+ * computation, on eq. (dis_jm)), the loop and star parts kept apart so that
+ * neither is lost in the other at low frequency.  Steps first ..
+ * first+count-1 (counted from 0, as in mot_get_steps) must be taken and kept;
+ * step s carries the unit pulse on (s dt, (s+1) dt).  With the exp(+i omega t)
+ * convention, omega = 2 pi freq, the spectrum of each part is
+ *   X(f) = sum_s x_s int_{s dt}^{(s+1) dt} exp(-i omega t) dt,
+ * x_s the loop or star coefficients of mot_run, and the far field of each
+ * part in the unit direction rhat (the exp(-i k r)/r factor dropped, k =
+ * omega, exterior c = eta = 1) is
+ *   E(rhat) = (i k / 4 pi) [rhat x L + rhat x (rhat x N)],
+ *   N = sum_n J_n int f_n exp(i k rhat.x) dS,  L likewise with M,
+ * the integrals on the 7-point rule of the incident-field testing.
+ *   dirs       host [ndir][3] unit vectors (|d|^2 within 1e-9 of 1);
+ *   field_out  host [ndir][nrhs][2 parts: loop, star][3][2: re, im];
+ *   spec_out   host [2 parts][n][nrhs][2: re, im], or NULL.
+ * ndir may be 0 (spectra only).  Scratch device memory is taken from the
+ * handle's pool for the call and released before it returns.  MOT_EINVAL for
+ * a range not taken or not kept, a negative or non-finite frequency, or a
+ * direction that is not a unit vector; MOT_ENOCONV if the CG form of
+ * P^Sigma (recovery = 1) hit its cap (outputs still written). */
+int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int32_t ndir,
+                  const double* dirs, double* field_out, double* spec_out);
+
 /* nsteps MOT steps (eq. MOT) on each of n independent handles, for serving
  * several scattering problems at once: the handles' windows of queued steps
  * are interleaved across their streams, so small solves share the device

@@ -50,7 +50,8 @@ class MotInfo(ctypes.Structure):
 
 EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr", "mot_step",
            "mot_run", "mot_get_matrix", "mot_get_info", "mot_reset", "mot_destroy",
-           "mot_last_error", "mot_footprint", "mot_get_steps", "mot_run_batch"]
+           "mot_last_error", "mot_footprint", "mot_get_steps", "mot_run_batch",
+           "mot_far_field"]
 
 _lib = None
 
@@ -85,6 +86,8 @@ def load():
     lib.mot_run.restype = _I
     lib.mot_get_steps.argtypes = [_P, _I, _I, _P, _P, _P, _I]
     lib.mot_get_steps.restype = _I
+    lib.mot_far_field.argtypes = [_P, _I, _I, _D, _I, _P, _P, _P]
+    lib.mot_far_field.restype = _I
     lib.mot_run_batch.argtypes = [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(_I)]
     lib.mot_run_batch.restype = _I
     lib.mot_get_matrix.argtypes = [_P, _I, _I, _P]

@@ -699,6 +699,25 @@ int gmres_solve(mot_handle* h) {
     return h->last_conv ? MOT_OK : MOT_ENOCONV;
 }
 
+// PX = P^Sigma X for X [ne][nc]; S and Z ([nf][nc]) are scratch of the CG
+// form and may be null with the dense one
+static int sigma_project(mot_handle* h, int nc, const double* X, double* PX, double* S, double* Z) {
+    if (h->opt.recovery == 1) {
+        // P^Sigma X = Sigma (Sigma^T Sigma)^+ Sigma^T X: incidence products and
+        // CG on the face graph Laplacian (Section IV-B)
+        motk::inc_T(h->stream, h->gf, nc, X, nc, S);
+        motk::col_center(h->stream, h->nf, nc, S);
+        auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
+        int rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        motk::inc_apply(h->stream, h->gf, nc, Z, PX, nc);
+        return rc;
+    }
+    // the dense P^Sigma formed at setup by the same incidence products and CG
+    motk::gemm(h->stream, h->ne, nc, h->ne, 1.0, h->PS, h->hs, X, nc, 0.0, PX, nc);
+    return MOT_OK;
+}
+
 int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
     // columns per batch: 4 R per step
     const int per = 4 * h->R;
@@ -716,20 +735,9 @@ int recover(mot_handle* h, int s0, int ns, double* loop, double* star) {
         int nb = std::min(bs, ns - b0);
         int nc = nb * per;
         motk_step::rec_gather(h, s0 + b0, nb, X);
-        if (cg) {
-            // P^Sigma X = Sigma (Sigma^T Sigma)^+ Sigma^T X: incidence products and
-            // CG on the face graph Laplacian (Section IV-B)
-            motk::inc_T(h->stream, h->gf, nc, X, nc, S);
-            motk::col_center(h->stream, h->nf, nc, S);
-            auto lap = [&](const double* Xi, double* Yo) { motk::spmm_lap(h->stream, h->gf, nc, Xi, Yo); };
-            rc = batched_cg(h, h->nf, nc, S, Z, lap, h->opt.cg_tol, h->opt.cg_maxit);
-            if (rc && rc != MOT_ENOCONV) return rc;
-            if (rc) worst = rc;
-            motk::inc_apply(h->stream, h->gf, nc, Z, PX, nc);
-        } else {
-            // the dense P^Sigma formed at setup by the same incidence products and CG
-            motk::gemm(h->stream, h->ne, nc, h->ne, 1.0, h->PS, h->hs, X, nc, 0.0, PX, nc);
-        }
+        rc = sigma_project(h, nc, X, PX, S, Z);
+        if (rc && rc != MOT_ENOCONV) return rc;
+        if (rc) worst = rc;
         size_t off = (size_t)b0 * 2 * h->ne * h->R;
         motk_step::rec_scatter(h, nb, X, PX, loop ? loop + off : nullptr, star ? star + off : nullptr);
     }
@@ -1518,6 +1526,70 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
     if (!h->hist || first + count > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
     if (count == 0 || !(w_out || loop_out || star_out)) return MOT_OK;
     return emit_steps(h, first, count, w_out, loop_out, star_out, out_on_device, MOT_OK);
+}
+
+int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int32_t ndir, const double* dirs,
+                  double* field_out, double* spec_out) {
+    if (!h) return MOT_EINVAL;
+    if (first < 0 || count < 1 || first + count > h->k)
+        return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be transformed");
+    if (!h->hist || first + count > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (!(freq >= 0) || !std::isfinite(freq)) return mot_fail(h, MOT_EINVAL, "frequency must be finite and >= 0");
+    if (ndir < 0 || (ndir > 0 && (!dirs || !field_out)) || ndir > 65535)
+        return mot_fail(h, MOT_EINVAL, "bad direction count or missing direction/field arrays");
+    for (int a = 0; a < ndir; ++a) {
+        const double* d = dirs + 3 * a;
+        const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(std::fabs(nn - 1.0) <= 1e-9)) return mot_fail(h, MOT_EINVAL, "directions must be unit vectors");
+    }
+    const int ne = h->ne, R = h->R, nc = 8 * R;
+    const double omega = 2 * M_PI * freq;               // c = 1 outside
+    int chunk = 0;
+    const int nchunk = motk_ff::chunks(h, count, &chunk);
+    const size_t E = (size_t)2 * ne * R;
+    const size_t nspec = 2 * E * 2;
+    double *phi = nullptr, *part = nullptr, *X = nullptr, *PX = nullptr, *S = nullptr, *Z = nullptr;
+    double *spec = nullptr, *ddir = nullptr, *dfield = nullptr;
+    auto release = [&]() {
+        dfree(h, phi); dfree(h, part); dfree(h, X); dfree(h, PX); dfree(h, S); dfree(h, Z);
+        dfree(h, spec); dfree(h, ddir); dfree(h, dfield);
+    };
+    int rc;
+    if ((rc = dalloc(h, &phi, (size_t)2 * count, false)) || (rc = dalloc(h, &part, (size_t)nchunk * E * 4, false)) ||
+        (rc = dalloc(h, &X, (size_t)ne * nc, false)) || (rc = dalloc(h, &PX, (size_t)ne * nc, false)) ||
+        (h->opt.recovery == 1 && ((rc = dalloc(h, &S, (size_t)h->nf * nc, false)) ||
+                                  (rc = dalloc(h, &Z, (size_t)h->nf * nc, false)))) ||
+        (rc = dalloc(h, &spec, nspec, false)) || (rc = dalloc(h, &ddir, (size_t)3 * std::max(ndir, 1), false)) ||
+        (rc = dalloc(h, &dfield, (size_t)12 * R * std::max(ndir, 1), false))) {
+        release();
+        return rc;
+    }
+    int worst = MOT_OK;
+    motk_ff::phase(h, first, count, omega, phi);
+    motk_ff::spectrum(h, first, count, chunk, nchunk, phi, part);
+    motk_ff::reduce(h, nchunk, part, X);
+    rc = sigma_project(h, nc, X, PX, S, Z);
+    if (rc && rc != MOT_ENOCONV) { release(); return rc; }
+    if (rc) worst = rc;
+    motk_ff::parts(h, X, PX, spec);
+    if (ndir > 0) {
+        if (hipMemcpyAsync(ddir, dirs, sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+            release();
+            return mot_fail(h, MOT_EHIP, "direction upload failed");
+        }
+        motk_ff::field(h, omega, ndir, ddir, spec, dfield);
+        hipError_t e = hipMemcpyAsync(field_out, dfield, sizeof(double) * 12 * R * ndir, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) { release(); return mot_fail(h, MOT_EHIP, hipGetErrorString(e)); }
+    }
+    if (spec_out) {
+        hipError_t e = hipMemcpyAsync(spec_out, spec, sizeof(double) * nspec, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) { release(); return mot_fail(h, MOT_EHIP, hipGetErrorString(e)); }
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    release();
+    if (e != hipSuccess) return mot_fail(h, MOT_EHIP, hipGetErrorString(e));
+    return worst;
 }
 
 // Several independent marches advanced together: every handle's speculative

@@ -214,3 +214,14 @@ int mot_fail(mot_handle* h, int code, const std::string& msg);
 // product on the handle's stream once all lags are folded; returns MOT_OK or
 // MOT_EHIP
 int mot_autotune(mot_handle* h);
+
+// far field of the kept currents (farfield.hip); every launcher queues on the
+// handle's stream.  X and PX are [ne][8R]; spec is [2 parts][2 ne][R][2].
+namespace motk_ff {
+void phase(mot_handle* h, int first, int count, double omega, double* phi);     // phi [count][2]
+int chunks(const mot_handle* h, int count, int* chunk);                         // step chunks of the pass
+void spectrum(mot_handle* h, int first, int count, int chunk, int nchunk, const double* phi, double* part);
+void reduce(mot_handle* h, int nchunk, const double* part, double* X);
+void parts(mot_handle* h, const double* X, const double* PX, double* spec);
+void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* out);
+}  // namespace motk_ff

@@ -162,6 +162,20 @@ class Solver:
                                             1 if device else 0))
         return outs
 
+    def far_field(self, first, count, freq, dirs=None):
+        """Spectra at freq of the loop and star currents of the kept steps
+        first .. first+count-1 and the far field each radiates in the unit
+        directions dirs (ndir, 3).  Returns dict(spec (2, n, nrhs) complex,
+        field (ndir, nrhs, 2, 3) complex, rc)."""
+        d = np.ascontiguousarray(np.zeros((0, 3)) if dirs is None else dirs, dtype=np.float64)
+        nd = d.shape[0]
+        field = np.zeros((max(nd, 1), self.nrhs, 2, 3, 2))
+        spec = np.zeros((2, self.n, self.nrhs, 2))
+        rc = self._lib.mot_far_field(self._h, int(first), int(count), float(freq), nd, _ptr(d) if nd else None,
+                                     _ptr(field) if nd else None, _ptr(spec))
+        self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
+        return dict(spec=spec[..., 0] + 1j * spec[..., 1], field=(field[..., 0] + 1j * field[..., 1])[:nd], rc=rc)
+
     def matrix(self, which, lag=0):
         shape = (self.n, self.n) if which == 0 else ((self.n, self.nrhs) if which == 6 else (self.ne, self.ne))
         out = np.empty(shape)

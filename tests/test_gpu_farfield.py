@@ -1,0 +1,85 @@
+"""Spectra and far fields of the loop and star currents (mot_far_field)
+against the oracle's, and against the oracle's transform of the GPU's own
+currents (MI355X only)."""
+import numpy as np
+import pytest
+
+from oracle import mot_oracle as mo
+from tests._problems import problem, oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(name, **opts):
+    import paper_2510_07989_amd as p
+    prob = problem(name)
+    s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                 prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=p.default_options(**opts))
+    s.load_raw(prob["raw"], prob["kmax"])
+    return s
+
+
+def _dirs(n=13):
+    th = np.linspace(0, np.pi, n)
+    ph = np.linspace(0.3, 2.0, n)
+    return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name,nsteps,opts", [
+    ("sphere_480", 200, {}),
+    ("tiny_torus", 160, dict(recovery=1)),          # P^Sigma by incidence products and CG
+    ("tiny_box", 120, {}),                           # two waves
+    ("sphere_480_r16", 120, {}),                     # sixteen waves
+])
+def test_far_field_matches_oracle(name, nsteps, opts):
+    print("case", name, nsteps, opts, flush=True)
+    prob = problem(name)
+    s = _solver(name, **opts)
+    out = s.run(nsteps)
+    O = oracle(name)
+    ref = O.run(nsteps)
+    dirs = _dirs()
+    dt = prob["dt"]
+    for freq, first, count in ((0.1, 0, nsteps), (0.0, 0, nsteps), (0.003, 0, nsteps), (0.37 / dt, 17, nsteps - 30)):
+        got = s.far_field(first, count, freq, dirs)
+        exp = O.far_field(ref, freq, dirs, first, count)
+        e_spec = _rel(got["spec"], exp["spec"])
+        e_field = _rel(got["field"], exp["field"])
+        # the GPU's own currents transformed by the oracle: the transform alone
+        own = {"loop": out["loop"], "star": out["star"], "W": out["w"]}
+        mine = O.far_field(own, freq, dirs, first, count)
+        e_own = max(_rel(got["spec"], mine["spec"]), _rel(got["field"], mine["field"]))
+        print("  f %.4g first %d count %d: spec %.2e field %.2e vs own currents %.2e"
+              % (freq, first, count, e_spec, e_field, e_own), flush=True)
+        assert e_own < 1e-12
+        assert e_spec < 1e-9 and e_field < 1e-9
+        for part in range(2):
+            assert _rel(got["field"][:, :, part], exp["field"][:, :, part]) < 1e-9
+    s.close()
+
+
+def test_far_field_arguments():
+    import paper_2510_07989_amd as p
+    s = _solver("tiny_box")
+    with pytest.raises(p.MotError):
+        s.far_field(0, 1, 0.1, _dirs())                 # no step taken yet
+    s.run(20, w=False, loop=False, star=False)
+    with pytest.raises(p.MotError):
+        s.far_field(5, 16, 0.1, _dirs())                # step 20 not taken
+    with pytest.raises(p.MotError):
+        s.far_field(0, 20, -0.1, _dirs())
+    with pytest.raises(p.MotError):
+        s.far_field(0, 20, 0.1, 2 * _dirs())            # not unit vectors
+    r = s.far_field(0, 20, 0.1)                         # spectra only
+    assert r["field"].shape == (0, s.nrhs, 2, 3)
+    assert np.abs(r["spec"]).max() > 0
+    s.close()
+    s = _solver("tiny_box", keep_history=0)
+    s.run(10, w=False, loop=False, star=False)
+    with pytest.raises(p.MotError):
+        s.far_field(0, 10, 0.1, _dirs())                # nothing kept
+    s.close()
