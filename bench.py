@@ -154,7 +154,28 @@ def history_kernel_name(R, precision, mix_group, sched_hist=11):
 PROFILE_EVERY = 16
 
 
-def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, outputs=True):
+def far_field_timing(s, nsteps, n, R, freq):
+    """mot_far_field over every kept step of a march: the spectra of the loop
+    and star currents at freq and the far field in 181 directions of one
+    plane.  Timed on the host around the (synchronous) call; the streaming
+    pass over the kept unknowns is its dominant kernel."""
+    import numpy as np
+    th = np.radians(np.arange(181.0))
+    dirs = np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], 1)
+    s.far_field(0, min(nsteps, 64), freq, dirs)                 # first call: code objects, pool
+    t = time.perf_counter()
+    r = s.far_field(0, nsteps, freq, dirs)
+    el = time.perf_counter() - t
+    nbytes = 8.0 * nsteps * n * R
+    mag = np.abs(r["field"]).max(axis=(0, 1, 3))
+    log("far field: %d steps, %d directions at f = %g: %.3f ms per call (scratch allocation, kernels, copies to "
+        "the host); largest loop / star field %.3e / %.3e" % (nsteps, len(dirs), freq, 1e3 * el, mag[0], mag[1]))
+    return {"steps": nsteps, "freq": freq, "directions": len(dirs), "call_ms": round(1e3 * el, 3),
+            "spectrum_pass_bytes": nbytes, "max_field_loop": float(mag[0]), "max_field_star": float(mag[1]),
+            "note": "host wall time of the whole call; per-kernel times in the rocprofv3 summary"}
+
+
+def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, outputs=True, far=None):
     """Set up one problem on the device, march W_ warm-up steps (kept as the
     parity sample), then time K steps with device-resident outputs."""
     import torch
@@ -182,6 +203,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     b = s.info()
+    ff = far_field_timing(s, W_ + K, 2 * prob["E"].shape[0], R, far) if far is not None else None
     s.close()
     ne, n, L = prob["E"].shape[0], 2 * prob["E"].shape[0], b["nlags"]
     hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
@@ -202,7 +224,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
                iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
                q0_launches=PROFILE_EVERY * (b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
                dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
-               device_gb=inf0["device_bytes"] / 1e9,
+               device_gb=inf0["device_bytes"] / 1e9, far_field=ff,
                schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
                          "autotuned": bool(inf0["tuned"] and opts.autotune), "tune_ms": round(inf0["tune_ms"], 1)})
     log("[%s R=%d] timed %d steps in %.3f s: %.1f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
@@ -254,6 +276,7 @@ def main():
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
     ap.add_argument("--no-step-batch", action="store_true", help="skip the mot_run_batch comparison")
+    ap.add_argument("--no-far-field", action="store_true", help="skip the far-field timing")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed (FP64 MFMA), 2 mixed (FP32 MFMA)")
@@ -280,7 +303,7 @@ def main():
     t_fixture = time.perf_counter() - t
     log("inputs assembled on the host in %.1f s" % t_fixture)
     m = measure(mot, prob, args.workload, args.precision, K, W_, args.precond, args.split, args.hilo,
-                args.mix_group)
+                args.mix_group, far=None if args.no_far_field else FAR_FIELD_FREQ.get(args.workload, 0.01))
     R = m["R"]
     result = {
         "metric": "MOT steps/s (%s, %d RHS)" % ("plain FP64" if args.precision == 0 else "mixed precision", R),
@@ -308,6 +331,8 @@ def main():
         "fixture_s": round(t_fixture, 1),
         "device_gb": round(m["device_gb"], 2),
     }
+    if m["far_field"] is not None:
+        result["far_field"] = m["far_field"]
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.cpu_budget, min(W_, 400))
@@ -399,6 +424,9 @@ def main():
         result["serving"] = serving(args.serving_requests, have)
     print(json.dumps(result), flush=True)
 
+
+# a frequency inside the incident pulse's band (sigma = 8 on the torus: up to ~1/(2 pi sigma))
+FAR_FIELD_FREQ = {"torus_3072": 0.01}
 
 SERVING_MESHES = ["tiny_torus", "tiny_box", "sphere_480", "sphere_480_r16", "sphere_1920_r16", "torus_3072"]
 

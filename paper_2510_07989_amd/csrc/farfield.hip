@@ -75,24 +75,72 @@ __global__ __launch_bounds__(256) void k_ff_spectrum(int ne, int hs, int n2, int
     o[0] = sr; o[1] = si; o[2] = dr; o[3] = di;
 }
 
-// sum the chunks; X is [ne][8R], column ((p * 2 + hh) * 2 + c) * R + r with
-// p 0 for S, 1 for D and c 0 re, 1 im
+// sum the chunks in order, one thread per (element, quantity); X is [ne][8R],
+// column ((p * 2 + hh) * 2 + c) * R + r with p 0 for S, 1 for D and c 0 re, 1 im
 __global__ void k_ff_reduce(int ne, int R, int nchunk, const double* __restrict__ part, double* __restrict__ X) {
     const int E = 2 * ne * R;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    double a[4] = {0, 0, 0, 0};
-    for (int c = 0; c < nchunk; ++c) {
-        const double* p = part + ((size_t)c * E + e) * 4;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * E) return;
+    const size_t ld = (size_t)4 * E;
+    double a = 0;
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 8) {
+        double v[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] += p[q];
+        for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(c + u) * ld + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += v[u];
     }
+    for (; c < nchunk; ++c) a += part[(size_t)c * ld + t];
+    const int e = t >> 2, q = t & 3;
     const int r = e % R, m = (e / R) % ne, hh = e / (R * ne);
-    const size_t row = (size_t)m * 8 * R;
+    const int p = q >> 1, ri = q & 1;
+    X[(size_t)m * 8 * R + ((p * 2 + hh) * 2 + ri) * R + r] = a;
+}
+
+__device__ __forceinline__ double ff_wave_sum(double v) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int p = q >> 1, c = q & 1;
-        X[row + ((p * 2 + hh) * 2 + c) * R + r] = a[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// PX = P^Sigma X for the 8R transformed columns, a tall-skinny product: one
+// wavefront per two rows of P^Sigma (read once per group of 8 columns), each
+// lane striding the row and reading its 8 columns of X (64 contiguous bytes,
+// L2-resident), then a wavefront sum.  grid (ceil(ne / 8), 8R / 8).
+__global__ __launch_bounds__(256) void k_ff_project(int ne, int hs, int nc, const double* __restrict__ PS,
+                                                    const double* __restrict__ X, double* __restrict__ PX) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = (blockIdx.x * 4 + wv) * 2;
+    if (m0 >= ne) return;
+    const bool two = m0 + 1 < ne;
+    const int cg = blockIdx.y * 8;
+    const double* a0 = PS + (size_t)m0 * hs;
+    const double* a1 = PS + (size_t)(two ? m0 + 1 : m0) * hs;
+    double c0[8] = {}, c1[8] = {};
+    for (int j = lane; j < ne; j += 64) {
+        const double p0 = __builtin_nontemporal_load(a0 + j), p1 = __builtin_nontemporal_load(a1 + j);
+        const d2* xr = reinterpret_cast<const d2*>(X + (size_t)j * nc + cg);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const d2 x = xr[u];
+            c0[2 * u] += p0 * x.x; c0[2 * u + 1] += p0 * x.y;
+            c1[2 * u] += p1 * x.x; c1[2 * u + 1] += p1 * x.y;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        c0[c] = ff_wave_sum(c0[c]);
+        c1[c] = ff_wave_sum(c1[c]);
+    }
+    if (lane < 8) {
+        double v0 = c0[0], v1 = c1[0];
+#pragma unroll
+        for (int c = 1; c < 8; ++c)
+            if (lane == c) { v0 = c0[c]; v1 = c1[c]; }
+        PX[(size_t)m0 * nc + cg + lane] = v0;
+        if (two) PX[(size_t)(m0 + 1) * nc + cg + lane] = v1;
     }
 }
 
@@ -109,24 +157,19 @@ __global__ void k_ff_parts(int ne, int R, double scale, const double* __restrict
     spec[t] = part == 0 ? X[row + colS] - PX[row + colS] : scale * PX[row + colD];
 }
 
-__device__ __forceinline__ double ff_wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// one workgroup per (direction a, wave r): radiation vectors F_n(rhat) on the
-// 14 quadrature points of each edge, N and L of both parts, then the field;
-// out [ndir][R][2 parts][3][2]
-__global__ __launch_bounds__(256) void k_ff_field(int ne, int R, double k, const double* __restrict__ dirs,
-                                                  const double* __restrict__ qx, const double* __restrict__ qf,
-                                                  const double* __restrict__ spec, double* __restrict__ out) {
-    const int a = blockIdx.x, r = blockIdx.y;
+// workgroup (direction a, wave r, edge slice z): radiation vectors F_n(rhat)
+// on the 14 quadrature points of each edge of the slice, and the slice's sums
+// N and L of both parts to part [ndir][R][nz][24] (part, N or L, xyz, re/im)
+__global__ __launch_bounds__(256) void k_ff_radiate(int ne, int R, int per_z, double k,
+                                                    const double* __restrict__ dirs, const double* __restrict__ qx,
+                                                    const double* __restrict__ qf, const double* __restrict__ spec,
+                                                    double* __restrict__ part) {
+    const int a = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
     const double dx = dirs[3 * a], dy = dirs[3 * a + 1], dz = dirs[3 * a + 2];
-    // acc[part][N or L][xyz][re, im]
     double acc[2][2][3][2] = {};
     const size_t per = (size_t)2 * ne * R * 2;
-    for (int n = threadIdx.x; n < ne; n += blockDim.x) {
+    const int n0 = z * per_z, n1 = min(ne, n0 + per_z);
+    for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
         double F[3][2] = {};
         for (int q = 0; q < 14; ++q) {
             const double* x = qx + ((size_t)n * 14 + q) * 3;
@@ -158,30 +201,40 @@ __global__ __launch_bounds__(256) void k_ff_field(int ne, int R, double k, const
         if (lane == 0) red[wv][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x >= 2) return;
-    const int p = threadIdx.x;
-    double NL[2][3][2];
-    for (int hh = 0; hh < 2; ++hh)
-        for (int d = 0; d < 3; ++d)
-            for (int c = 0; c < 2; ++c) {
-                double v = 0;
-                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][((p * 2 + hh) * 3 + d) * 2 + c];
-                NL[hh][d][c] = v;
-            }
-    const double rh[3] = {dx, dy, dz};
+    if (threadIdx.x < 24) {
+        double v = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        part[(((size_t)a * R + r) * gridDim.z + z) * 24 + threadIdx.x] = v;
+    }
+}
+
+// one thread per (direction, wave, part): the slices summed in order, then
+// E = (i k / 4 pi) [rhat x L + eta rhat x (rhat x N)], eta = 1;
+// out [ndir][R][2 parts][3][2]
+__global__ void k_ff_field(int ndir, int R, int nz, double k, const double* __restrict__ dirs,
+                           const double* __restrict__ part, double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ndir * R * 2) return;
+    const int p = t % 2, r = (t / 2) % R, a = t / (2 * R);
+    double NL[2][3][2] = {};
+    const double* src = part + ((size_t)a * R + r) * nz * 24;
+    for (int z = 0; z < nz; ++z)
+        for (int hh = 0; hh < 2; ++hh)
+            for (int d = 0; d < 3; ++d)
+                for (int c = 0; c < 2; ++c) NL[hh][d][c] += src[(size_t)z * 24 + ((p * 2 + hh) * 3 + d) * 2 + c];
+    const double rh[3] = {dirs[3 * a], dirs[3 * a + 1], dirs[3 * a + 2]};
+    const double g = k / (4.0 * M_PI);
+    double* o = out + (size_t)t * 6;
     double res[3][2];
     for (int c = 0; c < 2; ++c) {
-        double Nv[3] = {NL[0][0][c], NL[0][1][c], NL[0][2][c]}, Lv[3] = {NL[1][0][c], NL[1][1][c], NL[1][2][c]};
-        // rhat x L
-        double a1[3] = {rh[1] * Lv[2] - rh[2] * Lv[1], rh[2] * Lv[0] - rh[0] * Lv[2], rh[0] * Lv[1] - rh[1] * Lv[0]};
-        // rhat x (rhat x N) = rhat (rhat.N) - N
-        const double rn = rh[0] * Nv[0] + rh[1] * Nv[1] + rh[2] * Nv[2];
-        for (int d = 0; d < 3; ++d) res[d][c] = a1[d] + (rh[d] * rn - Nv[d]);   // eta = 1
+        double N[3] = {NL[0][0][c], NL[0][1][c], NL[0][2][c]}, L[3] = {NL[1][0][c], NL[1][1][c], NL[1][2][c]};
+        // rhat x L, and rhat x (rhat x N) = rhat (rhat.N) - N
+        const double rn = rh[0] * N[0] + rh[1] * N[1] + rh[2] * N[2];
+        res[0][c] = rh[1] * L[2] - rh[2] * L[1] + rh[0] * rn - N[0];
+        res[1][c] = rh[2] * L[0] - rh[0] * L[2] + rh[1] * rn - N[1];
+        res[2][c] = rh[0] * L[1] - rh[1] * L[0] + rh[2] * rn - N[2];
     }
-    // times i k / (4 pi)
-    const double g = k / (4.0 * M_PI);
-    double* o = out + (((size_t)a * R + r) * 2 + p) * 6;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d) {      // times i k / (4 pi)
         o[2 * d] = -g * res[d][1];
         o[2 * d + 1] = g * res[d][0];
     }
@@ -197,10 +250,10 @@ void phase(mot_handle* h, int first, int count, double omega, double* phi) {
 }
 
 int chunks(const mot_handle* h, int count, int* chunk) {
+    // at least 64 steps per thread, and about 4096 workgroups at most
     const int E = 2 * h->ne * h->R;
     const int bx = (E + 255) / 256;
-    int nch = std::max(1, std::min(count / 16, (2048 + bx - 1) / bx));
-    nch = std::max(1, std::min(nch, count));
+    int nch = std::max(1, std::min(count / 64, (4096 + bx - 1) / bx));
     *chunk = (count + nch - 1) / nch;
     return (count + *chunk - 1) / *chunk;
 }
@@ -213,7 +266,13 @@ void spectrum(mot_handle* h, int first, int count, int chunk, int nchunk, const 
 
 void reduce(mot_handle* h, int nchunk, const double* part, double* X) {
     const int E = 2 * h->ne * h->R;
-    hipLaunchKernelGGL(k_ff_reduce, dim3((E + 255) / 256), dim3(256), 0, h->stream, h->ne, h->R, nchunk, part, X);
+    hipLaunchKernelGGL(k_ff_reduce, dim3((4 * E + 255) / 256), dim3(256), 0, h->stream, h->ne, h->R, nchunk, part, X);
+}
+
+void project(mot_handle* h, const double* X, double* PX) {
+    const int nc = 8 * h->R;
+    hipLaunchKernelGGL(k_ff_project, dim3((h->ne + 7) / 8, nc / 8), dim3(256), 0, h->stream, h->ne, h->hs, nc, h->PS,
+                       X, PX);
 }
 
 void parts(mot_handle* h, const double* X, const double* PX, double* spec) {
@@ -222,9 +281,16 @@ void parts(mot_handle* h, const double* X, const double* PX, double* spec) {
                        X, PX, spec);
 }
 
-void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* out) {
-    hipLaunchKernelGGL(k_ff_field, dim3(ndir, h->R), dim3(256), 0, h->stream, h->ne, h->R, k, dirs, h->rq_x,
-                       h->rq_f, spec, out);
+int field_slices(const mot_handle* h) { return std::max(1, std::min(64, (h->ne + 255) / 256)); }
+
+void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* part, double* out) {
+    const int nz = field_slices(h);
+    const int per_z = (h->ne + nz - 1) / nz;
+    hipLaunchKernelGGL(k_ff_radiate, dim3(ndir, h->R, nz), dim3(256), 0, h->stream, h->ne, h->R, per_z, k, dirs,
+                       h->rq_x, h->rq_f, spec, part);
+    const int tot = ndir * h->R * 2;
+    hipLaunchKernelGGL(k_ff_field, dim3((tot + 255) / 256), dim3(256), 0, h->stream, ndir, h->R, nz, k, dirs, part,
+                       out);
 }
 
 }  // namespace motk_ff

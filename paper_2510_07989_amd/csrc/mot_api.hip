@@ -1549,10 +1549,10 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
     const size_t E = (size_t)2 * ne * R;
     const size_t nspec = 2 * E * 2;
     double *phi = nullptr, *part = nullptr, *X = nullptr, *PX = nullptr, *S = nullptr, *Z = nullptr;
-    double *spec = nullptr, *ddir = nullptr, *dfield = nullptr;
+    double *spec = nullptr, *ddir = nullptr, *dfield = nullptr, *fpart = nullptr;
     auto release = [&]() {
         dfree(h, phi); dfree(h, part); dfree(h, X); dfree(h, PX); dfree(h, S); dfree(h, Z);
-        dfree(h, spec); dfree(h, ddir); dfree(h, dfield);
+        dfree(h, spec); dfree(h, ddir); dfree(h, dfield); dfree(h, fpart);
     };
     int rc;
     if ((rc = dalloc(h, &phi, (size_t)2 * count, false)) || (rc = dalloc(h, &part, (size_t)nchunk * E * 4, false)) ||
@@ -1560,6 +1560,7 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
         (h->opt.recovery == 1 && ((rc = dalloc(h, &S, (size_t)h->nf * nc, false)) ||
                                   (rc = dalloc(h, &Z, (size_t)h->nf * nc, false)))) ||
         (rc = dalloc(h, &spec, nspec, false)) || (rc = dalloc(h, &ddir, (size_t)3 * std::max(ndir, 1), false)) ||
+        (rc = dalloc(h, &fpart, (size_t)24 * R * std::max(ndir, 1) * motk_ff::field_slices(h), false)) ||
         (rc = dalloc(h, &dfield, (size_t)12 * R * std::max(ndir, 1), false))) {
         release();
         return rc;
@@ -1568,7 +1569,8 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
     motk_ff::phase(h, first, count, omega, phi);
     motk_ff::spectrum(h, first, count, chunk, nchunk, phi, part);
     motk_ff::reduce(h, nchunk, part, X);
-    rc = sigma_project(h, nc, X, PX, S, Z);
+    if (h->opt.recovery == 1) rc = sigma_project(h, nc, X, PX, S, Z);
+    else motk_ff::project(h, X, PX);         // a few columns: the tall-skinny product
     if (rc && rc != MOT_ENOCONV) { release(); return rc; }
     if (rc) worst = rc;
     motk_ff::parts(h, X, PX, spec);
@@ -1577,7 +1579,7 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
             release();
             return mot_fail(h, MOT_EHIP, "direction upload failed");
         }
-        motk_ff::field(h, omega, ndir, ddir, spec, dfield);
+        motk_ff::field(h, omega, ndir, ddir, spec, fpart, dfield);
         hipError_t e = hipMemcpyAsync(field_out, dfield, sizeof(double) * 12 * R * ndir, hipMemcpyDeviceToHost, h->stream);
         if (e != hipSuccess) { release(); return mot_fail(h, MOT_EHIP, hipGetErrorString(e)); }
     }

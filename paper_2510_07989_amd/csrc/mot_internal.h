@@ -222,6 +222,8 @@ void phase(mot_handle* h, int first, int count, double omega, double* phi);     
 int chunks(const mot_handle* h, int count, int* chunk);                         // step chunks of the pass
 void spectrum(mot_handle* h, int first, int count, int chunk, int nchunk, const double* phi, double* part);
 void reduce(mot_handle* h, int nchunk, const double* part, double* X);
+void project(mot_handle* h, const double* X, double* PX);                      // PX = P^Sigma X (dense P^Sigma)
 void parts(mot_handle* h, const double* X, const double* PX, double* spec);
-void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* out);
+int field_slices(const mot_handle* h);                                          // edge slices of the field pass
+void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* part, double* out);
 }  // namespace motk_ff
