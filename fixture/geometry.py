@@ -150,6 +150,46 @@ def box(nx: int, ny: int, nz: int, lengths=(1.0, 1.0, 1.0)):
     return verts, _orient_outward(verts, tris)
 
 
+def star_pyramid(n_tips: int = 12, r_out: float = 1.0, r_in: float = 0.3, height: float = 0.5, nu: int = 1):
+    """Pyramid over a star polygon (the paper's third, highly non-smooth
+    scatterer, Section VI): the base has 2 n_tips vertices in the plane z = 0,
+    alternately on circles of radius r_out (tips) and r_in (notches); the
+    apex is at (0, 0, height).  Coarse facets: a fan of the base around its
+    centre (the star is star-shaped about it) and one flat side triangle per
+    base edge; each facet is split into nu^2 triangles.
+
+    8 n_tips nu^2 triangles, 12 n_tips nu^2 edges, 4 n_tips nu^2 + 2 vertices.
+    """
+    if nu < 1 or n_tips < 3:
+        raise ValueError("nu >= 1 and n_tips >= 3")
+    nb = 2 * n_tips
+    ang = 2.0 * np.pi * np.arange(nb) / nb
+    rad = np.where(np.arange(nb) % 2 == 0, r_out, r_in)
+    base = np.stack([rad * np.cos(ang), rad * np.sin(ang), np.zeros(nb)], axis=1)
+    centre = np.zeros(3)
+    apex = np.array([0.0, 0.0, height])
+    facets = []
+    for i in range(nb):
+        a, b = base[i], base[(i + 1) % nb]
+        facets.append((centre, b, a))
+        facets.append((a, b, apex))
+    pts, tris = [], []
+    for A, B, C in facets:
+        idx = {}
+        first = len(pts)
+        for i in range(nu + 1):
+            for j in range(nu + 1 - i):
+                idx[(i, j)] = first + len(idx)
+                pts.append(((nu - i - j) * A + i * B + j * C) / nu)
+        for i in range(nu):
+            for j in range(nu - i):
+                tris.append((idx[(i, j)], idx[(i + 1, j)], idx[(i, j + 1)]))
+                if i + j < nu - 1:
+                    tris.append((idx[(i + 1, j)], idx[(i + 1, j + 1)], idx[(i, j + 1)]))
+    verts, tris = _dedupe(np.asarray(pts), np.asarray(tris, dtype=np.int64))
+    return verts, _orient_outward(verts, tris)
+
+
 def _orient_outward(verts, tris):
     """Make every triangle counter-clockwise w.r.t. the outward normal.
 

@@ -54,6 +54,9 @@ CONFIGS = {
     "sphere_7680": dict(mesh=("icosphere", 16), eps_r=2.0, mu_r=1.0, dt=0.1, nsteps=1000, nrhs=64, sigma=0.4, nq=7, seeded=True),
     # sharp-edged cube, 10240 triangles / 15360 edges, 16 RHS
     "cube_15360": dict(mesh=("box", 32, 32, 24), eps_r=4.0, mu_r=1.0, dt=0.5, nsteps=5000, nrhs=16, sigma=2.0, nq=12, seeded=True),
+    # star-based pyramid (24 base vertices on radii 1 and 0.3, height 0.5), eps_r = 5, c dt = 2 m
+    "tiny_pyramid": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 1), eps_r=5.0, mu_r=1.0, dt=2.0, nsteps=60, nrhs=1, sigma=2.0, nq=12),
+    "pyramid_648": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 3), eps_r=5.0, mu_r=1.0, dt=2.0, nsteps=300, nrhs=1, sigma=4.0, nq=12),
     # free-space interior: the exact solution is the projected incident trace
     "sphere_vacuum": dict(mesh=("icosphere", 3), eps_r=1.0, mu_r=1.0, dt=0.2, nsteps=80, nrhs=1, sigma=0.6, nq=7),
 }
@@ -67,6 +70,8 @@ def make_mesh(spec):
         V, F = geo.torus(*spec[1:])
     elif kind == "box":
         V, F = geo.box(*spec[1:])
+    elif kind == "star_pyramid":
+        V, F = geo.star_pyramid(*spec[1:])
     else:
         raise ValueError(kind)
     E = geo.edge_table(F)

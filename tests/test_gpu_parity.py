@@ -23,7 +23,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("name", ["tiny", "tiny_torus", "sphere_480"])
+@pytest.mark.parametrize("name", ["tiny", "tiny_torus", "sphere_480", "tiny_pyramid"])
 def test_setup_operators(name):
     print("case", name, flush=True)
     O = oracle(name)
@@ -55,7 +55,8 @@ def test_rhs(name):
     s.close()
 
 
-@pytest.mark.parametrize("name,nsteps", [("tiny", 40), ("tiny_torus", 60), ("sphere_480", 200)])
+@pytest.mark.parametrize("name,nsteps", [("tiny", 40), ("tiny_torus", 60), ("sphere_480", 200),
+                                          ("tiny_pyramid", 60), ("pyramid_648", 300)])
 def test_march_parity(name, nsteps):
     print("case", name, nsteps, flush=True)
     O = oracle(name)

@@ -14,6 +14,8 @@ from fixture.bc import refine, gram_bc
     (("icosphere", 4), (162, 320, 480), 0),
     (("torus", 1.0, 0.4, 64, 16), (1024, 2048, 3072), 1),
     (("box", 32, 32, 24), (5122, 10240, 15360), 0),
+    (("star_pyramid", 12, 1.0, 0.3, 0.5, 1), (26, 48, 72), 0),
+    (("star_pyramid", 12, 1.0, 0.3, 0.5, 7), (1178, 2352, 3528), 0),
 ])
 def test_mesh_counts_and_topology(spec, counts, genus):
     from fixture.problem import make_mesh
@@ -141,3 +143,27 @@ def test_retarded_blocks_structure():
     assert np.allclose(D, Bs["T_hat"])
     # causality: the diameter is 2, so nothing reaches beyond lag ceil(2/dt)+2
     assert abs(B["T_h"][5]).max() == 0.0
+
+
+def test_star_pyramid_shape():
+    """Base vertices alternate between the two circles in z = 0, one apex at
+    the height; every vertex lies on a facet of the coarse pyramid."""
+    from fixture.problem import make_mesh
+    V, F, E = make_mesh(("star_pyramid", 12, 1.0, 0.3, 0.5, 2))
+    assert np.isclose(V[:, 2].max(), 0.5) and np.isclose(V[:, 2].min(), 0.0)
+    apex = V[np.argmax(V[:, 2])]
+    assert np.allclose(apex, [0, 0, 0.5])
+    r = np.hypot(V[:, 0], V[:, 1])
+    assert np.isclose(r.max(), 1.0)
+    base = V[np.isclose(V[:, 2], 0.0)]
+    ang = np.degrees(np.arctan2(base[:, 1], base[:, 0])) % 360
+    tips = np.isclose(np.hypot(base[:, 0], base[:, 1]), 1.0)
+    notches = np.isclose(np.hypot(base[:, 0], base[:, 1]), 0.3)
+    assert tips.sum() == 12 and notches.sum() == 12
+    assert np.allclose(np.sort(ang[tips]), np.arange(0, 360, 30))
+    assert np.allclose(np.sort(ang[notches]), np.arange(15, 360, 30))
+    # closed, outward: positive enclosed volume equal to the pyramid's
+    p0, p1, p2 = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    vol = np.einsum("ij,ij->i", p0, np.cross(p1, p2)).sum() / 6.0
+    star_area = 12 * 2 * 0.5 * 1.0 * 0.3 * np.sin(np.radians(15))
+    assert np.isclose(vol, star_area * 0.5 / 3)
