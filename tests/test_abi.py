@@ -72,3 +72,20 @@ def test_one_hip_runtime_in_the_process():
             % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.stdout.split() == ["1", "1"], out.stdout + out.stderr
+
+
+def test_argument_errors_without_gpu():
+    """The entry points reject bad arguments before any device call: a null
+    handle, negative sizes, a null handle array."""
+    import ctypes
+    from paper_2510_07989_amd import _lib
+    lib = _lib.load()
+    st = (ctypes.c_int32 * 2)()
+    assert lib.mot_run_batch(None, 2, 10, st) == _lib.MOT_EINVAL
+    assert lib.mot_run_batch(None, -1, 10, st) == _lib.MOT_EINVAL
+    hs = (ctypes.c_void_p * 2)(None, None)
+    assert lib.mot_run_batch(hs, 2, 10, st) == _lib.MOT_EINVAL       # null handles
+    assert lib.mot_run_batch(hs, 0, 10, st) == _lib.MOT_OK           # nothing to march
+    assert lib.mot_get_steps(None, 0, 1, None, None, None, 0) == _lib.MOT_EINVAL
+    assert lib.mot_far_field(None, 0, 1, 0.1, 0, None, None, None) == _lib.MOT_EINVAL
+    assert lib.mot_run(None, 1, None, None, None, 0, None) == _lib.MOT_EINVAL
