@@ -9,9 +9,10 @@ from tests._problems import problem, oracle
 pytestmark = pytest.mark.gpu
 
 # FP64 inverse; FP32 inverse (halted steps finished on the host); 16 plane
-# waves; host-waited steps (not speculative)
+# waves; host-waited steps (not speculative); graph replay; mixed precision
 CASES = [("sphere_480", dict(precond=2)), ("tiny_torus", dict(precond=1)),
-         ("sphere_480_r16", dict(precond=2)), ("tiny_box", dict(precond=2, spec_window=-1))]
+         ("sphere_480_r16", dict(precond=2)), ("tiny_box", dict(precond=2, spec_window=-1)),
+         ("sphere_480", dict(precond=2, graph=1)), ("sphere_480_r16", dict(precond=2, precision=1))]
 
 
 def _solver(name, opts, stream=True):
@@ -59,6 +60,8 @@ def test_batch_equals_alone(streams):
         s.close()
     ref = oracle("sphere_480").run(300)
     assert _rel(alone[0][0]["w"], ref["W"]) < 1e-10
+    if streams:
+        assert alone[4][1]["graph_windows"] >= 1            # the graph case replayed windows
 
 
 def test_batch_arguments():
