@@ -1459,7 +1459,7 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
             int32_t out_on_device, mot_step_info* last) {
     if (!h) return MOT_EINVAL;
     if (nsteps < 0) return mot_fail(h, MOT_EINVAL, "nsteps < 0");
-    if ((w_out || loop_out || star_out) && (!h->hist || h->k + nsteps > h->hist_cap))
+    if ((w_out || loop_out || star_out) && (!h->hist || (int64_t)h->k + nsteps > h->hist_cap))
         return mot_fail(h, MOT_EINVAL, "outputs need keep_history and max_steps >= steps taken");
     int s0 = h->k;
     int worst = MOT_OK;
@@ -1521,9 +1521,10 @@ static int emit_steps(mot_handle* h, int s0, int nsteps, double* w_out, double* 
 int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, double* loop_out,
                   double* star_out, int32_t out_on_device) {
     if (!h) return MOT_EINVAL;
-    if (first < 0 || count < 0 || first + count > h->k)
+    const int64_t end = (int64_t)first + count;
+    if (first < 0 || count < 0 || end > h->k)
         return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be read");
-    if (!h->hist || first + count > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
     if (count == 0 || !(w_out || loop_out || star_out)) return MOT_OK;
     return emit_steps(h, first, count, w_out, loop_out, star_out, out_on_device, MOT_OK);
 }
@@ -1531,9 +1532,10 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
 int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int32_t ndir, const double* dirs,
                   double* field_out, double* spec_out) {
     if (!h) return MOT_EINVAL;
-    if (first < 0 || count < 1 || first + count > h->k)
+    const int64_t end = (int64_t)first + count;
+    if (first < 0 || count < 1 || end > h->k)
         return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be transformed");
-    if (!h->hist || first + count > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
     if (!(freq >= 0) || !std::isfinite(freq)) return mot_fail(h, MOT_EINVAL, "frequency must be finite and >= 0");
     if (ndir < 0 || (ndir > 0 && (!dirs || !field_out)) || ndir > 65535)
         return mot_fail(h, MOT_EINVAL, "bad direction count or missing direction/field arrays");
