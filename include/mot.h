@@ -227,8 +227,9 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt,
  * T_max scalings and the media sum of eq. (PMCHWT).  Once the twelve blocks
  * of lag i (or the subset its range requires) have arrived, Q_i is folded on
  * the device and the raw blocks are dropped.  A lag outside its family's
- * range is MOT_EINVAL (the truncation is part of the method); uploading a
- * block twice is MOT_ESTATE. */
+ * range is MOT_EINVAL (the truncation is part of the method), so is a block
+ * with a non-finite entry (nothing is staged; the block may be sent again);
+ * uploading a block twice is MOT_ESTATE. */
 int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
                 const double* block);
 

@@ -1129,6 +1129,8 @@ int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int3
     if (rc) return rc;
     if (!block) return mot_fail(h, MOT_EINVAL, "NULL block");
     const int ne = h->ne, hs = h->hs;
+    for (size_t i = 0, nn = (size_t)ne * ne; i < nn; ++i)
+        if (!std::isfinite(block[i])) return mot_fail(h, MOT_EINVAL, "non-finite entry in a lag block");
     HIPCHK(h, hipMemcpy2DAsync(h->raw, hs * sizeof(double), block, ne * sizeof(double), ne * sizeof(double), ne,
                                hipMemcpyHostToDevice, h->stream));
     if ((rc = stage_add(h, family, lag, medium, op, h->raw))) return rc;
