@@ -286,6 +286,28 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
 int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int32_t ndir,
                   const double* dirs, double* field_out, double* spec_out);
 
+/* Checkpoint of the march of eq. (MOT) after the steps taken so far, to
+ * resume it later in a handle built from the same inputs: the step counter,
+ * the ring of the last unknowns, the last solution, the batched RHS, the
+ * Krylov state and, with with_history = 1, every kept step (with 0, the last
+ * kept step only, which the star recovery of the next step needs).
+ * mot_checkpoint_size gives the bytes; mot_checkpoint writes them to host
+ * memory buf (size at least that).  Call between marches, with nothing queued
+ * on the handle.  MOT_EINVAL for a null handle or a short buffer. */
+int mot_checkpoint_size(const mot_handle* h, int32_t with_history, uint64_t* bytes);
+int mot_checkpoint(mot_handle* h, int32_t with_history, void* buf, uint64_t size);
+
+/* Resume a march from a checkpoint (host memory): h must be created with the
+ * same mesh, media, dt, waves and options and hold every lag block.  The next
+ * steps then compute exactly what the checkpointed handle would have (the
+ * same launch schedules, fixed by options or chosen by the autotuner in the
+ * same process, give bit-identical results; others differ by summation
+ * order).  Kept steps before the checkpoint's are not held: mot_get_steps and
+ * mot_far_field refuse them.  MOT_EINVAL if buf is not a checkpoint of a
+ * matching problem, is truncated, or holds more kept steps than max_steps;
+ * MOT_ESTATE if a lag block is missing. */
+int mot_restore(mot_handle* h, const void* buf, uint64_t size);
+
 /* nsteps MOT steps (eq. MOT) on each of n independent handles, for serving
  * several scattering problems at once: the handles' windows of queued steps
  * are interleaved across their streams, so small solves share the device

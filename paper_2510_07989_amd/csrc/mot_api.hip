@@ -1165,6 +1165,7 @@ int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, 
 int mot_reset(mot_handle* h) {
     if (!h) return MOT_EINVAL;
     h->k = 0;
+    h->hist_first = 0;
     h->iters_total = 0;
     (void)ev_flush(h, h->ev_hist);
     (void)ev_flush(h, h->ev_q0);
@@ -1463,6 +1464,8 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
     if (nsteps < 0) return mot_fail(h, MOT_EINVAL, "nsteps < 0");
     if ((w_out || loop_out || star_out) && (!h->hist || (int64_t)h->k + nsteps > h->hist_cap))
         return mot_fail(h, MOT_EINVAL, "outputs need keep_history and max_steps >= steps taken");
+    if ((loop_out || star_out) && h->k > 0 && h->k - 1 < h->hist_first)
+        return mot_fail(h, MOT_EINVAL, "the star part needs the previous step, which the restored checkpoint did not hold");
     int s0 = h->k;
     int worst = MOT_OK;
     mot_step_info inf{};
@@ -1527,6 +1530,8 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
     if (first < 0 || count < 0 || end > h->k)
         return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be read");
     if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (count > 0 && first < h->hist_first)
+        return mot_fail(h, MOT_EINVAL, "steps before the restored checkpoint's kept history are not held");
     if (count == 0 || !(w_out || loop_out || star_out)) return MOT_OK;
     return emit_steps(h, first, count, w_out, loop_out, star_out, out_on_device, MOT_OK);
 }
@@ -1538,6 +1543,8 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
     if (first < 0 || count < 1 || end > h->k)
         return mot_fail(h, MOT_EINVAL, "steps out of range: only steps already taken can be transformed");
     if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (first < h->hist_first)
+        return mot_fail(h, MOT_EINVAL, "steps before the restored checkpoint's kept history are not held");
     if (!(freq >= 0) || !std::isfinite(freq)) return mot_fail(h, MOT_EINVAL, "frequency must be finite and >= 0");
     if (ndir < 0 || (ndir > 0 && (!dirs || !field_out)) || ndir > 65535)
         return mot_fail(h, MOT_EINVAL, "bad direction count or missing direction/field arrays");
@@ -1596,6 +1603,113 @@ int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int3
     release();
     if (e != hipSuccess) return mot_fail(h, MOT_EHIP, hipGetErrorString(e));
     return worst;
+}
+
+// ---- checkpoint and restore of the march ----
+// A checkpoint holds what the next step reads: the step counter, the ring of
+// the last unknowns (eq. (MOT) history), the last solution, both halves of the
+// batched RHS, the Krylov state words, the speculative Arnoldi count, and the
+// kept history (all of it, or the last step, which the star recovery of the
+// next step needs).  Host buffer layout: a header, then those arrays in that
+// order, raw FP64 / struct bytes.
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, ne, n2, R, Rp, nh, B, precision, precond, k, spec_iters, hist_first, hist_count;
+    int32_t pad;
+    double dt, Tmax;
+    int64_t iters_total;
+};
+const char kCkptMagic[8] = {'M', 'O', 'T', 'C', 'K', 'P', 'T', '1'};
+struct CkptLayout {
+    size_t ring, x, rb, gms, hist, total;   // byte counts
+    int hfirst, hcount;
+};
+CkptLayout ckpt_layout(const mot_handle* h, int with_history, int k, int hist_first) {
+    CkptLayout L{};
+    const size_t v = (size_t)h->n2 * h->Rp * sizeof(double);
+    L.ring = (size_t)h->nh * v;
+    L.x = v;
+    L.rb = (size_t)4 * h->ne * h->B * h->Rp * sizeof(double);
+    L.gms = (h->Rp > 1 ? (size_t)h->Rp : 0) * sizeof(GmState);
+    if (!h->hist || k == 0) { L.hfirst = k; L.hcount = 0; }
+    else if (with_history) { L.hfirst = hist_first; L.hcount = k - hist_first; }
+    else { L.hfirst = k - 1; L.hcount = 1; }
+    L.hist = (size_t)L.hcount * v;
+    L.total = sizeof(CkptHeader) + L.ring + L.x + L.rb + sizeof(GmState) + L.gms + L.hist;
+    return L;
+}
+}  // namespace
+
+int mot_checkpoint_size(const mot_handle* h, int32_t with_history, uint64_t* bytes) {
+    if (!h || !bytes) return MOT_EINVAL;
+    *bytes = ckpt_layout(h, with_history, h->k, h->hist_first).total;
+    return MOT_OK;
+}
+
+int mot_checkpoint(mot_handle* h, int32_t with_history, void* buf, uint64_t size) {
+    if (!h || !buf) return MOT_EINVAL;
+    const CkptLayout L = ckpt_layout(h, with_history, h->k, h->hist_first);
+    if (size < L.total) return mot_fail(h, MOT_EINVAL, "checkpoint buffer too small");
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1; hd.ne = h->ne; hd.n2 = h->n2; hd.R = h->R; hd.Rp = h->Rp; hd.nh = h->nh; hd.B = h->B;
+    hd.precision = h->opt.precision; hd.precond = h->opt.precond; hd.k = h->k; hd.spec_iters = h->spec_iters;
+    hd.hist_first = L.hfirst; hd.hist_count = L.hcount; hd.dt = h->dt; hd.Tmax = h->Tmax;
+    hd.iters_total = h->iters_total;
+    char* p = static_cast<char*>(buf);
+    std::memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    const size_t v = (size_t)h->n2 * h->Rp;
+    hipStream_t s = h->stream;
+    HIPCHK(h, hipMemcpyAsync(p, h->ring, L.ring, hipMemcpyDeviceToHost, s)); p += L.ring;
+    HIPCHK(h, hipMemcpyAsync(p, h->x, L.x, hipMemcpyDeviceToHost, s)); p += L.x;
+    HIPCHK(h, hipMemcpyAsync(p, h->rb, L.rb, hipMemcpyDeviceToHost, s)); p += L.rb;
+    HIPCHK(h, hipMemcpyAsync(p, h->gm, sizeof(GmState), hipMemcpyDeviceToHost, s)); p += sizeof(GmState);
+    if (L.gms) { HIPCHK(h, hipMemcpyAsync(p, h->gms, L.gms, hipMemcpyDeviceToHost, s)); p += L.gms; }
+    if (L.hist) { HIPCHK(h, hipMemcpyAsync(p, h->hist + (size_t)L.hfirst * v, L.hist, hipMemcpyDeviceToHost, s)); }
+    HIPCHK(h, hipStreamSynchronize(s));
+    return MOT_OK;
+}
+
+int mot_restore(mot_handle* h, const void* buf, uint64_t size) {
+    if (!h || !buf) return MOT_EINVAL;
+    if (size < sizeof(CkptHeader)) return mot_fail(h, MOT_EINVAL, "checkpoint too short");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, kCkptMagic, 8) || hd.version != 1) return mot_fail(h, MOT_EINVAL, "not a checkpoint");
+    if (hd.ne != h->ne || hd.n2 != h->n2 || hd.R != h->R || hd.Rp != h->Rp || hd.nh != h->nh || hd.B != h->B ||
+        hd.precision != h->opt.precision || hd.precond != h->opt.precond || hd.dt != h->dt || hd.Tmax != h->Tmax)
+        return mot_fail(h, MOT_EINVAL, "checkpoint taken from a different problem or options");
+    if (!all_folded(h)) return mot_fail(h, MOT_ESTATE, "lag matrices missing: upload every block first");
+    if (hd.k < 0 || hd.spec_iters < 1 || hd.spec_iters > h->M || hd.hist_count < 0 ||
+        hd.hist_first < 0 || (int64_t)hd.hist_first + hd.hist_count != (hd.hist_count ? hd.k : hd.hist_first))
+        return mot_fail(h, MOT_EINVAL, "corrupt checkpoint header");
+    if (hd.hist_count && (!h->hist || hd.k > h->hist_cap))
+        return mot_fail(h, MOT_EINVAL, "checkpoint holds kept steps beyond this handle's kept history");
+    const CkptLayout L = ckpt_layout(h, 1, hd.k, hd.hist_first);
+    const size_t need = L.total - L.hist + (size_t)hd.hist_count * h->n2 * h->Rp * sizeof(double);
+    if (size < need) return mot_fail(h, MOT_EINVAL, "checkpoint truncated");
+    const char* p = static_cast<const char*>(buf) + sizeof hd;
+    const size_t v = (size_t)h->n2 * h->Rp;
+    hipStream_t s = h->stream;
+    HIPCHK(h, hipMemcpyAsync(h->ring, p, L.ring, hipMemcpyHostToDevice, s)); p += L.ring;
+    HIPCHK(h, hipMemcpyAsync(h->x, p, L.x, hipMemcpyHostToDevice, s)); p += L.x;
+    HIPCHK(h, hipMemcpyAsync(h->rb, p, L.rb, hipMemcpyHostToDevice, s)); p += L.rb;
+    HIPCHK(h, hipMemcpyAsync(h->gm, p, sizeof(GmState), hipMemcpyHostToDevice, s)); p += sizeof(GmState);
+    if (L.gms) { HIPCHK(h, hipMemcpyAsync(h->gms, p, L.gms, hipMemcpyHostToDevice, s)); p += L.gms; }
+    if (hd.hist_count)
+        HIPCHK(h, hipMemcpyAsync(h->hist + (size_t)hd.hist_first * v, p, (size_t)hd.hist_count * v * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+    motk_step::set_step(h, hd.k);
+    motk_step::clear_halt(h);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->k = hd.k;
+    h->spec_iters = hd.spec_iters;
+    h->iters_total = hd.iters_total;
+    h->hist_first = hd.hist_count ? hd.hist_first : hd.k;
+    return MOT_OK;
 }
 
 // Several independent marches advanced together: every handle's speculative

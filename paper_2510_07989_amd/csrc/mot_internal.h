@@ -139,6 +139,7 @@ struct mot_handle {
     double* ring = nullptr;          // [nh][n2][R]
     double* hist = nullptr;          // [max_steps][n2][R]
     int hist_cap = 0;
+    int hist_first = 0;              // first kept step that holds data (after a restore without history)
     int B = 128;                     // steps per RHS batch
     // launch schedules of the one-RHS streaming products (fixed by options or
     // picked by the autotuner):  1, 2, 4: that many wavefronts share one

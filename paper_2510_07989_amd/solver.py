@@ -176,6 +176,19 @@ class Solver:
         self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
         return dict(spec=spec[..., 0] + 1j * spec[..., 1], field=(field[..., 0] + 1j * field[..., 1])[:nd], rc=rc)
 
+    def checkpoint(self, with_history=True):
+        """State of the march after the steps taken so far (numpy uint8 buffer)."""
+        n = ctypes.c_uint64()
+        self._check(self._lib.mot_checkpoint_size(self._h, 1 if with_history else 0, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self._lib.mot_checkpoint(self._h, 1 if with_history else 0, _ptr(buf), n.value))
+        return buf
+
+    def restore(self, buf):
+        """Resume the march from a checkpoint of a solver built from the same inputs."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._lib.mot_restore(self._h, _ptr(buf), buf.size))
+
     def matrix(self, which, lag=0):
         shape = (self.n, self.n) if which == 0 else ((self.n, self.nrhs) if which == 6 else (self.ne, self.ne))
         out = np.empty(shape)

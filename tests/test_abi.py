@@ -89,3 +89,7 @@ def test_argument_errors_without_gpu():
     assert lib.mot_get_steps(None, 0, 1, None, None, None, 0) == _lib.MOT_EINVAL
     assert lib.mot_far_field(None, 0, 1, 0.1, 0, None, None, None) == _lib.MOT_EINVAL
     assert lib.mot_run(None, 1, None, None, None, 0, None) == _lib.MOT_EINVAL
+    n = ctypes.c_uint64()
+    assert lib.mot_checkpoint_size(None, 1, ctypes.byref(n)) == _lib.MOT_EINVAL
+    assert lib.mot_checkpoint(None, 1, None, 0) == _lib.MOT_EINVAL
+    assert lib.mot_restore(None, None, 0) == _lib.MOT_EINVAL
