@@ -154,6 +154,22 @@ def history_kernel_name(R, precision, mix_group, sched_hist=11):
 PROFILE_EVERY = 16
 
 
+def late_time(s, nsteps):
+    """Sec. VI-A on the whole kept march: ||w_k|| of every step from the
+    device (mot_step_norms); the least-squares slope of log10 ||w_k|| over the
+    last min(2000, nsteps/5) steps and the last norm against the peak."""
+    import numpy as np
+    nr = s.step_norms(0, nsteps)[:, 0]
+    m = min(2000, nsteps // 5)
+    tail = np.log10(nr[-m:] + 1e-300)
+    slope = float(np.polyfit(np.arange(m), tail, 1)[0])
+    out = {"steps": nsteps, "window": m, "log10_slope_per_step": slope,
+           "last_over_peak": float(nr[-1] / nr.max()), "peak_step": int(np.argmax(nr)) + 1}
+    log("late time: %d steps, log10 ||w|| slope %.3e per step over the last %d, last / peak %.2e"
+        % (nsteps, slope, m, out["last_over_peak"]))
+    return out
+
+
 def far_field_timing(s, nsteps, n, R, freq):
     """mot_far_field over every kept step of a march: the spectra of the loop
     and star currents at freq and the far field in 181 directions of one
@@ -203,7 +219,14 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     b = s.info()
-    ff = far_field_timing(s, W_ + K, 2 * prob["E"].shape[0], R, far) if far is not None else None
+    ff = late = None
+    if far is not None:
+        # diagnostics after the timed march: a failure here must not cost the step-rate line
+        try:
+            ff = far_field_timing(s, W_ + K, 2 * prob["E"].shape[0], R, far)
+            late = late_time(s, W_ + K)
+        except Exception as e:  # noqa: BLE001
+            log("far-field / late-time diagnostics failed: %r" % (e,))
     s.close()
     ne, n, L = prob["E"].shape[0], 2 * prob["E"].shape[0], b["nlags"]
     hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
@@ -224,7 +247,7 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
                iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
                q0_launches=PROFILE_EVERY * (b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
                dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
-               device_gb=inf0["device_bytes"] / 1e9, far_field=ff,
+               device_gb=inf0["device_bytes"] / 1e9, far_field=ff, late_time=late,
                schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
                          "autotuned": bool(inf0["tuned"] and opts.autotune), "tune_ms": round(inf0["tune_ms"], 1)})
     log("[%s R=%d] timed %d steps in %.3f s: %.1f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
@@ -333,6 +356,8 @@ def main():
     }
     if m["far_field"] is not None:
         result["far_field"] = m["far_field"]
+    if m["late_time"] is not None:
+        result["late_time"] = m["late_time"]
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.cpu_budget, min(W_, 400))

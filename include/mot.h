@@ -262,6 +262,12 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out,
 int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, double* loop_out,
                   double* star_out, int32_t out_on_device);
 
+/* Euclidean norm of the unknowns w_s = (u_s; v_s) of each kept step s = first
+ * .. first+count-1 and wave: the late-time behaviour of the march of eq. (MOT)
+ * (Sec. VI-A), without copying the history out.  norms: host [count][nrhs].
+ * MOT_EINVAL for a range not taken or not kept. */
+int mot_step_norms(mot_handle* h, int32_t first, int32_t count, double* norms);
+
 /* Spectra and far fields of the currents of kept steps (Section VI, far-field
  * computation, on eq. (dis_jm)), the loop and star parts kept apart so that
  * neither is lost in the other at low frequency.  Steps first ..

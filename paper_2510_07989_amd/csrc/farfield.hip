@@ -240,9 +240,41 @@ __global__ void k_ff_field(int ndir, int R, int nz, double k, const double* __re
     }
 }
 
+// ||w_s|| over the unknowns of each kept step s and wave r (the late-time
+// behaviour of eq. (MOT)): one workgroup per step, norms [count][R]
+__global__ __launch_bounds__(256) void k_step_norms(int ne, int hs, int n2, int R, int Rp, int first,
+                                                    const double* __restrict__ hist, double* __restrict__ norms) {
+    const int s = blockIdx.x;
+    const double* w = hist + (size_t)(first + s) * n2 * Rp;
+    __shared__ double red[4];
+    for (int r = 0; r < R; ++r) {
+        double a = 0;
+        for (int i = threadIdx.x; i < 2 * ne; i += blockDim.x) {
+            const int row = i < ne ? i : hs + (i - ne);
+            const double v = w[(size_t)row * Rp + r];
+            a = fma(v, v, a);
+        }
+        a = ff_wave_sum(a);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+            norms[(size_t)s * R + r] = sqrt(t);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 namespace motk_ff {
+
+void step_norms(mot_handle* h, int first, int count, double* norms) {
+    hipLaunchKernelGGL(k_step_norms, dim3(count), dim3(256), 0, h->stream, h->ne, h->hs, h->n2, h->R, h->Rp, first,
+                       h->hist, norms);
+}
+
 
 void phase(mot_handle* h, int first, int count, double omega, double* phi) {
     hipLaunchKernelGGL(k_ff_phase, dim3((count + 255) / 256), dim3(256), 0, h->stream, first, count, omega, h->dt,

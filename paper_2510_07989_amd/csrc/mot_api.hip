@@ -1536,6 +1536,27 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
     return emit_steps(h, first, count, w_out, loop_out, star_out, out_on_device, MOT_OK);
 }
 
+int mot_step_norms(mot_handle* h, int32_t first, int32_t count, double* norms) {
+    if (!h) return MOT_EINVAL;
+    const int64_t end = (int64_t)first + count;
+    if (first < 0 || count < 0 || end > h->k || (!norms && count > 0))
+        return mot_fail(h, MOT_EINVAL, "steps out of range or no output array");
+    if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (count > 0 && first < h->hist_first)
+        return mot_fail(h, MOT_EINVAL, "steps before the restored checkpoint's kept history are not held");
+    if (count == 0) return MOT_OK;
+    double* d = nullptr;
+    int rc;
+    if ((rc = dalloc(h, &d, (size_t)count * h->R, false))) return rc;
+    motk_ff::step_norms(h, first, count, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(norms, d, sizeof(double) * count * h->R, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    dfree(h, d);
+    if (e != hipSuccess) return mot_fail(h, MOT_EHIP, hipGetErrorString(e));
+    return MOT_OK;
+}
+
 int mot_far_field(mot_handle* h, int32_t first, int32_t count, double freq, int32_t ndir, const double* dirs,
                   double* field_out, double* spec_out) {
     if (!h) return MOT_EINVAL;

@@ -225,6 +225,7 @@ void spectrum(mot_handle* h, int first, int count, int chunk, int nchunk, const 
 void reduce(mot_handle* h, int nchunk, const double* part, double* X);
 void project(mot_handle* h, const double* X, double* PX);                      // PX = P^Sigma X (dense P^Sigma)
 void parts(mot_handle* h, const double* X, const double* PX, double* spec);
+void step_norms(mot_handle* h, int first, int count, double* norms);          // norms [count][R]
 int field_slices(const mot_handle* h);                                          // edge slices of the field pass
 void field(mot_handle* h, double k, int ndir, const double* dirs, const double* spec, double* part, double* out);
 }  // namespace motk_ff

@@ -176,6 +176,12 @@ class Solver:
         self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
         return dict(spec=spec[..., 0] + 1j * spec[..., 1], field=(field[..., 0] + 1j * field[..., 1])[:nd], rc=rc)
 
+    def step_norms(self, first, count):
+        """||w_s|| of the kept steps first .. first+count-1, shape (count, nrhs)."""
+        out = np.empty((count, self.nrhs))
+        self._check(self._lib.mot_step_norms(self._h, int(first), int(count), _ptr(out)))
+        return out
+
     def checkpoint(self, with_history=True):
         """State of the march after the steps taken so far (numpy uint8 buffer)."""
         n = ctypes.c_uint64()

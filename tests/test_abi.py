@@ -93,3 +93,4 @@ def test_argument_errors_without_gpu():
     assert lib.mot_checkpoint_size(None, 1, ctypes.byref(n)) == _lib.MOT_EINVAL
     assert lib.mot_checkpoint(None, 1, None, 0) == _lib.MOT_EINVAL
     assert lib.mot_restore(None, None, 0) == _lib.MOT_EINVAL
+    assert lib.mot_step_norms(None, 0, 1, None) == _lib.MOT_EINVAL

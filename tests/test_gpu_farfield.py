@@ -119,3 +119,23 @@ def test_gpu_far_field_matches_mie():
                 keep = ref > 1e-3 * ref.max()
                 assert np.allclose(got[keep] / ref[keep], vol_ratio, rtol=2e-3)
     s.close()
+
+
+def test_step_norms_match_kept_unknowns():
+    """mot_step_norms against the norms of the unknowns read back, and the
+    late-time decay of the march they show (Sec. VI-A)."""
+    import paper_2510_07989_amd as p
+    for name in ("sphere_480", "sphere_480_r16"):
+        prob = problem(name)
+        s = _solver(name)
+        n = 200 if name == "sphere_480" else 120
+        out = s.run(n, loop=False, star=False)
+        nr = s.step_norms(0, n)
+        ref = np.linalg.norm(out["w"], axis=1)              # (n, nrhs)
+        assert np.allclose(nr, ref, rtol=1e-13, atol=0)
+        assert np.allclose(s.step_norms(37, 11), ref[37:48], rtol=1e-13, atol=0)
+        late = np.log10(nr[-n // 4:, 0])
+        assert np.polyfit(np.arange(late.size), late, 1)[0] < 0
+        with pytest.raises(p.MotError):
+            s.step_norms(n - 5, 6)
+        s.close()
