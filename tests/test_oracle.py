@@ -421,3 +421,20 @@ def test_sphere_far_field_matches_mie():
                 # whole remaining difference
                 keep = ref > 1e-3 * ref.max()
                 assert np.allclose(got[keep] / ref[keep], vol_ratio, rtol=2e-3), (ph, f)
+
+
+def test_oracle_triangle_rule_degree_five():
+    """The oracle's 7-point rule integrates every barycentric monomial of
+    degree <= 5 exactly: int_T l1^a l2^b l3^c = 2 A a! b! c! / (a+b+c+2)!,
+    and misses a degree-6 one (so it is the degree-5 rule, not a finer one)."""
+    from math import factorial
+    L, W = mo.tri_rule7()
+    assert abs(W.sum() - 1) < 1e-15
+    for a in range(6):
+        for b in range(6 - a):
+            for c in range(6 - a - b):
+                q = np.sum(W * L[:, 0] ** a * L[:, 1] ** b * L[:, 2] ** c)
+                ex = 2.0 * factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 2)
+                assert abs(q - ex) < 1e-15, (a, b, c)
+    q6 = np.sum(W * L[:, 0] ** 6)
+    assert abs(q6 - 2.0 * factorial(6) / factorial(8)) > 1e-6
