@@ -94,3 +94,34 @@ def test_argument_errors_without_gpu():
     assert lib.mot_checkpoint(None, 1, None, 0) == _lib.MOT_EINVAL
     assert lib.mot_restore(None, None, 0) == _lib.MOT_EINVAL
     assert lib.mot_step_norms(None, 0, 1, None) == _lib.MOT_EINVAL
+
+
+def test_header_is_c99_and_links_from_c(tmp_path):
+    """include/mot.h is plain C: a C99 program (pedantic, warnings as errors)
+    includes it, links libmot.so and calls an entry point that needs no GPU."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lib_dir = os.path.join(ROOT, "paper_2510_07989_amd")
+    if not os.path.exists(os.path.join(lib_dir, "libmot.so")):
+        pytest.skip("libmot.so not built")
+    src = tmp_path / "use_mot.c"
+    src.write_text(
+        '#include "mot.h"\n'
+        "int main(void) {\n"
+        "    mot_options o;\n"
+        "    uint64_t n = 0;\n"
+        "    mot_default_options(&o);\n"
+        "    if (o.gmres_restart != 40 || o.autotune != 1) return 1;\n"
+        "    if (mot_checkpoint_size(NULL, 1, &n) != MOT_EINVAL) return 2;\n"
+        "    if (mot_run_batch(NULL, 1, 1, NULL) != MOT_EINVAL) return 3;\n"
+        "    return 0;\n"
+        "}\n")
+    exe = tmp_path / "use_mot"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", lib_dir, "-l:libmot.so", "-Wl,-rpath," + lib_dir],
+                   check=True, capture_output=True, timeout=120)
+    out = subprocess.run([str(exe)], capture_output=True, timeout=120)
+    assert out.returncode == 0, out.stderr
