@@ -307,8 +307,8 @@ def main():
     ap.add_argument("--mix-group", type=int, default=4, help="precision 2: summation indices per FP32 sum")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the MOT march of one problem runs on one device "
-              "(multi-GPU sharding is described in DESIGN.md, not run).", file=sys.stderr)
+        print("bench.py measures one GPU: the MOT march of one problem runs on one device; "
+              "runs on several GPUs are not part of this benchmark.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
