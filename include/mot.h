@@ -211,6 +211,10 @@ void mot_default_options(mot_options* opt);
  *             BC basis (T0s SPD, T0h PSD).
  *   G: CSR [ne][ne] host, G_mn = <n x f_m, g_n>; g_rowptr has ne+1 entries.
  *   waves: nrhs plane waves (host).   stream: hipStream_t or NULL.
+ * Every host input is checked before anything is allocated (mesh integers
+ * and orientation, finite vertices and static blocks, Gram CSR row pointers
+ * non-decreasing and columns in range, each wave with width > 0 and unit,
+ * orthogonal pol and dir within 1e-6).
  * Returns MOT_EINVAL on a bad mesh or argument, MOT_ENOMEM, MOT_ENOCONV if a
  * setup solve fails to converge, MOT_EHIP. */
 int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt,

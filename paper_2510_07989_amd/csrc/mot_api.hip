@@ -874,7 +874,8 @@ int mot_footprint(const mot_mesh* mesh, double eps_r, double mu_r, double dt, in
     if (!mesh || !mesh->verts || !resident_bytes || !peak_bytes) return mot_fail(nullptr, MOT_EINVAL, "null argument");
     if (mesh->nv <= 0 || mesh->nf <= 0 || mesh->ne <= 0 || nrhs < 1 || nrhs > 64 || gram_nnz < 0)
         return mot_fail(nullptr, MOT_EINVAL, "bad sizes");
-    if (!(dt > 0) || !(eps_r > 0) || !(mu_r > 0)) return mot_fail(nullptr, MOT_EINVAL, "dt, eps_r and mu_r must be > 0");
+    if (!(dt > 0) || !(eps_r > 0) || !(mu_r > 0) || !std::isfinite(eps_r + mu_r + dt))
+        return mot_fail(nullptr, MOT_EINVAL, "dt, eps_r and mu_r must be finite and > 0");
     mot_handle h;
     if (opt) h.opt = *opt; else mot_default_options(&h.opt);
     plan_dims(&h, mesh->nv, mesh->nf, mesh->ne, nrhs, mesh->verts, eps_r, mu_r, dt);
@@ -960,6 +961,25 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     if (chi > 2 || chi % 2) return mot_fail(nullptr, MOT_EINVAL, "Euler characteristic of a closed orientable surface expected");
     for (size_t i = 0; i < (size_t)ne * ne; ++i)
         if (!std::isfinite(T0s[i]) || !std::isfinite(T0h[i])) return mot_fail(nullptr, MOT_EINVAL, "non-finite static block");
+    for (int i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(mesh->verts[i])) return mot_fail(nullptr, MOT_EINVAL, "non-finite vertex coordinate");
+    // Gram matrix CSR (host, before anything is allocated)
+    if (g_rowptr[0] != 0 || g_rowptr[ne] <= 0) return mot_fail(nullptr, MOT_EINVAL, "bad Gram CSR row pointers");
+    for (int r = 0; r < ne; ++r)
+        if (g_rowptr[r + 1] < g_rowptr[r]) return mot_fail(nullptr, MOT_EINVAL, "Gram CSR row pointers decrease");
+    for (int i = 0; i < g_rowptr[ne]; ++i)
+        if (g_col[i] < 0 || g_col[i] >= ne || !std::isfinite(g_val[i]))
+            return mot_fail(nullptr, MOT_EINVAL, "bad Gram CSR entry");
+    // plane waves (eq. (hin)): unit direction and polarisation, orthogonal
+    for (int r = 0; r < nrhs; ++r) {
+        const mot_planewave& w = waves[r];
+        double pp = 0, kk = 0, pk = 0;
+        for (int d = 0; d < 3; ++d) { pp += w.pol[d] * w.pol[d]; kk += w.dir[d] * w.dir[d]; pk += w.pol[d] * w.dir[d]; }
+        if (!(w.width > 0) || !std::isfinite(w.width + w.t0 + w.amp + pp + kk) || std::fabs(pp - 1) > 1e-6 ||
+            std::fabs(kk - 1) > 1e-6 || std::fabs(pk) > 1e-6)
+            return mot_fail(nullptr, MOT_EINVAL, "bad plane wave " + std::to_string(r) +
+                                                 ": width > 0, unit pol and dir, pol . dir = 0 expected");
+    }
 
     mot_handle* h = new mot_handle();
     if (opt) h->opt = *opt; else mot_default_options(&h->opt);
@@ -979,10 +999,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     }
     // ---- Gram matrix and its transpose (CSR) ----
     {
-        int nnz = g_rowptr[ne];
-        if (nnz <= 0 || g_rowptr[0] != 0) { h->err = "bad Gram CSR"; return bail(MOT_EINVAL); }
-        for (int i = 0; i < nnz; ++i)
-            if (g_col[i] < 0 || g_col[i] >= ne || !std::isfinite(g_val[i])) { h->err = "bad Gram CSR entry"; return bail(MOT_EINVAL); }
+        int nnz = g_rowptr[ne];          // validated above
         std::vector<int> tp(ne + 1, 0), tc(nnz);
         std::vector<double> tv(nnz);
         for (int i = 0; i < nnz; ++i) tp[g_col[i] + 1]++;
@@ -1031,8 +1048,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
             return bail(rc);
         std::vector<double> wv(9 * nrhs), tc(nrhs);
         for (int r = 0; r < nrhs; ++r) {
-            const mot_planewave& w = waves[r];
-            if (!(w.width > 0) || !std::isfinite(w.t0 + w.amp)) { h->err = "bad plane wave"; return bail(MOT_EINVAL); }
+            const mot_planewave& w = waves[r];  // validated above
             wv[9 * r] = w.amp;
             for (int d = 0; d < 3; ++d) { wv[9 * r + 1 + d] = w.pol[d]; wv[9 * r + 4 + d] = w.dir[d]; }
             wv[9 * r + 7] = w.width;

@@ -125,3 +125,60 @@ def test_header_is_c99_and_links_from_c(tmp_path):
                    check=True, capture_output=True, timeout=120)
     out = subprocess.run([str(exe)], capture_output=True, timeout=120)
     assert out.returncode == 0, out.stderr
+
+
+def test_create_rejects_bad_inputs_without_gpu():
+    """mot_create checks every host input before it allocates anything, so
+    each malformed input below is MOT_EINVAL on a host without a GPU."""
+    import ctypes
+    import numpy as np
+    from paper_2510_07989_amd import _lib
+    from paper_2510_07989_amd.solver import _ptr, _csr
+    from tests._problems import problem
+    lib = _lib.load()
+    prob = problem("tiny")
+    V = np.ascontiguousarray(prob["V"], dtype=np.float64)
+    F = np.ascontiguousarray(prob["F"], dtype=np.int32)
+    E = np.ascontiguousarray(prob["E"], dtype=np.int32)
+    ne = E.shape[0]
+    T0 = np.ascontiguousarray(prob["T0s"], dtype=np.float64)
+    T1 = np.ascontiguousarray(prob["T0h"], dtype=np.float64)
+    rp, col, val = _csr(prob["G"])
+
+    def wave(**kw):
+        w = _lib.MotPlaneWave()
+        w.amp, w.width, w.t0 = 1.0, 4.0, 6.0
+        w.pol[:] = (1.0, 0.0, 0.0)
+        w.dir[:] = (0.0, 0.0, -1.0)
+        for k, v in kw.items():
+            if k in ("pol", "dir"):
+                getattr(w, k)[:] = v
+            else:
+                setattr(w, k, v)
+        return w
+
+    def create(V=V, F=F, E=E, rp=rp, col=col, val=val, w=None, dt=0.5):
+        m = _lib.MotMesh(V.shape[0], F.shape[0], E.shape[0], _ptr(V), _ptr(F), _ptr(E))
+        h = ctypes.c_void_p()
+        ws = (_lib.MotPlaneWave * 1)(w or wave())
+        o = _lib.MotOptions()
+        lib.mot_default_options(ctypes.byref(o))
+        return lib.mot_create(ctypes.byref(m), 2.0, 1.0, dt, _ptr(T0), _ptr(T1), _ptr(rp), _ptr(col), _ptr(val), 1,
+                              ws, ctypes.byref(o), None, ctypes.byref(h))
+
+    bad_v = V.copy(); bad_v[3, 1] = np.nan
+    bad_f = F.copy(); bad_f[2, 0] = -1
+    bad_e = E.copy(); bad_e[4, 2] = F.shape[0] + 3
+    flip = E.copy(); flip[0, [0, 1]] = flip[0, [1, 0]]          # orientation broken
+    bad_rp = rp.copy(); bad_rp[5], bad_rp[6] = bad_rp[6], bad_rp[5] - 1
+    bad_col = col.copy(); bad_col[7] = ne
+    bad_val = val.copy(); bad_val[0] = np.inf
+    cases = {
+        "vertex": dict(V=bad_v), "triangle": dict(F=bad_f), "edge": dict(E=bad_e), "orientation": dict(E=flip),
+        "rowptr": dict(rp=bad_rp), "column": dict(col=bad_col), "value": dict(val=bad_val),
+        "width": dict(w=wave(width=-1.0)), "pol": dict(w=wave(pol=(1.0, 0.1, 0.0))),
+        "dir": dict(w=wave(dir=(0.0, 0.0, -2.0))), "pol.dir": dict(w=wave(pol=(0.0, 0.0, 1.0))),
+        "dt": dict(dt=float("inf")),
+    }
+    for what, kw in cases.items():
+        assert create(**kw) == _lib.MOT_EINVAL, what
