@@ -135,9 +135,7 @@ def test_retarded_blocks_structure():
     Lam, Sig = geo.incidence(E, V.shape[0], F.shape[0])
     for k, X in B.items():
         assert np.allclose(X, np.transpose(X, (0, 2, 1)))                # Galerkin symmetry
-    # the hyper-singular part vanishes on loops: T_hat Lambda depends only on the
-    # f.f part, so T_hat - (f.f part) ... check T_h and T_tilde are loop/star mixed
-    # while the div-div term of T_hat annihilates RWG loops from both sides:
+    # asking for one family alone gives the same blocks
     D = B["T_hat"]
     Bs = fx.retarded_blocks(V, F, E, dt, 1.0, 6, 7, 5, which=("T_hat",))
     assert np.allclose(D, Bs["T_hat"])
@@ -167,3 +165,21 @@ def test_star_pyramid_shape():
     vol = np.einsum("ij,ij->i", p0, np.cross(p1, p2)).sum() / 6.0
     star_area = 12 * 2 * 0.5 * 1.0 * 0.3 * np.sin(np.radians(15))
     assert np.isclose(vol, star_area * 0.5 / 3)
+
+
+def test_tilde_family_tail():
+    """Section V-B, tilde family: once i dt exceeds the diameter (c = 1), the
+    retarded time of every pair is past the pulse, so T~_i = 0 (p0 is zero
+    there) and K~_i is one constant matrix (the integrated pulse has reached
+    dt): the reason the tilde family is truncated at k_max - 1."""
+    from fixture.problem import make_mesh
+    V, F, E = make_mesh(("icosphere", 1))
+    dt = 0.5
+    B = fx.retarded_blocks(V, F, E, dt, 1.0, 6, 7, 9)
+    first = int(np.ceil(geo.diameter(V) / dt))
+    Kt, Tt = B["K_tilde"], B["T_tilde"]
+    assert abs(Kt[first]).max() > 0
+    for i in range(first, Kt.shape[0]):
+        assert abs(Tt[i]).max() == 0.0
+        assert np.allclose(Kt[i], Kt[first], rtol=0, atol=1e-15 * abs(Kt[first]).max())
+    assert abs(Kt[first - 1] - Kt[first]).max() > 1e-3 * abs(Kt[first]).max()    # still varying before
