@@ -356,7 +356,8 @@ int mot_footprint(const mot_mesh* mesh, double eps_r, double mu_r, double dt, in
                   int64_t gram_nnz, const mot_options* opt, uint64_t* resident_bytes,
                   uint64_t* peak_bytes);
 
-/* Restart the march at step 0 (keeps every operator). */
+/* Restart the march at step 0 (keeps every operator); the march that follows
+ * is the one a new handle would compute. */
 int mot_reset(mot_handle* h);
 
 void mot_destroy(mot_handle* h);

@@ -1183,6 +1183,7 @@ int mot_reset(mot_handle* h) {
     h->k = 0;
     h->hist_first = 0;
     h->iters_total = 0;
+    h->spec_iters = 1;               // as a new handle: the same Arnoldi counts, the same bits
     (void)ev_flush(h, h->ev_hist);
     (void)ev_flush(h, h->ev_q0);
     h->ev_hist.ms = h->ev_q0.ms = 0;

@@ -88,6 +88,22 @@ def test_step_api_matches_run():
     s.close(); s2.close()
 
 
+def test_reset_after_halted_windows_equals_new_handle():
+    """FP32 approximate inverse: speculative windows halt and raise the
+    Arnoldi count per step; after mot_reset the march is again bit for bit
+    that of a new handle."""
+    s = _solver("sphere_480", precond=1)
+    s.run(300, w=False, loop=False, star=False)
+    s.reset()
+    out = s.run(300)
+    s2 = _solver("sphere_480", precond=1)
+    out2 = s2.run(300)
+    for k in ("w", "loop", "star"):
+        assert np.array_equal(out[k], out2[k]), k
+    assert s.info()["gmres_iters_total"] == s2.info()["gmres_iters_total"]
+    s.close(); s2.close()
+
+
 def test_lag_errors():
     import paper_2510_07989_amd as p
     from paper_2510_07989_amd import _lib as L
