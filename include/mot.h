@@ -324,8 +324,9 @@ int mot_restore(mot_handle* h, const void* buf, uint64_t size);
  * instead of taking turns.  Every handle computes exactly what mot_run(h,
  * nsteps, NULL, NULL, NULL, 0, NULL) would; mot_get_steps reads the outputs
  * afterwards (keep_history).  Handles on distinct non-default streams
- * overlap; handles sharing a stream
- * run in turn.  hs: n distinct handles (host array); status: n codes out,
+ * overlap; handles sharing a stream run in turn.  The call drives every
+ * handle from the calling thread: no other thread may use them meanwhile.
+ * hs: n distinct handles (host array); status: n codes out,
  * each handle's worst step code (MOT_OK, MOT_ENOCONV) or its error, after
  * which that handle stops at its last completed step while the others go on.
  * Returns MOT_EINVAL for a bad argument or a repeated handle (nothing run),
