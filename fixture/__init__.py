@@ -28,14 +28,18 @@ _LIB = os.path.join(_HERE, "_assemble.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the assembler (gcc, OpenMP)."""
+def build(force: bool = True, gpu: bool = True) -> str:
+    """Compile the host assembler (gcc, OpenMP) and, with gpu, the device
+    assembler (hipcc, gfx950)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
                "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
+    if gpu:
+        from . import gpu as _gpu
+        _gpu.build(force=force)
     return _LIB
 
 

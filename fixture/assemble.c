@@ -608,3 +608,16 @@ int fx_temporal(double u, double dt, double* out) {
     out[6] = u <= -1 ? 0 : (u <= 0 ? (u + 1) * dt : dt);
     return 0;
 }
+
+/* Gauss-Legendre tables on [0, 1] (nodes, weights) as [MAXGL + 1][MAXGL], row n
+ * holding the n-point rule: shared with the device assembler so that both
+ * build the same point sets. */
+int fx_gl_tables(double* x, double* w) {
+    gl_init();
+    for (int n = 0; n <= MAXGL; ++n)
+        for (int i = 0; i < MAXGL; ++i) {
+            x[n * MAXGL + i] = gl_x[n][i];
+            w[n * MAXGL + i] = gl_w[n][i];
+        }
+    return MAXGL;
+}

@@ -211,27 +211,32 @@ def gram_bc(V, F, E, R):
     """Dense Gram matrix G_mn = <n x f_m, g_n> (Section III).
 
     The integrand is quadratic on every fine triangle, so a degree-2 rule
-    per fine triangle is exact.
+    per fine triangle is exact.  Every BC restriction (fine triangle t, BC
+    function n) meets the three RWG restrictions of t's primal parent; the
+    products are formed for all of them at once and added in restriction
+    order.
     """
     V = np.asarray(V, dtype=np.float64)
     F = np.asarray(F, dtype=np.int64)
-    ne = E.shape[0]
+    ne, nf = E.shape[0], F.shape[0]
     _, nrm = _tri_area_normal(V[F])
     rt, re_, ra, rb = rwg_local(V, F, E)
-    # RWG restrictions grouped by primal triangle
-    by_tri = {}
-    for i in range(rt.size):
-        by_tri.setdefault(int(rt[i]), []).append(i)
+    # the three RWG restrictions of every primal triangle, in restriction order
+    order = np.argsort(rt, kind="stable")
+    counts = np.bincount(rt, minlength=nf)
+    if not np.all(counts == 3):
+        raise ValueError("every primal triangle must carry three RWG restrictions")
+    by_tri = order.reshape(nf, 3)
     Lq, wq = _rule3()
-    G = np.zeros((ne, ne))
     xq = np.einsum("qk,tkd->tqd", Lq, R.fverts)          # (nft, 3, 3)
-    for j in range(R.bc_t.size):
-        t = int(R.bc_t[j])
-        n = int(R.bc_n[j])
-        g = R.bc_a[j] * xq[t] - R.bc_b[j]                  # (3 pts, 3)
-        c = int(R.fparent[t])
-        for i in by_tri[c]:
-            f = ra[i] * xq[t] - rb[i]
-            nxf = np.cross(nrm[c], f)
-            G[re_[i], n] += R.farea[t] * np.dot(wq, np.einsum("qd,qd->q", nxf, g))
+    T = R.bc_t
+    C = R.fparent[T]
+    I3 = by_tri[C]                                        # (nres, 3)
+    X = xq[T]                                             # (nres, 3 pts, 3)
+    g = R.bc_a[:, None, None] * X - R.bc_b[:, None, :]    # (nres, 3 pts, 3)
+    f = ra[I3][:, :, None, None] * X[:, None] - rb[I3][:, :, None, :]   # (nres, 3, 3 pts, 3)
+    nxf = np.cross(nrm[C][:, None, None, :], f)
+    val = R.farea[T][:, None] * np.einsum("q,rkq->rk", wq, np.einsum("rkqd,rqd->rkq", nxf, g))
+    G = np.zeros((ne, ne))
+    np.add.at(G, (re_[I3].ravel(), np.repeat(R.bc_n, 3)), val.ravel())
     return G

@@ -237,9 +237,23 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt,
 int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
                 const double* block);
 
-/* The same with a CSR block (row pointers ne+1, int32 columns, float64 values). */
+/* The same with a CSR block (row pointers ne+1, int32 columns, float64 values;
+ * nnz = rowptr[ne] may be 0, an all-zero block).  Row pointers must start at 0
+ * and not decrease, columns lie in 0..ne-1 and values are finite, else
+ * MOT_EINVAL and nothing is staged. */
 int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
                     const int64_t* rowptr, const int32_t* col, const double* val);
+
+/* The same with a dense block already in device memory (Section V-B blocks
+ * assembled on the GPU, so that large problems never stage their lags on the
+ * host): dblock [ne] rows of ld >= ne float64, row-major, on the handle's
+ * device.  The library reads it on the handle's stream during the call and
+ * keeps no reference; the caller owns it and may free or reuse it when the
+ * call returns.  Work that writes dblock must be complete, or ordered before
+ * the handle's stream, when the call is made.  Same checks and codes as
+ * mot_set_lag; MOT_EINVAL also when dblock is not device memory or ld < ne. */
+int mot_set_lag_device(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
+                       const double* dblock, int64_t ld);
 
 /* One MOT step (eq. MOT): tested incident fields, RHS, history convolution,
  * GMRES on Q_0 (warm start 2 w_{k-1} - w_{k-2}), ring update.  MOT_ESTATE if

@@ -248,18 +248,25 @@ def rhs(pre, Tmax, ebar, Ebar):
 
 
 # ------------------------------------------------------------------ march ---
-def march(Q, rhs_vectors):
+def march(Q, rhs_vectors, lu=None, W0=None):
     """Section V-A eq. (MOT): Q_0 w_i = r_i - sum_{k=1}^{i-1} Q_k w_{i-k},
-    with Q_k = 0 beyond the last stored lag.  rhs_vectors: (N_t, n, R)."""
+    with Q_k = 0 beyond the last stored lag.  rhs_vectors: (N_t, n, R).
+    lu: the LU factorization of Q_0 (scipy.linalg.lu_factor), formed here if
+    None.  W0: (M, n, R) unknowns of the M steps that precede the first of
+    rhs_vectors (none if None), so that a march can be resumed."""
     Nt = rhs_vectors.shape[0]
-    lu = sla.lu_factor(Q[0])
-    W = np.zeros_like(rhs_vectors)
-    for i in range(Nt):                      # step i+1 in the paper's numbering
-        b = rhs_vectors[i].copy()
+    if lu is None:
+        lu = sla.lu_factor(Q[0])
+    M = 0 if W0 is None else W0.shape[0]
+    W = np.zeros((M + Nt,) + rhs_vectors.shape[1:], dtype=rhs_vectors.dtype)
+    if M:
+        W[:M] = W0
+    for i in range(M, M + Nt):               # step i+1 in the paper's numbering
+        b = rhs_vectors[i - M].copy()
         for k in range(1, min(i, len(Q) - 1) + 1):
             b -= Q[k] @ W[i - k]
         W[i] = sla.lu_solve(lu, b)
-    return W
+    return W[M:]
 
 
 def block_toeplitz_solve(Q, rhs_vectors):

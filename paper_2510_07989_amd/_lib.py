@@ -52,7 +52,7 @@ EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr"
            "mot_run", "mot_get_matrix", "mot_get_info", "mot_reset", "mot_destroy",
            "mot_last_error", "mot_footprint", "mot_get_steps", "mot_run_batch",
            "mot_far_field", "mot_checkpoint_size", "mot_checkpoint", "mot_restore",
-           "mot_step_norms"]
+           "mot_step_norms", "mot_set_lag_device"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def load():
                                ctypes.POINTER(_P)]
     lib.mot_create.restype = _I
     lib.mot_set_lag.argtypes = [_P, _I, _I, _I, _I, _P]
+    lib.mot_set_lag_device.argtypes = [_P, _I, _I, _I, _I, _P, ctypes.c_int64]
+    lib.mot_set_lag_device.restype = _I
     lib.mot_set_lag.restype = _I
     lib.mot_set_lag_csr.argtypes = [_P, _I, _I, _I, _I, _P, _P, _P]
     lib.mot_set_lag_csr.restype = _I

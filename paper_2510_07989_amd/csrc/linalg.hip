@@ -124,6 +124,19 @@ __global__ void k_scatter_csr_add(int n, const int64_t* __restrict__ ptr, const 
         Y[(size_t)r * ldy + col[k]] += a * val[k];
 }
 
+// count of non-finite entries of a rows x cols block (leading dimension ldx)
+__global__ void k_count_nonfinite(int rows, int cols, const double* __restrict__ X, int64_t ldx,
+                                  int* __restrict__ count) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)rows * cols;
+    int bad = 0;
+    for (; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        int r = (int)(t / cols), c = (int)(t % cols);
+        if (!isfinite(X[(size_t)r * ldx + c])) ++bad;
+    }
+    if (bad) atomicAdd(count, bad);
+}
+
 // ------------------------------------------------- column-batched sparse ---
 __global__ void k_spmm_csr(int n, const int* __restrict__ ptr, const int* __restrict__ col,
                            const double* __restrict__ val, int ncol, const double* __restrict__ X,
@@ -299,6 +312,16 @@ void axpby2d(hipStream_t s, int rows, int cols, double a, const double* X, int l
              double* Y, int ldy) {
     hipLaunchKernelGGL(k_axpby2d, dim3(nblk((size_t)rows * cols)), dim3(256), 0, s, rows, cols, a, X,
                        ldx, b, Y, ldy);
+}
+
+int count_nonfinite(hipStream_t s, int rows, int cols, const double* X, int64_t ldx, int* d_count) {
+    int h = 0;
+    if (hipMemsetAsync(d_count, 0, sizeof(int), s) != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nblk((size_t)rows * cols)), dim3(256), 0, s, rows, cols, X, ldx,
+                       d_count);
+    if (hipMemcpyAsync(&h, d_count, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    return h;
 }
 
 void fill2d(hipStream_t s, int rows, int cols, double v, double* Y, int ldy) {

@@ -374,7 +374,7 @@ int fold_lag(mot_handle* h, int lag) {
     return MOT_OK;
 }
 
-int stage_add(mot_handle* h, int family, int lag, int medium, int op, const double* dev_block) {
+int stage_add(mot_handle* h, int family, int lag, int medium, int op, const double* dev_block, int64_t ldb) {
     const int ne = h->ne, hs = h->hs;
     const size_t blk = (size_t)ne * hs;
     double*& S = h->stage[(size_t)lag * 3 + family];
@@ -385,10 +385,10 @@ int stage_add(mot_handle* h, int family, int lag, int medium, int op, const doub
     double sc = family == MOT_FAM_HAT ? h->Tmax : (family == MOT_FAM_TILDE ? 1.0 / h->Tmax : 1.0);
     double et = medium == MOT_EXT ? h->eta : h->etap;
     if (op == MOT_OP_T) {
-        motk::axpby2d(h->stream, ne, ne, sc * et, dev_block, hs, 1.0, S, hs);          // q1 slot
-        motk::axpby2d(h->stream, ne, ne, sc / et, dev_block, hs, 1.0, S + 2 * blk, hs); // q2 slot
+        motk::axpby2d(h->stream, ne, ne, sc * et, dev_block, (int)ldb, 1.0, S, hs);          // q1 slot
+        motk::axpby2d(h->stream, ne, ne, sc / et, dev_block, (int)ldb, 1.0, S + 2 * blk, hs); // q2 slot
     } else {
-        motk::axpby2d(h->stream, ne, ne, sc, dev_block, hs, 1.0, S + blk, hs);         // qk slot
+        motk::axpby2d(h->stream, ne, ne, sc, dev_block, (int)ldb, 1.0, S + blk, hs);         // qk slot
     }
     return MOT_OK;
 }
@@ -1149,7 +1149,30 @@ int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int3
         if (!std::isfinite(block[i])) return mot_fail(h, MOT_EINVAL, "non-finite entry in a lag block");
     HIPCHK(h, hipMemcpy2DAsync(h->raw, hs * sizeof(double), block, ne * sizeof(double), ne * sizeof(double), ne,
                                hipMemcpyHostToDevice, h->stream));
-    if ((rc = stage_add(h, family, lag, medium, op, h->raw))) return rc;
+    if ((rc = stage_add(h, family, lag, medium, op, h->raw, hs))) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return after_block(h, family, lag, medium, op);
+}
+
+int mot_set_lag_device(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
+                       const double* dblock, int64_t ld) {
+    int rc = check_lag_args(h, family, lag, medium, op);
+    if (rc) return rc;
+    if (!dblock) return mot_fail(h, MOT_EINVAL, "NULL block");
+    const int ne = h->ne;
+    if (ld < ne || ld > INT32_MAX) return mot_fail(h, MOT_EINVAL, "leading dimension below ne or too large");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dblock) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return mot_fail(h, MOT_EINVAL, "block is not device memory");
+    }
+    int* cnt;
+    if ((rc = dalloc(h, &cnt, 1))) return rc;
+    int bad = motk::count_nonfinite(h->stream, ne, ne, dblock, ld, cnt);
+    dfree(h, cnt);
+    if (bad < 0) return mot_fail(h, MOT_EHIP, "non-finite check failed");
+    if (bad > 0) return mot_fail(h, MOT_EINVAL, "non-finite entry in a lag block");
+    if ((rc = stage_add(h, family, lag, medium, op, dblock, ld))) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return after_block(h, family, lag, medium, op);
 }
@@ -1166,15 +1189,21 @@ int mot_set_lag_csr(mot_handle* h, int32_t family, int32_t lag, int32_t medium, 
         if (rowptr[r + 1] < rowptr[r]) return mot_fail(h, MOT_EINVAL, "CSR row pointers decrease");
     for (int64_t i = 0; i < nnz; ++i)
         if (col[i] < 0 || col[i] >= ne || !std::isfinite(val[i])) return mot_fail(h, MOT_EINVAL, "bad CSR entry");
-    int64_t* dptr; int* dcol; double* dval;
-    if ((rc = upload(h, &dptr, rowptr, ne + 1)) || (rc = upload(h, &dcol, col, nnz ? nnz : 1)) ||
-        (rc = upload(h, &dval, val, nnz ? nnz : 1)))
-        return rc;
     motk::fill2d(h->stream, ne, hs, 0.0, h->raw, hs);
-    motk::scatter_csr_add(h->stream, ne, dptr, dcol, dval, 1.0, h->raw, hs);
-    if ((rc = stage_add(h, family, lag, medium, op, h->raw))) return rc;
+    if (nnz > 0) {
+        int64_t* dptr = nullptr; int* dcol = nullptr; double* dval = nullptr;
+        if (!(rc = upload(h, &dptr, rowptr, ne + 1)) && !(rc = upload(h, &dcol, col, nnz)) &&
+            !(rc = upload(h, &dval, val, nnz))) {
+            motk::scatter_csr_add(h->stream, ne, dptr, dcol, dval, 1.0, h->raw, hs);
+            if (hipStreamSynchronize(h->stream) != hipSuccess) rc = mot_fail(h, MOT_EHIP, "CSR scatter failed");
+        }
+        if (dptr) dfree(h, dptr);
+        if (dcol) dfree(h, dcol);
+        if (dval) dfree(h, dval);
+        if (rc) return rc;
+    }
+    if ((rc = stage_add(h, family, lag, medium, op, h->raw, hs))) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    dfree(h, dptr); dfree(h, dcol); dfree(h, dval);
     return after_block(h, family, lag, medium, op);
 }
 
@@ -1670,7 +1699,10 @@ CkptLayout ckpt_layout(const mot_handle* h, int with_history, int k, int hist_fi
     L.x = v;
     L.rb = (size_t)4 * h->ne * h->B * h->Rp * sizeof(double);
     L.gms = (h->Rp > 1 ? (size_t)h->Rp : 0) * sizeof(GmState);
-    if (!h->hist || k == 0) { L.hfirst = k; L.hcount = 0; }
+    // Kept steps are slots hist_first .. k-1, all below hist_cap: a march past
+    // the kept capacity (allowed when no outputs are asked for) or a restore
+    // without history leaves the last step unkept, and then nothing is saved.
+    if (!h->hist || k == 0 || k > h->hist_cap || k - 1 < hist_first) { L.hfirst = k; L.hcount = 0; }
     else if (with_history) { L.hfirst = hist_first; L.hcount = k - hist_first; }
     else { L.hfirst = k - 1; L.hcount = 1; }
     L.hist = (size_t)L.hcount * v;

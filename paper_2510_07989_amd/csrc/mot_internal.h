@@ -69,6 +69,8 @@ void gemm(hipStream_t s, int M, int N, int K, double alpha, const double* A, int
 void axpby2d(hipStream_t s, int rows, int cols, double a, const double* X, int ldx, double b,
              double* Y, int ldy);                       // Y = a X + b Y
 void fill2d(hipStream_t s, int rows, int cols, double v, double* Y, int ldy);
+// number of non-finite entries of X (synchronises s); -1 on a HIP error
+int count_nonfinite(hipStream_t s, int rows, int cols, const double* X, int64_t ldx, int* d_count);
 void set_identity(hipStream_t s, int n, double* Y, int ldy);
 void scatter_csr_add(hipStream_t s, int n, const int64_t* ptr, const int* col, const double* val,
                      double a, double* Y, int ldy);     // Y += a * CSR

@@ -111,6 +111,17 @@ class Solver:
         v = np.ascontiguousarray(A.data, dtype=np.float64)
         return self._check(self._lib.mot_set_lag_csr(self._h, family, lag, medium, op, _ptr(p), _ptr(c), _ptr(v)))
 
+    def set_lag_device(self, family, lag, medium, op, block):
+        """block: an (ne, ne) float64 tensor in device memory whose producing
+        work is complete or ordered before this solver's stream."""
+        if tuple(block.shape) != (self.ne, self.ne) or block.dtype.itemsize != 8:
+            raise ValueError("block must be an ne x ne float64 device tensor")
+        ld = int(block.stride(0))
+        if int(block.stride(1)) != 1:
+            raise ValueError("block rows must be contiguous")
+        return self._check(self._lib.mot_set_lag_device(self._h, family, lag, medium, op,
+                                                        ctypes.c_void_p(block.data_ptr()), ld))
+
     def load_raw(self, raw, kmax):
         """Upload every block of raw[medium][name][lag] within the families' ranges."""
         fams = (("h", L.FAM_H, kmax), ("hat", L.FAM_HAT, kmax + 1), ("tilde", L.FAM_TILDE, kmax - 1))

@@ -76,3 +76,45 @@ def test_restore_refuses_a_mismatch():
     b.restore(buf)                                      # the right one still works
     assert b.info()["steps_done"] == 20
     b.close()
+
+
+def test_checkpoint_after_marching_past_the_kept_capacity():
+    """A march without outputs may pass max_steps; the last step is then not
+    kept, and a checkpoint holds no history (rather than reading past the kept
+    range).  A handle restored from it continues bit for bit: the state saved
+    after ten more steps on each is byte-identical."""
+    print("case tiny_torus max_steps=30", flush=True)
+    a = _solver("tiny_torus", precond=2, max_steps=30)
+    a.run(45, w=False, loop=False, star=False)
+    full, last = a.checkpoint(True), a.checkpoint(False)
+    assert full.size == last.size                      # neither holds kept steps
+    b = _solver("tiny_torus", precond=2, max_steps=30)
+    b.restore(last)
+    assert b.info()["steps_done"] == 45
+    a.run(10, w=False, loop=False, star=False)
+    b.run(10, w=False, loop=False, star=False)
+    assert np.array_equal(a.checkpoint(False), b.checkpoint(False))
+    a.close()
+    b.close()
+
+
+def test_checkpoint_chained_through_a_restore_without_history():
+    """Restore a last-step-only checkpoint, then checkpoint again before any
+    step: the saved slot k-1 is the one that was restored, and a handle that
+    restores the second checkpoint continues bit for bit."""
+    print("case sphere_480 chained checkpoints", flush=True)
+    a = _solver("sphere_480", precond=2)
+    a.run(40)
+    buf1 = a.checkpoint(False)
+    ref = a.run(25)
+    a.close()
+    b = _solver("sphere_480", precond=2)
+    b.restore(buf1)
+    buf2 = b.checkpoint(False)
+    b.close()
+    c = _solver("sphere_480", precond=2)
+    c.restore(buf2)
+    out = c.run(25)
+    for k in ("w", "loop", "star"):
+        assert np.array_equal(out[k], ref[k]), k
+    c.close()

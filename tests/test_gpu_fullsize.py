@@ -22,37 +22,79 @@ def _solver(prob, **opts):
 
 
 def test_torus_6144_prefix_and_late_time():
-    """Torus, 6144 unknowns, dt = 2 (the headline workload), FP64 approximate
-    inverse and speculative stepping as in the benchmark: the first 20 steps
-    against the oracle to 1e-10; over 2000 steps, no late-time growth."""
+    """Torus, 6144 unknowns, dt = 2 (the torus workload), FP64 approximate
+    inverse and speculative stepping as in the benchmark, for the whole
+    10,000-step march: the first 20 steps against the oracle to 1e-10
+    (Section V-A eq. (MOT), eq. (dis_jm)); no late-time growth (Section VI-A):
+    over the last 2000 steps the least-squares slope of log10 ||w_k|| is not
+    positive and ||w_k|| stays below 1e-10 of its peak."""
     from oracle.mot_oracle import Oracle
-    print("case torus_3072", flush=True)
-    prob = problem("torus_3072", 2000)
-    s = _solver(prob, precond=2, max_steps=2000)
-    out = s.run(2000)
+    print("case torus_3072 10000 steps", flush=True)
+    nt = 10000
+    prob = problem("torus_3072", 20)
+    s = _solver(prob, precond=2, max_steps=nt)
+    s.run(nt, w=False, loop=False, star=False)
+    head = s.steps(0, 20)
+    nrm = s.step_norms(0, nt)[:, 0]
     s.close()
     ref = Oracle(prob).run(20)
-    e = [_rel(out[k][:20], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+    e = [_rel(head[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
     print("prefix errors", e, flush=True)
     assert max(e) < 1e-10
-    nrm = np.linalg.norm(out["w"].reshape(2000, -1), axis=1)
-    late = np.log10(nrm[-500:] + 1e-300)
+    late = np.log10(nrm[-2000:] + 1e-300)
     slope = np.polyfit(np.arange(late.size), late, 1)[0]
-    print("late-time slope %.3e decades/step, last/peak %.2e" % (slope, nrm[-1] / nrm.max()), flush=True)
-    assert slope <= 0.0 and nrm[-1] < 1e-6 * nrm.max()
+    print("late-time slope %.3e decades/step, late max/peak %.2e" % (slope, nrm[-2000:].max() / nrm.max()),
+          flush=True)
+    assert slope <= 0.0 and nrm[-2000:].max() <= 1e-10 * nrm.max()
 
 
 @pytest.mark.parametrize("precision,bound", [(0, 1e-10), (1, 1e-6)])
 def test_sphere_3840_16_waves_prefix(precision, bound):
-    """Sphere, 3840 unknowns, 16 waves (the batched workload), FP64 and mixed:
-    the first 10 steps against the oracle."""
+    """Sphere, 3840 unknowns, 16 waves, FP64 and mixed (FP32 storage, FP64
+    products): the first 10 steps against the oracle, w, loop and star parts."""
     from oracle.mot_oracle import Oracle
     print("case sphere_1920_r16 precision", precision, flush=True)
     prob = problem("sphere_1920_r16", 40)
     s = _solver(prob, precond=2, precision=precision, max_steps=40)
     out = s.run(10)
     s.close()
-    ref = Oracle(prob).run(10)
+    ref = _oracle_1920().run(10)
     e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
     print("prefix errors", e, flush=True)
-    assert e[0] < bound and e[1] < bound
+    assert max(e) < bound, e
+
+
+_O1920 = {}
+
+
+def _oracle_1920():
+    """The oracle of the 3840-unknown sphere (its lag matrices do not depend on
+    the waves; the right-hand sides do)."""
+    from oracle.mot_oracle import Oracle
+    if "o" not in _O1920:
+        _O1920["o"] = Oracle(problem("sphere_1920_r16", 40))
+    return _O1920["o"]
+
+
+@pytest.mark.parametrize("precision,bound_w,bound_star", [(1, 1e-6, 1e-6), (2, 1e-5, 1e-4)])
+def test_sphere_3840_64_waves_mixed_prefix(precision, bound_w, bound_star):
+    """64 seeded waves on the 3840-unknown sphere, the width at which the
+    history is a matrix-core product: the first 10 steps against the oracle.
+    MOT_MIXED (FP64 products of FP32-stored lags) meets 1e-6 on w, loop and
+    star; MOT_MIXED32 (FP32 matrix-core products, 4-index FP32 sums) is held
+    to its measured bounds (w 1e-5, star 1e-4) and is not the mixed path that
+    meets the 1e-6 target."""
+    import copy
+    from fixture.problem import make_waves, CONFIGS
+    print("case sphere_1920 64 waves precision", precision, flush=True)
+    prob = dict(problem("sphere_1920_r16", 40))
+    prob["waves"] = make_waves(64, CONFIGS["sphere_1920_r16"]["sigma"], True)
+    O = copy.copy(_oracle_1920())
+    O.prob = prob
+    ref = O.run(10)
+    s = _solver(prob, precond=2, precision=precision, max_steps=40)
+    out = s.run(10)
+    s.close()
+    e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+    print("prefix errors (precision %d): w %.3e loop %.3e star %.3e" % (precision, *e), flush=True)
+    assert e[0] < bound_w and e[1] < bound_w and e[2] < bound_star

@@ -37,13 +37,16 @@ def test_footprint_matches_allocations(name, opts):
 
 
 def test_same_result_alone_and_in_the_mix():
-    """Four solves on different meshes (one with two waves) arrive staggered
-    under a budget that makes some wait; each result equals the same request
-    served alone (FP64: to 1e-12, in practice bit for bit), and solves ran
-    concurrently."""
+    """Five solves on different meshes (one with two waves, one with 16 waves
+    in mixed precision) arrive staggered under a budget that makes some wait;
+    each result equals the same request served alone (to 1e-12, in practice
+    bit for bit, mixed precision included), solves ran concurrently, and the
+    served sphere matches the FP64 oracle (eq. (MOT), eq. (dis_jm))."""
     from paper_2510_07989_amd.serve import GpuBackend, Request, Server
-    specs = [("tiny", 60), ("tiny_torus", 60), ("tiny_box", 40), ("sphere_480", 150)]
-    reqs = [Request(i, problem(n), ns, arrival=0.03 * i, options=dict(precond=2)) for i, (n, ns) in enumerate(specs)]
+    specs = [("tiny", 60), ("tiny_torus", 60), ("tiny_box", 40), ("sphere_480", 150), ("sphere_480_r16", 80)]
+    reqs = [Request(i, problem(n), ns, arrival=0.03 * i,
+                    options=dict(precond=2, precision=1 if n == "sphere_480_r16" else 0))
+            for i, (n, ns) in enumerate(specs)]
     be = GpuBackend()
     alone = {}
     for r in reqs:
@@ -66,3 +69,10 @@ def test_same_result_alone_and_in_the_mix():
             assert e <= 1e-12, (rid, k, e)
     lat = summ["step_latency_s"]
     assert lat["n"] == sum(ns for _, ns in specs) and lat["p99"] >= lat["p50"] > 0
+    from tests._problems import oracle
+    ref = oracle("sphere_480").run(150)
+    for k, r in (("w", "W"), ("loop", "loop"), ("star", "star")):
+        assert _rel(res[3].outputs[k], ref[r]) < 1e-10, k
+    ref16 = oracle("sphere_480_r16").run(80)
+    for k, r in (("w", "W"), ("loop", "loop"), ("star", "star")):
+        assert _rel(res[4].outputs[k], ref16[r]) < 1e-6, k

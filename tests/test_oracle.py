@@ -471,3 +471,19 @@ def test_pyramid_gmres_counts_qhp_against_classical():
     print("qHP: %d (MOT rhs), %d (random); classical: %d" % (it_rhs, it_q, it_z))
     assert it_rhs < 80
     assert it_z > 5 * it_q
+
+
+def test_march_resumes_from_earlier_steps():
+    """The march of eq. (MOT) resumed from its first steps (W0) and given the
+    LU factorization of Q_0 computes exactly the steps the whole march does."""
+    import scipy.linalg as sla
+    from oracle.mot_oracle import march
+    rng = np.random.default_rng(7)
+    n, R, L, Nt = 12, 3, 4, 10
+    Q = [np.eye(n) * 3 + 0.1 * rng.standard_normal((n, n))] + [0.2 * rng.standard_normal((n, n)) for _ in range(L - 1)]
+    r = rng.standard_normal((Nt, n, R))
+    full = march(Q, r)
+    head = march(Q, r[:4])
+    tail = march(Q, r[4:], lu=sla.lu_factor(Q[0]), W0=head)
+    assert np.array_equal(head, full[:4])
+    assert np.array_equal(tail, full[4:])
