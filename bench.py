@@ -1,19 +1,24 @@
 #!/usr/bin/env python3
 """MOT throughput on one MI355X: steps/s of the qHP TD-PMCHWT march.
 
-Headline workload: torus R = 1, r = 0.4, 2048 triangles / 3072 edges -> 6144
-unknowns, eps_r = 4, mu_r = 1, dt = 2.0 (c dt comparable to the diameter),
-one Gaussian plane wave, plain FP64, 10,000 steps.  A step is the whole hot
-path: tested incident fields, preconditioned RHS, history convolution over
-Q_1..Q_{L-1}, GMRES on Q_0, ring update, and the loop/star current recovery
-of the timed steps.  Inputs are assembled on the host and resident on the
-device before the timed region.
+Headline workload (the largest single solve): unit cube, 32 x 32 x 24 cells,
+10,240 triangles / 15,360 edges -> 30,720 unknowns, eps_r = 4, mu_r = 1,
+dt = 0.5 (k_max 7, 9 lag matrices), 16 seeded Gaussian plane waves marched
+together, plain FP64.  A step is the whole hot path: tested incident fields,
+preconditioned RHS, history convolution over Q_1..Q_8, GMRES on Q_0 (FP64
+approximate inverse as right preconditioner), ring update, and the loop/star
+current recovery of the timed steps into device buffers.  The inputs (static
+blocks and the retarded blocks of both media, lag by lag) are assembled on
+the device and folded before the timed region.
 
-The `batched` object compares, on one sphere mesh (1280 triangles / 1920
-edges -> 3840 unknowns, eps_r = 2, dt = 0.15): plain FP64 with one wave, FP64
-with 16 seeded waves marched together, and the mixed path (FP32-stored lags,
-FP64 MFMA products) with the same 16 waves, whose error is stated against the
-FP64 run.
+`batched` compares, on the 5120-triangle sphere (15,360 unknowns, eps_r = 2,
+dt = 0.1, 31 lag matrices) with 64 seeded waves: plain FP64 against the mixed
+path (FP32-stored lags with an FP32 low part on the first two, FP64 products;
+Q_0, GMRES, projectors and recovery FP64), with the recovery inside the timed
+region, and the mixed error against the FP64 run.
+
+`torus` marches the 2048-triangle torus (6144 unknowns, dt = 2, one wave) for
+10,000 steps: steps/s of the one-RHS path and its late-time behaviour.
 
 Prints one JSON line.
 """
@@ -30,12 +35,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 WORKLOADS = {
+    "cube_15360": "unit cube 32x32x24 cells, 10240 triangles / 15360 edges -> 30720 unknowns, eps_r=4, mu_r=1, "
+                  "dt=0.5 (k_max 7, 9 lags), 16 seeded Gaussian plane waves marched together",
+    "sphere_7680": "sphere r=1, 5120 triangles / 7680 edges -> 15360 unknowns, eps_r=2, mu_r=1, dt=0.1 "
+                   "(k_max 29, 31 lags), 64 seeded Gaussian plane waves marched together",
     "torus_3072": "torus R=1 r=0.4, 2048 triangles / 3072 edges -> 6144 unknowns, eps_r=4, mu_r=1, "
                   "dt=2.0, 1 Gaussian plane wave",
-    "sphere_480": "sphere r=1, 320 triangles / 480 edges -> 960 unknowns, eps_r=2, dt=0.25, "
-                  "1 Gaussian plane wave",
-    "sphere_1920_r16": "sphere r=1, 1280 triangles / 1920 edges -> 3840 unknowns, eps_r=2, dt=0.15, "
-                       "16 seeded Gaussian plane waves marched together",
 }
 PRECISION = {0: "fp64", 1: "mixed: fp32-stored lags, fp64 mfma products",
              2: "mixed32: fp32-stored lags, fp32 mfma products"}
@@ -80,23 +85,36 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(prob, budget_s, nmax):
-    """The oracle, as it stands, on the first steps of the same problem."""
-    from oracle.mot_oracle import Oracle, march, recover
+def cpu_baseline(n, R, L, budget_s, seed=251007989):
+    """The oracle's march (eq. (MOT), oracle.mot_oracle.march as it stands) on
+    a bounded sample of the workload's shape: n unknowns, R waves, L - 1
+    history lags, every timed step with the whole history active (resumed
+    from L - 1 earlier steps), the Q_0 solve through a given LU factorization.
+    The matrices are synthetic (one n x n array serves every history lag,
+    a unit triangular pair the LU): the dense products and triangular solves
+    cost what they cost on the real values, without the O(n^3) setup (fold
+    of the lag matrices, LU of Q_0) that a bench run cannot afford on the
+    host."""
+    import numpy as np
+    from oracle.mot_oracle import march
+    rng = np.random.Generator(np.random.PCG64(seed))
     t = time.perf_counter()
-    O = Oracle(prob)
+    Qh = np.full((n, n), 1e-4)
+    lu = np.full((n, n), 1e-6)
+    np.fill_diagonal(lu, 1.0)
+    piv = np.arange(n, dtype=np.int32)
+    Q = [None] + [Qh] * (L - 1)
+    W0 = rng.standard_normal((L - 1, n, R))
     prep = time.perf_counter() - t
     t = time.perf_counter()
-    r1 = O.rhs_all(1)
-    march(O.Q, r1)
+    march(Q, rng.standard_normal((1, n, R)), lu=(lu, piv), W0=W0)
     one = time.perf_counter() - t
-    ns = int(max(3, min(nmax, budget_s / max(one, 1e-6))))
+    ns = int(max(2, min(200, budget_s / max(one, 1e-6))))
+    r = rng.standard_normal((ns, n, R))
     t = time.perf_counter()
-    r = O.rhs_all(ns)
-    W = march(O.Q, r)
-    loop, star = recover(O.P, O.Tmax, prob["dt"], W)
+    march(Q, r, lu=(lu, piv), W0=W0)
     el = time.perf_counter() - t
-    return dict(steps=ns, seconds=el, prep_s=prep, W=W, loop=loop, star=star)
+    return dict(steps=ns, seconds=el, prep_s=prep)
 
 
 def history_model(ne, n, L, R, precision, hilo):
@@ -191,43 +209,44 @@ def far_field_timing(s, nsteps, n, R, freq):
             "note": "host wall time of the whole call; per-kernel times in the rocprofv3 summary"}
 
 
-def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, outputs=True, far=None):
-    """Set up one problem on the device, march W_ warm-up steps (kept as the
-    parity sample), then time K steps with device-resident outputs."""
+def make_solvers(mot, prob, variants, max_steps):
+    """One solver per variant (dict of options), all fed by one device
+    assembly pass of the problem's retarded blocks; returns the solvers and
+    the wall times of create and of assembly + fold (+ preconditioner)."""
+    import torch
+    from fixture import gpu as fxgpu
+    t = time.perf_counter()
+    ss = []
+    for v in variants:
+        kw = dict(profile=PROFILE_EVERY, max_steps=max_steps)
+        kw.update(v)
+        opts = mot.default_options(**kw)
+        ss.append(mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
+                             prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
+                             stream=torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t
+    t = time.perf_counter()
+    fxgpu.load_solvers(ss, prob)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t
+    return ss, t_create, t_load
+
+
+def timed(s, prob, name, precision, K, W_, hilo, mix_group, outputs=True, keep_warm=True):
+    """W_ warm-up steps (outputs to the host when keep_warm), then K timed
+    steps with device-resident outputs (recovery included when outputs)."""
     import torch
     R = len(prob["waves"])
-    opts = mot.default_options(profile=PROFILE_EVERY, max_steps=W_ + K + 8, precond=precond, stream_split=split,
-                               precision=precision, hilo_lags=hilo, mix_group=mix_group)
-    t = time.perf_counter()
-    s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
-                   prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
-                   stream=torch.cuda.current_stream().cuda_stream)
-    s.load_raw(prob["raw"], prob["kmax"])
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t
     inf0 = s.info()
-    log("[%s R=%d %s] device setup %.2f s (preconditioner %.0f ms, fold %.0f ms), %d lags, %.2f GB on device; "
-        "schedules history %d, Q0 %d, preconditioner %d (tuned in %.1f ms)"
-        % (name, R, PRECISION[precision], t_setup, inf0["setup_ms"], inf0["fold_ms"], inf0["nlags"],
-           inf0["device_bytes"] / 1e9, inf0["sched_hist"], inf0["sched_q0"], inf0["sched_pc"], inf0["tune_ms"]))
-    warm = s.run(W_, w=True, loop=True, star=True, device=False)
+    warm = s.run(W_, w=keep_warm, loop=keep_warm, star=keep_warm, device=False)
     torch.cuda.synchronize()
     a = s.info()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.run(K, w=outputs, loop=outputs, star=outputs, device=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     b = s.info()
-    ff = late = None
-    if far is not None:
-        # diagnostics after the timed march: a failure here must not cost the step-rate line
-        try:
-            ff = far_field_timing(s, W_ + K, 2 * prob["E"].shape[0], R, far)
-            late = late_time(s, W_ + K)
-        except Exception as e:  # noqa: BLE001
-            log("far-field / late-time diagnostics failed: %r" % (e,))
-    s.close()
     ne, n, L = prob["E"].shape[0], 2 * prob["E"].shape[0], b["nlags"]
     hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
     q0_us = 1e3 * (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
@@ -243,66 +262,136 @@ def measure(mot, prob, name, precision, K, W_, precond, split, hilo, mix_group, 
                   measured_traffic(q0name if R == 1 else q0name + " (Q_0)", name))
     hist_tot = b["hist_ms"] - a["hist_ms"]
     q0_tot = b["q0_ms"] - a["q0_ms"]
-    out = dict(steps_s=K / el, el=el, K=K, W=W_, R=R, n=n, L=L, kmax=b["kmax"], setup_s=t_setup,
+    out = dict(steps_s=K / el, el=el, K=K, W=W_, R=R, n=n, L=L, kmax=b["kmax"],
                iters=(b["gmres_iters_total"] - a["gmres_iters_total"]) / K,
                q0_launches=PROFILE_EVERY * (b["q0_launches"] - a["q0_launches"]) / K, hist=hist, q0=q0,
                dominant=hist if hist_tot >= q0_tot else q0, warm=warm, recover_ms=b["recover_ms"],
-               device_gb=inf0["device_bytes"] / 1e9, far_field=ff, late_time=late,
+               device_gb=inf0["device_bytes"] / 1e9, setup_ms=inf0["setup_ms"], fold_ms=inf0["fold_ms"],
+               precond_iters=inf0["precond_iters"],
                schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
-                         "autotuned": bool(inf0["tuned"] and opts.autotune), "tune_ms": round(inf0["tune_ms"], 1)})
-    log("[%s R=%d] timed %d steps in %.3f s: %.1f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
-        "history %.1f us (%s %.4g %s), Q0 product %.1f us"
-        % (name, R, K, el, K / el, R * K / el, out["iters"], hist_us, hist["bound"], hist["achieved"],
-           hist["unit"], q0_us))
+                         "autotuned": bool(inf0["tuned"]), "tune_ms": round(inf0["tune_ms"], 1)})
+    log("[%s R=%d %s] timed %d steps in %.3f s: %.2f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
+        "history %.1f us (%s %.4g %s, %.3f of peak), Q0 product %.1f us; %.1f GB on device"
+        % (name, R, PRECISION[precision], K, el, K / el, R * K / el, out["iters"], hist_us, hist["bound"],
+           hist["achieved"], hist["unit"], hist["frac"], q0_us, out["device_gb"]))
     return out
 
 
-def graph_compare(mot, prob, K, W_, precond):
-    """The same march with its speculative windows queued launch by launch and
-    replayed from captured HIP graphs, on a stream of its own, no events."""
+def brief(r):
+    return {"steps_s": round(r["steps_s"], 3), "rhs_steps_per_s": round(r["steps_s"] * r["R"], 1),
+            "ms_per_step": round(1e3 * r["el"] / r["K"], 4), "gmres_iters_per_step": round(r["iters"], 2),
+            "history_kernel": r["hist"], "q0_product": r["q0"], "schedule": r["schedule"],
+            "device_gb": round(r["device_gb"], 2)}
+
+
+def rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def torus_leg(mot, args):
+    """The torus, one wave, FP64, 10,000 timed steps after 100: the one-RHS
+    step rate, its late-time behaviour over the whole march and the far field
+    of every kept step; then the same march replayed from captured graphs."""
     import torch
-    out = {}
-    for g in (0, 1):
-        st = torch.cuda.Stream()
-        opts = mot.default_options(max_steps=W_ + K + 8, precond=precond, graph=g)
-        s = mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
-                       prob["T0h"], prob["G"], prob["waves"], options=opts, stream=st.cuda_stream)
-        s.load_raw(prob["raw"], prob["kmax"])
-        with torch.cuda.stream(st):
-            s.run(W_, w=False, loop=False, star=False, device=True)
-            st.synchronize()
-            t0 = time.perf_counter()
-            s.run(K, w=True, loop=True, star=True, device=True)
-            st.synchronize()
-            el = time.perf_counter() - t0
-        inf = s.info()
+    from fixture import gpu as fxgpu
+    name = "torus_3072"
+    t = time.perf_counter()
+    prob = fxgpu.build_problem_device(name)
+    t_in = time.perf_counter() - t
+    W_, K = 100, 10000
+    (s,), t_create, t_load = make_solvers(mot, prob, [dict(precond=args.precond)], W_ + K + 8)
+    log("[%s] inputs %.1f s, create %.1f s, device assembly and fold %.1f s" % (name, t_in, t_create, t_load))
+    m = timed(s, prob, name, 0, K, W_, args.hilo, args.mix_group, keep_warm=False)
+    out = dict(brief(m), workload=name + ": " + WORKLOADS[name], steps=K, warmup=W_,
+               setup_s=round(t_create + t_load, 2))
+    try:
+        out["late_time"] = late_time(s, W_ + K)
+        out["far_field"] = far_field_timing(s, W_ + K, m["n"], 1, FAR_FIELD_FREQ[name])
+    except Exception as e:  # noqa: BLE001
+        log("late-time / far-field diagnostics failed: %r" % (e,))
+    s.close()
+    if not args.no_graph:
+        gr = {}
+        for g in (0, 1):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                (sg,), _, _ = make_solvers(mot, prob, [dict(precond=args.precond, graph=g, profile=0)], 5200)
+                sg.run(100, w=False, loop=False, star=False, device=True)
+                st.synchronize()
+                t0 = time.perf_counter()
+                sg.run(5000, w=True, loop=True, star=True, device=True)
+                st.synchronize()
+                el = time.perf_counter() - t0
+            gr["graph" if g else "launches"] = {"steps_s": round(5000 / el, 1),
+                                                "graph_windows": sg.info()["graph_windows"]}
+            sg.close()
+        out["graph_replay"] = dict(gr, steps=5000)
+        log("window replay: launches %.1f steps/s, graphs %.1f steps/s" % (gr["launches"]["steps_s"],
+                                                                          gr["graph"]["steps_s"]))
+    return out
+
+
+def batched_leg(mot, args):
+    """The 15,360-unknown sphere with 64 seeded waves: FP64 against the mixed
+    path (and, with --mixed32, the FP32 matrix-core path) on the same device
+    assembly, recovery inside the timed region; the mixed error against the
+    FP64 run over the warm-up steps."""
+    import numpy as np
+    import torch
+    from fixture import gpu as fxgpu
+    name = "sphere_7680"
+    t = time.perf_counter()
+    prob = fxgpu.build_problem_device(name)
+    t_in = time.perf_counter() - t
+    Kb, Wb = args.batched_steps, args.batched_warmup
+    variants = [(0, dict(precond=args.precond, precision=0)),
+                (1, dict(precond=args.precond, precision=1, hilo_lags=args.hilo))]
+    if args.mixed32:
+        variants.append((2, dict(precond=args.precond, precision=2, hilo_lags=args.hilo, mix_group=args.mix_group)))
+    ss, t_create, t_load = make_solvers(mot, prob, [v for _, v in variants], Wb + Kb + 8)
+    log("[%s] inputs %.1f s, create %.1f s, device assembly and fold of %d solvers %.1f s"
+        % (name, t_in, t_create, len(ss), t_load))
+    res = {}
+    for (prec, _), s in zip(variants, ss):
+        res[prec] = timed(s, prob, name, prec, Kb, Wb, args.hilo, args.mix_group)
         s.close()
-        out["graph" if g else "launches"] = {"steps_s": round(K / el, 1), "graph_windows": inf["graph_windows"]}
-    log("window replay: launches %.1f steps/s, graphs %.1f steps/s (%d windows)"
-        % (out["launches"]["steps_s"], out["graph"]["steps_s"], out["graph"]["graph_windows"]))
+    torch.cuda.empty_cache()
+    ref = res[0]["warm"]
+    out = {"workload": name + ": " + WORKLOADS[name], "steps": Kb, "warmup": Wb,
+           "setup_s": round(t_create + t_load, 2), "fp64_64rhs": brief(res[0])}
+    for prec, key in ((1, "mixed_64rhs"), (2, "mixed32_64rhs")):
+        if prec not in res:
+            continue
+        e = {k: rel(res[prec]["warm"][k], ref[k]) for k in ("w", "loop", "star")}
+        nrm = np.linalg.norm(res[prec]["warm"]["w"].reshape(Wb, -1), axis=1)
+        out[key] = dict(brief(res[prec]), precision=PRECISION[prec], hilo_lags=args.hilo,
+                        err_vs_fp64={"steps": Wb, **e},
+                        speedup_vs_fp64=round(res[prec]["steps_s"] / res[0]["steps_s"], 3))
+        log("[%s] %s: %.2f steps/s against FP64 %.2f (x%.3f); error vs FP64 over %d steps: w %.2e loop %.2e "
+            "star %.2e" % (name, PRECISION[prec], res[prec]["steps_s"], res[0]["steps_s"],
+                           res[prec]["steps_s"] / res[0]["steps_s"], Wb, e["w"], e["loop"], e["star"]))
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="torus_3072", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched/mixed comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-wave sphere comparison")
+    ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--batched-warmup", type=int, default=40)
+    ap.add_argument("--mixed32", action="store_true", help="also time the FP32 matrix-core mixed path")
+    ap.add_argument("--no-torus", action="store_true", help="skip the 10,000-step torus march")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison")
-    ap.add_argument("--no-wide", action="store_true", help="skip the 64-wave batched runs")
-    ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
     ap.add_argument("--no-step-batch", action="store_true", help="skip the mot_run_batch comparison")
-    ap.add_argument("--no-far-field", action="store_true", help="skip the far-field timing")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
-    ap.add_argument("--split", type=int, default=0, help="wavefronts per matrix row (0: by size)")
-    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed (FP64 MFMA), 2 mixed (FP32 MFMA)")
     ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with an FP32 low part (-1: none)")
     ap.add_argument("--mix-group", type=int, default=4, help="precision 2: summation indices per FP32 sum")
     args = ap.parse_args()
@@ -311,25 +400,28 @@ def main():
               "runs on several GPUs are not part of this benchmark.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
     import paper_2510_07989_amd as mot
-    from fixture.problem import build_problem
+    from fixture import gpu as fxgpu
 
+    name = "cube_15360"
     W_, K = args.warmup, args.steps
     t = time.perf_counter()
-    prob = build_problem(args.workload, nsteps=W_ + K, verbose=True)
-    t_fixture = time.perf_counter() - t
-    log("inputs assembled on the host in %.1f s" % t_fixture)
-    m = measure(mot, prob, args.workload, args.precision, K, W_, args.precond, args.split, args.hilo,
-                args.mix_group, far=None if args.no_far_field else FAR_FIELD_FREQ.get(args.workload, 0.01))
+    prob = fxgpu.build_problem_device(name)
+    t_in = time.perf_counter() - t
+    (s,), t_create, t_load = make_solvers(mot, prob, [dict(precond=args.precond)], W_ + K + 8)
+    log("[%s] inputs (mesh, BC basis, Gram, static blocks on the device) %.1f s, create %.1f s, device assembly "
+        "and fold %.1f s" % (name, t_in, t_create, t_load))
+    m = timed(s, prob, name, 0, K, W_, args.hilo, args.mix_group, keep_warm=False)
+    s.close()
+    torch.cuda.empty_cache()
     R = m["R"]
     result = {
-        "metric": "MOT steps/s (%s, %d RHS)" % ("plain FP64" if args.precision == 0 else "mixed precision", R),
+        "metric": "MOT steps/s (plain FP64, %d RHS)" % R,
         "value": round(m["steps_s"], 3),
         "unit": "steps/s",
         "rhs_steps_per_s": round(m["steps_s"] * R, 2),
@@ -340,113 +432,39 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32 storage, f64 arithmetic" if args.precision == 1 else "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "nrhs": R,
-                   "unknowns": m["n"], "lags": m["L"], "kmax": m["kmax"], "precision": PRECISION[args.precision],
+        "config": {"workload": name + ": " + WORKLOADS[name], "nrhs": R, "unknowns": m["n"], "lags": m["L"],
+                   "kmax": m["kmax"], "precision": PRECISION[0],
                    "q0_preconditioner": ["none", "fp32 approximate inverse", "fp64 approximate inverse"][args.precond]},
         "roofline": m["dominant"],
         "history_kernel": m["hist"],
         "q0_product": dict(m["q0"], launches_per_step=round(m["q0_launches"], 2)),
         "gmres_iters_per_step": round(m["iters"], 2),
         "schedule": m["schedule"],
-        "setup_s": round(m["setup_s"], 3),
-        "fixture_s": round(t_fixture, 1),
+        "setup_s": {"inputs": round(t_in, 1), "create": round(t_create, 1), "assembly_and_fold": round(t_load, 1),
+                    "fold_ms": round(m["fold_ms"], 1), "preconditioner_ms": round(m["setup_ms"], 1),
+                    "newton_schulz_iters": m["precond_iters"]},
         "device_gb": round(m["device_gb"], 2),
     }
-    if m["far_field"] is not None:
-        result["far_field"] = m["far_field"]
-    if m["late_time"] is not None:
-        result["late_time"] = m["late_time"]
-
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(prob, args.cpu_budget, min(W_, 400))
-        ns = cb["steps"]
-        warm = m["warm"]
-        e_w = float(np.linalg.norm(warm["w"][:ns] - cb["W"]) / np.linalg.norm(cb["W"]))
-        e_l = float(np.linalg.norm(warm["loop"][:ns] - cb["loop"]) / np.linalg.norm(cb["loop"]))
-        e_s = float(np.linalg.norm(warm["star"][:ns] - cb["star"]) / max(np.linalg.norm(cb["star"]), 1e-300))
-        result["cpu_baseline"] = {"value": round(ns / cb["seconds"], 4), "unit": "steps/s",
-                                  "cores": blas_threads(), "kind": "oracle",
-                                  "sample": "first %d steps of the same workload (RHS, march with LU of Q_0, "
-                                            "recovery), oracle setup %.1f s not timed" % (ns, cb["prep_s"])}
-        result["err_vs_oracle"] = {"steps": ns, "w": e_w, "loop": e_l, "star": e_s}
-        log("oracle: %d steps in %.1f s; GPU vs oracle: w %.2e loop %.2e star %.2e" % (ns, cb["seconds"], e_w, e_l, e_s))
-
-    if not args.no_graph:
-        result["graph_replay"] = dict(graph_compare(mot, prob, min(K, 5000), W_, args.precond),
-                                      steps=min(K, 5000), workload=args.workload)
-
+        cb = cpu_baseline(m["n"], R, m["L"], args.cpu_budget)
+        result["cpu_baseline"] = {
+            "value": round(cb["steps"] / cb["seconds"], 4), "unit": "steps/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the oracle's march (eq. MOT) at this workload's shape: %d unknowns, %d waves, "
+                      "%d history lags all active, Q_0 solved through a given LU factorization; synthetic matrix "
+                      "values (one array for every lag); the oracle's O(n^3) setup (lag fold, LU of Q_0) is not "
+                      "run" % (cb["steps"], m["n"], R, m["L"] - 1)}
+        log("oracle march: %d steps in %.1f s on %d threads" % (cb["steps"], cb["seconds"], blas_threads()))
     if not args.no_batched:
-        name = "sphere_1920_r16"
-        Kb, Wb = args.batched_steps, 300
-        t = time.perf_counter()
-        pb = build_problem(name, nsteps=Wb + Kb, verbose=True)
-        log("batched inputs assembled on the host in %.1f s" % (time.perf_counter() - t))
-        one = dict(pb, waves=pb["waves"][:1])
-        r1 = measure(mot, one, name, 0, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
-        r16 = measure(mot, pb, name, 0, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
-        rmx = measure(mot, pb, name, 1, Kb, Wb, args.precond, args.split, args.hilo, args.mix_group, outputs=False)
-
-        def rel(a, b):
-            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-        err = {k: rel(rmx["warm"][k], r16["warm"][k]) for k in ("w", "loop", "star")}
-        nrm = np.linalg.norm(rmx["warm"]["w"].reshape(Wb, -1), axis=1)
-        tail = np.log10(nrm[-Wb // 4:] + 1e-300)
-        growth = float(np.polyfit(np.arange(tail.size), tail, 1)[0])
-
-        def brief(r):
-            return {"steps_s": round(r["steps_s"], 2), "rhs_steps_per_s": round(r["steps_s"] * r["R"], 1),
-                    "ms_per_step": round(1e3 * r["el"] / r["K"], 4), "gmres_iters_per_step": round(r["iters"], 2),
-                    "history_kernel": r["hist"], "schedule": r["schedule"], "device_gb": round(r["device_gb"], 2)}
-
-        result["batched"] = {
-            "workload": name + ": " + WORKLOADS[name],
-            "steps": Kb, "warmup": Wb,
-            "fp64_1rhs": brief(r1),
-            "fp64_16rhs": brief(r16),
-            "mixed_16rhs": dict(brief(rmx), precision=PRECISION[1], hilo_lags=args.hilo,
-                                err_vs_fp64_16rhs={"steps": Wb, **err},
-                                late_log10_growth_per_step=growth),
-            "mixed_vs_fp64_1rhs_steps_ratio": round(rmx["steps_s"] / r1["steps_s"], 3),
-            "mixed_vs_fp64_1rhs_rhs_steps_ratio": round(rmx["steps_s"] * rmx["R"] / r1["steps_s"], 2),
-        }
-        log("batched: FP64 1 RHS %.1f steps/s; FP64 16 RHS %.1f; mixed 16 RHS %.1f (err w %.2e star %.2e vs FP64)"
-            % (r1["steps_s"], r16["steps_s"], rmx["steps_s"], err["w"], err["star"]))
-        if not args.no_wide:
-            # 64 waves on the same mesh (the lag blocks do not depend on the
-            # waves): the history products become MFMA-bound
-            from fixture.problem import CONFIGS, make_waves
-            cfg = CONFIGS[name]
-            p64 = dict(pb, waves=make_waves(64, cfg["sigma"], True))
-            K64, W64 = 300, 100
-            w64 = {}
-            for key, prec in (("fp64_64rhs", 0), ("mixed_64rhs", 1), ("mixed32_64rhs", 2)):
-                w64[key] = measure(mot, p64, name, prec, K64, W64, args.precond, args.split, args.hilo,
-                                   args.mix_group, outputs=False)
-            ref = w64["fp64_64rhs"]["warm"]
-            wide = {"workload": name + " with 64 seeded waves", "steps": K64, "warmup": W64}
-            for key, prec in (("fp64_64rhs", 0), ("mixed_64rhs", 1), ("mixed32_64rhs", 2)):
-                e = dict(brief(w64[key]), precision=PRECISION[prec])
-                if prec:
-                    e["err_vs_fp64_64rhs"] = {"steps": W64, **{k: rel(w64[key]["warm"][k], ref[k])
-                                                               for k in ("w", "loop", "star")}}
-                    if prec == 2:
-                        e["mix_group"] = args.mix_group
-                wide[key] = e
-            result["batched"]["wide"] = wide
-            log("batched, 64 waves: FP64 %.1f steps/s, mixed %.1f (err w %.2e), mixed32 %.1f (err w %.2e)"
-                % (w64["fp64_64rhs"]["steps_s"], w64["mixed_64rhs"]["steps_s"],
-                   wide["mixed_64rhs"]["err_vs_fp64_64rhs"]["w"], w64["mixed32_64rhs"]["steps_s"],
-                   wide["mixed32_64rhs"]["err_vs_fp64_64rhs"]["w"]))
+        result["batched"] = batched_leg(mot, args)
+    if not args.no_torus:
+        result["torus"] = torus_leg(mot, args)
     if not args.no_step_batch:
         result["step_batch"] = step_batch(mot)
     if args.serving:
-        have = {args.workload: prob}
-        if not args.no_batched:
-            have["sphere_1920_r16"] = pb
-        result["serving"] = serving(args.serving_requests, have)
+        result["serving"] = serving(args.serving_requests)
     print(json.dumps(result), flush=True)
 
 

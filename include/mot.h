@@ -167,7 +167,9 @@ typedef struct {
     int32_t folded;          /* 1 once every lag matrix is formed            */
     int32_t steps_done;
     uint64_t device_bytes;   /* device memory held by the handle             */
-    double setup_ms;         /* preconditioner construction time             */
+    double setup_ms;         /* setup time: projectors, Gram inverse and the
+                                C1 / C2 factors at create, plus the approximate
+                                inverse of Q_0 built once lag 0 is folded     */
     double fold_ms;          /* lag-matrix fold time (sum over lags)         */
     int64_t gmres_iters_total;  /* Arnoldi steps over all steps taken        */
     double hist_ms;          /* profile: summed history-kernel time          */
