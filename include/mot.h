@@ -288,6 +288,22 @@ int mot_get_steps(mot_handle* h, int32_t first, int32_t count, double* w_out, do
  * MOT_EINVAL for a range not taken or not kept. */
 int mot_step_norms(mot_handle* h, int32_t first, int32_t count, double* norms);
 
+/* mot_step_norms for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops that poll the late-time behaviour
+ * between windows, harnesses that forbid hipMalloc.  Same arguments and the
+ * same results, bit for bit; the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine): the per-step norms are staged in a
+ * static device array of MOT_NOALLOC_DOUBLES doubles (1 MiB), one per GPU,
+ * which the library holds from its first mot_create on that GPU until the
+ * process ends.  count * nrhs must not exceed MOT_NOALLOC_DOUBLES (else
+ * MOT_EINVAL; split the range).  Every handle on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (handles on different streams
+ * or host threads) race and must be serialised by the caller.  The array
+ * keeps the last call's contents; nothing in it needs clearing, as each call
+ * writes every value it reads back. */
+#define MOT_NOALLOC_DOUBLES 131072
+int mot_step_norms_noalloc(mot_handle* h, int32_t first, int32_t count, double* norms);
+
 /* Spectra and far fields of the currents of kept steps (Section VI, far-field
  * computation, on eq. (dis_jm)), the loop and star parts kept apart so that
  * neither is lost in the other at low frequency.  Steps first ..

@@ -52,7 +52,7 @@ EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr"
            "mot_run", "mot_get_matrix", "mot_get_info", "mot_reset", "mot_destroy",
            "mot_last_error", "mot_footprint", "mot_get_steps", "mot_run_batch",
            "mot_far_field", "mot_checkpoint_size", "mot_checkpoint", "mot_restore",
-           "mot_step_norms", "mot_set_lag_device"]
+           "mot_step_norms", "mot_set_lag_device", "mot_step_norms_noalloc"]
 
 _lib = None
 
@@ -99,6 +99,8 @@ def load():
     lib.mot_restore.restype = _I
     lib.mot_step_norms.argtypes = [_P, _I, _I, _P]
     lib.mot_step_norms.restype = _I
+    lib.mot_step_norms_noalloc.argtypes = [_P, _I, _I, _P]
+    lib.mot_step_norms_noalloc.restype = _I
     lib.mot_run_batch.argtypes = [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(_I)]
     lib.mot_run_batch.restype = _I
     lib.mot_get_matrix.argtypes = [_P, _I, _I, _P]

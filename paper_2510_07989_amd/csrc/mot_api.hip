@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <algorithm>
+#include <mutex>
 #include <thread>
 
 #include "mot_internal.h"
@@ -888,6 +889,36 @@ void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* 
 
 }  // namespace
 
+// ---- static scratch of the allocation-free calls ----
+// One array per device, in the code object: each GPU the library runs on
+// holds MOT_NOALLOC_DOUBLES doubles (1 MiB) from load until the process ends.
+// Host code never uses the array's name as an address (on the host it names a
+// stand-in): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in g_scratch_dev.
+static __device__ __align__(256) double scratch[MOT_NOALLOC_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Address of this device's scratch array; dev must be the current device.
+int scratch_address(mot_handle* h, int dev, double** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return mot_fail(h, MOT_EHIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return mot_fail(h, MOT_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return MOT_OK;
+}
+}  // namespace
+
 // ======================================================================= ABI
 extern "C" {
 
@@ -1030,6 +1061,11 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     double t_start = now_ms();
     int rc = MOT_OK;
     auto bail = [&](int code) { g_create_err = h->err; mot_destroy(h); return code; };
+    {
+        hipError_t e = hipGetDevice(&h->device);
+        if (e != hipSuccess) { mot_fail(h, MOT_EHIP, hipGetErrorString(e)); return bail(MOT_EHIP); }
+        if ((rc = scratch_address(h, h->device, &h->scratch))) return bail(rc);
+    }
 
     // ---- graphs ----
     {
@@ -1640,6 +1676,32 @@ int mot_step_norms(mot_handle* h, int32_t first, int32_t count, double* norms) {
     if (e == hipSuccess) e = hipMemcpyAsync(norms, d, sizeof(double) * count * h->R, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     dfree(h, d);
+    if (e != hipSuccess) return mot_fail(h, MOT_EHIP, hipGetErrorString(e));
+    return MOT_OK;
+}
+
+// Same results as mot_step_norms (same kernel, same order of sums), staged in
+// the device's static scratch array instead of a buffer allocated per call.
+int mot_step_norms_noalloc(mot_handle* h, int32_t first, int32_t count, double* norms) {
+    if (!h) return MOT_EINVAL;
+    if ((int64_t)count * h->R > MOT_NOALLOC_DOUBLES)
+        return mot_fail(h, MOT_EINVAL, "count * nrhs = " + std::to_string((int64_t)count * h->R) +
+                                           " exceeds the static scratch of " + std::to_string(MOT_NOALLOC_DOUBLES) +
+                                           " values: split the range");
+    const int64_t end = (int64_t)first + count;
+    if (first < 0 || count < 0 || end > h->k || (!norms && count > 0))
+        return mot_fail(h, MOT_EINVAL, "steps out of range or no output array");
+    if (!h->hist || end > h->hist_cap) return mot_fail(h, MOT_EINVAL, "steps not kept: needs keep_history");
+    if (count > 0 && first < h->hist_first)
+        return mot_fail(h, MOT_EINVAL, "steps before the restored checkpoint's kept history are not held");
+    if (count == 0) return MOT_OK;
+    if (!h->scratch) return mot_fail(h, MOT_ESTATE, "no scratch address for this handle's device");
+    // every value of scratch[0 .. count*R) is written by the kernel: nothing to clear
+    motk_ff::step_norms(h, first, count, h->scratch);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(norms, h->scratch, sizeof(double) * count * h->R, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return mot_fail(h, MOT_EHIP, hipGetErrorString(e));
     return MOT_OK;
 }

@@ -114,6 +114,8 @@ struct mot_handle {
     double setup_ms = 0, fold_ms = 0;
     uint64_t bytes = 0;
     uint64_t peak_bytes = 0;         // high-water mark of bytes
+    int device = -1;                 // HIP device current at create
+    double* scratch = nullptr;       // this device's static scratch array (mot_step_norms_noalloc)
     std::vector<void*> allocs;
     std::vector<size_t> sizes;
 

@@ -193,6 +193,13 @@ class Solver:
         self._check(self._lib.mot_step_norms(self._h, int(first), int(count), _ptr(out)))
         return out
 
+    def step_norms_noalloc(self, first, count):
+        """step_norms through the allocation-free call (mot_step_norms_noalloc):
+        count * nrhs at most MOT_NOALLOC_DOUBLES."""
+        out = np.empty((count, self.nrhs))
+        self._check(self._lib.mot_step_norms_noalloc(self._h, int(first), int(count), _ptr(out)))
+        return out
+
     def checkpoint(self, with_history=True):
         """State of the march after the steps taken so far (numpy uint8 buffer)."""
         n = ctypes.c_uint64()
