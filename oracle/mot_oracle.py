@@ -49,7 +49,7 @@ from scipy.special import erf, erfc
 
 __all__ = [
     "medium", "time_constants", "incidence", "projectors", "preconditioner",
-    "media_sum", "lag_matrices", "tri_rule7", "tested_fields", "rhs",
+    "media_sum", "lag_blocks", "lag_matrices", "LagOperator", "tri_rule7", "tested_fields", "rhs",
     "march", "recover", "Oracle", "block_toeplitz_solve", "star_cut",
     "rwg_at_rule_points", "current_spectrum", "radiation_vectors", "far_field",
 ]
@@ -128,37 +128,65 @@ def blk(X):
     return np.block([[X, Z], [Z, X]])
 
 
-def lag_matrices(raw, pre, P, eps_r, mu_r, Tmax, kmax):
-    """Section V-B: Q_i for i = 0 .. k_max + 1,
+def lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i):
+    """Section V-B: the media-summed raw blocks of lag i with their time
+    scalings, each zero beyond its family's truncation:
+        Z_i^h (i <= k_max),  T_max Z_i^hat (i <= k_max + 1),
+        Z_i^tilde / T_max (i <= k_max - 1).
+    raw[medium][name] has shape (nlags, ne, ne), name in T_h, K_h, T_hat,
+    K_hat, T_tilde, K_tilde; medium in ext, int; lags past the stored ones
+    are zero."""
+    _, eta, _, etap = medium(eps_r, mu_r)
+    ne = raw["ext"]["T_h"].shape[1]
+    n = 2 * ne
+
+    def Z(fam, limit, scale):
+        if i > limit or i >= raw["ext"]["T_" + fam].shape[0]:
+            return np.zeros((n, n))
+        return scale * media_sum(raw["ext"]["T_" + fam][i], raw["int"]["T_" + fam][i],
+                                 raw["ext"]["K_" + fam][i], raw["int"]["K_" + fam][i], eta, etap)
+
+    return Z("h", kmax, 1.0), Z("hat", kmax + 1, Tmax), Z("tilde", kmax - 1, 1.0 / Tmax)
+
+
+def lag_matrices(raw, pre, P, eps_r, mu_r, Tmax, kmax, nlag=None):
+    """Section V-B: Q_i for i = 0 .. k_max + 1 (only the first nlag of them
+    when nlag is given, enough for the first nlag steps of the march),
 
         Q_i^ll = C1 Z_i^h  P^{Lambda H}      (h family, i <= k_max)
         Q_i^ls = C1 Z_i^hat P^Sigma          (hat family times T_max, i <= k_max + 1)
         Q_i^ss = C2 Z_i^h  P^Sigma           (h family, i <= k_max)
         Q_i^sl = C2 Z_i^til P^{Lambda H}     (tilde family over T_max, i <= k_max - 1,
                                               truncated beyond as the paper enforces)
-    each acting block-wise on the (u; v) halves.
-    raw[medium][name] has shape (nlags, ne, ne), name in T_h, K_h, T_hat, K_hat,
-    T_tilde, K_tilde; medium in ext, int.
+    each acting block-wise on the (u; v) halves (lag_blocks for the Z's).
     """
-    _, eta, _, etap = medium(eps_r, mu_r)
-    ne = pre["C1"].shape[0]
-    n = 2 * ne
     C1b, C2b = blk(pre["C1"]), blk(pre["C2"])
     PLb, PSb = blk(P["PL"]), blk(P["PS"])
-
-    def Z(fam, i, limit, scale):
-        if i > limit or i >= raw["ext"]["T_" + fam].shape[0]:
-            return np.zeros((n, n))
-        return scale * media_sum(raw["ext"]["T_" + fam][i], raw["int"]["T_" + fam][i],
-                                 raw["ext"]["K_" + fam][i], raw["int"]["K_" + fam][i], eta, etap)
-
     Q = []
-    for i in range(kmax + 2):
-        Zh = Z("h", i, kmax, 1.0)
-        Zhat = Z("hat", i, kmax + 1, Tmax)
-        Ztil = Z("tilde", i, kmax - 1, 1.0 / Tmax)
+    for i in range(kmax + 2 if nlag is None else min(kmax + 2, nlag)):
+        Zh, Zhat, Ztil = lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i)
         Q.append(C1b @ (Zh @ PLb + Zhat @ PSb) + C2b @ (Zh @ PSb + Ztil @ PLb))
     return Q
+
+
+class LagOperator:
+    """Q_i of Section V-B as an operator, for meshes on which forming every
+    dense Q_i costs too much: the products of lag_matrices taken right to left,
+        Q_i X = C1 (Z_i^h P^{Lambda H} X + Z_i^hat P^Sigma X)
+              + C2 (Z_i^h P^Sigma X + Z_i^til P^{Lambda H} X)   (block-wise C, P),
+    equal to lag_matrices(...)[i] @ X up to the order of the roundings.
+    Q_i @ X works as with the dense matrix (march accepts either)."""
+
+    def __init__(self, raw, pre, P, eps_r, mu_r, Tmax, kmax, i, blocks=None):
+        self.Zh, self.Zhat, self.Ztil = lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i)
+        self.blocks = blocks if blocks is not None else dict(
+            C1b=blk(pre["C1"]), C2b=blk(pre["C2"]), PLb=blk(P["PL"]), PSb=blk(P["PS"]))
+
+    def __matmul__(self, X):
+        b = self.blocks
+        xl = b["PLb"] @ X
+        xs = b["PSb"] @ X
+        return b["C1b"] @ (self.Zh @ xl + self.Zhat @ xs) + b["C2b"] @ (self.Zh @ xs + self.Ztil @ xl)
 
 
 # ------------------------------------------------------------------- RHS ---
@@ -373,16 +401,34 @@ def far_field(V, F, E, spec, freq, dirs, eta=1.0, c=1.0):
 class Oracle:
     """All oracle stages for one problem dict (see fixture.problem)."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, nlag=None, operators=False, log=None):
+        """nlag: build Q_0 .. Q_{nlag-1} only; run() is then exact for the
+        first nlag steps (eq. (MOT) uses Q_1 .. Q_{i-1} at step i).
+        operators: Q_0 dense (its LU solves each step), Q_1 .. as LagOperator.
+        log: called with the name of each stage as it completes."""
         self.prob = prob
+        self.nlag = nlag
+        self.log = log if log is not None else (lambda stage: None)
         V, F, E = prob["V"], prob["F"], prob["E"]
         self.D, self.Tmax, self.kmax = time_constants(V, prob["dt"], prob["eps_r"], prob["mu_r"])
         Lam, Sig = incidence(E, V.shape[0], F.shape[0])
         self.Lam, self.Sig = Lam, Sig
         self.P = projectors(Lam, Sig)
+        self.log("projectors")
         self.pre = preconditioner(prob["T0s"], prob["T0h"], prob["G"], self.P)
-        self.Q = lag_matrices(prob["raw"], self.pre, self.P, prob["eps_r"], prob["mu_r"],
-                              self.Tmax, self.kmax)
+        self.log("preconditioner")
+        if not operators:
+            self.Q = lag_matrices(prob["raw"], self.pre, self.P, prob["eps_r"], prob["mu_r"],
+                                  self.Tmax, self.kmax, nlag)
+        else:
+            self.Q = lag_matrices(prob["raw"], self.pre, self.P, prob["eps_r"], prob["mu_r"],
+                                  self.Tmax, self.kmax, 1)
+            blocks = dict(C1b=blk(self.pre["C1"]), C2b=blk(self.pre["C2"]), PLb=blk(self.P["PL"]),
+                          PSb=blk(self.P["PS"]))
+            last = self.kmax + 2 if nlag is None else min(self.kmax + 2, nlag)
+            self.Q += [LagOperator(prob["raw"], self.pre, self.P, prob["eps_r"], prob["mu_r"], self.Tmax,
+                                   self.kmax, i, blocks) for i in range(1, last)]
+        self.log("lag matrices")
 
     def rhs_all(self, nsteps):
         p = self.prob
@@ -394,8 +440,12 @@ class Oracle:
 
     def run(self, nsteps=None):
         nsteps = self.prob["nsteps"] if nsteps is None else nsteps
+        if self.nlag is not None and nsteps > self.nlag:
+            raise ValueError("only the first %d steps are exact with %d lag matrices" % (self.nlag, self.nlag))
         r = self.rhs_all(nsteps)
+        self.log("right-hand sides")
         W = march(self.Q, r)
+        self.log("march")
         loop, star = recover(self.P, self.Tmax, self.prob["dt"], W)
         return dict(r=r, W=W, loop=loop, star=star)
 

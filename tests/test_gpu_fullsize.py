@@ -98,3 +98,57 @@ def test_sphere_3840_64_waves_mixed_prefix(precision, bound_w, bound_star):
     e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
     print("prefix errors (precision %d): w %.3e loop %.3e star %.3e" % (precision, *e), flush=True)
     assert e[0] < bound_w and e[1] < bound_w and e[2] < bound_star
+
+
+NL_C3 = 4
+
+
+def test_sphere_15360_64_waves_prefix():
+    """The 15,360-unknown sphere with 64 seeded waves (the batched benchmark
+    solve) in the configuration the benchmark times (FP64 approximate inverse,
+    speculative stepping, autotuned tiles, all 31 lags folded): one device
+    assembly pass feeds an FP64 and a mixed solver; the first 4 steps against
+    the oracle on the same inputs (Q_0 dense with its LU, the later lags as
+    operators; eq. (MOT), eq. (dis_jm)): FP64 to 1e-10, MOT_MIXED to 1e-6 on
+    w, loop and star."""
+    import torch
+    import paper_2510_07989_amd as p
+    from fixture import gpu
+    from oracle.mot_oracle import Oracle
+    print("case sphere_7680 64 waves: inputs", flush=True)
+    prob = gpu.build_problem_device("sphere_7680")
+    ne = prob["E"].shape[0]
+    assert len(prob["waves"]) == 64
+    st = torch.cuda.current_stream().cuda_stream
+    ss = [p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                   prob["T0h"], prob["G"], prob["waves"], stream=st,
+                   options=p.default_options(precond=2, precision=prec, max_steps=16)) for prec in (0, 1)]
+    names = {(0, 0): "T_h", (0, 1): "K_h", (1, 0): "T_hat", (1, 1): "K_hat", (2, 0): "T_tilde", (2, 1): "K_tilde"}
+    raw = {m: {k: np.zeros((NL_C3, ne, ne)) for k in names.values()} for m in ("ext", "int")}
+
+    def upload(fam, lag, med, op, t):
+        for s in ss:
+            s.set_lag_device(fam, lag, med, op, t)
+        if lag < NL_C3:
+            raw[("ext", "int")[med]][names[(fam, op)]][lag] = t.cpu().numpy()
+
+    def progress(i):
+        if i % 8 == 0:
+            print("lag", i, "uploaded", flush=True)
+
+    gpu.upload_lags(upload, prob["V"], prob["F"], prob["E"], prob["dt"], prob["eps_r"], prob["mu_r"],
+                    prob["kmax"], nq=prob["nq"], on_lag=progress)
+    assert all(s.info()["folded"] == 1 for s in ss)
+    print("march", flush=True)
+    outs = [s.run(NL_C3) for s in ss]
+    for s in ss:
+        s.close()
+    del ss
+    torch.cuda.empty_cache()
+    print("oracle", flush=True)
+    ref = Oracle(dict(prob, raw=raw), nlag=NL_C3, operators=True,
+                 log=lambda stage: print("oracle:", stage, flush=True)).run(NL_C3)
+    for out, bound, tag in ((outs[0], 1e-10, "fp64"), (outs[1], 1e-6, "mixed")):
+        e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+        print("%s prefix errors: w %.3e loop %.3e star %.3e" % (tag, *e), flush=True)
+        assert max(e) < bound, (tag, e)

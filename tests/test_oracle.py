@@ -487,3 +487,67 @@ def test_march_resumes_from_earlier_steps():
     tail = march(Q, r[4:], lu=sla.lu_factor(Q[0]), W0=head)
     assert np.array_equal(head, full[:4])
     assert np.array_equal(tail, full[4:])
+
+
+def test_lag_operator_and_prefix_oracle_match_the_dense_form():
+    """The operator form of Q_i (Section V-B, the same products right to left)
+    against lag_matrices on every lag, with every family's truncation crossed;
+    an oracle built on the first lags only, dense or with operators, marches
+    the first steps as the full one does (bitwise for the dense prefix)."""
+    from oracle.mot_oracle import Oracle, LagOperator, lag_matrices
+    prob = problem("tiny_box")
+    O = oracle("tiny_box")
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((O.Q[0].shape[0], 3))
+    for i in range(O.kmax + 2):
+        op = LagOperator(prob["raw"], O.pre, O.P, prob["eps_r"], prob["mu_r"], O.Tmax, O.kmax, i)
+        ref = O.Q[i] @ X
+        assert np.linalg.norm(op @ X - ref) <= 1e-13 * max(np.linalg.norm(ref), 1e-300), i
+    # truncations: hat is the last family alive at k_max + 1, tilde stops at k_max - 1
+    assert np.abs(O.Q[O.kmax + 1]).max() > 0
+    full = O.run(6)
+    pre = Oracle(prob, nlag=6).run(6)
+    for k in ("W", "loop", "star"):
+        assert np.array_equal(pre[k], full[k])
+    ops = Oracle(prob, nlag=6, operators=True).run(6)
+    for k in ("W", "loop", "star"):
+        assert np.linalg.norm(ops[k] - full[k]) <= 1e-12 * np.linalg.norm(full[k]), k
+    with pytest.raises(ValueError):
+        Oracle(prob, nlag=6).run(7)
+    assert len(lag_matrices(prob["raw"], O.pre, O.P, prob["eps_r"], prob["mu_r"], O.Tmax, O.kmax, 3)) == 3
+
+
+@pytest.mark.parametrize("name", ["tiny_torus", "tiny_box"])
+def test_lag0_tilde_k_is_the_static_double_layer_when_kmax_is_1(name):
+    """Sec. V-B, eq. (spec_prop): once c_min dt >= D (k_max = 1), the lag-0
+    tilde K block is dt K_0 (the same block over dt at every such dt), and
+    T^Lambda G^-1 P^{Lambda H} K_0 P^{Lambda H} vanishes but for the
+    quadrature error of K_0.  Kept in Q_0, that error grows like dt / T_max
+    and with it cond(Q_0) (6.6e3 at c dt = 1024 m on the torus); dropped, as
+    the paper drops the tilde K tail beyond k_max - 1, cond(Q_0) stays put."""
+    from fixture.problem import CONFIGS, build_problem
+    from oracle.mot_oracle import Oracle, blk
+    K0, conds, full = [], [], []
+    for dt in (64.0, 1024.0):
+        prob = build_problem(cfg=dict(CONFIGS[name], dt=dt), nsteps=2)
+        O = Oracle(prob, nlag=1)
+        assert O.kmax == 1
+        K = prob["raw"]["ext"]["K_tilde"][0] + prob["raw"]["int"]["K_tilde"][0]
+        K0.append(K / dt)
+        # the identity holds to the quadrature error only
+        res = np.linalg.norm(O.pre["C2"] @ K0[-1] @ O.P["PL"]) / (np.linalg.norm(O.pre["C2"]) * np.linalg.norm(K0[-1]))
+        assert 1e-5 < res < 1e-2, res
+        # Q_0 with the block kept: the oracle's plus the K part of C2 Z^tilde P^{Lambda H}
+        Z = np.zeros((2 * K.shape[0],) * 2)
+        ne = K.shape[0]
+        Z[:ne, ne:] = -K / O.Tmax
+        Z[ne:, :ne] = K / O.Tmax
+        Qk = O.Q[0] + blk(O.pre["C2"]) @ Z @ blk(O.P["PL"])
+        s = np.linalg.svd(O.Q[0], compute_uv=False)
+        sk = np.linalg.svd(Qk, compute_uv=False)
+        conds.append(s[0] / s[-1])
+        full.append(sk[0] / sk[-1])
+    assert np.linalg.norm(K0[1] - K0[0]) <= 1e-12 * np.linalg.norm(K0[0])
+    print(name, "cond with the block dropped", conds, "kept", full)
+    assert max(conds) / min(conds) < 1.05
+    assert full[1] > 2 * full[0]
