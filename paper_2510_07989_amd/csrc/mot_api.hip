@@ -1542,7 +1542,9 @@ static int spec_settle(SpecRun& r) {
     if (src && src != MOT_ENOCONV) return src;
     if (src) r.worst = src;
     if ((rc = read_spec(h, &r.w0))) return rc;
-    h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
+    // a step that needed more Arnoldi steps raises the count the later queued
+    // steps take; one that did not converge at all tells nothing about them
+    if (h->last_conv) h->spec_iters = std::min(h->M, std::max(h->spec_iters, h->last_iters));
     r.done += w.halt_k - r.k0;
     return MOT_OK;
 }

@@ -59,6 +59,26 @@ struct GmFlag {
     volatile double relres;
 };
 
+// Norm of a GMRES opening (||y||, ||r||) from two sums of squares of its
+// entries: the plain one, and one of the entries scaled by 2^600.  The plain
+// sum is used while it is at least 2^-960; below that every entry is under
+// 2^-480, its scaled square cannot overflow, and the scaled sum keeps the
+// digits that the plain one loses once the squares fall below the normal
+// range (entries under ~1.5e-154, which late steps of a decaying march reach).
+// An inaccurate norm would leave the first Krylov vector off unit length,
+// after which the Gram-Schmidt steps cannot bring the residual to tolerance.
+// Norms at or below MOT_ZERO_NORM count as a zero right-hand side (x = 0):
+// their reciprocal would overflow.
+#define MOT_NORM_SCALE 0x1p600
+#define MOT_ZERO_NORM 0x1p-1000
+__device__ __forceinline__ double sq_scaled(double v) {
+    const double t = v * MOT_NORM_SCALE;
+    return t * t;
+}
+__device__ __forceinline__ double open_norm(double plain, double scaled) {
+    return plain >= 0x1p-960 ? sqrt(plain) : sqrt(scaled) * 0x1p-600;
+}
+
 // --------------------------------------------------------- kernel entry ---
 namespace motk {
 // dense

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB
     __shared__ double red[256];
     const int c = threadIdx.x % RP, r0 = threadIdx.x / RP, stride = 256 / RP;
     const int i0 = blockIdx.x * RB, i1 = min(n2, i0 + RB);
-    double s1 = 0, s2 = 0;
+    double s1 = 0, s2 = 0, t1 = 0, t2 = 0;      // plain and scaled sums of squares
     for (int i = i0 + r0; i < i1; i += stride) {
         const size_t o = (size_t)i * RP + c;
         if (xzero) xzero[o] = 0.0;
@@ -201,28 +201,34 @@ __global__ __launch_bounds__(256) void k_gmb_start(int n2, int RP, int R, int RB
         r[o] = ri;
         s1 = fma(ri, ri, s1);
         s2 = fma(bi, bi, s2);
+        t1 += sq_scaled(ri);
+        t2 += sq_scaled(bi);
     }
     double* P = part + (size_t)blockIdx.x * (MOT_MAXM + 1) * RP;
     col_sums(s1, RP, red, P);
     col_sums(s2, RP, red, P + RP);
+    col_sums(t1, RP, red, P + 2 * RP);
+    col_sums(t2, RP, red, P + 3 * RP);
     if (!last_of_grid(&agg->counter)) return;
-    // part[b][0][c] and part[b][RP + c] = part[b][1][c]
+    // part[b][l][c], l = 0, 1: plain sums of r and y; 2, 3: scaled sums
     const double a1 = grid_col_sum(part, gridDim.x, RP, 0, red);
     const double a2 = grid_col_sum(part, gridDim.x, RP, 1, red);
+    const double b1 = grid_col_sum(part, gridDim.x, RP, 2, red);
+    const double b2 = grid_col_sum(part, gridDim.x, RP, 3, red);
     if ((int)threadIdx.x < RP) {
         GmState* g = gms + c;
-        const double beta = sqrt(a1);
-        if (first) { g->bnorm = sqrt(a2); g->total = 0; }
+        const double beta = open_norm(a1, b1);
+        if (first) { g->bnorm = open_norm(a2, b2); g->total = 0; }
         g->beta = beta;
         g->g[0] = beta;
         g->j = 0;
         g->cycle_iters = 0;
         const double bn = g->bnorm;
         g->relres = bn > 0 ? beta / bn : 0.0;
-        const int conv = (bn == 0.0) || (beta <= tol * bn);
+        const int conv = (bn <= MOT_ZERO_NORM) || (beta <= MOT_ZERO_NORM) || (beta <= tol * bn);
         g->converged = conv;
         g->done = conv;
-        g->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+        g->inv_h = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
     }
     __syncthreads();
     if (first && threadIdx.x == 0) agg->seq = 0;

@@ -122,9 +122,10 @@ __device__ __forceinline__ void row1(const double* __restrict__ A, const double*
     }
 }
 
-// row1 that also adds the squares of the vector entries it reads into sq
+// row1 that also adds the squares of the vector entries it reads into sq,
+// and their squares scaled by 2^600 into ss (open_norm)
 __device__ __forceinline__ void row1sq(const double* __restrict__ A, const double* __restrict__ xa,
-                                       int len, int lane, double& sa, double& sq) {
+                                       int len, int lane, double& sa, double& sq, double& ss) {
     const d2v* a2 = reinterpret_cast<const d2v*>(A);
     const d2v* x2 = reinterpret_cast<const d2v*>(xa);
     const int n2 = len >> 1;
@@ -138,6 +139,7 @@ __device__ __forceinline__ void row1sq(const double* __restrict__ A, const doubl
             d2v xu = x2[c + 64 * u];
             sa = fma(a[u].x, xu.x, sa); sa = fma(a[u].y, xu.y, sa);
             sq = fma(xu.x, xu.x, sq); sq = fma(xu.y, xu.y, sq);
+            ss += sq_scaled(xu.x); ss += sq_scaled(xu.y);
         }
     }
     for (; c < n2; c += 64) {
@@ -145,6 +147,7 @@ __device__ __forceinline__ void row1sq(const double* __restrict__ A, const doubl
         d2v u0 = x2[c];
         sa = fma(a0.x, u0.x, sa); sa = fma(a0.y, u0.y, sa);
         sq = fma(u0.x, u0.x, sq); sq = fma(u0.y, u0.y, sq);
+        ss += sq_scaled(u0.x); ss += sq_scaled(u0.y);
     }
 }
 
@@ -159,10 +162,10 @@ __device__ __forceinline__ void open_cycle(GmState* gm, double beta, double tol)
     gm->cycle_iters = 0;
     gm->breakdown = 0;
     gm->relres = beta > 0 ? beta / beta : 0.0;
-    const int conv = (beta == 0.0) || (beta <= tol * beta);
+    const int conv = (beta <= MOT_ZERO_NORM) || (beta <= tol * beta);
     gm->converged = conv;
     gm->done = conv;
-    gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+    gm->inv_h = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
     gm->seq = 1;
 }
 
@@ -361,8 +364,8 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
     const int m = blockIdx.x * (4 / wpr) + wv / wpr;
     const int part = wv % wpr;
     const int plen = n2 / wpr, off = part * plen;
-    __shared__ double red[4], rq[4];
-    double s0 = 0, s1 = 0, sq = 0;
+    __shared__ double red[4], rq[4], rs[4];
+    double s0 = 0, s1 = 0, sq = 0, ss = 0;
     if (m < n2) {
         const T* row = M + (size_t)m * n2 + off;
         const double* xs = src + off;
@@ -391,24 +394,24 @@ __global__ __launch_bounds__(256) void k_precond(int n2, const T* __restrict__ M
                 s1 = fma((double)a0.z, u0.z, s1); s1 = fma((double)a0.w, u0.w, s1);
             }
         } else if (start) {
-            row1sq(reinterpret_cast<const double*>(row), xs, plen, lane, s0, sq);
+            row1sq(reinterpret_cast<const double*>(row), xs, plen, lane, s0, sq, ss);
         } else {
             row1(reinterpret_cast<const double*>(row), xs, plen, lane, s0);
         }
     }
     double s = wave_sum(s0 + s1);
-    if (start) sq = wave_sum(sq);
-    if (lane == 0) { red[wv] = s; rq[wv] = sq; }
+    if (start) { sq = wave_sum(sq); ss = wave_sum(ss); }
+    if (lane == 0) { red[wv] = s; rq[wv] = sq; rs[wv] = ss; }
     __syncthreads();
     if (lane == 0 && part == 0 && m < n2) {
         double t = 0;
         for (int p = 0; p < wpr; ++p) t += red[wv + p];
         double sc = start ? 0.0 : gm->inv_h;
         if (start) {
-            double q = 0;
-            for (int p = 0; p < wpr; ++p) q += rq[wv + p];
-            const double beta = sqrt(q);
-            sc = beta > 0 ? 1.0 / beta : 0.0;
+            double q = 0, qs = 0;
+            for (int p = 0; p < wpr; ++p) { q += rq[wv + p]; qs += rs[wv + p]; }
+            const double beta = open_norm(q, qs);
+            sc = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
             x[m] = 0.0;
             if (m == 0) open_cycle(gm, beta, tol);
         }
@@ -632,7 +635,7 @@ __global__ __launch_bounds__(256) void k_precond_rows(int n2, const T* __restric
     double s[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[r] = 0.0;
-    double sq = 0.0;
+    double sq = 0.0, ss = 0.0;
     if constexpr (sizeof(T) == 8) {
         const int np = n2 >> 1;
         const d2v* A = reinterpret_cast<const d2v*>(M);
@@ -656,12 +659,18 @@ __global__ __launch_bounds__(256) void k_precond_rows(int n2, const T* __restric
                     s[r] = fma(a[u][r].x, xx.x, s[r]);
                     s[r] = fma(a[u][r].y, xx.y, s[r]);
                 }
-                if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
+                if (start) {
+                    sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq);
+                    ss += sq_scaled(xx.x); ss += sq_scaled(xx.y);
+                }
             }
         }
         for (; c < c1; c += 64) {
             const d2v xx = x2[c];
-            if (start) { sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq); }
+            if (start) {
+                sq = fma(xx.x, xx.x, sq); sq = fma(xx.y, xx.y, sq);
+                ss += sq_scaled(xx.x); ss += sq_scaled(xx.y);
+            }
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
                 const d2v a = __builtin_nontemporal_load(A + ro[r] + c);
@@ -706,7 +715,7 @@ __global__ __launch_bounds__(256) void k_precond_rows(int n2, const T* __restric
             }
         }
     }
-    __shared__ double red[4][RPW + 1];
+    __shared__ double red[4][RPW + 2];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         s[r] = wave_sum(s[r]);
@@ -714,16 +723,17 @@ __global__ __launch_bounds__(256) void k_precond_rows(int n2, const T* __restric
     }
     if (start) {
         sq = wave_sum(sq);
-        if (lane == 0) red[part][RPW] = sq;
+        ss = wave_sum(ss);
+        if (lane == 0) { red[part][RPW] = sq; red[part][RPW + 1] = ss; }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double sc = start ? 0.0 : gm->inv_h;
         if (start) {
-            double q = 0;
-            for (int p = 0; p < cs; ++p) q += red[p][RPW];
-            const double beta = sqrt(q);
-            sc = beta > 0 ? 1.0 / beta : 0.0;
+            double q = 0, qs = 0;
+            for (int p = 0; p < cs; ++p) { q += red[p][RPW]; qs += red[p][RPW + 1]; }
+            const double beta = open_norm(q, qs);
+            sc = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
             if (m0 == 0) open_cycle(gm, beta, tol);
         }
 #pragma unroll
@@ -826,26 +836,37 @@ __global__ __launch_bounds__(256) void k_gm_residual(int n2, const double* __res
                                                      double* __restrict__ r, GmState* gm,
                                                      GmFlag* flag, double tol, int first) {
     __shared__ double sh[8];
-    double s1 = 0, s2 = 0;
+    double s1 = 0, s2 = 0, t1 = 0, t2 = 0;      // plain and scaled sums of squares
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
         double bi = b[i];
         double ri = bi - r[i];
         r[i] = ri;
         s1 = fma(ri, ri, s1);
         s2 = fma(bi, bi, s2);
+        t1 += sq_scaled(ri);
+        t2 += sq_scaled(bi);
     }
     s1 = block_sum(s1, sh);
     s2 = block_sum(s2, sh);
+    t1 = block_sum(t1, sh);
+    t2 = block_sum(t2, sh);
     if (threadIdx.x == 0) {
         gm->partial[blockIdx.x] = s1;
         gm->partial[MOT_GM_BLOCKS + blockIdx.x] = s2;
+        gm->partial[2 * MOT_GM_BLOCKS + blockIdx.x] = t1;
+        gm->partial[3 * MOT_GM_BLOCKS + blockIdx.x] = t2;
     }
     if (!last_block(&gm->counter)) return;
     if (threadIdx.x == 0) {
-        double rr = 0, bb = 0;
-        for (int i = 0; i < (int)gridDim.x; ++i) { rr += gm->partial[i]; bb += gm->partial[MOT_GM_BLOCKS + i]; }
-        double beta = sqrt(rr);
-        if (first) { gm->bnorm = sqrt(bb); gm->total = 0; }
+        double rr = 0, bb = 0, rs = 0, bs = 0;
+        for (int i = 0; i < (int)gridDim.x; ++i) {
+            rr += gm->partial[i];
+            bb += gm->partial[MOT_GM_BLOCKS + i];
+            rs += gm->partial[2 * MOT_GM_BLOCKS + i];
+            bs += gm->partial[3 * MOT_GM_BLOCKS + i];
+        }
+        double beta = open_norm(rr, rs);
+        if (first) { gm->bnorm = open_norm(bb, bs); gm->total = 0; }
         gm->beta = beta;
         gm->g[0] = beta;
         gm->j = 0;
@@ -853,10 +874,10 @@ __global__ __launch_bounds__(256) void k_gm_residual(int n2, const double* __res
         gm->breakdown = 0;
         double bn = gm->bnorm;
         gm->relres = bn > 0 ? beta / bn : 0.0;
-        int conv = (bn == 0.0) || (beta <= tol * bn);
+        int conv = (bn <= MOT_ZERO_NORM) || (beta <= MOT_ZERO_NORM) || (beta <= tol * bn);
         gm->converged = conv;
         gm->done = conv;
-        gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+        gm->inv_h = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
         gm->counter = 0;
         flag->relres = gm->relres;
         flag->converged = conv;
@@ -1014,7 +1035,7 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
                                                     double* __restrict__ xzero) {
     if (gm->halt) return;
     __shared__ double sh[kSW / 64];
-    double s1 = 0, s2 = 0;
+    double s1 = 0, s2 = 0, t1 = 0, t2 = 0;      // plain and scaled sums of squares
     for (int i = threadIdx.x; i < n2; i += kSW) {
         if (xzero) xzero[i] = 0.0;      // cold start x0 = 0
         double bi = b[i];
@@ -1022,12 +1043,16 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
         r[i] = ri;
         s1 = fma(ri, ri, s1);
         s2 = fma(bi, bi, s2);
+        t1 += sq_scaled(ri);
+        t2 += sq_scaled(bi);
     }
     s1 = block_sum_sw(s1, sh);
     s2 = block_sum_sw(s2, sh);
+    t1 = block_sum_sw(t1, sh);
+    t2 = block_sum_sw(t2, sh);
     if (threadIdx.x == 0) {
-        double beta = sqrt(s1);
-        if (first) { gm->bnorm = sqrt(s2); gm->total = 0; gm->seq = 0; }
+        double beta = open_norm(s1, t1);
+        if (first) { gm->bnorm = open_norm(s2, t2); gm->total = 0; gm->seq = 0; }
         gm->beta = beta;
         gm->g[0] = beta;
         gm->j = 0;
@@ -1035,10 +1060,10 @@ __global__ __launch_bounds__(kSW) void k_gm_start1(int n2, const double* __restr
         gm->breakdown = 0;
         double bn = gm->bnorm;
         gm->relres = bn > 0 ? beta / bn : 0.0;
-        int conv = (bn == 0.0) || (beta <= tol * bn);
+        int conv = (bn <= MOT_ZERO_NORM) || (beta <= MOT_ZERO_NORM) || (beta <= tol * bn);
         gm->converged = conv;
         gm->done = conv;
-        gm->inv_h = beta > 0 ? 1.0 / beta : 0.0;
+        gm->inv_h = beta > MOT_ZERO_NORM ? 1.0 / beta : 0.0;
         ++gm->seq;
         if (flag) {               // null: queued steps, nobody waits on the host
             flag->relres = gm->relres;
