@@ -235,7 +235,10 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt,
  * the device and the raw blocks are dropped.  A lag outside its family's
  * range is MOT_EINVAL (the truncation is part of the method), so is a block
  * with a non-finite entry (nothing is staged; the block may be sent again);
- * uploading a block twice is MOT_ESTATE. */
+ * uploading a block twice is MOT_ESTATE.  With k_max = 1 the lag-0 tilde K
+ * block (exactly dt times the static double layer, every pair lying inside
+ * the first shell) is accepted and not used: by eq. (spec_prop) it adds
+ * nothing to Q_0, as the tilde K tail adds nothing beyond k_max - 1. */
 int mot_set_lag(mot_handle* h, int32_t family, int32_t lag, int32_t medium, int32_t op,
                 const double* block);
 

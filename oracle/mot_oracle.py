@@ -12,8 +12,8 @@ Formulation"):
 * quasi-Helmholtz projectors ............... Section IV-B (projector defs)
 * static preconditioner, loop-star form .... Section III, eq. (CP)
 * media sum of the PMCHWT blocks ........... Section II, eq. (PMCHWT)
-* lag matrices Q_i = Q^ll + Q^ls + Q^sl + Q^ss and the truncations
-  ............................................. Section V-B
+* lag matrices Q_i = Q^ll + Q^ls + Q^sl + Q^ss and the truncations,
+  eq. (spec_prop) ................................ Section V-B
 * right-hand side, loop and star parts ..... Section V-C, eq. (rhs), (hin)
 * marching-on-in-time recurrence ........... Section V-A, eq. (MOT)
 * current recovery, loop/star kept apart ... Section V-A, eq. (dis_jm)
@@ -29,6 +29,9 @@ Readings where the paper is silent (also listed in the design notes):
 * exterior c = eta = 1; interior c' = 1/sqrt(eps_r mu_r), eta' = sqrt(mu_r/eps_r);
 * D = largest vertex distance, T_max = D / min(c, c'), k_max = ceil(T_max/dt);
 * the raw hat and tilde blocks arrive without their T_max, 1/T_max factors;
+* when k_max = 1 the lag-0 tilde K block is exactly dt K_0 (every pair inside
+  the first shell) and is dropped like the tilde tail beyond k_max - 1, by
+  eq. (spec_prop), so that its quadrature error does not grow with dt;
 * RWG testing of the incident field uses the 7-point degree-5 triangle rule;
 * the star part of the RHS is set to zero once the pulse has passed every
   point of the surface: t > t0 + (max_x k.x + 1.6 w)/c (erfc(6.4) ~ 1e-19);
@@ -133,6 +136,13 @@ def lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i):
     scalings, each zero beyond its family's truncation:
         Z_i^h (i <= k_max),  T_max Z_i^hat (i <= k_max + 1),
         Z_i^tilde / T_max (i <= k_max - 1).
+    The K part of Z_i^tilde is the time integral of the double layer; where it
+    equals its constant tail (dt/T_max) K_0, eq. (spec_prop) makes its
+    contribution to Q_i^sl vanish, and the paper sets it to zero (i > k_max - 1,
+    where the whole tilde family is truncated).  The same holds at lag 0 when
+    k_max = 1 (c_min dt >= D): every pair lies in the first shell, where the
+    integral of p_0 is dt - R/c and its constant part has no gradient, so the
+    lag-0 tilde K block is exactly dt K_0 and is set to zero as well.
     raw[medium][name] has shape (nlags, ne, ne), name in T_h, K_h, T_hat,
     K_hat, T_tilde, K_tilde; medium in ext, int; lags past the stored ones
     are zero."""
@@ -140,13 +150,16 @@ def lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i):
     ne = raw["ext"]["T_h"].shape[1]
     n = 2 * ne
 
-    def Z(fam, limit, scale):
+    def Z(fam, limit, scale, static_k=False):
         if i > limit or i >= raw["ext"]["T_" + fam].shape[0]:
             return np.zeros((n, n))
-        return scale * media_sum(raw["ext"]["T_" + fam][i], raw["int"]["T_" + fam][i],
-                                 raw["ext"]["K_" + fam][i], raw["int"]["K_" + fam][i], eta, etap)
+        Ke, Ki = raw["ext"]["K_" + fam][i], raw["int"]["K_" + fam][i]
+        if static_k:
+            Ke, Ki = np.zeros_like(Ke), np.zeros_like(Ki)
+        return scale * media_sum(raw["ext"]["T_" + fam][i], raw["int"]["T_" + fam][i], Ke, Ki, eta, etap)
 
-    return Z("h", kmax, 1.0), Z("hat", kmax + 1, Tmax), Z("tilde", kmax - 1, 1.0 / Tmax)
+    return (Z("h", kmax, 1.0), Z("hat", kmax + 1, Tmax),
+            Z("tilde", kmax - 1, 1.0 / Tmax, static_k=(i == 0 and kmax <= 1)))
 
 
 def lag_matrices(raw, pre, P, eps_r, mu_r, Tmax, kmax, nlag=None):

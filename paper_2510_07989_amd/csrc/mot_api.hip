@@ -424,6 +424,15 @@ int stage_add(mot_handle* h, int family, int lag, int medium, int op, const doub
         int rc = dalloc(h, &S, 3 * blk);
         if (rc) return rc;
     }
+    // Eq. (spec_prop): T^Lambda G^-1 P^{Lambda H} K_0 P^{Lambda H} = 0 for the
+    // static double layer K_0, so the tilde K blocks that equal their constant
+    // tail dt K_0 add nothing to Q_i^sl (the paper drops them beyond k_max - 1,
+    // where the family is truncated).  With k_max = 1 (c_min dt >= D) every
+    // pair lies in the first shell, where the integral of p_0 is dt - R/c and
+    // its constant part has no gradient: the lag-0 tilde K block is exactly
+    // dt K_0 and is dropped too, so that its quadrature error, amplified by
+    // dt / T_max, stays out of Q_0.
+    if (family == MOT_FAM_TILDE && op == MOT_OP_K && lag == 0 && h->kmax <= 1) return MOT_OK;
     double sc = family == MOT_FAM_HAT ? h->Tmax : (family == MOT_FAM_TILDE ? 1.0 / h->Tmax : 1.0);
     double et = medium == MOT_EXT ? h->eta : h->etap;
     if (op == MOT_OP_T) {

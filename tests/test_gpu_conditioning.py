@@ -13,7 +13,7 @@ def test_gmres_iterations_flat_in_dt():
     from fixture.problem import CONFIGS, build_problem
     from oracle.mot_oracle import Oracle
     its = []
-    for dt in (4.0, 16.0, 64.0):
+    for dt in (4.0, 16.0, 64.0, 256.0, 512.0):         # c dt up to 512 m, as in Sec. VI
         print("dt", dt, flush=True)
         prob = build_problem(cfg=dict(CONFIGS["tiny_box"], dt=dt), nsteps=20)
         waves = prob["waves"][:1]

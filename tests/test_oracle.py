@@ -178,11 +178,12 @@ def test_rhs_time_integral_and_star_tail():
 def test_q0_condition_flat_in_dt(name):
     """Sec. VI (conditioning versus time step): the qHP Q_0 stays equally well
     conditioned as c dt grows past the diameter, where the classical system
-    degrades like dt^2.  Here c dt runs from 2 D to 32 D (k_max = 1 or 2)."""
+    degrades like dt^2.  Here c dt runs from 4 m to 512 m, the top of the
+    paper's range (1.4 D to 510 D on these meshes; k_max = 1 from 16 m on)."""
     from fixture.problem import CONFIGS, build_problem
     from oracle.mot_oracle import Oracle
     conds = []
-    for dt in (4.0, 16.0, 64.0):
+    for dt in (4.0, 16.0, 64.0, 256.0, 512.0):
         O = Oracle(build_problem(cfg=dict(CONFIGS[name], dt=dt), nsteps=4))
         s = np.linalg.svd(O.Q[0], compute_uv=False)
         conds.append(s[0] / s[-1])
@@ -191,13 +192,13 @@ def test_q0_condition_flat_in_dt(name):
 
 
 def test_pyramid_q0_condition_does_not_grow_with_dt():
-    """The star pyramid (48 thin facets, sharp tips): as c dt runs from 2 D to
-    32 D the qHP Q_0 does not degrade (it improves, 361 -> 187), where the
-    classical system's condition number grows like dt^2."""
+    """The star pyramid (48 thin facets, sharp tips): as c dt runs from 4 m to
+    512 m (2 D to 256 D) the qHP Q_0 does not degrade, where the classical
+    system's condition number grows like dt^2."""
     from fixture.problem import CONFIGS, build_problem
     from oracle.mot_oracle import Oracle
     conds = []
-    for dt in (4.0, 16.0, 64.0):
+    for dt in (4.0, 16.0, 64.0, 256.0, 512.0):
         O = Oracle(build_problem(cfg=dict(CONFIGS["tiny_pyramid"], dt=dt), nsteps=4))
         s = np.linalg.svd(O.Q[0], compute_uv=False)
         conds.append(s[0] / s[-1])
