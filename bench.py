@@ -178,7 +178,7 @@ def col_blocks(R):
     return min(4, (rp + 15) // 16)
 
 
-def history_kernel_name(R, precision, mix_group, sched_hist=11):
+def history_kernel_name(R, precision, mix_group, sched_hist=11, wg=4):
     if R == 1:
         if sched_hist in (11, 22, 24):
             return "k_history_co"
@@ -186,7 +186,7 @@ def history_kernel_name(R, precision, mix_group, sched_hist=11):
     if precision == 2:
         fl = {64: 16, 16: 4}.get(mix_group, 1)
         return "k_hist_mfma<%d, %d>" % (col_blocks(R), fl)
-    return "k_tile_gemm<%s, %d>" % ("double" if precision == 0 else "float", col_blocks(R))
+    return "k_tile_gemm<%s, %d, %d>" % ("double" if precision == 0 else "float", col_blocks(R), wg)
 
 
 # HIP events bracket every PROFILE_EVERY-th history and Q_0 launch of the timed
@@ -276,13 +276,13 @@ def timed(s, prob, name, precision, K, W_, hilo, mix_group, outputs=True, keep_w
     hist_us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
     q0_us = 1e3 * (b["q0_ms"] - a["q0_ms"]) / max(1, b["q0_launches"] - a["q0_launches"])
     hb, hf = history_model(ne, n, L, R, precision, hilo)
-    kname = history_kernel_name(R, precision, mix_group, inf0["sched_hist"])
+    kname = history_kernel_name(R, precision, mix_group, inf0["sched_hist"], inf0["hist_wg"])
     dtype = "f32" if precision == 2 else "f64"
     hist = roofline(kname, hb, hf, hist_us, dtype, R > 1, measured_traffic(kname, name))
     q0b = 8.0 * (3 * ne * ne + 2 * n * R)
     sq = inf0["sched_q0"]
     q0name = (("k_q0_rows<%d>" % (sq % 10) if sq > 10 else "k_q0_matvec") if R == 1
-              else "k_tile_gemm<double, %d>" % col_blocks(R))
+              else "k_tile_gemm<double, %d, %d>" % (col_blocks(R), inf0["q0_wg"]))
     q0 = roofline(q0name, q0b, 2.0 * 4 * ne * ne * R, q0_us, "f64", R > 1,
                   measured_traffic(q0name if R == 1 else q0name + " (Q_0)", name))
     hist_tot = b["hist_ms"] - a["hist_ms"]
@@ -294,6 +294,7 @@ def timed(s, prob, name, precision, K, W_, hilo, mix_group, outputs=True, keep_w
                device_gb=inf0["device_bytes"] / 1e9, setup_ms=inf0["setup_ms"], fold_ms=inf0["fold_ms"],
                precond_iters=inf0["precond_iters"], precond_resid=inf0["precond_resid"],
                schedule={"history": inf0["sched_hist"], "q0": inf0["sched_q0"], "precond": inf0["sched_pc"],
+                         "history_wg": inf0["hist_wg"], "q0_wg": inf0["q0_wg"],
                          "autotuned": bool(inf0["tuned"]), "tune_ms": round(inf0["tune_ms"], 1)})
     log("[%s R=%d %s] timed %d steps in %.3f s: %.2f steps/s (%.1f RHS-steps/s), %.2f GMRES its/step; "
         "history %.1f us (%s %.4g %s, %.3f of peak), Q0 product %.1f us; %.1f GB on device"
@@ -416,6 +417,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--no-serving-c4", action="store_true", help="skip the time-boxed serving stream")
+    ap.add_argument("--serving-c4-requests", type=int, default=256)
+    ap.add_argument("--serving-c4-box", type=float, default=120.0, help="seconds before the stream is cut")
+    ap.add_argument("--serving-c4-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-step-batch", action="store_true", help="skip the mot_run_batch comparison")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with an FP32 low part (-1: none)")
@@ -500,6 +505,8 @@ def run_legs(mot, args, result):
         result["torus"] = torus_leg(mot, args)
     if not args.no_step_batch:
         result["step_batch"] = step_batch(mot)
+    if not args.no_serving_c4:
+        result["serving_c4"] = serving_c4(args)
     if args.serving:
         result["serving"] = serving(args.serving_requests)
     print(json.dumps(result), flush=True)
@@ -569,6 +576,117 @@ def step_batch(mot, nsteps=1024, copies=4):
     log("step batch: %d solves x %d steps: one after another %.1f steps/s, mot_run_batch %.1f steps/s (x%.2f), "
         "identical %s" % (len(ss), nsteps, tot / t_seq, tot / t_bat, t_seq / t_bat, same))
     return res
+
+
+def c4_requests(nreq, seed=251007991, rate=2.0):
+    """The serving stream: nreq seeded requests with Poisson arrivals (rate per
+    second), each a random sphere, torus or cube whose unknown count is drawn
+    log-uniformly from 500 to 20,000, eps_r uniform in [1.5, 6], mu_r = 1,
+    c dt = D / 4 (so k_max = ceil(4 sqrt(eps_r)), 5 to 10), 1 to 32 seeded
+    plane waves (sigma = 4 dt), 500 to 5,000 steps.  The mesh is built here;
+    the BC basis, Gram matrix, static blocks and every retarded block are
+    built in the request's setup (the last two on the device), so setup time
+    counts in its end-to-end latency."""
+    import math
+    import numpy as np
+    from fixture import gpu as fxgpu
+    from fixture import geometry as geo
+    from fixture.problem import make_mesh, make_waves, tmax_kmax
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    out = []
+    for i in range(nreq):
+        kind = ("sphere", "torus", "cube")[int(rng.integers(3))]
+        n_target = math.exp(rng.uniform(math.log(500), math.log(20000)))
+        if kind == "sphere":                      # 60 nu^2 unknowns
+            spec = ("icosphere", max(3, int(round(math.sqrt(n_target / 60)))))
+        elif kind == "torus":                     # 6 nmaj nmin unknowns, nmaj = 4 nmin
+            nmin = max(3, int(round(math.sqrt(n_target / 24))))
+            spec = ("torus", 1.0, 0.4, 4 * nmin, nmin)
+        else:                                     # 36 m^2 unknowns
+            spec = ("box", *(3 * [max(2, int(round(math.sqrt(n_target / 36))))]))
+        eps_r = float(rng.uniform(1.5, 6.0))
+        R = int(rng.integers(1, 33))
+        nsteps = int(rng.integers(500, 5001))
+        wseed = int(rng.integers(1 << 30))
+        V, F, E = make_mesh(spec)
+        D = geo.diameter(V)
+        dt = D / 4.0
+        Tmax, kmax = tmax_kmax(D, dt, eps_r, 1.0)
+        ne = E.shape[0]
+        waves = make_waves(R, 4.0 * dt, True, seed=wseed)
+
+        def prepare(V=V, F=F, E=E, eps_r=eps_r, dt=dt, kmax=kmax):
+            inp = fxgpu.device_inputs(V, F, E)
+
+            def loader(s, V=V, F=F, E=E, eps_r=eps_r, dt=dt, kmax=kmax):
+                fxgpu.load_solvers([s], dict(V=V, F=F, E=E, eps_r=eps_r, mu_r=1.0, dt=dt, kmax=kmax, nq=7))
+            return dict(G=inp["G"], T0s=inp["T0s"], T0h=inp["T0h"], loader=loader)
+
+        prob = dict(name="%s_%d" % (kind, 2 * ne), V=V, F=F, E=E, eps_r=eps_r, mu_r=1.0, dt=dt, kmax=kmax,
+                    waves=waves, gnnz=24 * ne, prepare=prepare,
+                    # the assembler's rings: three lags of six blocks per medium, while it runs
+                    extra_bytes=2 * 3 * 6 * 8 * ne * ne)
+        out.append((prob, nsteps, float(arrivals[i])))
+    return out
+
+
+def serving_c4(args):
+    """Continuous batching at serving scale (see c4_requests for the stream):
+    the batch server (every active solve stepped together through
+    mot_run_batch, windows of 128 steps in speculative windows of 32, three
+    setup threads beside it), admission by peak footprint plus the assembler's
+    memory under a budget, at most 16 solves at once, time-boxed: at the box
+    the solves still running are stopped with mot_cancel and requests not yet
+    admitted are not served.  Step latency: a batch call's wall time over its
+    steps, for every solve in it."""
+    import numpy as np
+    import torch
+    from paper_2510_07989_amd.serve import BatchServer, GpuBackend, Request, latency_stats
+    t = time.perf_counter()
+    stream = c4_requests(args.serving_c4_requests)
+    log("[c4] %d requests generated in %.1f s" % (len(stream), time.perf_counter() - t))
+    reqs = [Request(i, p, ns, arr, dict(precond=2, spec_window=32)) for i, (p, ns, arr) in enumerate(stream)]
+    be = GpuBackend(keep_outputs=False)
+    budget = int(args.serving_c4_budget_gb * 1e9)
+    srv = BatchServer(be, mem_budget=budget, max_active=16, window=128, setup_workers=3,
+                      time_box=args.serving_c4_box, request_timeout=args.serving_c4_box, log=log)
+    res, summ = srv.run(reqs)
+    torch.cuda.empty_cache()
+    done = [r for r in res.values() if r.error is None]
+    sizes = sorted(2 * q.problem["E"].shape[0] for q in reqs)
+    out = {
+        "workload": "C4 stream: %d requests, Poisson arrivals at 2/s, sphere/torus/cube of %d to %d unknowns "
+                    "(log-uniform), eps_r U[1.5, 6], 1-32 waves, 500-5000 steps, c dt = D/4; inputs built in "
+                    "each request's setup (static and retarded blocks on the device)"
+                    % (len(reqs), sizes[0], sizes[-1]),
+        "server": "batch (mot_run_batch, 128-step calls, 32-step windows, 3 setup threads, <= 16 active)",
+        "time_box_s": args.serving_c4_box, "mem_budget_gb": args.serving_c4_budget_gb,
+        "completed": summ["completed"], "cancelled_at_box": summ["cancelled"], "not_served": summ["not_served"],
+        "errors": summ["errors"], "wall_s": round(summ["wall_s"], 2),
+        "steps_marched": summ["steps_marched"], "steps_per_s": round(summ["steps_per_s"], 1),
+        "rhs_steps_per_s": round(summ["rhs_steps_per_s"], 1),
+        "step_latency_us": {k: round(1e6 * v, 1) if k != "n" else v for k, v in summ["step_latency_s"].items()},
+        "end_to_end_s": {k: round(v, 3) if k != "n" else v for k, v in summ["end_to_end_s"].items()},
+        "setup_s": {k: round(v, 3) if k != "n" else v
+                    for k, v in latency_stats(r.t_ready - r.t_admit for r in res.values()
+                                              if r.t_ready > 0).items()},
+        "queue_wait_s": {k: round(v, 3) if k != "n" else v for k, v in summ["queue_wait_s"].items()},
+        "max_concurrent": summ["max_concurrent"], "peak_budget_gb": round(summ["peak_budget_used"] / 1e9, 2),
+        "completed_unknowns": {"max": max((2 * q.problem["E"].shape[0] for q in reqs
+                                           if res[q.rid].error is None), default=0),
+                               "median": float(np.median([2 * q.problem["E"].shape[0] for q in reqs
+                                                          if res[q.rid].error is None] or [0]))},
+    }
+    errs = [r.error for r in res.values() if r.error and not r.error.startswith(("CancelledRun", "NotServed"))]
+    if errs:
+        out["first_errors"] = errs[:3]
+    log("[c4] %d completed, %d cancelled at the box, %d not served, %d errors in %.1f s; %.0f steps/s, step p50 "
+        "%.0f us p99 %.0f us; end-to-end p50 %.2f s p99 %.2f s"
+        % (summ["completed"], summ["cancelled"], summ["not_served"], summ["errors"], summ["wall_s"],
+           summ["steps_per_s"], 1e6 * summ["step_latency_s"]["p50"], 1e6 * summ["step_latency_s"]["p99"],
+           summ["end_to_end_s"]["p50"], summ["end_to_end_s"]["p99"]))
+    return out
 
 
 def serving(nreq, have=None, seed=251007990):

@@ -204,6 +204,21 @@ def upload_lags(upload, V, F, E, dt, eps_r, mu_r, kmax, nq=7, nth=5, nrh=5, lags
             a.close()
 
 
+def device_inputs(V, F, E, nq_static=6):
+    """Host BC refinement and Gram matrix, and the static blocks assembled on
+    the device (returned as host arrays): the keys G, T0s, T0h, D, refinement."""
+    import torch
+    from . import geometry as geo, bc as bcmod
+    D = geo.diameter(V)
+    R = bcmod.refine(V, F, E)
+    G = bcmod.gram_bc(V, F, E, R)
+    T0s, T0h = static_blocks(R, D, nq=nq_static)
+    torch.cuda.current_stream().synchronize()
+    out = dict(G=G, T0s=T0s.cpu().numpy(), T0h=T0h.cpu().numpy(), D=D, refinement=R)
+    del T0s, T0h
+    return out
+
+
 def build_problem_device(name=None, cfg=None, nsteps=None):
     """Inputs of a configuration with the static blocks assembled on the device
     and no retarded blocks (those are streamed by upload_lags): the keys of

@@ -40,7 +40,8 @@ enum {
     MOT_ENOMEM = -2,   /* device allocation failed or over mem_cap_bytes    */
     MOT_ENOCONV = -3,  /* GMRES hit its iteration cap; the step is kept     */
     MOT_EHIP = -4,     /* a HIP runtime call failed                         */
-    MOT_ESTATE = -5    /* call out of order (e.g. a required lag missing)   */
+    MOT_ESTATE = -5,   /* call out of order (e.g. a required lag missing)   */
+    MOT_ECANCEL = -6   /* the run was stopped by mot_cancel; steps kept    */
 };
 
 enum { MOT_FP64 = 0, MOT_MIXED = 1, MOT_MIXED32 = 2 }; /* history precision     */
@@ -149,6 +150,12 @@ typedef struct {
                                 legacy default stream, queue their launches
                                 one by one.  Ignored with profile = 1.
                                 Results are identical to graph = 0.           */
+    int32_t tile_wg;         /* several RHS: wavefronts per workgroup of the
+                                history and Q_0 tile products, 4 (64 rows) or
+                                8 (128 rows sharing each staged slice of the
+                                history vectors); 0 (default): the autotuner
+                                picks (4 without it).  Results do not depend
+                                on it.                                         */
 } mot_options;
 
 typedef struct {
@@ -195,6 +202,8 @@ typedef struct {
     int32_t sched_pc;        /* approximate inverse: as sched_q0 / K chunks   */
     double tune_ms;          /* time spent timing candidates (0 on a cache hit) */
     int64_t graph_windows;   /* windows replayed from captured graphs          */
+    int32_t hist_wg, q0_wg;  /* several RHS: wavefronts per workgroup of the
+                                history and Q_0 tile products (4 or 8)        */
 } mot_info;
 
 typedef struct mot_handle mot_handle;
@@ -368,6 +377,19 @@ int mot_restore(mot_handle* h, const void* buf, uint64_t size);
  * else the first error among the handles, else MOT_ENOCONV if any step hit
  * its iteration cap, else MOT_OK. */
 int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* status);
+
+/* Stop a mot_run or mot_run_batch in progress on h, for a server whose
+ * request outlives its time limit: safe to call from any host thread.  The
+ * run stops at its next window boundary (at most spec_window steps of the
+ * speculative march, or the next step when it steps one at a time) and
+ * returns MOT_ECANCEL (in h's status slot for mot_run_batch, the other
+ * handles going on); every completed step is kept and the handle stays
+ * usable, a later mot_run continuing from there.  mot_run's outputs then
+ * hold the completed steps (mot_get_info: steps_done), the rest of its
+ * output arrays untouched.  A request made while no run is in progress stops
+ * the next run before its first window; mot_reset clears it.  Returns MOT_OK,
+ * or MOT_EINVAL for a NULL handle. */
+int mot_cancel(mot_handle* h);
 
 /* Copy internal operators to host memory (diagnostics and parity checks):
  *   which 0: Q_lag as dense [n][n]; 1: C1 [ne][ne]; 2: C2 [ne][ne];

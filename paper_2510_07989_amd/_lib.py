@@ -5,7 +5,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmot.so")
 
-MOT_OK, MOT_EINVAL, MOT_ENOMEM, MOT_ENOCONV, MOT_EHIP, MOT_ESTATE = 0, -1, -2, -3, -4, -5
+MOT_OK, MOT_EINVAL, MOT_ENOMEM, MOT_ENOCONV, MOT_EHIP, MOT_ESTATE, MOT_ECANCEL = 0, -1, -2, -3, -4, -5, -6
 MOT_FP64, MOT_MIXED, MOT_MIXED32 = 0, 1, 2
 FAM_H, FAM_HAT, FAM_TILDE = 0, 1, 2
 MED_EXT, MED_INT = 0, 1
@@ -30,7 +30,7 @@ class MotOptions(ctypes.Structure):
                 ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
                 ("precond", _I), ("stream_split", _I), ("history_order", _I),
                 ("hilo_lags", _I), ("mix_group", _I), ("spec_window", _I),
-                ("recovery", _I), ("autotune", _I), ("graph", _I)]
+                ("recovery", _I), ("autotune", _I), ("graph", _I), ("tile_wg", _I)]
 
 
 class MotStepInfo(ctypes.Structure):
@@ -45,14 +45,14 @@ class MotInfo(ctypes.Structure):
                 ("q0_ms", _D), ("q0_launches", ctypes.c_int64), ("recover_ms", _D),
                 ("precond_iters", _I), ("precond_resid", _D), ("peak_bytes", ctypes.c_uint64),
                 ("tuned", _I), ("sched_hist", _I), ("sched_q0", _I), ("sched_pc", _I), ("tune_ms", _D),
-                ("graph_windows", ctypes.c_int64)]
+                ("graph_windows", ctypes.c_int64), ("hist_wg", _I), ("q0_wg", _I)]
 
 
 EXPORTS = ["mot_default_options", "mot_create", "mot_set_lag", "mot_set_lag_csr", "mot_step",
            "mot_run", "mot_get_matrix", "mot_get_info", "mot_reset", "mot_destroy",
            "mot_last_error", "mot_footprint", "mot_get_steps", "mot_run_batch",
            "mot_far_field", "mot_checkpoint_size", "mot_checkpoint", "mot_restore",
-           "mot_step_norms", "mot_set_lag_device", "mot_step_norms_noalloc"]
+           "mot_step_norms", "mot_set_lag_device", "mot_step_norms_noalloc", "mot_cancel"]
 
 _lib = None
 
@@ -103,6 +103,8 @@ def load():
     lib.mot_step_norms_noalloc.restype = _I
     lib.mot_run_batch.argtypes = [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(_I)]
     lib.mot_run_batch.restype = _I
+    lib.mot_cancel.argtypes = [_P]
+    lib.mot_cancel.restype = _I
     lib.mot_get_matrix.argtypes = [_P, _I, _I, _P]
     lib.mot_get_matrix.restype = _I
     lib.mot_get_info.argtypes = [_P, ctypes.POINTER(MotInfo)]

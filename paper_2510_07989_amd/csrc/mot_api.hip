@@ -1005,6 +1005,8 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
         return mot_fail(nullptr, MOT_EINVAL, "recovery must be 0 (dense projector) or 1 (graph-Laplacian CG)");
     if (opt && opt->mix_group != 0 && opt->mix_group != 4 && opt->mix_group != 16 && opt->mix_group != 64)
         return mot_fail(nullptr, MOT_EINVAL, "mix_group must be 4, 16 or 64 (0: 4)");
+    if (opt && opt->tile_wg != 0 && opt->tile_wg != 4 && opt->tile_wg != 8)
+        return mot_fail(nullptr, MOT_EINVAL, "tile_wg must be 0 (tuned), 4 or 8");
     // ---- mesh validation (host, integers) ----
     const int32_t* E = mesh->edges;
     const int32_t* F = mesh->tris;
@@ -1067,6 +1069,7 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     plan_dims(h, nv, nf, ne, nrhs, mesh->verts, eps_r, mu_r, dt);
     h->stream = (hipStream_t)stream;
     h->genus = (2 - chi) / 2;
+    h->hist_wg = h->q0_wg = h->opt.tile_wg == 8 ? 8 : 4;
     double t_start = now_ms();
     int rc = MOT_OK;
     auto bail = [&](int code) { g_create_err = h->err; mot_destroy(h); return code; };
@@ -1299,6 +1302,7 @@ int mot_reset(mot_handle* h) {
     h->hist_first = 0;
     h->iters_total = 0;
     h->spec_iters = 1;               // as a new handle: the same Arnoldi counts, the same bits
+    h->cancel.store(0);
     (void)ev_flush(h, h->ev_hist);
     (void)ev_flush(h, h->ev_q0);
     h->ev_hist.ms = h->ev_q0.ms = 0;
@@ -1569,16 +1573,22 @@ static void spec_abort(mot_handle* h) {
     (void)hipStreamSynchronize(h->stream);
 }
 
+// a pending mot_cancel, consumed by the run it stops
+static bool take_cancel(mot_handle* h) { return h->cancel.exchange(0) != 0; }
+
 static int run_spec_windows(mot_handle* h, int nsteps, int* worst) {
     SpecRun r;
     int rc = spec_begin(r, h, nsteps);
+    bool cancelled = false;
     while (!rc && r.done < nsteps) {
+        if (take_cancel(h)) { cancelled = true; break; }
         rc = spec_queue(r);
         if (!rc) rc = spec_settle(r);
     }
     if (rc) return rc;
     spec_end(r);
     if (r.worst) *worst = r.worst;
+    if (cancelled) *worst = MOT_ECANCEL;
     return MOT_OK;
 }
 
@@ -1613,17 +1623,19 @@ int mot_run(mot_handle* h, int32_t nsteps, double* w_out, double* loop_out, doub
         inf.converged = h->last_conv;
     } else {
         for (int i = 0; i < nsteps; ++i) {
+            if (take_cancel(h)) { worst = MOT_ECANCEL; break; }
             int rc = mot_step(h, &inf);
             if (rc && rc != MOT_ENOCONV) return rc;
             if (rc) worst = rc;
         }
     }
     if (last) *last = inf;
-    if (!(w_out || loop_out || star_out) || nsteps == 0) {
+    const int done = h->k - s0;          // all nsteps unless cancelled
+    if (!(w_out || loop_out || star_out) || done == 0) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
         return worst;
     }
-    return emit_steps(h, s0, nsteps, w_out, loop_out, star_out, out_on_device, worst);
+    return emit_steps(h, s0, done, w_out, loop_out, star_out, out_on_device, worst);
 }
 
 // outputs of the kept steps s0 .. s0+nsteps-1: the unknowns as computed and
@@ -1922,7 +1934,14 @@ int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* sta
     }
     auto drop = [&](int i, int rc) { status[i] = rc; spec_abort(hs[i]); };
     std::vector<int> next;
+    // a handle whose run is cancelled stops at a window boundary, its steps kept
+    auto stop = [&](int i) {
+        spec_end(runs[i]);
+        hipError_t e = hipStreamSynchronize(hs[i]->stream);
+        status[i] = e != hipSuccess ? mot_fail(hs[i], MOT_EHIP, hipGetErrorString(e)) : MOT_ECANCEL;
+    };
     for (int i : live) {
+        if (take_cancel(hs[i])) { stop(i); continue; }
         int rc = spec_queue(runs[i]);
         if (rc) drop(i, rc); else next.push_back(i);
     }
@@ -1932,6 +1951,7 @@ int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* sta
         for (int i : live) {
             SpecRun& r = runs[i];
             int rc = spec_settle(r);
+            if (!rc && r.done < nsteps && take_cancel(r.h)) { stop(i); continue; }
             if (!rc && r.done < nsteps) rc = spec_queue(r);
             if (rc) { drop(i, rc); continue; }
             if (r.done < nsteps) { next.push_back(i); continue; }
@@ -1948,6 +1968,12 @@ int mot_run_batch(mot_handle* const* hs, int32_t n, int32_t nsteps, int32_t* sta
     for (int i = 0; i < n; ++i)
         if (status[i] && (worst == MOT_OK || worst == MOT_ENOCONV)) worst = status[i];
     return worst;
+}
+
+int mot_cancel(mot_handle* h) {
+    if (!h) return MOT_EINVAL;
+    h->cancel.store(1);
+    return MOT_OK;
 }
 
 int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
@@ -2039,6 +2065,8 @@ int mot_get_info(const mot_handle* hc, mot_info* info) {
     info->sched_pc = h->Rp > 1 ? h->plain_kc : h->sch_pc;
     info->tune_ms = h->tune_ms;
     info->graph_windows = h->graph_windows;
+    info->hist_wg = h->hist_wg;
+    info->q0_wg = h->q0_wg;
     return MOT_OK;
 }
 

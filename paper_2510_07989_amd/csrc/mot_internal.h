@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -134,6 +135,7 @@ struct mot_handle {
     double setup_ms = 0, fold_ms = 0;
     uint64_t bytes = 0;
     uint64_t peak_bytes = 0;         // high-water mark of bytes
+    std::atomic<int> cancel{0};      // mot_cancel: stop the run at its next window boundary
     int device = -1;                 // HIP device current at create
     double* scratch = nullptr;       // this device's static scratch array (mot_step_norms_noalloc)
     std::vector<void*> allocs;
@@ -209,6 +211,7 @@ struct mot_handle {
     int hilo = 0;                    // lags with a low part
     int spec_iters = 1;              // Arnoldi steps queued per speculative step
     int hist_kc = 1, q0_kc = 1;      // K chunks of the tile products
+    int hist_wg = 4, q0_wg = 4;      // wavefronts per workgroup of the tile products (4 or 8)
     int plain_kc = 1;                // K chunks of the preconditioner product (Rp > 1)
     std::vector<int> hist_kc_c, q0_kc_c, plain_kc_c;   // autotuner candidates (Rp > 1)
     int orth_nb = 1, orth_rb = 1;    // workgroups and rows of the multi-RHS Krylov sweeps

@@ -509,8 +509,11 @@ __device__ __forceinline__ void unpack(const RawTiles<float>& r, bool hl, double
 // History (q0_mode 0): lag j = blockIdx.y + 1, At = tiles of lag 1, W = ring
 // slot of w_{k-j}.  Q_0 (q0_mode 1): At = tiles of lag 0, W = X.
 // Partial results part[(blockIdx.y * KC + kc)][2][ne][Rp].
-template <typename T, int CB>
-__global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int KT, int Rp,
+// WG wavefronts per workgroup (4 or 8: 64 or 128 rows) share each staged slice
+// of the history vectors: with 8, every slice read from L2 serves twice the
+// rows.  The rows' sums are the same either way.
+template <typename T, int CB, int WG>
+__global__ __launch_bounds__(64 * WG) void k_tile_gemm(int ne, int hs, int G16, int KT, int Rp,
                                                    const int* __restrict__ dk, int nh, int q0_mode,
                                                    const T* __restrict__ At, const float* __restrict__ Alo,
                                                    int hilo, const double* __restrict__ ring,
@@ -535,9 +538,10 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
 
     constexpr int NC = CB * 16;                // columns staged
     constexpr int ST = CB >= 4 ? 2 : 4;        // tiles per staged slice
+    constexpr int NT = 64 * WG;                // threads
     __shared__ double Ws[2][ST * 16][NC + 2];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int g = blockIdx.x * 4 + wv;
+    const int g = blockIdx.x * WG + wv;
     const bool gok = g < G16;
     const int kq = 4 * (lane >> 4), cl = lane & 15;
 
@@ -566,13 +570,13 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
     // LDS after the barrier; with four, the registers are worth more as
     // occupancy and the slice is loaded between the barriers.
     constexpr bool WPF = CB < 4;
-    constexpr int WE = ST * 16 * NC / 256;     // staged (u, v) pairs per thread
+    constexpr int WE = ST * 16 * NC / NT;      // staged (u, v) pairs per thread
     double pu[WPF ? WE : 1], pv[WPF ? WE : 1];
     auto wfetch = [&](int cs) {
         const int nst = min(ST, c1 - cs);
 #pragma unroll
         for (int q = 0; q < WE; ++q) {
-            const int e = t + 256 * q;
+            const int e = t + NT * q;
             const int col = e % NC, kk = e / NC;
             const int gk = cs * 16 + kk;
             pu[q] = pv[q] = 0.0;
@@ -591,12 +595,12 @@ __global__ __launch_bounds__(256) void k_tile_gemm(int ne, int hs, int G16, int 
         if constexpr (WPF) {
 #pragma unroll
             for (int q = 0; q < WE; ++q) {
-                const int e = t + 256 * q;
+                const int e = t + NT * q;
                 Ws[0][e / NC][e % NC] = pu[q];
                 Ws[1][e / NC][e % NC] = pv[q];
             }
         } else {
-            for (int e = t; e < ST * 16 * NC; e += 256) {
+            for (int e = t; e < ST * 16 * NC; e += NT) {
                 const int col = e % NC, kk = e / NC;
                 const int gk = cs * 16 + kk;
                 double wu = 0.0, wvv = 0.0;
@@ -906,16 +910,20 @@ void plain_product(mot_handle* h, const double* src, double* vj, double* z) {
 
 template <typename T>
 void tile_launch(mot_handle* h, int q0_mode, const T* At, const float* Alo, const double* X, int KC, int groups) {
-    dim3 grid((h->G16 + 3) / 4, groups, KC);
+    const int WG = (q0_mode ? h->q0_wg : h->hist_wg) == 8 ? 8 : 4;
+    dim3 grid((h->G16 + WG - 1) / WG, groups, KC);
     const int CB = (h->Rp + 15) / 16;
-#define L_(CB_) hipLaunchKernelGGL((k_tile_gemm<T, CB_>), grid, dim3(256), 0, h->stream, h->ne, h->hs, h->G16, h->KT, \
-                                   h->Rp, h->d_k, h->nh, q0_mode, At, Alo, h->hilo, h->ring, X, KC, h->mr_part, h->gm)
+#define L_(CB_, WG_) hipLaunchKernelGGL((k_tile_gemm<T, CB_, WG_>), grid, dim3(64 * WG_), 0, h->stream, h->ne, h->hs, \
+                                        h->G16, h->KT, h->Rp, h->d_k, h->nh, q0_mode, At, Alo, h->hilo, h->ring, X, \
+                                        KC, h->mr_part, h->gm)
+#define W_(CB_) do { if (WG == 8) L_(CB_, 8); else L_(CB_, 4); } while (0)
     if (CB == 1)
-        L_(1);
+        W_(1);
     else if (CB == 2)
-        L_(2);
+        W_(2);
     else
-        L_(4);
+        W_(4);
+#undef W_
 #undef L_
 }
 

@@ -8,7 +8,9 @@
 //                 history the loop order (column slices across all lag blocks,
 //                 or whole rows of one block);
 //   several RHS:  the number of K chunks of the tile products on MFMA (more
-//                 chunks: more workgroups in flight, more partial sums to add).
+//                 chunks: more workgroups in flight, more partial sums to add),
+//                 and their workgroup shape: 4 or 8 wavefronts (64 or 128
+//                 rows) sharing each staged slice of the history vectors.
 // The fastest schedule depends on the sizes, the lag count and the chip, so it
 // is measured: once all lags are folded, each candidate runs on the real
 // operands a few times on the handle's stream, timed with HIP events, and the
@@ -43,6 +45,7 @@ namespace {
 struct Schedule {
     int sch_hist, sch_q0, sch_pc;
     int hist_kc, q0_kc, plain_kc;
+    int hist_wg, q0_wg;
 };
 
 typedef std::tuple<int, int, int, int, int, int, int, int, int, int> Key;
@@ -53,11 +56,11 @@ std::map<Key, Schedule> g_cache;
 Key key_of(const mot_handle* h, int dev) {
     return Key(dev, h->ne, h->nh, h->Rp, h->opt.precision, h->hilo, h->opt.precond,
                h->opt.precision == MOT_MIXED32 ? h->opt.mix_group : 0, 2 * h->tune_hist + h->tune_mv,
-               h->tune_hist ? 0 : h->sch_hist);
+               (h->tune_hist ? 0 : h->sch_hist) + 100000 * h->opt.tile_wg);
 }
 
 Schedule current(const mot_handle* h) {
-    return Schedule{h->sch_hist, h->sch_q0, h->sch_pc, h->hist_kc, h->q0_kc, h->plain_kc};
+    return Schedule{h->sch_hist, h->sch_q0, h->sch_pc, h->hist_kc, h->q0_kc, h->plain_kc, h->hist_wg, h->q0_wg};
 }
 
 void apply(mot_handle* h, const Schedule& s) {
@@ -67,6 +70,8 @@ void apply(mot_handle* h, const Schedule& s) {
     h->hist_kc = s.hist_kc;
     h->q0_kc = s.q0_kc;
     h->plain_kc = s.plain_kc;
+    h->hist_wg = s.hist_wg;
+    h->q0_wg = s.q0_wg;
 }
 
 // Smallest time (ms) of `reps` launches of f, after one untimed launch.
@@ -140,7 +145,17 @@ int tune(mot_handle* h) {
                           [&] { motk_step::precond(h, h->wA, h->V, h->Z); }, reps);
         }
     } else {
-        rc = pick(h, "history K chunks", h->hist_kc_c, [&](int v) { h->hist_kc = v; }, [&] { motk_multi::history_gemm(h); }, reps);
+        // workgroup shape at the sized K chunks, then the K chunks at that shape
+        const std::vector<int> wg = {4, 8};
+        // the FP32-product kernel has one shape; tile_wg fixes it
+        const bool tiles = h->opt.precision != MOT_MIXED32 && h->opt.tile_wg == 0;
+        if (tiles)
+            rc = pick(h, "history workgroup wavefronts", wg, [&](int v) { h->hist_wg = v; },
+                      [&] { motk_multi::history_gemm(h); }, reps);
+        if (!rc) rc = pick(h, "history K chunks", h->hist_kc_c, [&](int v) { h->hist_kc = v; }, [&] { motk_multi::history_gemm(h); }, reps);
+        if (!rc && h->opt.tile_wg == 0)
+            rc = pick(h, "Q_0 workgroup wavefronts", wg, [&](int v) { h->q0_wg = v; },
+                      [&] { motk_multi::q0_gemm(h, h->x); }, reps);
         if (!rc) rc = pick(h, "Q_0 K chunks", h->q0_kc_c, [&](int v) { h->q0_kc = v; }, [&] { motk_multi::q0_gemm(h, h->x); }, reps);
         if (!rc && (h->M32 || h->M64))
             rc = pick(h, "approximate inverse K chunks", h->plain_kc_c, [&](int v) { h->plain_kc = v; },

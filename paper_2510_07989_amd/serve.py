@@ -22,6 +22,20 @@ Per request the server records:
 
 Overall it records p50/p99 step and end-to-end latency and aggregate steps/s.
 
+Two servers share the admission rule:
+
+* ``Server`` runs every admitted solve on its own HIP stream and host thread
+  (windows of ``mot_run``);
+* ``BatchServer`` keeps one marching thread that steps all active solves
+  together through ``mot_run_batch`` (their windows interleaved across their
+  streams, as one host thread can queue them), while a small pool of setup
+  threads creates and loads newly admitted solves; a solve joins the batch at
+  the next window after its setup and leaves it when done.
+
+A request past its time limit, or still running when the server's time box
+closes, is stopped with ``mot_cancel`` at its next window boundary; its slot
+and memory are then released.
+
 The backend is pluggable: ``GpuBackend`` drives ``paper_2510_07989_amd.Solver``;
 tests substitute a host-only backend to check the scheduling on its own.
 """
@@ -34,14 +48,15 @@ from typing import Any, Callable, Dict, List, Optional
 
 import numpy as np
 
-__all__ = ["Request", "Result", "Server", "GpuBackend", "latency_stats"]
+__all__ = ["Request", "Result", "Server", "BatchServer", "GpuBackend", "latency_stats"]
 
 
 @dataclass
 class Request:
     """One scattering solve: ``problem`` carries the mot_create inputs and the
-    raw lag blocks (keys V, F, E, eps_r, mu_r, dt, T0s, T0h, G, waves, raw,
-    kmax); ``arrival`` is seconds after the server starts."""
+    raw lag blocks (keys V, F, E, eps_r, mu_r, dt, T0s, T0h, G, waves, and
+    raw with kmax, or instead a callable ``loader(solver)`` that uploads the
+    blocks itself); ``arrival`` is seconds after the server starts."""
     rid: int
     problem: Dict[str, Any]
     nsteps: int
@@ -79,12 +94,87 @@ def latency_stats(values) -> Dict[str, float]:
             "mean": float(v.mean()), "max": float(v.max())}
 
 
+class CancelledRun(RuntimeError):
+    """A solve stopped by mot_cancel (time limit or time box)."""
+
+
 class GpuBackend:
     """Runs a request on the current GPU through the C ABI, on a stream of its own."""
 
     def __init__(self, options: Optional[Dict[str, Any]] = None, keep_outputs: bool = True):
         self.options = dict(options or {})
         self.keep_outputs = keep_outputs
+        self._live: Dict[int, Any] = {}
+        self._live_lock = threading.Lock()
+
+    def cancel(self, rid: int) -> bool:
+        """Stop request rid's march at its next window boundary (mot_cancel)."""
+        with self._live_lock:
+            s = self._live.get(rid)
+        if s is None:
+            return False
+        s.cancel()
+        return True
+
+    def _load(self, s, p):
+        if p.get("loader") is not None:
+            p["loader"](s)
+        else:
+            s.load_raw(p["raw"], p["kmax"])
+
+    def setup(self, req: Request):
+        """Create and load request req's solver on a stream of its own (batch server)."""
+        import torch
+        import paper_2510_07989_amd as mot
+        torch.cuda.set_device(0)
+        stream = torch.cuda.Stream()          # default priority
+        with torch.cuda.stream(stream):
+            p = self._inputs(req.problem)
+            s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
+                           p["waves"], options=self._opts(req), stream=stream.cuda_stream)
+            try:
+                self._load(s, p)
+                stream.synchronize()
+            except Exception:
+                s.close()
+                raise
+        s._serve_stream = stream
+        with self._live_lock:
+            self._live[req.rid] = s
+        return s
+
+    def outputs(self, req: Request, s, nsteps: int) -> Dict[str, np.ndarray]:
+        if not self.keep_outputs or nsteps == 0:
+            return {}
+        out = s.steps(0, nsteps)
+        return {k: out[k] for k in ("w", "loop", "star")}
+
+    def close(self, req: Request, s) -> None:
+        with self._live_lock:
+            self._live.pop(req.rid, None)
+        s.close()
+
+    def run_batch(self, solvers, nsteps):
+        """March the solvers together (mot_run_batch); per solver 0 (done or
+        iteration cap), "cancelled", or an error message."""
+        import paper_2510_07989_amd as mot
+        from paper_2510_07989_amd import _lib as L
+        lib = L.load()
+        import ctypes
+        n = len(solvers)
+        hs = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
+        st = (ctypes.c_int32 * n)()
+        lib.mot_run_batch(hs, n, int(nsteps), st)
+        out = []
+        for i, s in enumerate(solvers):
+            c = st[i]
+            if c in (L.MOT_OK, L.MOT_ENOCONV):
+                out.append(0)
+            elif c == L.MOT_ECANCEL:
+                out.append("cancelled")
+            else:
+                out.append("MotError(%d): %s" % (c, lib.mot_last_error(s._h).decode()))
+        return out
 
     def _opts(self, req: Request):
         import paper_2510_07989_amd as mot
@@ -94,11 +184,22 @@ class GpuBackend:
         return mot.default_options(**o)
 
     def footprint(self, req: Request) -> int:
+        """Peak device bytes of the solve (mot_footprint), plus the request's
+        own extra_bytes (device memory its loader needs while it runs)."""
         import paper_2510_07989_amd as mot
         p = req.problem
-        _, peak = mot.footprint(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], len(p["waves"]), p["G"],
-                                self._opts(req))
-        return peak
+        _, peak = mot.footprint(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], len(p["waves"]), p.get("G"),
+                                self._opts(req), gnnz=p.get("gnnz"))
+        return peak + int(p.get("extra_bytes", 0))
+
+    @staticmethod
+    def _inputs(p):
+        """A request whose inputs are built at setup carries prepare() -> the
+        missing keys (G, T0s, T0h, and raw with kmax or a loader)."""
+        if p.get("prepare") is not None:
+            p = dict(p)
+            p.update(p.pop("prepare")())
+        return p
 
     def execute(self, req: Request, window: int, clock: Callable[[], float], res: Result) -> None:
         import torch
@@ -109,11 +210,13 @@ class GpuBackend:
             self._march(mot, torch, stream, req, window, clock, res)
 
     def _march(self, mot, torch, stream, req, window, clock, res):
-        p = req.problem
+        p = self._inputs(req.problem)
         s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
                        p["waves"], options=self._opts(req), stream=stream.cuda_stream)
+        with self._live_lock:
+            self._live[req.rid] = s
         try:
-            s.load_raw(p["raw"], p["kmax"])
+            self._load(s, p)
             stream.synchronize()
             res.t_ready = clock()
             parts = {"w": [], "loop": [], "star": []}
@@ -124,15 +227,21 @@ class GpuBackend:
                 out = s.run(nw, w=self.keep_outputs, loop=self.keep_outputs, star=self.keep_outputs, device=True)
                 stream.synchronize()
                 dt = clock() - t0
-                res.step_latency.extend([dt / nw] * nw)
+                got = nw if not out["cancelled"] else s.info()["steps_done"] - done
+                if got:
+                    res.step_latency.extend([dt / got] * got)
                 if self.keep_outputs:
                     for k in parts:
                         parts[k].append(out[k])
-                done += nw
+                done += got
+                if out["cancelled"]:
+                    raise CancelledRun("stopped by mot_cancel after %d of %d steps" % (done, req.nsteps))
             if self.keep_outputs:
                 for k, v in parts.items():
                     res.outputs[k] = torch.cat(v).cpu().numpy()
         finally:
+            with self._live_lock:
+                self._live.pop(req.rid, None)
             s.close()
 
 
@@ -170,6 +279,7 @@ class Server:
         used = 0
         lock = threading.Lock()
         finished: List[int] = []
+        cancelled = set()
 
         def worker(req: Request):
             res = results[req.rid]
@@ -195,14 +305,18 @@ class Server:
                     r = results[rid]
                     self.log("[serve %.2fs] request %d done (%d steps, %.3f s end to end%s); %d active"
                              % (clock(), rid, r.nsteps, r.end_to_end, ", " + r.error if r.error else "", len(active)))
-            # a request past its time limit is reported and its slot and memory
-            # stay held (its thread cannot be stopped from here)
+            # a request past its time limit is stopped at its next window
+            # boundary (mot_cancel); its thread then ends and frees the slot
             for rid in list(active):
                 r = results[rid]
-                if r.error is None and clock() - r.t_admit > self.request_timeout:
-                    r.error = "TimeoutError: still running after %.0f s" % self.request_timeout
+                if r.error is None and rid not in cancelled and clock() - r.t_admit > self.request_timeout:
+                    cancelled.add(rid)
+                    stopped = getattr(self.backend, "cancel", lambda _rid: False)(rid)
                     if self.log:
-                        self.log("[serve %.2fs] request %d exceeded %.0f s" % (clock(), rid, self.request_timeout))
+                        self.log("[serve %.2fs] request %d exceeded %.0f s%s" % (clock(), rid, self.request_timeout,
+                                                                              ", cancelled" if stopped else ""))
+                    if not stopped:
+                        r.error = "TimeoutError: still running after %.0f s" % self.request_timeout
             if active and all(results[rid].error for rid in active) and not queue and not pending:
                 break
             # strict arrival order: the head waits until it fits
@@ -238,6 +352,204 @@ class Server:
             "step_latency_s": latency_stats(x for r in results.values() for x in r.step_latency),
             "end_to_end_s": latency_stats(r.end_to_end for r in results.values() if r.error is None),
             "queue_wait_s": latency_stats(r.queue_wait for r in results.values()),
+            "max_concurrent": max((t[3] for t in self.trace), default=0),
+            "peak_budget_used": max((t[4] for t in self.trace), default=0),
+        }
+        return results, summary
+
+
+class BatchServer:
+    """Continuous batching from one marching thread (see module doc).
+
+    The backend provides footprint(req), setup(req) -> solver (created and
+    loaded, on its own stream), outputs(req, solver, nsteps), close(req,
+    solver), and a run_batch(solvers, nsteps) -> codes that marches them
+    together and returns each one's code (0, or "cancelled" for one stopped by
+    its cancel()).  window: steps per batch call; a solve joins or leaves the
+    batch between calls.  time_box: seconds after start when every solve still
+    running is cancelled and requests not yet admitted are dropped (reported
+    as not served)."""
+
+    def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 128, setup_workers: int = 2,
+                 poll: float = 0.002, request_timeout: float = 600.0, time_box: Optional[float] = None,
+                 log: Optional[Callable[[str], None]] = None):
+        self.backend = backend
+        self.mem_budget = int(mem_budget)
+        self.max_active = int(max_active)
+        self.window = int(window)
+        self.setup_workers = int(setup_workers)
+        self.poll = poll
+        self.request_timeout = float(request_timeout)
+        self.time_box = time_box
+        self.log = log
+        self.trace: List[tuple] = []          # (time, event, rid, active, used bytes)
+
+    def run(self, requests: List[Request]):
+        """Serve every request; returns (results by rid, summary dict)."""
+        from concurrent.futures import ThreadPoolExecutor
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        fp = {r.rid: int(self.backend.footprint(r)) for r in reqs}
+        for r in reqs:
+            if fp[r.rid] > self.mem_budget:
+                raise ValueError("request %d needs %d bytes, more than the budget %d" % (r.rid, fp[r.rid],
+                                                                                          self.mem_budget))
+        t_start = time.perf_counter()
+
+        def clock():
+            return time.perf_counter() - t_start
+
+        def say(msg):
+            if self.log:
+                self.log("[batch %.2fs] %s" % (clock(), msg))
+
+        results = {r.rid: Result(r.rid, r.nsteps, fp[r.rid], r.arrival) for r in reqs}
+        byid = {r.rid: r for r in reqs}
+        pending = list(reqs)
+        queue: List[Request] = []
+        setting_up: Dict[int, Any] = {}        # rid -> future
+        running: Dict[int, Any] = {}           # rid -> solver
+        done_steps: Dict[int, int] = {}
+        used = 0
+        closed = threading.Event()             # the time box has closed
+        deadline_hit = set()
+        lock = threading.Lock()
+
+        def watchdog():
+            # cancels solves past their time limit and, at the time box, every
+            # solve still running: their batch call returns at the next window
+            # (under the lock: the marching thread removes a solve from
+            # `running` under it before closing the solve)
+            while not stop_watch.is_set():
+                now = clock()
+                box = self.time_box is not None and now >= self.time_box
+                if box and not closed.is_set():
+                    closed.set()
+                with lock:
+                    for rid, s in running.items():
+                        if rid in deadline_hit:
+                            continue
+                        if box or now - results[rid].t_admit > self.request_timeout:
+                            deadline_hit.add(rid)
+                            s.cancel()
+                stop_watch.wait(0.01)
+
+        stop_watch = threading.Event()
+        wd = threading.Thread(target=watchdog, daemon=True)
+        wd.start()
+        pool = ThreadPoolExecutor(max_workers=max(1, self.setup_workers))
+
+        def finish(rid, s, error=None):
+            nonlocal used
+            r = results[rid]
+            req = byid[rid]
+            if error is None and s is not None:
+                try:
+                    r.outputs = self.backend.outputs(req, s, done_steps.get(rid, 0))
+                except Exception as e:
+                    error = "%s: %s" % (type(e).__name__, e)
+            if s is not None:
+                try:
+                    self.backend.close(req, s)
+                except Exception as e:
+                    error = error or "%s: %s" % (type(e).__name__, e)
+            r.error = error
+            r.t_done = clock()
+            used -= fp[rid]
+            self.trace.append((clock(), "done", rid, len(running) + len(setting_up), used))
+            say("request %d done (%d of %d steps, %.3f s end to end%s)" % (
+                rid, done_steps.get(rid, 0), req.nsteps, r.end_to_end, ", " + error if error else ""))
+
+        try:
+            while pending or queue or setting_up or running:
+                now = clock()
+                while pending and pending[0].arrival <= now:
+                    queue.append(pending.pop(0))
+                if closed.is_set():
+                    # the time box has closed: nothing more is admitted
+                    for req in pending + queue:
+                        results[req.rid].error = "NotServed: the time box closed before admission"
+                    pending, queue = [], []
+                # strict arrival order: the head waits until it fits
+                while (queue and len(running) + len(setting_up) < self.max_active
+                       and used + fp[queue[0].rid] <= self.mem_budget):
+                    req = queue.pop(0)
+                    used += fp[req.rid]
+                    results[req.rid].t_admit = clock()
+                    setting_up[req.rid] = pool.submit(self.backend.setup, req)
+                    self.trace.append((clock(), "admit", req.rid, len(running) + len(setting_up), used))
+                    say("request %d admitted (%d steps, %d waves, %.1f MB)" % (
+                        req.rid, req.nsteps, len(req.problem["waves"]), fp[req.rid] / 1e6))
+                for rid in [q for q, f in setting_up.items() if f.done()]:
+                    f = setting_up.pop(rid)
+                    try:
+                        s = f.result()
+                    except Exception as e:
+                        finish(rid, None, "%s: %s" % (type(e).__name__, e))
+                        continue
+                    results[rid].t_ready = clock()
+                    if closed.is_set():
+                        finish(rid, s, "CancelledRun: the time box closed during setup")
+                        continue
+                    with lock:
+                        running[rid] = s
+                    done_steps[rid] = 0
+                if running:
+                    rids = list(running)
+                    n = min([self.window] + [byid[q].nsteps - done_steps[q] for q in rids])
+                    t0 = clock()
+                    codes = self.backend.run_batch([running[q] for q in rids], n)
+                    el = clock() - t0
+                    for q, code in zip(rids, codes):
+                        s = running[q]
+                        if code == "cancelled":
+                            got = s.info()["steps_done"] - done_steps[q]
+                        elif isinstance(code, str):
+                            got = 0
+                        else:
+                            got = n
+                        if got:
+                            results[q].step_latency.extend([el / n] * got)
+                        done_steps[q] += got
+                        err = None
+                        if code == "cancelled":
+                            err = "CancelledRun: stopped by mot_cancel after %d of %d steps" % (done_steps[q],
+                                                                                               byid[q].nsteps)
+                        elif isinstance(code, str):
+                            err = code
+                        if err or done_steps[q] >= byid[q].nsteps:
+                            with lock:
+                                running.pop(q)
+                            finish(q, s, err)
+                    continue
+                wait = self.poll
+                if pending and not queue and not setting_up:
+                    wait = min(max(pending[0].arrival - clock(), 0.0), 0.05) or self.poll
+                time.sleep(wait)
+        finally:
+            stop_watch.set()
+            wd.join()
+            pool.shutdown(wait=True)
+        wall = clock()
+        nrhs = {q.rid: len(q.problem["waves"]) for q in reqs}
+        ok = [r for r in results.values() if r.error is None]
+        steps = sum(r.nsteps for r in ok)
+        rhs_steps = sum(r.nsteps * nrhs[r.rid] for r in ok)
+        summary = {
+            "requests": len(reqs),
+            "completed": len(ok),
+            "cancelled": sum(1 for r in results.values() if r.error and r.error.startswith("CancelledRun")),
+            "not_served": sum(1 for r in results.values() if r.error and r.error.startswith("NotServed")),
+            "errors": sum(1 for r in results.values() if r.error and not r.error.startswith(("CancelledRun",
+                                                                                             "NotServed"))),
+            "wall_s": wall,
+            "steps": steps,
+            "steps_marched": sum(len(r.step_latency) for r in results.values()),
+            "steps_per_s": sum(len(r.step_latency) for r in results.values()) / wall if wall > 0 else float("nan"),
+            "rhs_steps_per_s": (sum(len(r.step_latency) * nrhs[r.rid] for r in results.values()) / wall
+                                if wall > 0 else float("nan")),
+            "step_latency_s": latency_stats(x for r in results.values() for x in r.step_latency),
+            "end_to_end_s": latency_stats(r.end_to_end for r in ok),
+            "queue_wait_s": latency_stats(r.queue_wait for r in results.values() if r.t_admit > 0),
             "max_concurrent": max((t[3] for t in self.trace), default=0),
             "peak_budget_used": max((t[4] for t in self.trace), default=0),
         }

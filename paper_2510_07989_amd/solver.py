@@ -37,15 +37,16 @@ def _csr(G):
             np.ascontiguousarray(A.data, dtype=np.float64))
 
 
-def footprint(V, F, E, eps_r, mu_r, dt, nrhs, G, options=None):
+def footprint(V, F, E, eps_r, mu_r, dt, nrhs, G, options=None, gnnz=None):
     """Device bytes (resident, peak) that a Solver with these arguments will
-    hold, from mot_footprint: nothing is allocated."""
+    hold, from mot_footprint: nothing is allocated.  gnnz: the Gram matrix's
+    nonzero count, or a bound on it, when G itself is not built yet (G None)."""
     lib = L.load()
     V = np.ascontiguousarray(V, dtype=np.float64)
     F = np.ascontiguousarray(F, dtype=np.int32)
     E = np.ascontiguousarray(E, dtype=np.int32)
     mesh = L.MotMesh(V.shape[0], F.shape[0], E.shape[0], _ptr(V), _ptr(F), _ptr(E))
-    nnz = len(_csr(G)[1])
+    nnz = int(gnnz) if gnnz is not None else len(_csr(G)[1])
     opt = options if options is not None else default_options()
     res, peak = ctypes.c_uint64(), ctypes.c_uint64()
     rc = lib.mot_footprint(ctypes.byref(mesh), float(eps_r), float(mu_r), float(dt), int(nrhs), int(nnz),
@@ -157,14 +158,28 @@ class Solver:
         return outs, ptrs
 
     def run(self, nsteps, w=True, loop=True, star=True, device=False):
-        """March nsteps; return arrays of shape (nsteps, n, nrhs) (numpy, or torch on device)."""
+        """March nsteps; return arrays of shape (nsteps, n, nrhs) (numpy, or torch on device).
+        A run stopped by cancel() returns the completed steps only, with
+        outs["cancelled"] True."""
         outs, ptrs = self._outputs(nsteps, w, loop, star, device)
         inf = L.MotStepInfo()
+        k0 = self.info()["steps_done"]
         rc = self._lib.mot_run(self._h, int(nsteps), ptrs[0], ptrs[1], ptrs[2], 1 if device else 0, ctypes.byref(inf))
-        self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV))
+        self._check(rc, ok=(L.MOT_OK, L.MOT_ENOCONV, L.MOT_ECANCEL))
+        outs["cancelled"] = rc == L.MOT_ECANCEL
+        if outs["cancelled"]:
+            done = self.info()["steps_done"] - k0
+            for name in ("w", "loop", "star"):
+                if outs[name] is not None:
+                    outs[name] = outs[name][:done]
         outs["last"] = dict(step=inf.step, iters=inf.gmres_iters, relres=inf.gmres_relres, converged=inf.converged)
         outs["rc"] = rc
         return outs
+
+    def cancel(self):
+        """Stop a run in progress (from another thread) at its next window
+        boundary, or the next run before its first window (mot_cancel)."""
+        self._check(self._lib.mot_cancel(self._h))
 
     def steps(self, first, count, w=True, loop=True, star=True, device=False):
         """Outputs of the kept steps first .. first+count-1 (counted from 0), as run returns them."""
@@ -241,8 +256,9 @@ class Solver:
 
 def run_batch(solvers, nsteps):
     """March every solver nsteps with their windows interleaved on the device
-    (mot_run_batch); returns each solver's code (MOT_OK or MOT_ENOCONV) and
-    raises MotError for the first solver that failed."""
+    (mot_run_batch); returns each solver's code (MOT_OK, MOT_ENOCONV, or
+    MOT_ECANCEL for one stopped by cancel()) and raises MotError for the first
+    solver that failed."""
     lib = L.load()
     n = len(solvers)
     hs = (ctypes.c_void_p * max(n, 1))(*[s._h.value for s in solvers])
@@ -251,6 +267,6 @@ def run_batch(solvers, nsteps):
     if rc == L.MOT_EINVAL and not any(st[i] for i in range(n)):
         raise MotError(rc, "mot_run_batch: bad argument")
     for i, s in enumerate(solvers):
-        if st[i] not in (L.MOT_OK, L.MOT_ENOCONV):
+        if st[i] not in (L.MOT_OK, L.MOT_ENOCONV, L.MOT_ECANCEL):
             raise MotError(st[i], lib.mot_last_error(s._h).decode())
     return [st[i] for i in range(n)]

@@ -68,3 +68,25 @@ def test_explicit_split_is_kept():
     i = s.info()
     s.close()
     assert i["sched_hist"] == 2 and i["sched_q0"] == 2 and i["sched_pc"] == 2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_workgroup_shapes_give_the_same_bits(precision):
+    """The tile products with 4 or 8 wavefronts per workgroup (64 or 128 rows
+    sharing each staged slice of the history vectors) sum every row in the
+    same order: with the K chunks fixed, the marches agree bit for bit, and
+    both match the oracle; the shape is reported back."""
+    print("case sphere_480_r16 tile_wg precision", precision, flush=True)
+    outs = {}
+    for wg in (4, 8):
+        s = _solver("sphere_480_r16", precond=2, precision=precision, autotune=0, tile_wg=wg)
+        outs[wg] = s.run(40)
+        inf = s.info()
+        assert inf["hist_wg"] == wg and inf["q0_wg"] == wg
+        s.close()
+    for k in ("w", "loop", "star"):
+        assert np.array_equal(outs[4][k], outs[8][k]), k
+    ref = oracle("sphere_480_r16").run(40)
+    bound = 1e-10 if precision == 0 else 1e-6
+    for k, r in (("w", "W"), ("loop", "loop"), ("star", "star")):
+        assert _rel(outs[8][k], ref[r]) < bound, k

@@ -76,3 +76,96 @@ def test_same_result_alone_and_in_the_mix():
     ref16 = oracle("sphere_480_r16").run(80)
     for k, r in (("w", "W"), ("loop", "loop"), ("star", "star")):
         assert _rel(res[4].outputs[k], ref16[r]) < 1e-6, k
+
+
+def test_cancel_stops_at_a_window_and_keeps_the_steps():
+    """mot_cancel from another thread stops mot_run at a window boundary:
+    the completed steps are kept and returned, and the march continued with a
+    second run is bit for bit the march that was never interrupted; the same
+    inside mot_run_batch, where the other handle goes on."""
+    import threading
+    import paper_2510_07989_amd as p
+    from paper_2510_07989_amd import _lib as L
+    print("case sphere_480_r16 cancel", flush=True)
+    prob = problem("sphere_480_r16")
+    n = 2400                       # about 0.4 s of marching; the cancel comes at 0.05 s
+
+    def make():
+        s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
+                     prob["T0h"], prob["G"], prob["waves"],
+                     options=p.default_options(precond=2, max_steps=n, spec_window=32))
+        s.load_raw(prob["raw"], prob["kmax"])
+        return s
+
+    ref_s = make()
+    ref = ref_s.run(n, loop=False, star=False)["w"]
+    ref_s.close()
+    s = make()
+    t = threading.Timer(0.05, s.cancel)
+    t.start()
+    out = s.run(n, loop=False, star=False)
+    t.join()
+    k = s.info()["steps_done"]
+    print("cancelled after %d of %d steps" % (k, n), flush=True)
+    assert out["cancelled"] and 0 < k < n and out["w"].shape[0] == k
+    assert np.array_equal(out["w"], ref[:k])
+    rest = s.run(n - k, loop=False, star=False)
+    assert not rest["cancelled"]
+    assert np.array_equal(rest["w"], ref[k:])
+    # a cancel made while nothing runs stops the next run before it starts
+    s.reset()
+    s.cancel()
+    r0 = s.run(10, loop=False, star=False)
+    assert r0["cancelled"] and r0["w"].shape[0] == 0 and s.info()["steps_done"] == 0
+    # in a batch: the cancelled handle stops, the other completes
+    a, b = make(), make()
+    t = threading.Timer(0.05, a.cancel)
+    t.start()
+    codes = p.run_batch([a, b], n)
+    t.join()
+    assert codes[0] == L.MOT_ECANCEL and codes[1] == L.MOT_OK
+    ka = a.info()["steps_done"]
+    assert 0 < ka < n and b.info()["steps_done"] == n
+    assert np.array_equal(a.steps(0, ka, loop=False, star=False)["w"], ref[:ka])
+    assert np.array_equal(b.steps(0, n, loop=False, star=False)["w"], ref)
+    for x in (s, a, b):
+        x.close()
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_eight_concurrent_solves_same_as_alone(batch):
+    """Eight solves on four meshes (1 to 16 waves, FP64 and mixed) all admitted
+    at once: with one thread and stream per solve, or stepped together through
+    mot_run_batch by one thread (solves joining as their setup ends); every
+    result equals the same request served alone, eight ran at
+    once, and the budget held.  The unknowns are bit for bit those served
+    alone; the recovered loop and star parts agree to 1e-12."""
+    from paper_2510_07989_amd.serve import BatchServer, GpuBackend, Request, Server
+    names = ["tiny", "tiny_torus", "tiny_box", "sphere_480", "sphere_480_r16", "tiny_torus", "sphere_480",
+             "sphere_480_r16"]
+    probs = {m: problem(m) for m in set(names)}
+    reqs = [Request(i, probs[m], 96 + 16 * i, arrival=0.0,
+                    options=dict(precond=2, precision=1 if (m == "sphere_480_r16" and i > 4) else 0))
+            for i, m in enumerate(names)]
+    be = GpuBackend()
+    alone = {}
+    for r in reqs:
+        res, _ = Server(be, mem_budget=1 << 40, window=32).run([Request(r.rid, r.problem, r.nsteps, 0.0,
+                                                                        r.options)])
+        assert res[r.rid].error is None, res[r.rid].error
+        alone[r.rid] = res[r.rid].outputs
+    budget = sum(be.footprint(r) for r in reqs)
+    print("mix of 8, batch", batch, "budget", budget, flush=True)
+    if batch:
+        srv = BatchServer(be, mem_budget=budget, max_active=8, window=32, setup_workers=8)
+    else:
+        srv = Server(be, mem_budget=budget, max_active=8, window=32)
+    res, summ = srv.run(reqs)
+    print("summary", {k: summ[k] for k in ("wall_s", "steps_per_s", "max_concurrent", "peak_budget_used")},
+          flush=True)
+    assert summ["errors"] == 0, [r.error for r in res.values()]
+    assert summ["max_concurrent"] == 8 and summ["peak_budget_used"] <= budget
+    for rid, r in res.items():
+        assert np.array_equal(r.outputs["w"], alone[rid]["w"]), rid
+        for k in ("loop", "star"):       # the recovery's batches of steps may differ
+            assert _rel(r.outputs[k], alone[rid][k]) <= 1e-12, (rid, k)

@@ -104,3 +104,156 @@ def test_request_time_limit_is_reported():
     assert res[0].error and "Timeout" in res[0].error
     assert res[1].error is None
     assert any("exceeded" in l for l in lines) and any("admitted" in l for l in lines)
+
+
+class FakeSolver:
+    def __init__(self):
+        self.k = 0
+        self.cancel_flag = False
+        self.closed = False
+
+    def cancel(self):
+        assert not self.closed
+        self.cancel_flag = True
+
+    def info(self):
+        return {"steps_done": self.k}
+
+
+class SleepBatchBackend:
+    """The batch server's backend on the host: setup sleeps, a batch call
+    sleeps per step (once for all its solvers) and honours cancel flags at
+    its start and halfway through, as mot_run_batch does at window
+    boundaries."""
+
+    def __init__(self, step_s=0.001, setup_s=0.01):
+        self.step_s, self.setup_s = step_s, setup_s
+        self.lock = threading.Lock()
+        self.live = {}
+        self.max_live = 0
+        self.max_batch = 0
+        self.max_bytes = 0
+
+    def footprint(self, req):
+        return req.problem["bytes"]
+
+    def setup(self, req):
+        time.sleep(self.setup_s)
+        s = FakeSolver()
+        with self.lock:
+            self.live[req.rid] = req.problem["bytes"]
+            self.max_live = max(self.max_live, len(self.live))
+            self.max_bytes = max(self.max_bytes, sum(self.live.values()))
+        return s
+
+    def run_batch(self, solvers, n):
+        self.max_batch = max(self.max_batch, len(solvers))
+        codes = []
+        half = n // 2
+        time.sleep(self.step_s * half)
+        for s in solvers:
+            if s.cancel_flag:
+                s.cancel_flag = False
+                codes.append("cancelled")
+            else:
+                s.k += half
+                codes.append(None)
+        time.sleep(self.step_s * (n - half))
+        for i, s in enumerate(solvers):
+            if codes[i] is None:
+                if s.cancel_flag:
+                    s.cancel_flag = False
+                    codes[i] = "cancelled"
+                else:
+                    s.k += n - half
+                    codes[i] = 0
+        return codes
+
+    def outputs(self, req, s, nsteps):
+        return {"w": [s.k]}
+
+    def close(self, req, s):
+        s.closed = True
+        with self.lock:
+            del self.live[req.rid]
+
+
+def test_batch_server_budget_overlap_and_all_finish():
+    from paper_2510_07989_amd.serve import BatchServer
+    be = SleepBatchBackend()
+    reqs = [_req(i, 300 + 100 * (i % 3), 40 + 7 * i, 0.004 * i) for i in range(12)]
+    srv = BatchServer(be, mem_budget=1000, max_active=8, window=16)
+    res, summ = srv.run(reqs)
+    assert summ["errors"] == 0 and summ["completed"] == 12 and summ["cancelled"] == 0
+    assert be.max_bytes <= 1000 and summ["peak_budget_used"] <= 1000
+    assert be.max_batch >= 2                       # solves marched together
+    for r in res.values():
+        assert len(r.step_latency) == r.nsteps and r.outputs["w"] == [r.nsteps]
+        assert r.t_arrival <= r.t_admit <= r.t_ready <= r.t_done
+
+
+def test_batch_server_time_box_cancels_and_drops():
+    """At the time box every running solve is cancelled at its next window
+    boundary (its completed steps counted), requests not yet admitted are not
+    served, and every slot and byte is given back."""
+    from paper_2510_07989_amd.serve import BatchServer
+    be = SleepBatchBackend(step_s=0.002)
+    reqs = [_req(i, 400, 400, 0.05 * i) for i in range(8)]
+    srv = BatchServer(be, mem_budget=1000, max_active=2, window=32, time_box=0.3)
+    res, summ = srv.run(reqs)
+    assert summ["cancelled"] >= 1 and summ["not_served"] >= 1 and summ["errors"] == 0
+    assert summ["completed"] + summ["cancelled"] + summ["not_served"] == 8
+    assert not be.live                              # every solve closed
+    for r in res.values():
+        if r.error and r.error.startswith("CancelledRun"):
+            assert 0 < len(r.step_latency) < r.nsteps
+    assert summ["wall_s"] < 0.3 + 0.5
+
+
+def test_batch_server_request_timeout_frees_the_slot():
+    """A request past its time limit is cancelled and its slot goes to the
+    next one, which completes."""
+    from paper_2510_07989_amd.serve import BatchServer
+    be = SleepBatchBackend(step_s=0.002)
+    reqs = [_req(0, 900, 100000, 0.0), _req(1, 900, 50, 0.01)]
+    srv = BatchServer(be, mem_budget=1000, max_active=2, window=32, request_timeout=0.2)
+    res, summ = srv.run(reqs)
+    assert res[0].error.startswith("CancelledRun") and res[1].error is None
+    assert res[1].t_admit >= res[0].t_done - 1e-6
+    assert summ["completed"] == 1 and summ["cancelled"] == 1
+
+
+class CancellableSleepBackend(SleepBackend):
+    """SleepBackend whose requests stop at a window boundary once cancelled."""
+
+    def __init__(self, step_s=0.002):
+        super().__init__(step_s)
+        self.flags = {}
+
+    def cancel(self, rid):
+        self.flags[rid] = True
+        return True
+
+    def execute(self, req, window, clock, res):
+        from paper_2510_07989_amd.serve import CancelledRun
+        res.t_ready = clock()
+        done = 0
+        while done < req.nsteps:
+            if self.flags.pop(req.rid, False):
+                raise CancelledRun("stopped after %d steps" % done)
+            nw = min(window, req.nsteps - done)
+            t0 = clock()
+            time.sleep(self.step_s * nw)
+            res.step_latency.extend([(clock() - t0) / nw] * nw)
+            done += nw
+
+
+def test_thread_server_cancels_a_request_past_its_limit():
+    """The per-thread server stops a request past its time limit through the
+    backend's cancel; its slot and memory then go to the next request."""
+    be = CancellableSleepBackend()
+    reqs = [_req(0, 900, 100000, 0.0), _req(1, 900, 40, 0.01)]
+    srv = Server(be, mem_budget=1000, max_active=2, window=16, request_timeout=0.2)
+    res, summ = srv.run(reqs)
+    assert res[0].error.startswith("CancelledRun") and res[1].error is None
+    assert res[1].t_admit >= res[0].t_done - 1e-6
