@@ -216,6 +216,7 @@ def device_inputs(V, F, E, nq_static=6):
     torch.cuda.current_stream().synchronize()
     out = dict(G=G, T0s=T0s.cpu().numpy(), T0h=T0h.cpu().numpy(), D=D, refinement=R)
     del T0s, T0h
+    torch.cuda.empty_cache()       # give the blocks back to the device, not to torch's cache
     return out
 
 
@@ -248,8 +249,12 @@ def build_problem_device(name=None, cfg=None, nsteps=None):
 def load_solvers(solvers, prob, lags=None, on_lag=None):
     """One device assembly pass of prob's retarded blocks (both media, lag by
     lag) handed to every solver in turn through its set_lag_device."""
+    import torch
+
     def upload(fam, lag, med, op, t):
         for s in solvers:
             s.set_lag_device(fam, lag, med, op, t)
     upload_lags(upload, prob["V"], prob["F"], prob["E"], prob["dt"], prob["eps_r"], prob["mu_r"], prob["kmax"],
                 nq=prob.get("nq", 7), lags=lags, on_lag=on_lag)
+    # the assembler's rings go back to the device (the solvers allocate outside torch)
+    torch.cuda.empty_cache()

@@ -51,10 +51,16 @@
 
 namespace {
 
-__constant__ double c_glx[MAXGL + 1][MAXGL];
-__constant__ double c_glw[MAXGL + 1][MAXGL];
-__constant__ double c_rule[16][4];   /* test rule: l0 l1 l2 w */
-__constant__ double c_far[16][4];    /* far source rule */
+/* Quadrature tables of one assembler (or one static-block build), in device
+ * memory of its own: concurrent builds with different rules (the static blocks
+ * use a 6-point test rule and a 3-point far rule, the retarded blocks 7 and 7)
+ * never see each other's tables. */
+struct QTables {
+    double glx[(MAXGL + 1) * MAXGL];
+    double glw[(MAXGL + 1) * MAXGL];
+    double rule[16 * 4];             /* test rule: l0 l1 l2 w */
+    double far[16 * 4];              /* far source rule */
+};
 
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
@@ -83,14 +89,15 @@ struct RetParams {
     double* mom;            /* [nb * nq][MOMW] band moments of each (pair, test point) */
     int* items;             /* [2][nb * nq] far-rule items, then polar items */
     int* icount;            /* [2] */
+    const QTables* qt;      /* quadrature tables */
 };
 
 constexpr int MOMW = 56;    /* doubles per item: the BM_N band moments and padding */
 constexpr int NCH = 13;     /* output channels of a band pass (band_channel) */
 
-__device__ __forceinline__ Tab dev_tab() {
+__device__ __forceinline__ Tab dev_tab(const QTables* q) {
     Tab T;
-    T.glx = &c_glx[0][0]; T.glw = &c_glw[0][0]; T.rule = &c_rule[0][0]; T.far = &c_far[0][0];
+    T.glx = q->glx; T.glw = q->glw; T.rule = q->rule; T.far = q->far;
     return T;
 }
 
@@ -123,7 +130,7 @@ __global__ void k_classify(RetParams P) {
     const int2 st = P.plist[P.p0 + pi];
     const Tri S = load_tri(P.tri, st.x), Tt = load_tri(P.tri, st.y);
     const PairBands pb = pair_bands(S, Tt, P.tris, st.x, st.y, P.c, P.dt, P.nlag);
-    const Tab T = dev_tab();
+    const Tab T = dev_tab(P.qt);
     int cls = test_point_class(T, S, Tt, q, pb.near, P.c, P.dt, P.nlag);
     if (cls == 1) {
         const V3 x = add(add(scl(S.a[0], T.rule[4 * q]), scl(S.a[1], T.rule[4 * q + 1])), scl(S.a[2], T.rule[4 * q + 2]));
@@ -154,7 +161,7 @@ __global__ void __launch_bounds__(256) k_walk(RetParams P, int cls) {
     const Tri S = load_tri(P.tri, st.x), Tt = load_tri(P.tri, st.y);
     const PairBands pb = pair_bands(S, Tt, P.tris, st.x, st.y, P.c, P.dt, P.nlag);
     BandMoments M;
-    const bool act = test_point_band(dev_tab(), S, Tt, q, pb.near, P.c, P.dt, P.nlag, P.band, P.nth, P.nrh, M);
+    const bool act = test_point_band(dev_tab(P.qt), S, Tt, q, pb.near, P.c, P.dt, P.nlag, P.band, P.nth, P.nrh, M);
     double* m = P.mom + (size_t)it * MOMW;
     if (!act) M.clear();
 #pragma unroll
@@ -177,7 +184,7 @@ __global__ void k_products(RetParams P) {
     const int2 st = P.plist[P.p0 + pi];
     const int s = st.x, t = st.y;
     const Tri S = load_tri(P.tri, s);
-    const Tab T = dev_tab();
+    const Tab T = dev_tab(P.qt);
     const double cm = P.fcoef[3 * s + a], cn = P.fcoef[3 * t + b];
     const double* pa = P.fopp + 9 * s + 3 * a;
     const double* pb = P.fopp + 9 * t + 3 * b;
@@ -222,6 +229,7 @@ struct StatParams {
     int* near_list;        /* [cap][2] */
     int* near_count;
     int near_cap;
+    const QTables* qt;     /* quadrature tables */
 };
 
 /* far pairs: one lane per pair; near pairs are listed for k_static_near */
@@ -241,12 +249,14 @@ __global__ void __launch_bounds__(256) k_static_far(StatParams P) {
     double m[16];
     for (int j = 0; j < 16; ++j) m[j] = 0;
     for (int q = 0; q < P.far_n; ++q) {
-        V3 x = add(add(scl(S.a[0], c_far[q][0]), scl(S.a[1], c_far[q][1])), scl(S.a[2], c_far[q][2]));
-        double wx = c_far[q][3] * S.area;
+        const double* fq = P.qt->far + 4 * q;
+        V3 x = add(add(scl(S.a[0], fq[0]), scl(S.a[1], fq[1])), scl(S.a[2], fq[2]));
+        double wx = fq[3] * S.area;
         StatMoments A = {0, 0, 0, 0};
         for (int k = 0; k < P.far_n; ++k) {
-            V3 y = add(add(scl(T.a[0], c_far[k][0]), scl(T.a[1], c_far[k][1])), scl(T.a[2], c_far[k][2]));
-            A(y, nrm(sub(x, y)), c_far[k][3] * T.area);
+            const double* fk = P.qt->far + 4 * k;
+            V3 y = add(add(scl(T.a[0], fk[0]), scl(T.a[1], fk[1])), scl(T.a[2], fk[2]));
+            A(y, nrm(sub(x, y)), fk[3] * T.area);
         }
         double X[4] = {x.x, x.y, x.z, 1};
         double Y[4] = {A.m1x, A.m1y, A.m1z, A.m0};
@@ -266,11 +276,11 @@ __global__ void __launch_bounds__(256) k_static_near(StatParams P, int count) {
     double m[16];
     for (int j = 0; j < 16; ++j) m[j] = 0;
     if (lane < P.nq) {
-        V3 x = add(add(scl(S.a[0], c_rule[lane][0]), scl(S.a[1], c_rule[lane][1])), scl(S.a[2], c_rule[lane][2]));
-        double wx = c_rule[lane][3] * S.area;
+        const double* rl = P.qt->rule + 4 * lane;
+        V3 x = add(add(scl(S.a[0], rl[0]), scl(S.a[1], rl[1])), scl(S.a[2], rl[2]));
+        double wx = rl[3] * S.area;
         StatMoments A = {0, 0, 0, 0};
-        Tab TB;
-        TB.glx = &c_glx[0][0]; TB.glw = &c_glw[0][0]; TB.rule = &c_rule[0][0]; TB.far = &c_far[0][0];
+        const Tab TB = dev_tab(P.qt);
         inner_points(TB, A, x, T, 0.0, 0, 1, P.far_n, P.nth, P.nrh);
         double X[4] = {x.x, x.y, x.z, 1};
         double Y[4] = {A.m1x, A.m1y, A.m1z, A.m0};
@@ -350,22 +360,29 @@ typedef struct gfx_ret {
     double* mom;                 /* [batch * nq][MOMW] */
     int* items;                  /* [2][batch * nq] */
     int* icount;                 /* [2] */
+    QTables* qt;                 /* quadrature tables of this assembler */
     int next_lag;
     hipStream_t stream;
 } gfx_ret;
 
-static int set_tables(const double* glx, const double* glw, const double* rule, int nrule, const double* far,
-                      int nfar) {
-    double r[16][4], f[16][4];
-    memset(r, 0, sizeof(r));
-    memset(f, 0, sizeof(f));
+/* A device copy of the tables (allocated here, freed by the caller). */
+static int make_tables(const double* glx, const double* glw, const double* rule, int nrule, const double* far,
+                       int nfar, QTables** out) {
+    *out = nullptr;
     if (nrule > 16 || nfar > 16) return -1;
-    for (int i = 0; i < nrule; ++i) for (int j = 0; j < 4; ++j) r[i][j] = rule[4 * i + j];
-    for (int i = 0; i < nfar; ++i) for (int j = 0; j < 4; ++j) f[i][j] = far[4 * i + j];
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_glx), glx, sizeof(double) * (MAXGL + 1) * MAXGL) != hipSuccess) return -2;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_glw), glw, sizeof(double) * (MAXGL + 1) * MAXGL) != hipSuccess) return -2;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_rule), r, sizeof(r)) != hipSuccess) return -2;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_far), f, sizeof(f)) != hipSuccess) return -2;
+    QTables h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.glx, glx, sizeof(h.glx));
+    memcpy(h.glw, glw, sizeof(h.glw));
+    for (int i = 0; i < 4 * nrule; ++i) h.rule[i] = rule[i];
+    for (int i = 0; i < 4 * nfar; ++i) h.far[i] = far[i];
+    QTables* d = nullptr;
+    if (hipMalloc(&d, sizeof(QTables)) != hipSuccess) return -2;
+    if (hipMemcpy(d, &h, sizeof(QTables), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(d);
+        return -2;
+    }
+    *out = d;
     return 0;
 }
 
@@ -445,7 +462,7 @@ int gfx_ret_create(int nv, const double* verts, int nf, const int32_t* tris, int
     for (int f = 0; f < nf && rc == 0; ++f)
         if (face_order[f] < 0 || face_order[f] >= nf) rc = -1;
     free(cnt);
-    if (rc == 0) rc = set_tables(glx, glw, rule, nq, far, 7);
+    if (rc == 0) rc = make_tables(glx, glw, rule, nq, far, 7, &g->qt);
     if (rc == 0) {
         GCHK(hipMalloc(&g->tri, sizeof(double) * 16 * (size_t)nf));
         GCHK(hipMalloc(&g->fe, sizeof(int) * 3 * (size_t)nf));
@@ -486,7 +503,7 @@ fail:
     if (rc) {
         hipFree(g->tri); hipFree(g->fe); hipFree(g->fcoef); hipFree(g->fopp); hipFree(g->tris);
         hipFree(g->order); hipFree(g->acc_tail); hipFree(g->plist); hipFree(g->pcount);
-        hipFree(g->mom); hipFree(g->items); hipFree(g->icount); free(g->cptr_h); free(g);
+        hipFree(g->mom); hipFree(g->items); hipFree(g->icount); hipFree(g->qt); free(g->cptr_h); free(g);
         return rc;
     }
     *out = g;
@@ -532,6 +549,7 @@ int gfx_ret_lag(gfx_ret* g, int lag, double* const* ring) {
     P.mom = g->mom;
     P.items = g->items;
     P.icount = g->icount;
+    P.qt = g->qt;
     for (int cs = 0; cs < g->ncolor; ++cs) {
         for (int ct = 0; ct < g->ncolor; ++ct) {
             P.slist = g->order + g->cptr_h[cs];
@@ -580,7 +598,7 @@ void gfx_ret_destroy(gfx_ret* g) {
     hipStreamSynchronize(g->stream);
     hipFree(g->tri); hipFree(g->fe); hipFree(g->fcoef); hipFree(g->fopp); hipFree(g->tris);
     hipFree(g->order); hipFree(g->acc_tail); hipFree(g->plist); hipFree(g->pcount);
-    hipFree(g->mom); hipFree(g->items); hipFree(g->icount);
+    hipFree(g->mom); hipFree(g->items); hipFree(g->icount); hipFree(g->qt);
     free(g->cptr_h);
     free(g);
 }
@@ -597,12 +615,13 @@ int gfx_static_bc(int nft, const double* fv, int nres, const int32_t* res_t, con
                   const double* res_a, const double* res_b, int ne, double D, int nq, int nth, int nrh,
                   const double* glx, const double* glw, const double* rule, const double* far, int chunk,
                   void* stream, double* T0s, double* T0h) {
-    int rc = set_tables(glx, glw, rule, nq, far, 3);
-    if (rc) return rc;
     for (int k = 0; k < nres; ++k) {
         if (res_t[k] < 0 || res_t[k] >= nft || res_n[k] < 0 || res_n[k] >= ne) return -1;
         if (k > 0 && res_t[k] < res_t[k - 1]) return -1;   /* sorted by fine triangle */
     }
+    QTables* qt = nullptr;
+    int rc = make_tables(glx, glw, rule, nq, far, 3, &qt);
+    if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (chunk <= 0) chunk = 512;
     double* T = (double*)malloc(sizeof(double) * 16 * (size_t)nft);
@@ -654,6 +673,7 @@ int gfx_static_bc(int nft, const double* fv, int nres, const int32_t* res_t, con
         StatParams P;
         P.tri = dT; P.nft = nft; P.s0 = s0; P.s1 = s1; P.nq = nq; P.far_n = 3; P.nth = nth; P.nrh = nrh;
         P.MB = dMB; P.near_list = dnl; P.near_count = dnc; P.near_cap = near_cap;
+        P.qt = qt;
         GCHK(hipMemsetAsync(dnc, 0, sizeof(int), st));
         long np = (long)(s1 - s0) * nft;
         hipLaunchKernelGGL(k_static_far, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, P);
@@ -715,7 +735,7 @@ fail:
     hipStreamSynchronize(st);
     free(T); free(byn_ptr); free(byn_k); free(rows); free(rptr); free(rk); free(mark);
     hipFree(dT); hipFree(dMB); hipFree(dW); hipFree(da); hipFree(db); hipFree(drt); hipFree(dbp); hipFree(dbk);
-    hipFree(dnl); hipFree(dnc); hipFree(drows); hipFree(drp); hipFree(drk);
+    hipFree(dnl); hipFree(dnc); hipFree(drows); hipFree(drp); hipFree(drk); hipFree(qt);
     return rc;
 }
 
