@@ -417,7 +417,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
-    ap.add_argument("--no-serving-c4", action="store_true", help="skip the time-boxed serving stream")
+    ap.add_argument("--no-serving-c4", action="store_true", help="leave the stream out (the default)")
+    ap.add_argument("--serving-c4", action="store_true",
+                    help="also serve the time-boxed 256-request stream (batch server; off by default while a stall "
+                         "of the batch server with eight concurrent setups is unexplained)")
     ap.add_argument("--serving-c4-requests", type=int, default=256)
     ap.add_argument("--serving-c4-box", type=float, default=120.0, help="seconds before the stream is cut")
     ap.add_argument("--serving-c4-budget-gb", type=float, default=200.0)
@@ -505,8 +508,12 @@ def run_legs(mot, args, result):
         result["torus"] = torus_leg(mot, args)
     if not args.no_step_batch:
         result["step_batch"] = step_batch(mot)
-    if not args.no_serving_c4:
-        result["serving_c4"] = serving_c4(args)
+    if args.serving_c4 and not args.no_serving_c4:
+        try:
+            result["serving_c4"] = serving_c4(args)
+        except Exception as e:          # the headline line is printed whatever this leg does
+            log("[c4] serving stream failed: %s: %s" % (type(e).__name__, e))
+            result["serving_c4"] = {"error": "%s: %s" % (type(e).__name__, e)}
     if args.serving:
         result["serving"] = serving(args.serving_requests)
     print(json.dumps(result), flush=True)
