@@ -565,11 +565,14 @@ __global__ __launch_bounds__(64 * WG) void k_tile_gemm(int ne, int hs, int G16, 
     if (gok && c0 < c1) fetch(c0, rs[0]);
     if (gok && c0 + 1 < c1) fetch(c0 + 1, rs[1]);
 
-    // With one or two column blocks, the history slice of the next K step is
-    // loaded into registers while the current one is multiplied, and stored to
-    // LDS after the barrier; with four, the registers are worth more as
-    // occupancy and the slice is loaded between the barriers.
-    constexpr bool WPF = CB < 4;
+    // With one or two column blocks, or eight wavefronts, the history slice of
+    // the next K step is loaded into registers while the current one is
+    // multiplied, and stored to LDS after the barrier.  With four column
+    // blocks in a four-wavefront workgroup those registers would halve the
+    // occupancy (two workgroups per CU, whose barriers cover each other), so
+    // the slice is loaded between the barriers; an eight-wavefront workgroup
+    // fills a CU alone, and only the prefetch hides its slice loads.
+    constexpr bool WPF = CB < 4 || WG == 8;
     constexpr int WE = ST * 16 * NC / NT;      // staged (u, v) pairs per thread
     double pu[WPF ? WE : 1], pv[WPF ? WE : 1];
     auto wfetch = [&](int cs) {

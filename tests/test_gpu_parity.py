@@ -239,17 +239,21 @@ def _waves_problem(name, R):
     return prob
 
 
-@pytest.mark.parametrize("R,precision", [(24, 0), (40, 0), (40, 1)])
-def test_multi_rhs_wide(R, precision):
+@pytest.mark.parametrize("R,precision,wg", [(24, 0, 0), (40, 0, 0), (40, 1, 0), (40, 0, 4), (40, 0, 8),
+                                             (40, 1, 8)])
+def test_multi_rhs_wide(R, precision, wg):
     """24 and 40 waves (2 and 4 column blocks of 16, the last partly masked) on
-    the 960-unknown sphere, FP64 and mixed, against the oracle."""
+    the 960-unknown sphere, FP64 and mixed, against the oracle; with four
+    column blocks also each tile workgroup shape fixed (wg 4, or 8 with the
+    history slices prefetched into registers)."""
     import paper_2510_07989_amd as p
     from oracle.mot_oracle import Oracle
-    print("case sphere_480 R", R, "precision", precision, flush=True)
+    print("case sphere_480 R", R, "precision", precision, "tile_wg", wg, flush=True)
     prob = _waves_problem("sphere_480", R)
     ref = Oracle(prob).run(80)
     s = p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
-                 prob["T0h"], prob["G"], prob["waves"], options=p.default_options(precond=2, precision=precision))
+                 prob["T0h"], prob["G"], prob["waves"],
+                 options=p.default_options(precond=2, precision=precision, tile_wg=wg))
     s.load_raw(prob["raw"], prob["kmax"])
     out = s.run(80)
     s.close()
