@@ -13,7 +13,8 @@ Formulation"):
 * static preconditioner, loop-star form .... Section III, eq. (CP)
 * media sum of the PMCHWT blocks ........... Section II, eq. (PMCHWT)
 * lag matrices Q_i = Q^ll + Q^ls + Q^sl + Q^ss and the truncations,
-  eq. (spec_prop) ................................ Section V-B
+  eq. (spec_prop); their inner sums block by block from one lag's raw
+  blocks (lag_products) ........................ Section V-B
 * right-hand side, loop and star parts ..... Section V-C, eq. (rhs), (hin)
 * marching-on-in-time recurrence ........... Section V-A, eq. (MOT)
 * current recovery, loop/star kept apart ... Section V-A, eq. (dis_jm)
@@ -22,8 +23,10 @@ Formulation"):
   computation) with eq. (dis_jm); the radiation integral itself is the
   textbook one, which the paper does not print
 
-Dense linear algebra throughout: pseudo-inverses by numpy.linalg.pinv, G^-1
-and Q_0^-1 by LU (scipy.linalg), no blocking or fusion.
+Dense linear algebra throughout: pseudo-inverses by numpy.linalg.pinv (of the
+symmetric Gram matrices Sigma^T Sigma and Lambda^T Lambda, through their
+symmetric eigendecomposition), G^-1 and Q_0^-1 by LU (scipy.linalg), no
+blocking or fusion.
 
 Readings where the paper is silent (also listed in the design notes):
 * exterior c = eta = 1; interior c' = 1/sqrt(eps_r mu_r), eta' = sqrt(mu_r/eps_r);
@@ -52,7 +55,7 @@ from scipy.special import erf, erfc
 
 __all__ = [
     "medium", "time_constants", "incidence", "projectors", "preconditioner",
-    "media_sum", "lag_blocks", "lag_matrices", "LagOperator", "tri_rule7", "tested_fields", "rhs",
+    "media_sum", "lag_blocks", "lag_matrices", "LagOperator", "lag_products", "tri_rule7", "tested_fields", "rhs",
     "march", "recover", "Oracle", "block_toeplitz_solve", "star_cut",
     "rwg_at_rule_points", "current_spectrum", "radiation_vectors", "far_field",
 ]
@@ -97,8 +100,8 @@ def projectors(Lam, Sig):
     (BC space)."""
     ne = Lam.shape[0]
     I = np.eye(ne)
-    PS = Sig @ np.linalg.pinv(Sig.T @ Sig) @ Sig.T
-    BL = Lam @ np.linalg.pinv(Lam.T @ Lam) @ Lam.T
+    PS = Sig @ np.linalg.pinv(Sig.T @ Sig, hermitian=True) @ Sig.T
+    BL = Lam @ np.linalg.pinv(Lam.T @ Lam, hermitian=True) @ Lam.T
     return dict(PS=PS, PL=I - PS, BL=BL, BSH=I - BL)
 
 
@@ -200,6 +203,39 @@ class LagOperator:
         xl = b["PLb"] @ X
         xs = b["PSb"] @ X
         return b["C1b"] @ (self.Zh @ xl + self.Zhat @ xs) + b["C2b"] @ (self.Zh @ xs + self.Ztil @ xl)
+
+
+def lag_products(raw_i, eps_r, mu_r, Tmax, kmax, i, XL, XS):
+    """Section V-B, the inner sums of Q_i X from the raw blocks of lag i alone,
+    block by block, without forming the media sums:
+        Y1 = Z_i^h XL + Z_i^hat XS,    Y2 = Z_i^h XS + Z_i^til XL,
+    each Z with the block pattern of eq. (PMCHWT) (media_sum) and its family's
+    time scaling and truncation (lag_blocks); so that Q_i X = C1b Y1 + C2b Y2
+    for XL = P^{Lambda H} X, XS = P^Sigma X block-wise (LagOperator).
+    raw_i[medium][name]: the (ne, ne) blocks of lag i (a family whose blocks
+    are absent counts as zero); XL, XS: (2 ne, c), halves (u; v)."""
+    _, eta, _, etap = medium(eps_r, mu_r)
+    ne = XL.shape[0] // 2
+    Y1 = np.zeros(XL.shape)
+    Y2 = np.zeros(XL.shape)
+
+    def apply(fam, limit, scale, static_k, X, Y):
+        if i > limit or ("T_" + fam) not in raw_i["ext"]:
+            return
+        a, b = X[:ne], X[ne:]
+        Te, Ti = raw_i["ext"]["T_" + fam], raw_i["int"]["T_" + fam]
+        Y[:ne] += scale * (eta * (Te @ a) + etap * (Ti @ a))          # eta T + eta' T'
+        Y[ne:] += scale * ((Te @ b) / eta + (Ti @ b) / etap)          # T/eta + T'/eta'
+        if not static_k:
+            Ke, Ki = raw_i["ext"]["K_" + fam], raw_i["int"]["K_" + fam]
+            Y[:ne] -= scale * (Ke @ b + Ki @ b)                       # -(K + K')
+            Y[ne:] += scale * (Ke @ a + Ki @ a)                       # K + K'
+
+    apply("h", kmax, 1.0, False, XL, Y1)
+    apply("hat", kmax + 1, Tmax, False, XS, Y1)
+    apply("h", kmax, 1.0, False, XS, Y2)
+    apply("tilde", kmax - 1, 1.0 / Tmax, i == 0 and kmax <= 1, XL, Y2)
+    return Y1, Y2
 
 
 # ------------------------------------------------------------------- RHS ---

@@ -1,5 +1,7 @@
 """Parity at the benchmark sizes, in the configuration bench.py times: the
 oracle computes a prefix of the march; properties cover the rest."""
+import time
+
 import numpy as np
 import pytest
 
@@ -152,3 +154,91 @@ def test_sphere_15360_64_waves_prefix():
         e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
         print("%s prefix errors: w %.3e loop %.3e star %.3e" % (tag, *e), flush=True)
         assert max(e) < bound, (tag, e)
+
+
+C5_STEPS = 30
+C5_CHECK = (9, 12, 16, 20, 25, 30)     # every lag active from step 9; the pulses cross the cube by step 40
+
+
+def test_cube_30720_16_waves_step_equation():
+    """The 30,720-unknown cube with 16 seeded waves (the headline solve) in
+    the configuration the benchmark times (FP64 approximate inverse,
+    speculative stepping, autotuned tiles, all 9 lags folded), 30 steps on the
+    device.  The oracle then checks eq. (MOT) on those unknowns at six steps
+    spread over the pulse: sum_j Q_j w_{k-j} = r_k, with every Q_j applied from
+    the raw blocks of its lag (a second device assembly pass, lag by lag; the
+    oracle's lag_products, C1 and C2 of eq. (CP), the RHS of eq. (rhs)), to
+    1e-9 of ||r_k|| (GMRES stops at 1e-13 of its right-hand side); and the
+    loop and star parts of every step against eq. (dis_jm) to 1e-10."""
+    import torch
+    import paper_2510_07989_amd as p
+    from fixture import gpu
+    from oracle.mot_oracle import (incidence, projectors, preconditioner, lag_products, tested_fields, rhs,
+                                   recover, blk, time_constants)
+    print("case cube_15360 16 waves: inputs", flush=True)
+    prob = gpu.build_problem_device("cube_15360")
+    V, F, E = prob["V"], prob["F"], prob["E"]
+    ne, R, K = E.shape[0], len(prob["waves"]), C5_STEPS
+    assert R == 16 and ne == 15360
+    st = torch.cuda.current_stream().cuda_stream
+    s = p.Solver(V, F, E, prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"], prob["T0h"], prob["G"],
+                 prob["waves"], stream=st, options=p.default_options(precond=2, max_steps=K + 8))
+    t0 = time.perf_counter()
+    gpu.load_solvers([s], prob, on_lag=lambda i: print("lag %d folded (%.0f s)" % (i, time.perf_counter() - t0),
+                                                      flush=True))
+    assert s.info()["folded"] == 1
+    print("march", flush=True)
+    out = s.run(K)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    W = out["w"]                                            # (K, 2 ne, R); W[m - 1] = w_m
+    _, Tmax, kmax = time_constants(V, prob["dt"], prob["eps_r"], prob["mu_r"])
+    assert kmax == prob["kmax"]
+    L = kmax + 2
+    print("oracle: projectors", flush=True)
+    P = projectors(*incidence(E, V.shape[0], F.shape[0]))
+    print("oracle: preconditioner", flush=True)
+    pre = preconditioner(prob["T0s"], prob["T0h"], prob["G"], P)
+    # projected unknowns, block-wise: (P (u), P (v)) of every step
+    XL = np.concatenate([P["PL"] @ W[:, :ne], P["PL"] @ W[:, ne:]], axis=1)
+    XS = W - XL
+    Y1 = {k: np.zeros((2 * ne, R)) for k in C5_CHECK}
+    Y2 = {k: np.zeros((2 * ne, R)) for k in C5_CHECK}
+    names = {(0, 0): "T_h", (0, 1): "K_h", (1, 0): "T_hat", (1, 1): "K_hat", (2, 0): "T_tilde", (2, 1): "K_tilde"}
+    raw_i = {"ext": {}, "int": {}}
+
+    def keep(fam, lag, med, op, t):
+        raw_i[("ext", "int")[med]][names[(fam, op)]] = t.cpu().numpy()
+
+    def lag_done(j):
+        ks = [k for k in C5_CHECK if k - j >= 1]
+        if ks:
+            xl = np.concatenate([XL[k - j - 1] for k in ks], axis=1)
+            xs = np.concatenate([XS[k - j - 1] for k in ks], axis=1)
+            y1, y2 = lag_products(raw_i, prob["eps_r"], prob["mu_r"], Tmax, kmax, j, xl, xs)
+            for c, k in enumerate(ks):
+                Y1[k] += y1[:, c * R:(c + 1) * R]
+                Y2[k] += y2[:, c * R:(c + 1) * R]
+        raw_i["ext"].clear()
+        raw_i["int"].clear()
+        print("oracle: lag %d of %d applied (%.0f s)" % (j, L - 1, time.perf_counter() - t0), flush=True)
+
+    t0 = time.perf_counter()
+    gpu.upload_lags(keep, V, F, E, prob["dt"], prob["eps_r"], prob["mu_r"], kmax, nq=prob["nq"], on_lag=lag_done)
+    torch.cuda.empty_cache()
+    fields = [tested_fields(V, F, E, prob["waves"], prob["dt"], k) for k in C5_CHECK]
+    r = rhs(pre, Tmax, np.concatenate([f[0] for f in fields], axis=1), np.concatenate([f[1] for f in fields], axis=1))
+    C1b, C2b = blk(pre["C1"]), blk(pre["C2"])
+    for c, k in enumerate(C5_CHECK):
+        rk = r[:, c * R:(c + 1) * R]
+        res = C1b @ Y1[k] + C2b @ Y2[k] - rk
+        e = np.linalg.norm(res) / np.linalg.norm(rk)
+        print("step %d: ||r_k|| %.3e, ||sum_j Q_j w_(k-j) - r_k|| / ||r_k|| = %.3e" % (k, np.linalg.norm(rk), e),
+              flush=True)
+        assert e < 1e-9, (k, e)
+    loop, star = recover(P, Tmax, prob["dt"], W)
+    for part, ref in (("loop", loop), ("star", star)):
+        e = _rel(out[part], ref)
+        print("%s part vs eq. (dis_jm): %.3e" % (part, e), flush=True)
+        assert e < 1e-10, (part, e)

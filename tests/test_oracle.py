@@ -518,6 +518,41 @@ def test_lag_operator_and_prefix_oracle_match_the_dense_form():
     assert len(lag_matrices(prob["raw"], O.pre, O.P, prob["eps_r"], prob["mu_r"], O.Tmax, O.kmax, 3)) == 3
 
 
+@pytest.mark.parametrize("kmax_override", [None, 1])
+def test_lag_products_from_one_lag_match_the_dense_form(kmax_override):
+    """lag_products, the inner sums of Q_i X taken block by block from one
+    lag's raw blocks, against C1b, C2b and the dense media sums of lag_blocks
+    (Section V-B): Q_i X equals C1b Y1 + C2b Y2 on every lag, every family's
+    truncation crossed; with k_max forced to 1 the lag-0 tilde K block is
+    dropped in both (eq. (spec_prop)); a lag whose family blocks are absent
+    counts them as zero."""
+    from oracle.mot_oracle import lag_products, lag_blocks, blk
+    prob = problem("tiny_box")
+    O = oracle("tiny_box")
+    kmax = O.kmax if kmax_override is None else kmax_override
+    rng = np.random.default_rng(12)
+    n = O.Q[0].shape[0]
+    X = rng.standard_normal((n, 3))
+    XL, XS = blk(O.P["PL"]) @ X, blk(O.P["PS"]) @ X
+    C1b, C2b = blk(O.pre["C1"]), blk(O.pre["C2"])
+    raw = prob["raw"]
+    for i in range(kmax + 2):
+        raw_i = {m: {k: v[i] for k, v in raw[m].items() if i < v.shape[0]} for m in raw}
+        Y1, Y2 = lag_products(raw_i, prob["eps_r"], prob["mu_r"], O.Tmax, kmax, i, XL, XS)
+        Zh, Zhat, Ztil = lag_blocks(raw, prob["eps_r"], prob["mu_r"], O.Tmax, kmax, i)
+        ref = C1b @ (Zh @ XL + Zhat @ XS) + C2b @ (Zh @ XS + Ztil @ XL)
+        got = C1b @ Y1 + C2b @ Y2
+        assert np.linalg.norm(got - ref) <= 1e-13 * max(np.linalg.norm(ref), 1e-300), (i, kmax)
+        if kmax_override is None:
+            assert np.linalg.norm(got - O.Q[i] @ X) <= 1e-12 * np.linalg.norm(O.Q[i] @ X), i
+    # the h family alone: Y2 - (tilde part) is Z^h XS, whose K blocks enter with opposite signs
+    raw_h = {m: {k: v[1] for k, v in raw[m].items() if k.endswith("_h")} for m in raw}
+    Y1, Y2 = lag_products(raw_h, prob["eps_r"], prob["mu_r"], O.Tmax, O.kmax, 1, XL, XS)
+    Zh = lag_blocks(raw, prob["eps_r"], prob["mu_r"], O.Tmax, O.kmax, 1)[0]
+    assert np.allclose(Y1, Zh @ XL, rtol=0, atol=1e-13 * np.abs(Zh @ XL).max())
+    assert np.allclose(Y2, Zh @ XS, rtol=0, atol=1e-13 * np.abs(Zh @ XS).max())
+
+
 @pytest.mark.parametrize("name", ["tiny_torus", "tiny_box"])
 def test_lag0_tilde_k_is_the_static_double_layer_when_kmax_is_1(name):
     """Sec. V-B, eq. (spec_prop): once c_min dt >= D (k_max = 1), the lag-0
