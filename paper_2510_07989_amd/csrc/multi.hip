@@ -512,8 +512,14 @@ __device__ __forceinline__ void unpack(const RawTiles<float>& r, bool hl, double
 // WG wavefronts per workgroup (4 or 8: 64 or 128 rows) share each staged slice
 // of the history vectors: with 8, every slice read from L2 serves twice the
 // rows.  The rows' sums are the same either way.
+//
+// One column block is bound by HBM, not by the matrix cores: there the
+// compiler is held to three wavefronts per SIMD (accumulators in VGPRs, no
+// AGPRs), so that more tile loads are in flight per CU than at the two its
+// register-hungry schedule would allow.
 template <typename T, int CB, int WG>
-__global__ __launch_bounds__(64 * WG) void k_tile_gemm(int ne, int hs, int G16, int KT, int Rp,
+__global__ __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(CB == 1 ? 3 : 1)))
+void k_tile_gemm(int ne, int hs, int G16, int KT, int Rp,
                                                    const int* __restrict__ dk, int nh, int q0_mode,
                                                    const T* __restrict__ At, const float* __restrict__ Alo,
                                                    int hilo, const double* __restrict__ ring,
