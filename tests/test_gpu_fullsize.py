@@ -103,16 +103,86 @@ def test_sphere_3840_64_waves_mixed_prefix(precision, bound_w, bound_star):
 
 
 NL_C3 = 4
+C3_STEPS = 38
+C3_CHECK = (31, 34, 38)     # every one of the 31 lags active from step 31; the pulses pass by step 50
+
+
+def _step_equation(prob, runs, checks, log):
+    """eq. (MOT) on given unknowns: for each k in checks,
+    || sum_j Q_j w_{k-j} - r_k || / || r_k || per run, every Q_j applied from
+    the raw blocks of its lag as a second device assembly pass hands them over
+    (lag_products, then C1b, C2b of eq. (CP)); r_k by eq. (rhs).
+    runs: name -> W (K, 2 ne, R) with W[m - 1] = w_m.  Returns name -> errors."""
+    import torch
+    from fixture import gpu
+    from oracle.mot_oracle import (incidence, projectors, preconditioner, lag_products, tested_fields, rhs, blk,
+                                   time_constants)
+    V, F, E = prob["V"], prob["F"], prob["E"]
+    ne, R = E.shape[0], len(prob["waves"])
+    _, Tmax, kmax = time_constants(V, prob["dt"], prob["eps_r"], prob["mu_r"])
+    L = kmax + 2
+    log("oracle: projectors")
+    P = projectors(*incidence(E, V.shape[0], F.shape[0]))
+    log("oracle: preconditioner")
+    pre = preconditioner(prob["T0s"], prob["T0h"], prob["G"], P)
+    names = list(runs)
+    proj = {}
+    for nm in names:
+        W = runs[nm]
+        XL = np.concatenate([P["PL"] @ W[:, :ne], P["PL"] @ W[:, ne:]], axis=1)
+        proj[nm] = (XL, W - XL)
+    Y1 = {(nm, k): np.zeros((2 * ne, R)) for nm in names for k in checks}
+    Y2 = {(nm, k): np.zeros((2 * ne, R)) for nm in names for k in checks}
+    codes = {(0, 0): "T_h", (0, 1): "K_h", (1, 0): "T_hat", (1, 1): "K_hat", (2, 0): "T_tilde", (2, 1): "K_tilde"}
+    raw_i = {"ext": {}, "int": {}}
+    t0 = time.perf_counter()
+
+    def keep(fam, lag, med, op, t):
+        raw_i[("ext", "int")[med]][codes[(fam, op)]] = t.cpu().numpy()
+
+    def lag_done(j):
+        cols = [(nm, k) for nm in names for k in checks if k - j >= 1]
+        if cols:
+            xl = np.concatenate([proj[nm][0][k - j - 1] for nm, k in cols], axis=1)
+            xs = np.concatenate([proj[nm][1][k - j - 1] for nm, k in cols], axis=1)
+            y1, y2 = lag_products(raw_i, prob["eps_r"], prob["mu_r"], Tmax, kmax, j, xl, xs)
+            for c, key in enumerate(cols):
+                Y1[key] += y1[:, c * R:(c + 1) * R]
+                Y2[key] += y2[:, c * R:(c + 1) * R]
+        raw_i["ext"].clear()
+        raw_i["int"].clear()
+        log("oracle: lag %d of %d applied (%.0f s)" % (j, L - 1, time.perf_counter() - t0))
+
+    gpu.upload_lags(keep, V, F, E, prob["dt"], prob["eps_r"], prob["mu_r"], kmax, nq=prob["nq"], on_lag=lag_done)
+    torch.cuda.empty_cache()
+    fields = [tested_fields(V, F, E, prob["waves"], prob["dt"], k) for k in checks]
+    r = rhs(pre, Tmax, np.concatenate([f[0] for f in fields], axis=1), np.concatenate([f[1] for f in fields], axis=1))
+    C1b, C2b = blk(pre["C1"]), blk(pre["C2"])
+    errs = {nm: [] for nm in names}
+    for nm in names:
+        for c, k in enumerate(checks):
+            rk = r[:, c * R:(c + 1) * R]
+            res = C1b @ Y1[(nm, k)] + C2b @ Y2[(nm, k)] - rk
+            errs[nm].append(np.linalg.norm(res) / np.linalg.norm(rk))
+            log("%s step %d: ||r_k|| %.3e, ||sum_j Q_j w_(k-j) - r_k|| / ||r_k|| = %.3e"
+                % (nm, k, np.linalg.norm(rk), errs[nm][-1]))
+    return errs, P, Tmax
+
+
+def _say(msg):
+    print(msg, flush=True)
 
 
 def test_sphere_15360_64_waves_prefix():
     """The 15,360-unknown sphere with 64 seeded waves (the batched benchmark
     solve) in the configuration the benchmark times (FP64 approximate inverse,
     speculative stepping, autotuned tiles, all 31 lags folded): one device
-    assembly pass feeds an FP64 and a mixed solver; the first 4 steps against
-    the oracle on the same inputs (Q_0 dense with its LU, the later lags as
-    operators; eq. (MOT), eq. (dis_jm)): FP64 to 1e-10, MOT_MIXED to 1e-6 on
-    w, loop and star."""
+    assembly pass feeds an FP64 and a mixed solver, each marched 38 steps.
+    The first 4 steps against the oracle on the same inputs (Q_0 dense with
+    its LU, the later lags as operators; eq. (MOT), eq. (dis_jm)): FP64 to
+    1e-10, MOT_MIXED to 1e-6 on w, loop and star.  Then eq. (MOT) with all 31
+    lags at steps 31, 34 and 38 (every Q_j applied from a second assembly
+    pass): FP64 to 1e-9 of ||r_k||, MOT_MIXED (lags stored in FP32) to 1e-6."""
     import torch
     import paper_2510_07989_amd as p
     from fixture import gpu
@@ -124,7 +194,7 @@ def test_sphere_15360_64_waves_prefix():
     st = torch.cuda.current_stream().cuda_stream
     ss = [p.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"], prob["T0s"],
                    prob["T0h"], prob["G"], prob["waves"], stream=st,
-                   options=p.default_options(precond=2, precision=prec, max_steps=16)) for prec in (0, 1)]
+                   options=p.default_options(precond=2, precision=prec, max_steps=C3_STEPS + 8)) for prec in (0, 1)]
     names = {(0, 0): "T_h", (0, 1): "K_h", (1, 0): "T_hat", (1, 1): "K_hat", (2, 0): "T_tilde", (2, 1): "K_tilde"}
     raw = {m: {k: np.zeros((NL_C3, ne, ne)) for k in names.values()} for m in ("ext", "int")}
 
@@ -142,7 +212,7 @@ def test_sphere_15360_64_waves_prefix():
                     prob["kmax"], nq=prob["nq"], on_lag=progress)
     assert all(s.info()["folded"] == 1 for s in ss)
     print("march", flush=True)
-    outs = [s.run(NL_C3) for s in ss]
+    outs = [s.run(C3_STEPS) for s in ss]
     for s in ss:
         s.close()
     del ss
@@ -150,10 +220,15 @@ def test_sphere_15360_64_waves_prefix():
     print("oracle", flush=True)
     ref = Oracle(dict(prob, raw=raw), nlag=NL_C3, operators=True,
                  log=lambda stage: print("oracle:", stage, flush=True)).run(NL_C3)
+    del raw
     for out, bound, tag in ((outs[0], 1e-10, "fp64"), (outs[1], 1e-6, "mixed")):
-        e = [_rel(out[k], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
+        e = [_rel(out[k][:NL_C3], ref[r]) for k, r in (("w", "W"), ("loop", "loop"), ("star", "star"))]
         print("%s prefix errors: w %.3e loop %.3e star %.3e" % (tag, *e), flush=True)
         assert max(e) < bound, (tag, e)
+    del ref
+    errs, _, _ = _step_equation(prob, {"fp64": outs[0]["w"], "mixed": outs[1]["w"]}, C3_CHECK, _say)
+    assert max(errs["fp64"]) < 1e-9, errs["fp64"]
+    assert max(errs["mixed"]) < 1e-6, errs["mixed"]
 
 
 C5_STEPS = 30
@@ -173,8 +248,7 @@ def test_cube_30720_16_waves_step_equation():
     import torch
     import paper_2510_07989_amd as p
     from fixture import gpu
-    from oracle.mot_oracle import (incidence, projectors, preconditioner, lag_products, tested_fields, rhs,
-                                   recover, blk, time_constants)
+    from oracle.mot_oracle import recover
     print("case cube_15360 16 waves: inputs", flush=True)
     prob = gpu.build_problem_device("cube_15360")
     V, F, E = prob["V"], prob["F"], prob["E"]
@@ -192,52 +266,9 @@ def test_cube_30720_16_waves_step_equation():
     s.close()
     del s
     torch.cuda.empty_cache()
-    W = out["w"]                                            # (K, 2 ne, R); W[m - 1] = w_m
-    _, Tmax, kmax = time_constants(V, prob["dt"], prob["eps_r"], prob["mu_r"])
-    assert kmax == prob["kmax"]
-    L = kmax + 2
-    print("oracle: projectors", flush=True)
-    P = projectors(*incidence(E, V.shape[0], F.shape[0]))
-    print("oracle: preconditioner", flush=True)
-    pre = preconditioner(prob["T0s"], prob["T0h"], prob["G"], P)
-    # projected unknowns, block-wise: (P (u), P (v)) of every step
-    XL = np.concatenate([P["PL"] @ W[:, :ne], P["PL"] @ W[:, ne:]], axis=1)
-    XS = W - XL
-    Y1 = {k: np.zeros((2 * ne, R)) for k in C5_CHECK}
-    Y2 = {k: np.zeros((2 * ne, R)) for k in C5_CHECK}
-    names = {(0, 0): "T_h", (0, 1): "K_h", (1, 0): "T_hat", (1, 1): "K_hat", (2, 0): "T_tilde", (2, 1): "K_tilde"}
-    raw_i = {"ext": {}, "int": {}}
-
-    def keep(fam, lag, med, op, t):
-        raw_i[("ext", "int")[med]][names[(fam, op)]] = t.cpu().numpy()
-
-    def lag_done(j):
-        ks = [k for k in C5_CHECK if k - j >= 1]
-        if ks:
-            xl = np.concatenate([XL[k - j - 1] for k in ks], axis=1)
-            xs = np.concatenate([XS[k - j - 1] for k in ks], axis=1)
-            y1, y2 = lag_products(raw_i, prob["eps_r"], prob["mu_r"], Tmax, kmax, j, xl, xs)
-            for c, k in enumerate(ks):
-                Y1[k] += y1[:, c * R:(c + 1) * R]
-                Y2[k] += y2[:, c * R:(c + 1) * R]
-        raw_i["ext"].clear()
-        raw_i["int"].clear()
-        print("oracle: lag %d of %d applied (%.0f s)" % (j, L - 1, time.perf_counter() - t0), flush=True)
-
-    t0 = time.perf_counter()
-    gpu.upload_lags(keep, V, F, E, prob["dt"], prob["eps_r"], prob["mu_r"], kmax, nq=prob["nq"], on_lag=lag_done)
-    torch.cuda.empty_cache()
-    fields = [tested_fields(V, F, E, prob["waves"], prob["dt"], k) for k in C5_CHECK]
-    r = rhs(pre, Tmax, np.concatenate([f[0] for f in fields], axis=1), np.concatenate([f[1] for f in fields], axis=1))
-    C1b, C2b = blk(pre["C1"]), blk(pre["C2"])
-    for c, k in enumerate(C5_CHECK):
-        rk = r[:, c * R:(c + 1) * R]
-        res = C1b @ Y1[k] + C2b @ Y2[k] - rk
-        e = np.linalg.norm(res) / np.linalg.norm(rk)
-        print("step %d: ||r_k|| %.3e, ||sum_j Q_j w_(k-j) - r_k|| / ||r_k|| = %.3e" % (k, np.linalg.norm(rk), e),
-              flush=True)
-        assert e < 1e-9, (k, e)
-    loop, star = recover(P, Tmax, prob["dt"], W)
+    errs, P, Tmax = _step_equation(prob, {"fp64": out["w"]}, C5_CHECK, _say)
+    assert max(errs["fp64"]) < 1e-9, errs["fp64"]
+    loop, star = recover(P, Tmax, prob["dt"], out["w"])
     for part, ref in (("loop", loop), ("star", star)):
         e = _rel(out[part], ref)
         print("%s part vs eq. (dis_jm): %.3e" % (part, e), flush=True)
