@@ -243,9 +243,10 @@ def make_solvers(mot, prob, variants, max_steps):
     for v in variants:
         kw = dict(profile=PROFILE_EVERY, max_steps=max_steps)
         kw.update(v)
+        waves = kw.pop("waves", prob["waves"])          # a variant may march a subset of the waves
         opts = mot.default_options(**kw)
         ss.append(mot.Solver(prob["V"], prob["F"], prob["E"], prob["eps_r"], prob["mu_r"], prob["dt"],
-                             prob["T0s"], prob["T0h"], prob["G"], prob["waves"], options=opts,
+                             prob["T0s"], prob["T0h"], prob["G"], waves, options=opts,
                              stream=torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t
@@ -362,7 +363,9 @@ def batched_leg(mot, args):
     """The 15,360-unknown sphere with 64 seeded waves: FP64 against the mixed
     path (and, with --mixed32, the FP32 matrix-core path) on the same device
     assembly, recovery inside the timed region; the mixed error against the
-    FP64 run over the warm-up steps."""
+    FP64 run over the warm-up steps; and the plain FP64 march of the first wave
+    alone (one RHS), the single-excitation rate the batched solves are
+    compared with."""
     import numpy as np
     import torch
     from fixture import gpu as fxgpu
@@ -375,17 +378,33 @@ def batched_leg(mot, args):
                 (1, dict(precond=args.precond, precision=1, hilo_lags=args.hilo))]
     if args.mixed32:
         variants.append((2, dict(precond=args.precond, precision=2, hilo_lags=args.hilo, mix_group=args.mix_group)))
+    if not args.no_single_rhs:
+        variants.append(("1rhs", dict(precond=args.precond, precision=0, waves=prob["waves"][:1])))
     ss, t_create, t_load = make_solvers(mot, prob, [v for _, v in variants], Wb + Kb + 8)
     log("[%s] inputs %.1f s, create %.1f s, device assembly and fold of %d solvers %.1f s"
         % (name, t_in, t_create, len(ss), t_load))
     res = {}
-    for (prec, _), s in zip(variants, ss):
-        res[prec] = timed(s, prob, name, prec, Kb, Wb, args.hilo, args.mix_group)
+    for (prec, v), s in zip(variants, ss):
+        p_ = dict(prob, waves=v["waves"]) if "waves" in v else prob
+        res[prec] = timed(s, p_, name, v["precision"], Kb, Wb, args.hilo, args.mix_group)
         s.close()
     torch.cuda.empty_cache()
     ref = res[0]["warm"]
     out = {"workload": name + ": " + WORKLOADS[name], "steps": Kb, "warmup": Wb,
            "setup_s": round(t_create + t_load, 2), "fp64_64rhs": brief(res[0])}
+    if "1rhs" in res:
+        one = res["1rhs"]
+        out["fp64_1rhs"] = brief(one)
+        for prec, key in ((0, "fp64_64rhs"), (1, "mixed_64rhs")):
+            if prec in res:
+                r = res[prec]
+                out.setdefault("vs_fp64_1rhs", {})[key] = {
+                    "steps_ratio": round(r["steps_s"] / one["steps_s"], 3),
+                    "rhs_steps_ratio": round(r["steps_s"] * r["R"] / one["steps_s"], 2)}
+        log("[%s] plain FP64, one wave: %.1f steps/s; 64 waves mixed: %.1f steps/s = %.0f RHS-steps/s (x%.1f)"
+            % (name, one["steps_s"], res[1]["steps_s"] if 1 in res else float("nan"),
+               res[1]["steps_s"] * 64 if 1 in res else float("nan"),
+               res[1]["steps_s"] * 64 / one["steps_s"] if 1 in res else float("nan")))
     for prec, key in ((1, "mixed_64rhs"), (2, "mixed32_64rhs")):
         if prec not in res:
             continue
@@ -412,6 +431,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-warmup", type=int, default=40)
     ap.add_argument("--mixed32", action="store_true", help="also time the FP32 matrix-core mixed path")
+    ap.add_argument("--no-single-rhs", action="store_true",
+                    help="skip the one-wave FP64 march of the 64-wave sphere's mesh")
     ap.add_argument("--no-torus", action="store_true", help="skip the 10,000-step torus march")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison")
     ap.add_argument("--serving", action="store_true",
