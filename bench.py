@@ -438,6 +438,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="also measure continuous batching of a request stream (not run by default)")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--no-serving-smoke", action="store_true",
+                    help="skip the time-boxed 32-request smoke stream (thread-per-solve server)")
+    ap.add_argument("--serving-smoke-requests", type=int, default=32)
+    ap.add_argument("--serving-smoke-box", type=float, default=60.0, help="seconds before the smoke stream is cut")
     ap.add_argument("--no-serving-c4", action="store_true", help="leave the stream out (the default)")
     ap.add_argument("--serving-c4", action="store_true",
                     help="also serve the time-boxed 256-request stream (batch server; off by default while a stall "
@@ -529,6 +533,9 @@ def run_legs(mot, args, result):
         result["torus"] = torus_leg(mot, args)
     if not args.no_step_batch:
         result["step_batch"] = step_batch(mot)
+    if not args.no_serving_smoke:
+        result["serving_smoke"] = guarded(lambda: serving_smoke(args), args.serving_smoke_box + 150.0, result,
+                                          "serving_smoke")
     if args.serving_c4 and not args.no_serving_c4:
         try:
             result["serving_c4"] = serving_c4(args)
@@ -648,7 +655,9 @@ def c4_requests(nreq, seed=251007991, rate=2.0):
             inp = fxgpu.device_inputs(V, F, E)
 
             def loader(s, V=V, F=F, E=E, eps_r=eps_r, dt=dt, kmax=kmax):
-                fxgpu.load_solvers([s], dict(V=V, F=F, E=E, eps_r=eps_r, mu_r=1.0, dt=dt, kmax=kmax, nq=7))
+                from paper_2510_07989_amd.serve import stop_if_cancelled
+                fxgpu.load_solvers([s], dict(V=V, F=F, E=E, eps_r=eps_r, mu_r=1.0, dt=dt, kmax=kmax, nq=7),
+                                   on_lag=lambda i: stop_if_cancelled(s))
             return dict(G=inp["G"], T0s=inp["T0s"], T0h=inp["T0h"], loader=loader)
 
         prob = dict(name="%s_%d" % (kind, 2 * ne), V=V, F=F, E=E, eps_r=eps_r, mu_r=1.0, dt=dt, kmax=kmax,
@@ -657,6 +666,96 @@ def c4_requests(nreq, seed=251007991, rate=2.0):
                     extra_bytes=2 * 3 * 6 * 8 * ne * ne)
         out.append((prob, nsteps, float(arrivals[i])))
     return out
+
+
+def serving_smoke(args):
+    """The serving stream's smoke variant, on by default: the first requests
+    of a C4 stream (see c4_requests; its own seed) with a tenth of their steps
+    (50 to 500), served by the thread-per-solve server (each request creates,
+    loads and marches its solve on its own host thread and stream, in windows
+    of mot_run; inputs built on the device in its setup, at most three setups
+    at a time), at most 8 at once under a 200 GB budget of peak footprints
+    plus the assembler's memory,
+    time-boxed: at the box running requests are stopped with mot_cancel (one
+    still uploading its lags stops between lags) and requests not yet admitted
+    are not served."""
+    import numpy as np
+    import torch
+    from paper_2510_07989_amd.serve import GpuBackend, Request, Server, latency_stats
+    t = time.perf_counter()
+    stream = c4_requests(args.serving_smoke_requests, seed=251007992)
+    log("[smoke] %d requests generated in %.1f s" % (len(stream), time.perf_counter() - t))
+    reqs = [Request(i, p, max(1, ns // 10), arr, dict(precond=2, spec_window=32))
+            for i, (p, ns, arr) in enumerate(stream)]
+    be = GpuBackend(keep_outputs=False, setup_slots=3)
+    srv = Server(be, mem_budget=int(200e9), max_active=8, window=128, time_box=args.serving_smoke_box,
+                 request_timeout=args.serving_smoke_box, log=log)
+    res, summ = srv.run(reqs)
+    torch.cuda.empty_cache()
+    sizes = sorted(2 * q.problem["E"].shape[0] for q in reqs)
+    served = [q for q in reqs if res[q.rid].error is None]
+    out = {
+        "workload": "C4 smoke stream: %d requests, Poisson arrivals at 2/s, sphere/torus/cube of %d to %d unknowns "
+                    "(log-uniform), eps_r U[1.5, 6], 1-32 waves, 50-500 steps (a tenth of C4's), c dt = D/4; inputs "
+                    "built in each request's setup (static and retarded blocks on the device)"
+                    % (len(reqs), sizes[0], sizes[-1]),
+        "server": "thread per solve (mot_run windows of 128 steps, speculative windows of 32, <= 8 at once, "
+                  "<= 3 setups at once)",
+        "time_box_s": args.serving_smoke_box, "mem_budget_gb": 200.0,
+        "completed": summ["completed"], "cancelled_at_box": summ["cancelled"], "not_served": summ["not_served"],
+        "errors": summ["errors"], "wall_s": round(summ["wall_s"], 2),
+        "steps_marched": summ["steps_marched"], "steps_per_s": round(summ["steps_per_s"], 1),
+        "rhs_steps_per_s": round(summ["rhs_steps_per_s"], 1),
+        "step_latency_us": {k: round(1e6 * v, 1) if k != "n" else v for k, v in summ["step_latency_s"].items()},
+        "end_to_end_s": {k: round(v, 3) if k != "n" else v for k, v in summ["end_to_end_s"].items()},
+        "setup_s": {k: round(v, 3) if k != "n" else v
+                    for k, v in latency_stats(r.t_ready - r.t_admit for r in res.values()
+                                              if r.t_ready > 0).items()},
+        "queue_wait_s": {k: round(v, 3) if k != "n" else v for k, v in summ["queue_wait_s"].items()},
+        "max_concurrent": summ["max_concurrent"], "peak_budget_gb": round(summ["peak_budget_used"] / 1e9, 2),
+        "completed_unknowns": {"max": max((2 * q.problem["E"].shape[0] for q in served), default=0),
+                               "median": float(np.median([2 * q.problem["E"].shape[0] for q in served] or [0]))},
+    }
+    errs = [r.error for r in res.values() if r.error and not r.error.startswith(("CancelledRun", "NotServed"))]
+    if errs:
+        out["first_errors"] = errs[:3]
+    for v in out.values():              # statistics of an empty set are NaN, which JSON does not carry
+        if isinstance(v, dict):
+            for k in v:
+                if isinstance(v[k], float) and v[k] != v[k]:
+                    v[k] = None
+    log("[smoke] %d completed, %d cancelled at the box, %d not served, %d errors in %.1f s; %.0f steps/s, step p50 "
+        "%.0f us p99 %.0f us; end-to-end p50 %.2f s p99 %.2f s"
+        % (summ["completed"], summ["cancelled"], summ["not_served"], summ["errors"], summ["wall_s"],
+           summ["steps_per_s"], 1e6 * summ["step_latency_s"]["p50"], 1e6 * summ["step_latency_s"]["p99"],
+           summ["end_to_end_s"]["p50"], summ["end_to_end_s"]["p99"]))
+    return out
+
+
+def guarded(fn, limit, result, key):
+    """Run a leg under a hard wall-clock limit: if it has not returned by then
+    (a request stuck inside the runtime), the JSON line is printed with the leg
+    marked and the process ends, so the measured legs are not lost."""
+    import threading
+    box = {}
+    done = threading.Event()
+
+    def target():
+        try:
+            box["out"] = fn()
+        except Exception as e:           # the headline line is printed whatever this leg does
+            box["out"] = {"error": "%s: %s" % (type(e).__name__, e)}
+        finally:
+            done.set()
+
+    threading.Thread(target=target, daemon=True).start()
+    if not done.wait(limit):
+        result[key] = {"error": "did not finish within %.0f s; the process ended there" % limit}
+        log("[%s] did not finish within %.0f s" % (key, limit))
+        print(json.dumps(result), flush=True)
+        sys.stderr.flush()
+        os._exit(0)
+    return box["out"]
 
 
 def serving_c4(args):

@@ -48,7 +48,8 @@ from typing import Any, Callable, Dict, List, Optional
 
 import numpy as np
 
-__all__ = ["Request", "Result", "Server", "BatchServer", "GpuBackend", "latency_stats"]
+__all__ = ["Request", "Result", "Server", "BatchServer", "GpuBackend", "latency_stats", "CancelledRun",
+           "stop_if_cancelled"]
 
 
 @dataclass
@@ -98,23 +99,57 @@ class CancelledRun(RuntimeError):
     """A solve stopped by mot_cancel (time limit or time box)."""
 
 
+def stop_if_cancelled(s):
+    """For loaders (Request.problem['loader']): raise CancelledRun between
+    uploads once the server has cancelled solver s, so that a request whose
+    time ran out during its setup does not finish assembling its inputs."""
+    if getattr(s, "_serve_cancelled", False):
+        raise CancelledRun("cancelled during setup")
+
+
 class GpuBackend:
     """Runs a request on the current GPU through the C ABI, on a stream of its own."""
 
-    def __init__(self, options: Optional[Dict[str, Any]] = None, keep_outputs: bool = True):
+    def __init__(self, options: Optional[Dict[str, Any]] = None, keep_outputs: bool = True,
+                 setup_slots: Optional[int] = None):
+        """setup_slots: at most this many requests build their inputs and
+        solvers at once (execute; None: no limit); the others wait, admitted."""
         self.options = dict(options or {})
         self.keep_outputs = keep_outputs
+        self._setup_gate = threading.Semaphore(setup_slots) if setup_slots else None
         self._live: Dict[int, Any] = {}
+        self._pending_cancel = set()
         self._live_lock = threading.Lock()
 
     def cancel(self, rid: int) -> bool:
-        """Stop request rid's march at its next window boundary (mot_cancel)."""
+        """Stop request rid's march at its next window boundary (mot_cancel);
+        a request still creating its solver is stopped as soon as it exists."""
         with self._live_lock:
             s = self._live.get(rid)
-        if s is None:
-            return False
-        s.cancel()
+            if s is None:
+                self._pending_cancel.add(rid)
+                return True
+        self._stop(s)
         return True
+
+    @staticmethod
+    def _stop(s):
+        # the flag lets a loader that is still uploading stop between lags
+        # (stop_if_cancelled); mot_cancel stops the march
+        s._serve_cancelled = True
+        s.cancel()
+
+    def _register(self, rid, s):
+        with self._live_lock:
+            self._live[rid] = s
+            if rid in self._pending_cancel:
+                self._pending_cancel.discard(rid)
+                self._stop(s)
+
+    def _unregister(self, rid):
+        with self._live_lock:
+            self._live.pop(rid, None)
+            self._pending_cancel.discard(rid)
 
     def _load(self, s, p):
         if p.get("loader") is not None:
@@ -129,18 +164,22 @@ class GpuBackend:
         torch.cuda.set_device(0)
         stream = torch.cuda.Stream()          # default priority
         with torch.cuda.stream(stream):
-            p = self._inputs(req.problem)
-            s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
-                           p["waves"], options=self._opts(req), stream=stream.cuda_stream)
+            try:
+                p = self._inputs(req.problem)
+                s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"],
+                               p["G"], p["waves"], options=self._opts(req), stream=stream.cuda_stream)
+            except Exception:
+                self._unregister(req.rid)
+                raise
             try:
                 self._load(s, p)
                 stream.synchronize()
             except Exception:
+                self._unregister(req.rid)
                 s.close()
                 raise
         s._serve_stream = stream
-        with self._live_lock:
-            self._live[req.rid] = s
+        self._register(req.rid, s)
         return s
 
     def outputs(self, req: Request, s, nsteps: int) -> Dict[str, np.ndarray]:
@@ -150,8 +189,7 @@ class GpuBackend:
         return {k: out[k] for k in ("w", "loop", "star")}
 
     def close(self, req: Request, s) -> None:
-        with self._live_lock:
-            self._live.pop(req.rid, None)
+        self._unregister(req.rid)
         s.close()
 
     def run_batch(self, solvers, nsteps):
@@ -206,18 +244,36 @@ class GpuBackend:
         import paper_2510_07989_amd as mot
         torch.cuda.set_device(0)
         stream = torch.cuda.Stream()          # default priority
-        with torch.cuda.stream(stream):       # output tensors belong to this stream
-            self._march(mot, torch, stream, req, window, clock, res)
+        try:
+            with torch.cuda.stream(stream):   # output tensors belong to this stream
+                self._march(mot, torch, stream, req, window, clock, res)
+        finally:
+            self._unregister(req.rid)         # also a cancel left pending by a failed setup
 
     def _march(self, mot, torch, stream, req, window, clock, res):
-        p = self._inputs(req.problem)
-        s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
-                       p["waves"], options=self._opts(req), stream=stream.cuda_stream)
-        with self._live_lock:
-            self._live[req.rid] = s
+        gate = self._setup_gate
+        if gate is not None:
+            gate.acquire()
+        s = None
         try:
+            with self._live_lock:
+                if req.rid in self._pending_cancel:       # stopped while it waited for a setup slot
+                    raise CancelledRun("cancelled before its setup")
+            p = self._inputs(req.problem)
+            s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
+                           p["waves"], options=self._opts(req), stream=stream.cuda_stream)
+            self._register(req.rid, s)
             self._load(s, p)
             stream.synchronize()
+        except BaseException:
+            if s is not None:
+                self._unregister(req.rid)
+                s.close()
+            raise
+        finally:
+            if gate is not None:
+                gate.release()
+        try:
             res.t_ready = clock()
             parts = {"w": [], "loop": [], "star": []}
             done = 0
@@ -240,8 +296,7 @@ class GpuBackend:
                 for k, v in parts.items():
                     res.outputs[k] = torch.cat(v).cpu().numpy()
         finally:
-            with self._live_lock:
-                self._live.pop(req.rid, None)
+            self._unregister(req.rid)
             s.close()
 
 
@@ -249,12 +304,18 @@ class Server:
     """Admission by memory footprint and concurrent execution (see module doc)."""
 
     def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 64, poll: float = 0.001,
-                 request_timeout: float = 600.0, log: Optional[Callable[[str], None]] = None):
+                 request_timeout: float = 600.0, time_box: Optional[float] = None,
+                 log: Optional[Callable[[str], None]] = None):
+        """time_box: seconds after start when every request still running is
+        cancelled (at its next window boundary; it is then reported as
+        cancelled with the steps it completed) and requests not yet admitted
+        are not served."""
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_active = int(max_active)
         self.window = int(window)
         self.poll = poll
+        self.time_box = time_box
         self.request_timeout = float(request_timeout)
         self.log = log
         self.trace: List[tuple] = []          # (time, event, rid, active, used bytes)
@@ -291,10 +352,23 @@ class Server:
             with lock:
                 finished.append(req.rid)
 
+        boxed = False
         while pending or queue or active:
             now = clock()
             while pending and pending[0].arrival <= now:
                 queue.append(pending.pop(0))
+            if self.time_box is not None and now >= self.time_box and not boxed:
+                # the box closes: nothing more is admitted, running requests stop at their next window
+                boxed = True
+                for req in pending + queue:
+                    results[req.rid].error = "NotServed: the time box closed before admission"
+                pending, queue = [], []
+                for rid in list(active):
+                    if rid not in cancelled:
+                        cancelled.add(rid)
+                        getattr(self.backend, "cancel", lambda _rid: False)(rid)
+                if self.log:
+                    self.log("[serve %.2fs] time box closed; %d running cancelled" % (now, len(active)))
             with lock:
                 done_now, finished[:] = list(finished), []
             for rid in done_now:
@@ -340,18 +414,25 @@ class Server:
             time.sleep(wait)
         wall = clock()
         nrhs = {q.rid: len(q.problem["waves"]) for q in reqs}
-        steps = sum(r.nsteps for r in results.values() if r.error is None)
-        rhs_steps = sum(r.nsteps * nrhs[r.rid] for r in results.values() if r.error is None)
+        ok = [r for r in results.values() if r.error is None]
+        steps = sum(r.nsteps for r in ok)
+        marched = sum(len(r.step_latency) for r in results.values())
+        rhs_marched = sum(len(r.step_latency) * nrhs[r.rid] for r in results.values())
+        stopped = ("CancelledRun", "NotServed")
         summary = {
             "requests": len(reqs),
-            "errors": sum(1 for r in results.values() if r.error),
+            "completed": len(ok),
+            "cancelled": sum(1 for r in results.values() if r.error and r.error.startswith("CancelledRun")),
+            "not_served": sum(1 for r in results.values() if r.error and r.error.startswith("NotServed")),
+            "errors": sum(1 for r in results.values() if r.error and not r.error.startswith(stopped)),
             "wall_s": wall,
             "steps": steps,
-            "steps_per_s": steps / wall if wall > 0 else float("nan"),
-            "rhs_steps_per_s": rhs_steps / wall if wall > 0 else float("nan"),
+            "steps_marched": marched,
+            "steps_per_s": marched / wall if wall > 0 else float("nan"),
+            "rhs_steps_per_s": rhs_marched / wall if wall > 0 else float("nan"),
             "step_latency_s": latency_stats(x for r in results.values() for x in r.step_latency),
-            "end_to_end_s": latency_stats(r.end_to_end for r in results.values() if r.error is None),
-            "queue_wait_s": latency_stats(r.queue_wait for r in results.values()),
+            "end_to_end_s": latency_stats(r.end_to_end for r in ok),
+            "queue_wait_s": latency_stats(r.queue_wait for r in results.values() if r.t_admit > 0),
             "max_concurrent": max((t[3] for t in self.trace), default=0),
             "peak_budget_used": max((t[4] for t in self.trace), default=0),
         }

@@ -257,3 +257,23 @@ def test_thread_server_cancels_a_request_past_its_limit():
     res, summ = srv.run(reqs)
     assert res[0].error.startswith("CancelledRun") and res[1].error is None
     assert res[1].t_admit >= res[0].t_done - 1e-6
+
+
+def test_thread_server_time_box_cancels_and_drops():
+    """At the time box the per-thread server cancels every running request at
+    its next window boundary (the steps it completed are kept and counted),
+    admits nothing more and reports the rest as not served; every request is
+    accounted for once."""
+    be = CancellableSleepBackend(step_s=0.002)
+    reqs = [_req(i, 400, 400, 0.05 * i) for i in range(8)]
+    srv = Server(be, mem_budget=1000, max_active=2, window=32, time_box=0.3)
+    res, summ = srv.run(reqs)
+    assert summ["cancelled"] >= 1 and summ["not_served"] >= 1 and summ["errors"] == 0
+    assert summ["completed"] + summ["cancelled"] + summ["not_served"] == 8
+    for r in res.values():
+        if r.error and r.error.startswith("CancelledRun"):
+            assert 0 < len(r.step_latency) < r.nsteps
+        if r.error and r.error.startswith("NotServed"):
+            assert not r.step_latency and r.t_admit == 0
+    assert summ["steps_marched"] == sum(len(r.step_latency) for r in res.values())
+    assert summ["wall_s"] < 0.3 + 0.5
