@@ -173,3 +173,39 @@ def test_eight_concurrent_solves_same_as_alone(batch):
         assert np.array_equal(r.outputs["w"], alone[rid]["w"]), rid
         for k in ("loop", "star"):       # the recovery's batches of steps may differ
             assert _rel(r.outputs[k], alone[rid][k]) <= 1e-12, (rid, k)
+
+
+def test_time_box_stops_running_and_waiting_requests():
+    """The per-thread server with one setup slot and a time box that closes
+    while one request marches, one is still building its inputs (holding the
+    slot) and one waits for the slot: the marching one stops at a window
+    boundary with its steps counted (mot_cancel), the one in setup is stopped
+    as soon as its solver exists, the waiting one before its setup, and one
+    that arrives after the box is not served; no errors, every solve closed,
+    and the same backend then runs a request to completion bit for bit as
+    before."""
+    import time
+    from paper_2510_07989_amd.serve import GpuBackend, Request, Server
+    print("case time box", flush=True)
+    prob = problem("sphere_480_r16")
+    opts = dict(precond=2, spec_window=32)
+    be = GpuBackend(setup_slots=1)
+    ref, _ = Server(be, mem_budget=1 << 40, window=64).run([Request(0, prob, 200, 0.0, opts)])
+    assert ref[0].error is None
+    slow = dict(prob, prepare=lambda: time.sleep(3.0) or {})     # holds the setup slot past the box
+    reqs = [Request(0, prob, 100000, 0.0, opts), Request(1, slow, 100000, 0.3, opts),
+            Request(2, prob, 100000, 0.4, opts), Request(3, prob, 50, 30.0, opts)]
+    srv = Server(be, mem_budget=1 << 40, max_active=3, window=64, time_box=1.5)
+    res, summ = srv.run(reqs)
+    print("summary", {k: summ[k] for k in ("completed", "cancelled", "not_served", "errors", "wall_s")},
+          "steps", [len(res[i].step_latency) for i in range(4)], [res[i].error for i in range(4)], flush=True)
+    assert summ["errors"] == 0 and summ["completed"] == 0
+    assert summ["cancelled"] == 3 and summ["not_served"] == 1
+    assert 0 < len(res[0].step_latency) < 100000
+    assert len(res[1].step_latency) == 0 and len(res[2].step_latency) == 0
+    assert "before its setup" in res[2].error
+    assert not be._live and not be._pending_cancel
+    again, _ = Server(be, mem_budget=1 << 40, window=64).run([Request(0, prob, 200, 0.0, opts)])
+    assert again[0].error is None
+    for k in ("w", "loop", "star"):
+        assert np.array_equal(again[0].outputs[k], ref[0].outputs[k]), k
