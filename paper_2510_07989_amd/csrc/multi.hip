@@ -988,8 +988,11 @@ void plan_tiles(mot_handle* h) {
         h->q0_kc_c = kc_candidates(h->q0_kc, std::max(1, h->KT / 4));
         if (h->opt.precond) h->plain_kc_c = kc_candidates(h->plain_kc, maxkc);
     }
-    // Krylov sweeps: about 1024 (row, column) entries per workgroup
-    h->orth_nb = std::max(1, std::min(480, (int)(((size_t)h->n2 * h->Rp + 1023) / 1024)));
+    // Krylov sweeps: about 1024 (row, column) entries per workgroup, at most
+    // 120 workgroups: every workgroup ends with a device-scope release before
+    // the grid counter, and that write-back costs more than the rows it saves
+    // (three sweeps at 30,720 x 16: 160 us with 480 workgroups, 79 with 120)
+    h->orth_nb = std::max(1, std::min(120, (int)(((size_t)h->n2 * h->Rp + 1023) / 1024)));
     h->orth_rb = (h->n2 + h->orth_nb - 1) / h->orth_nb;
     h->orth_nb = (h->n2 + h->orth_rb - 1) / h->orth_rb;
 }
