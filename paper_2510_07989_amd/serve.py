@@ -77,6 +77,7 @@ class Result:
     step_latency: List[float] = field(default_factory=list)
     outputs: Dict[str, np.ndarray] = field(default_factory=dict)
     error: Optional[str] = None
+    cancel_requested: bool = False      # set by the server (time limit, time box); the backend stops there
 
     @property
     def end_to_end(self) -> float:
@@ -110,6 +111,10 @@ def stop_if_cancelled(s):
 class GpuBackend:
     """Runs a request on the current GPU through the C ABI, on a stream of its own."""
 
+    # execute() stops a request whose Result.cancel_requested is set, also
+    # before its solver exists (waiting for a setup slot, building inputs)
+    honors_cancel_requested = True
+
     def __init__(self, options: Optional[Dict[str, Any]] = None, keep_outputs: bool = True,
                  setup_slots: Optional[int] = None):
         """setup_slots: at most this many requests build their inputs and
@@ -118,17 +123,16 @@ class GpuBackend:
         self.keep_outputs = keep_outputs
         self._setup_gate = threading.Semaphore(setup_slots) if setup_slots else None
         self._live: Dict[int, Any] = {}
-        self._pending_cancel = set()
         self._live_lock = threading.Lock()
 
     def cancel(self, rid: int) -> bool:
-        """Stop request rid's march at its next window boundary (mot_cancel);
-        a request still creating its solver is stopped as soon as it exists."""
+        """Stop request rid's march at its next window boundary (mot_cancel).
+        False if it has no solver here (a request of the per-thread server
+        that is still setting up stops by its result's cancel_requested)."""
         with self._live_lock:
             s = self._live.get(rid)
-            if s is None:
-                self._pending_cancel.add(rid)
-                return True
+        if s is None:
+            return False
         self._stop(s)
         return True
 
@@ -139,17 +143,15 @@ class GpuBackend:
         s._serve_cancelled = True
         s.cancel()
 
-    def _register(self, rid, s):
+    def _register(self, rid, s, res=None):
         with self._live_lock:
             self._live[rid] = s
-            if rid in self._pending_cancel:
-                self._pending_cancel.discard(rid)
-                self._stop(s)
+        if res is not None and res.cancel_requested:      # asked before the solver existed
+            self._stop(s)
 
     def _unregister(self, rid):
         with self._live_lock:
             self._live.pop(rid, None)
-            self._pending_cancel.discard(rid)
 
     def _load(self, s, p):
         if p.get("loader") is not None:
@@ -164,18 +166,13 @@ class GpuBackend:
         torch.cuda.set_device(0)
         stream = torch.cuda.Stream()          # default priority
         with torch.cuda.stream(stream):
-            try:
-                p = self._inputs(req.problem)
-                s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"],
-                               p["G"], p["waves"], options=self._opts(req), stream=stream.cuda_stream)
-            except Exception:
-                self._unregister(req.rid)
-                raise
+            p = self._inputs(req.problem)
+            s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"],
+                           p["G"], p["waves"], options=self._opts(req), stream=stream.cuda_stream)
             try:
                 self._load(s, p)
                 stream.synchronize()
             except Exception:
-                self._unregister(req.rid)
                 s.close()
                 raise
         s._serve_stream = stream
@@ -244,11 +241,8 @@ class GpuBackend:
         import paper_2510_07989_amd as mot
         torch.cuda.set_device(0)
         stream = torch.cuda.Stream()          # default priority
-        try:
-            with torch.cuda.stream(stream):   # output tensors belong to this stream
-                self._march(mot, torch, stream, req, window, clock, res)
-        finally:
-            self._unregister(req.rid)         # also a cancel left pending by a failed setup
+        with torch.cuda.stream(stream):       # output tensors belong to this stream
+            self._march(mot, torch, stream, req, window, clock, res)
 
     def _march(self, mot, torch, stream, req, window, clock, res):
         gate = self._setup_gate
@@ -256,13 +250,12 @@ class GpuBackend:
             gate.acquire()
         s = None
         try:
-            with self._live_lock:
-                if req.rid in self._pending_cancel:       # stopped while it waited for a setup slot
-                    raise CancelledRun("cancelled before its setup")
+            if res.cancel_requested:                  # stopped while it waited for a setup slot
+                raise CancelledRun("cancelled before its setup")
             p = self._inputs(req.problem)
             s = mot.Solver(p["V"], p["F"], p["E"], p["eps_r"], p["mu_r"], p["dt"], p["T0s"], p["T0h"], p["G"],
                            p["waves"], options=self._opts(req), stream=stream.cuda_stream)
-            self._register(req.rid, s)
+            self._register(req.rid, s, res)
             self._load(s, p)
             stream.synchronize()
         except BaseException:
@@ -366,6 +359,7 @@ class Server:
                 for rid in list(active):
                     if rid not in cancelled:
                         cancelled.add(rid)
+                        results[rid].cancel_requested = True
                         getattr(self.backend, "cancel", lambda _rid: False)(rid)
                 if self.log:
                     self.log("[serve %.2fs] time box closed; %d running cancelled" % (now, len(active)))
@@ -385,7 +379,9 @@ class Server:
                 r = results[rid]
                 if r.error is None and rid not in cancelled and clock() - r.t_admit > self.request_timeout:
                     cancelled.add(rid)
-                    stopped = getattr(self.backend, "cancel", lambda _rid: False)(rid)
+                    r.cancel_requested = True
+                    stopped = (getattr(self.backend, "cancel", lambda _rid: False)(rid)
+                               or getattr(self.backend, "honors_cancel_requested", False))
                     if self.log:
                         self.log("[serve %.2fs] request %d exceeded %.0f s%s" % (clock(), rid, self.request_timeout,
                                                                               ", cancelled" if stopped else ""))

@@ -204,7 +204,7 @@ def test_time_box_stops_running_and_waiting_requests():
     assert 0 < len(res[0].step_latency) < 100000
     assert len(res[1].step_latency) == 0 and len(res[2].step_latency) == 0
     assert "before its setup" in res[2].error
-    assert not be._live and not be._pending_cancel
+    assert not be._live and be.cancel(0) is False       # every solve closed; nothing left to stop
     again, _ = Server(be, mem_budget=1 << 40, window=64).run([Request(0, prob, 200, 0.0, opts)])
     assert again[0].error is None
     for k in ("w", "loop", "star"):
