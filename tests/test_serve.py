@@ -277,3 +277,37 @@ def test_thread_server_time_box_cancels_and_drops():
             assert not r.step_latency and r.t_admit == 0
     assert summ["steps_marched"] == sum(len(r.step_latency) for r in res.values())
     assert summ["wall_s"] < 0.3 + 0.5
+
+
+def test_gpu_backend_cancel_bookkeeping_without_a_device():
+    """The GPU backend's cancel path on the host: a request flagged before its
+    solver exists is stopped when the solver registers (mot_cancel and the
+    loader flag), a live solver is stopped by cancel(), an unknown request is
+    left alone, and a loader that checks stop_if_cancelled stops between lags."""
+    from paper_2510_07989_amd.serve import CancelledRun, GpuBackend, Result, stop_if_cancelled
+
+    class FakeSolver:
+        def __init__(self):
+            self.cancels = 0
+
+        def cancel(self):
+            self.cancels += 1
+
+    be = GpuBackend(setup_slots=2)
+    assert be.cancel(7) is False
+    early = Result(1, 10, 0, 0.0)
+    early.cancel_requested = True
+    s1 = FakeSolver()
+    be._register(1, s1, early)
+    assert s1.cancels == 1 and s1._serve_cancelled
+    with pytest.raises(CancelledRun):
+        stop_if_cancelled(s1)
+    s2 = FakeSolver()
+    be._register(2, s2, Result(2, 10, 0, 0.0))
+    stop_if_cancelled(s2)                       # not cancelled: the loader goes on
+    assert s2.cancels == 0 and be.cancel(2) is True and s2.cancels == 1
+    with pytest.raises(CancelledRun):
+        stop_if_cancelled(s2)
+    be._unregister(1)
+    be._unregister(2)
+    assert be.cancel(1) is False and be.cancel(2) is False and not be._live
