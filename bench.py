@@ -450,6 +450,8 @@ def main():
     ap.add_argument("--serving-c4-box", type=float, default=120.0, help="seconds before the stream is cut")
     ap.add_argument("--serving-c4-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-step-batch", action="store_true", help="skip the mot_run_batch comparison")
+    ap.add_argument("--raw-history", action="store_true",
+                    help="also time the history from the raw families (history_form 1) against the folded lags")
     ap.add_argument("--precond", type=int, default=2, help="0 none, 1 FP32, 2 FP64 approximate inverse")
     ap.add_argument("--hilo", type=int, default=2, help="mixed: lags with an FP32 low part (-1: none)")
     ap.add_argument("--mix-group", type=int, default=4, help="precision 2: summation indices per FP32 sum")
@@ -533,6 +535,8 @@ def run_legs(mot, args, result):
         result["torus"] = torus_leg(mot, args)
     if not args.no_step_batch:
         result["step_batch"] = step_batch(mot)
+    if args.raw_history:
+        result["raw_history"] = raw_history_leg(mot, args)
     if not args.no_serving_smoke:
         result["serving_smoke"] = guarded(lambda: serving_smoke(args), args.serving_smoke_box + 150.0, result,
                                           "serving_smoke")
@@ -545,6 +549,62 @@ def run_legs(mot, args, result):
     if args.serving:
         result["serving"] = serving(args.serving_requests)
     print(json.dumps(result), flush=True)
+
+
+def raw_history_bytes(ne, kmax):
+    """Algorithmic bytes of one step's history: folded, the three blocks of
+    every Q_i, i >= 1; raw, the three blocks of each family present at lag i
+    (h to k_max, hat to k_max + 1, tilde to k_max - 1) plus P^Sigma, C1, C2."""
+    blk = 8.0 * ne * ne
+    fam = sum((i <= kmax) + (i <= kmax + 1) + (i <= kmax - 1) for i in range(1, kmax + 2))
+    return 3 * blk * (kmax + 1), 3 * blk * fam + 3 * blk
+
+
+def raw_history_leg(mot, args, K=1000, W_=20):
+    """One wave, FP64: the folded lags (speculative windows, and host-driven
+    steps like the raw form) against the raw media-summed families of each lag
+    with C1, C2 and the projector applied once per step.  Steps/s, the
+    history's time per step and its algorithmic bytes."""
+    import torch
+    from fixture import gpu as fxgpu
+    out = {}
+    for name in ("sphere_1920_r16", "torus_3072"):
+        prob = fxgpu.build_problem_device(name)
+        one = prob["waves"][:1]
+        keys = ("folded", "folded_host_driven", "raw")
+        variants = [dict(precond=args.precond, waves=one), dict(precond=args.precond, waves=one, spec_window=-1),
+                    dict(precond=args.precond, waves=one, history_form=1)]
+        ss, t_create, t_load = make_solvers(mot, prob, variants, W_ + K + 8)
+        ne, kmax = prob["E"].shape[0], prob["kmax"]
+        fb, rb_ = raw_history_bytes(ne, kmax)
+        res = {"unknowns": 2 * ne, "kmax": kmax, "setup_s": round(t_create + t_load, 2)}
+        ws = []
+        for key, s in zip(keys, ss):
+            ws.append(s.run(W_, loop=False, star=False)["w"])
+            a = s.info()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run(K, w=False, loop=False, star=False, device=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            b = s.info()
+            us = 1e3 * (b["hist_ms"] - a["hist_ms"]) / max(1, b["hist_launches"] - a["hist_launches"])
+            nb = rb_ if key == "raw" else fb
+            res[key] = {"steps_s": round(K / el, 1), "history_us": round(us, 2),
+                        "history_bytes": int(nb), "history_gb_s": round(nb / us / 1e3, 1) if us > 0 else None,
+                        "device_gb": round(b["device_bytes"] / 1e9, 3)}
+            s.close()
+        res["raw_vs_folded"] = {"bytes": round(rb_ / fb, 3),
+                                "history_time": round(res["raw"]["history_us"] / res["folded_host_driven"]["history_us"], 3),
+                                "steps": round(res["raw"]["steps_s"] / res["folded"]["steps_s"], 3)}
+        res["warmup_rel_diff_raw_vs_folded"] = rel(ws[2], ws[0])
+        torch.cuda.empty_cache()
+        log("[%s raw history] folded %.1f steps/s (host-driven %.1f), raw %.1f; history %.1f / %.1f us; bytes x%.2f"
+            % (name, res["folded"]["steps_s"], res["folded_host_driven"]["steps_s"], res["raw"]["steps_s"],
+               res["folded_host_driven"]["history_us"], res["raw"]["history_us"], rb_ / fb))
+        out[name] = res
+    out["steps"], out["warmup"] = K, W_
+    return out
 
 
 # a frequency inside the incident pulse's band (sigma = 8 on the torus: up to ~1/(2 pi sigma))

@@ -156,6 +156,20 @@ typedef struct {
                                 history vectors); 0 (default): the autotuner
                                 picks (4 without it).  Results do not depend
                                 on it.                                         */
+    int32_t history_form;    /* history convolution of eq. (MOT) (Sec. V-B):
+                                0 (default) the folded lags
+                                Q_i = C1 (Z^h_i P^{Lambda H} + Z^hat_i P^Sigma)
+                                + C2 (Z^h_i P^Sigma + Z^til_i P^{Lambda H});
+                                1 the raw media-summed families Z^h_i, Z^hat_i,
+                                Z^til_i of lags i >= 1 kept as uploaded and
+                                applied to the projected unknowns
+                                P^{Lambda H} w, P^Sigma w of every step, with
+                                C1 and C2 applied once per step (Q_0 stays
+                                folded).  Form 1: one right-hand side,
+                                host-driven steps (no speculative windows or
+                                graphs); mot_get_matrix(0, i >= 1) fails with
+                                MOT_ESTATE; the same results up to the order
+                                of the sums.  Other values: MOT_EINVAL.        */
 } mot_options;
 
 typedef struct {

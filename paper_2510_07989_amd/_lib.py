@@ -30,7 +30,7 @@ class MotOptions(ctypes.Structure):
                 ("max_steps", _I), ("mem_cap_bytes", ctypes.c_uint64), ("profile", _I),
                 ("precond", _I), ("stream_split", _I), ("history_order", _I),
                 ("hilo_lags", _I), ("mix_group", _I), ("spec_window", _I),
-                ("recovery", _I), ("autotune", _I), ("graph", _I), ("tile_wg", _I)]
+                ("recovery", _I), ("autotune", _I), ("graph", _I), ("tile_wg", _I), ("history_form", _I)]
 
 
 class MotStepInfo(ctypes.Structure):

@@ -13,6 +13,8 @@
 namespace motk_step {
 void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase = nullptr);
 void history(mot_handle* h);
+void raw_history(mot_handle* h);
+void raw_reproject(mot_handle* h);
 void gm_start1(mot_handle* h, const double* b, double* r, int have_t, int first, double* xzero, int publish = 1);
 void gm_orth1(mot_handle* h, double* w, int publish = 1, int fin_kq = 0);
 void gm_finish(mot_handle* h, const double* basis, int force, int spec = 0, int kq = 0);
@@ -361,11 +363,35 @@ bool all_folded(const mot_handle* h) {
     return true;
 }
 
+// After a lag is folded (or kept raw): once every lag is in, the table of the
+// kept raw families goes to the device, then the launch schedule is tuned.
+int raw_ready(mot_handle* h) {
+    if (!all_folded(h)) return MOT_OK;
+    if (h->opt.history_form == 1 && !h->rawtab_ok) {
+        HIPCHK(h, hipMemcpyAsync(h->rawZtab, h->rawZ.data(), h->rawZ.size() * sizeof(double*),
+                                 hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        h->rawtab_ok = 1;
+    }
+    if (!h->tuned) return mot_autotune(h);
+    return MOT_OK;
+}
+
 // Section V-B fold of lag i:  with blocks X in {1 = eta T + eta' T', k = K + K', 2 = T/eta + T'/eta'}
 //   a_X = Zh_X + (Zhat_X - Zh_X) P^Sigma,  b_X = Ztil_X + (Zh_X - Ztil_X) P^Sigma
 //   q_X = C1 a_X + C2 b_X                 (Q_i = [[q_1, -q_k], [q_k, q_2]])
 int fold_lag(mot_handle* h, int lag) {
     double t0 = now_ms();
+    if (h->opt.history_form == 1 && lag > 0) {
+        // kept as staged (media summed, time-scaled); applied by the history
+        for (int f = 0; f < 3; ++f) {
+            h->rawZ[(size_t)lag * 3 + f] = h->stage[(size_t)lag * 3 + f];
+            h->stage[(size_t)lag * 3 + f] = nullptr;
+        }
+        h->lag_done[lag] = 1;
+        h->fold_ms += now_ms() - t0;
+        return raw_ready(h);
+    }
     const int ne = h->ne, hs = h->hs;
     const size_t blk = (size_t)ne * hs;
     hipStream_t s = h->stream;
@@ -412,8 +438,7 @@ int fold_lag(mot_handle* h, int lag) {
         int rc = build_precond(h);
         if (rc) return rc;
     }
-    if (all_folded(h) && !h->tuned) return mot_autotune(h);
-    return MOT_OK;
+    return raw_ready(h);
 }
 
 int stage_add(mot_handle* h, int family, int lag, int medium, int op, const double* dev_block, int64_t ldb) {
@@ -827,7 +852,7 @@ void plan_dims(mot_handle* h, int nv, int nf, int ne, int nrhs, const double* V,
         else if (!sp_set || sp == 1) h->sch_hist = 11;
         else if (sp > 30) h->sch_hist = sp;
         else h->sch_hist = sp > 10 ? std::min(sp, 14) : 20 + sp;
-        h->tune_hist = h->opt.autotune && !sp_set && !ho_set;
+        h->tune_hist = h->opt.autotune && !sp_set && !ho_set && h->opt.history_form != 1;
         h->tune_mv = h->opt.autotune && !sp_set;
     }
     h->eps_r = eps_r; h->mu_r = mu_r; h->dt = dt;
@@ -869,7 +894,16 @@ void footprint(const mot_handle* h, int64_t gnnz, uint64_t* resident, uint64_t* 
     b += 2 * (4.0 * (ne + 1) + 4.0 * gnnz + 8.0 * gnnz);                          // G, G^T (CSR)
     b += 8.0 * (2 * ne * 42 + 9 * R + R);                                         // RHS quadrature, waves
     b += 8.0 * 5 * blk;                                                           // PS, BL, G^-1, C1, C2
-    b += 8.0 * ((double)h->nlags * 3 + 4) * blk;                                  // Q, fold scratch, raw block
+    if (h->opt.history_form == 1) {
+        // Q_0, fold scratch, upload block; the kept families of lags >= 1; the
+        // projected rings, sums and pointer table
+        double fam = 0;
+        for (int i = 1; i < h->nlags; ++i)
+            for (int f = 0; f < 3; ++f) fam += i <= fam_limit(h, f);
+        b += 8.0 * (7 + 3 * fam) * blk + 8.0 * (2.0 * h->nh * h->n2 + 2.0 * h->n2 + 3.0 * h->nlags);
+    } else {
+        b += 8.0 * ((double)h->nlags * 3 + 4) * blk;                              // Q, fold scratch, raw block
+    }
     b += 8.0 + 8.0 * (h->nh * n2r + 4 * hs * NB + 4 * ne * NB + 4 * n2r + 2 * (M + 1) * n2r) + sizeof(GmState);
     if (h->Rp > 1) {
         const double t3 = 3.0 * motk_multi::tile_elems(h);
@@ -995,6 +1029,10 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     if (nv < 4 || nf < 4 || ne < 6 || 2 * ne != 3 * nf)
         return mot_fail(nullptr, MOT_EINVAL, "mesh sizes are not those of a closed triangulation");
     if (nrhs < 1 || nrhs > 64) return mot_fail(nullptr, MOT_EINVAL, "nrhs must be in 1..64");
+    if (opt && (opt->history_form < 0 || opt->history_form > 1))
+        return mot_fail(nullptr, MOT_EINVAL, "history_form must be 0 (folded lags) or 1 (raw families)");
+    if (opt && opt->history_form == 1 && nrhs > 1)
+        return mot_fail(nullptr, MOT_EINVAL, "history_form 1 takes one right-hand side");
     if (nrhs > 1 && opt && opt->precond == 0)
         return mot_fail(nullptr, MOT_EINVAL, "several right-hand sides need the Q_0 preconditioner (precond 1 or 2)");
     if (opt && opt->precision != MOT_FP64 && opt->precision != MOT_MIXED && opt->precision != MOT_MIXED32)
@@ -1187,9 +1225,17 @@ int mot_create(const mot_mesh* mesh, double eps_r, double mu_r, double dt, const
     h->stage.assign((size_t)h->nlags * 3, nullptr);
     h->got.assign(h->nlags, 0);
     h->lag_done.assign(h->nlags, 0);
-    if ((rc = dalloc(h, &h->Q, (size_t)h->nlags * 3 * blk)) || (rc = dalloc(h, &h->tmp, 3 * blk, false)) ||
+    const bool rawh = h->opt.history_form == 1;
+    if ((rc = dalloc(h, &h->Q, (size_t)(rawh ? 1 : h->nlags) * 3 * blk)) || (rc = dalloc(h, &h->tmp, 3 * blk, false)) ||
         (rc = dalloc(h, &h->raw, blk)))
         return bail(rc);
+    if (rawh) {
+        h->rawZ.assign((size_t)h->nlags * 3, nullptr);
+        if ((rc = dalloc(h, &h->rawZtab, (size_t)h->nlags * 3)) ||
+            (rc = dalloc(h, &h->rawL, (size_t)h->nh * h->n2)) || (rc = dalloc(h, &h->rawS, (size_t)h->nh * h->n2)) ||
+            (rc = dalloc(h, &h->ry1, h->n2)) || (rc = dalloc(h, &h->ry2, h->n2)))
+            return bail(rc);
+    }
     // every march vector holds all Rp columns: [n2][Rp]
     const size_t n2 = (size_t)h->n2 * h->Rp;
     const size_t NB = (size_t)h->B * h->Rp;
@@ -1326,7 +1372,9 @@ int mot_step(mot_handle* h, mot_step_info* info) {
     // reduction follows it)
     int prc = ev_begin(h, h->ev_hist);
     if (prc) return prc;
-    if (h->Rp > 1) motk_multi::history_gemm(h); else history(h);
+    if (h->Rp > 1) motk_multi::history_gemm(h);
+    else if (h->opt.history_form == 1) raw_history(h);
+    else history(h);
     if ((prc = ev_end(h, h->ev_hist))) return prc;
     if (h->Rp > 1) motk_multi::history_reduce(h);
     int rc;
@@ -1365,7 +1413,7 @@ int mot_step(mot_handle* h, mot_step_info* info) {
 struct SpecWord { int halt, halt_k, iters_all; double relres; };
 
 static bool spec_ok(const mot_handle* h) {
-    if (h->opt.spec_window < 0 || !(h->M32 || h->M64)) return false;
+    if (h->opt.spec_window < 0 || !(h->M32 || h->M64) || h->opt.history_form == 1) return false;
     return h->Rp > 1 ? (h->gms && h->mr_part) : h->n2 <= 32768;
 }
 
@@ -1899,6 +1947,7 @@ int mot_restore(mot_handle* h, const void* buf, uint64_t size) {
                                  hipMemcpyHostToDevice, s));
     motk_step::set_step(h, hd.k);
     motk_step::clear_halt(h);
+    if (h->opt.history_form == 1) motk_step::raw_reproject(h);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     h->k = hd.k;
@@ -1990,6 +2039,8 @@ int mot_get_matrix(mot_handle* h, int32_t which, int32_t lag, double* out) {
     if (which == 0) {
         if (lag < 0 || lag >= h->nlags) return mot_fail(h, MOT_EINVAL, "lag out of range");
         if (!h->lag_done[lag]) return mot_fail(h, MOT_ESTATE, "lag not folded yet");
+        if (h->opt.history_form == 1 && lag > 0)
+            return mot_fail(h, MOT_ESTATE, "history_form 1 keeps the raw families of lags >= 1, not Q_i");
         const double* q = h->Q + (size_t)lag * 3 * blk;
         const int n = 2 * ne;
         std::vector<double> buf((size_t)ne * ne);

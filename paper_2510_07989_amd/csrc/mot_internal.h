@@ -156,6 +156,14 @@ struct mot_handle {
     std::vector<double*> stage;      // index lag*3 + family
     std::vector<uint32_t> got;       // arrival bits per lag: family*4 + medium*2 + op
     std::vector<char> lag_done;
+    // history_form 1: the staged families of lags >= 1 kept (rawZ[lag*3 + f],
+    // a device copy of the table in rawZtab), the projected unknowns in rings,
+    // and the two family sums
+    std::vector<double*> rawZ;
+    double** rawZtab = nullptr;
+    double *rawL = nullptr, *rawS = nullptr;   // [nh][n2]: P^{Lambda H} w, P^Sigma w
+    double *ry1 = nullptr, *ry2 = nullptr;     // [n2]
+    int rawtab_ok = 0;
     double* tmp = nullptr;           // [3][ne][hs] fold temporaries
     double* raw = nullptr;           // [ne][hs] upload buffer
 

@@ -56,6 +56,10 @@ def test_footprint_without_gpu():
     assert r16f <= r16
     r1f, _ = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=100, autotune=0))
     assert r1f == r1                            # one RHS: schedules need no memory
+    # the raw families of every lag >= 1 (up to three blocks each where the
+    # folded form keeps one) outweigh the folded lags they replace
+    rraw, kraw = p.footprint(*args, 1, prob["G"], p.default_options(max_steps=100, history_form=1))
+    assert r1 < rraw < kraw
 
 
 def test_one_hip_runtime_in_the_process():
@@ -114,7 +118,7 @@ def test_header_is_c99_and_links_from_c(tmp_path):
         "    mot_options o;\n"
         "    uint64_t n = 0;\n"
         "    mot_default_options(&o);\n"
-        "    if (o.gmres_restart != 40 || o.autotune != 1) return 1;\n"
+        "    if (o.gmres_restart != 40 || o.autotune != 1 || o.history_form != 0) return 1;\n"
         "    if (mot_checkpoint_size(NULL, 1, &n) != MOT_EINVAL) return 2;\n"
         "    if (mot_run_batch(NULL, 1, 1, NULL) != MOT_EINVAL) return 3;\n"
         "    return 0;\n"
@@ -157,14 +161,16 @@ def test_create_rejects_bad_inputs_without_gpu():
                 setattr(w, k, v)
         return w
 
-    def create(V=V, F=F, E=E, rp=rp, col=col, val=val, w=None, dt=0.5):
+    def create(V=V, F=F, E=E, rp=rp, col=col, val=val, w=None, dt=0.5, nrhs=1, **opts):
         m = _lib.MotMesh(V.shape[0], F.shape[0], E.shape[0], _ptr(V), _ptr(F), _ptr(E))
         h = ctypes.c_void_p()
-        ws = (_lib.MotPlaneWave * 1)(w or wave())
+        ws = (_lib.MotPlaneWave * nrhs)(*[w or wave() for _ in range(nrhs)])
         o = _lib.MotOptions()
         lib.mot_default_options(ctypes.byref(o))
-        return lib.mot_create(ctypes.byref(m), 2.0, 1.0, dt, _ptr(T0), _ptr(T1), _ptr(rp), _ptr(col), _ptr(val), 1,
-                              ws, ctypes.byref(o), None, ctypes.byref(h))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        return lib.mot_create(ctypes.byref(m), 2.0, 1.0, dt, _ptr(T0), _ptr(T1), _ptr(rp), _ptr(col), _ptr(val),
+                              nrhs, ws, ctypes.byref(o), None, ctypes.byref(h))
 
     bad_v = V.copy(); bad_v[3, 1] = np.nan
     bad_f = F.copy(); bad_f[2, 0] = -1
@@ -179,6 +185,7 @@ def test_create_rejects_bad_inputs_without_gpu():
         "width": dict(w=wave(width=-1.0)), "pol": dict(w=wave(pol=(1.0, 0.1, 0.0))),
         "dir": dict(w=wave(dir=(0.0, 0.0, -2.0))), "pol.dir": dict(w=wave(pol=(0.0, 0.0, 1.0))),
         "dt": dict(dt=float("inf")),
+        "history_form": dict(history_form=2), "raw history, two waves": dict(history_form=1, nrhs=2),
     }
     for what, kw in cases.items():
         assert create(**kw) == _lib.MOT_EINVAL, what

@@ -23,6 +23,7 @@ def _solver(name, **opts):
     ("sphere_480", dict(precond=1), 137, 140),            # FP32 inverse: halts, grown Arnoldi count
     ("tiny_torus", dict(precond=2, spec_window=-1), 61, 50),
     ("sphere_480_r16", dict(precond=2, precision=1), 90, 60),
+    ("sphere_480", dict(precond=2, history_form=1), 150, 130),   # projected rings rebuilt at the restore
 ])
 def test_resume_is_bit_identical(name, opts, n1, n2):
     import paper_2510_07989_amd as p

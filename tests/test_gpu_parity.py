@@ -198,6 +198,36 @@ def test_kernel_variants(opts):
     s.close()
 
 
+@pytest.mark.parametrize("name,nsteps,opts", [("tiny", 40, {}), ("sphere_480", 200, dict(precond=2)),
+                                               ("sphere_480", 100, dict(precond=0)),
+                                               ("tiny_pyramid", 60, dict(precond=2))])
+def test_raw_family_history_parity(name, nsteps, opts):
+    """history_form 1 (Sec. V-B without the fold: the media-summed raw families
+    of every lag >= 1 applied to the projected unknowns P^{Lambda H} w and
+    P^Sigma w, C1 and C2 once per step) marches the oracle's solution, and the
+    folded form's up to the order of the sums; Q_0 is folded as before and the
+    folded Q_i of later lags do not exist."""
+    import paper_2510_07989_amd as p
+    print("case raw history", name, nsteps, opts, flush=True)
+    O = oracle(name)
+    ref = O.run(nsteps)
+    f = _solver(name, **opts)
+    fo = f.run(nsteps)
+    q0 = f.matrix(0, 0)
+    f.close()
+    s = _solver(name, history_form=1, **opts)
+    assert np.array_equal(s.matrix(0, 0), q0)
+    with pytest.raises(p.MotError):
+        s.matrix(0, 1)
+    out = s.run(nsteps)
+    assert out["rc"] == 0
+    for k, r in (("w", "W"), ("loop", "loop"), ("star", "star")):
+        e, ef = _rel(out[k], ref[r]), _rel(out[k], fo[k])
+        print("%s: against the oracle %.3e, against the folded lags %.3e" % (k, e, ef), flush=True)
+        assert e < 1e-10 and ef < 1e-10, k
+    s.close()
+
+
 @pytest.mark.parametrize("name,nsteps", [("tiny_box", 40), ("sphere_480_r16", 100)])
 def test_multi_rhs_parity(name, nsteps):
     """R plane waves marched together (tall-skinny GEMM history and Q_0 products,

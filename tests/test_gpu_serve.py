@@ -13,7 +13,8 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("name,opts", [("sphere_480", {}), ("sphere_480", dict(precond=2)),
                                        ("sphere_480_r16", dict(precond=2)),
-                                       ("sphere_480_r16", dict(precond=2, precision=1))])
+                                       ("sphere_480_r16", dict(precond=2, precision=1)),
+                                       ("sphere_480", dict(precond=2, history_form=1))])
 def test_footprint_matches_allocations(name, opts):
     """mot_footprint before create equals the bytes the handle holds after
     setup and the fold, and bounds the high-water mark through a run."""
