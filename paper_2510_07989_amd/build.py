@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmot.so")
-SOURCES = ["linalg.hip", "step.hip", "multi.hip", "tune.hip", "farfield.hip", "mot_api.hip"]
+SOURCES = ["linalg.hip", "step.hip", "raw.hip", "multi.hip", "tune.hip", "farfield.hip", "mot_api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -294,116 +294,6 @@ __global__ __launch_bounds__(256) void k_history_co(int ne, int hs, const int* _
     }
 }
 
-// ------------------------------------------------- raw-family history ---
-// History convolution from the raw families (history_form 1; Sec. V-B): per
-// row m,
-//   y1 = sum_j (Z^h_j XL_{k-j} + Z^hat_j XS_{k-j}),
-//   y2 = sum_j (Z^h_j XS_{k-j} + Z^til_j XL_{k-j}),
-// each Z = [[M1, -Ks], [Ks, M2]] on the (u; v) halves (blocks [3][ne][hs] as
-// staged: media summed, time-scaled), XL = P^{Lambda H} w and XS = P^Sigma w
-// in rings of nh slots [2 hs].  Z[3 j + f] null: family f absent at lag j.
-// One wavefront per row, four rows per workgroup.
-__global__ __launch_bounds__(256) void k_raw_lags(int ne, int hs, int k, int nh, double* const* __restrict__ Z,
-                                                  const double* __restrict__ RL, const double* __restrict__ RS,
-                                                  double* __restrict__ y1, double* __restrict__ y2) {
-    const int lane = threadIdx.x & 63, m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= ne) return;                         // the whole wavefront: m is the same in all lanes
-    const size_t blk = (size_t)ne * hs, row = (size_t)m * hs;
-    const int n2 = 2 * hs;
-    const int nact = k - 1 < nh ? k - 1 : nh;
-    double p1u = 0, p1v = 0, p2u = 0, p2v = 0;   // y1 (u, v), y2 (u, v)
-    for (int j = 1; j <= nact; ++j) {
-        const double* L = RL + (size_t)((k - j) % nh) * n2;
-        const double* S = RS + (size_t)((k - j) % nh) * n2;
-        const double* zh = Z[3 * j];
-        const double* zt = Z[3 * j + 1];
-        const double* zl = Z[3 * j + 2];
-        for (int n = lane; n < ne; n += 64) {
-            const double lu = L[n], lv = L[hs + n], su = S[n], sv = S[hs + n];
-            if (zh) {                            // h: XL into y1, XS into y2
-                const double a = zh[row + n], kk = zh[blk + row + n], q = zh[2 * blk + row + n];
-                p1u = fma(a, lu, p1u); p1u = fma(-kk, lv, p1u);
-                p1v = fma(kk, lu, p1v); p1v = fma(q, lv, p1v);
-                p2u = fma(a, su, p2u); p2u = fma(-kk, sv, p2u);
-                p2v = fma(kk, su, p2v); p2v = fma(q, sv, p2v);
-            }
-            if (zt) {                            // hat: XS into y1
-                const double a = zt[row + n], kk = zt[blk + row + n], q = zt[2 * blk + row + n];
-                p1u = fma(a, su, p1u); p1u = fma(-kk, sv, p1u);
-                p1v = fma(kk, su, p1v); p1v = fma(q, sv, p1v);
-            }
-            if (zl) {                            // tilde: XL into y2
-                const double a = zl[row + n], kk = zl[blk + row + n], q = zl[2 * blk + row + n];
-                p2u = fma(a, lu, p2u); p2u = fma(-kk, lv, p2u);
-                p2v = fma(kk, lu, p2v); p2v = fma(q, lv, p2v);
-            }
-        }
-    }
-    p1u = wave_sum(p1u);
-    p1v = wave_sum(p1v);
-    p2u = wave_sum(p2u);
-    p2v = wave_sum(p2v);
-    if (lane == 0) {
-        y1[m] = p1u;
-        y1[hs + m] = p1v;
-        y2[m] = p2u;
-        y2[hs + m] = p2v;
-    }
-}
-
-// One wavefront per row m of the [ne][hs] blocks: P^Sigma applied to both
-// halves of w, giving XS = P^Sigma w and XL = w - XS (the padding rows are
-// never read).
-__global__ __launch_bounds__(256) void k_raw_project(int ne, int hs, const double* __restrict__ PS,
-                                                     const double* __restrict__ w, double* __restrict__ xs,
-                                                     double* __restrict__ xl) {
-    const int lane = threadIdx.x & 63, m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= ne) return;
-    const double* a = PS + (size_t)m * hs;
-    double su = 0, sv = 0;
-    for (int n = lane; n < ne; n += 64) {
-        const double p = a[n];
-        su = fma(p, w[n], su);
-        sv = fma(p, w[hs + n], sv);
-    }
-    su = wave_sum(su);
-    sv = wave_sum(sv);
-    if (lane == 0) {
-        xs[m] = su;
-        xs[hs + m] = sv;
-        xl[m] = w[m] - su;
-        xl[hs + m] = w[hs + m] - sv;
-    }
-}
-
-// y = r_k - (C1b y1 + C2b y2) for step k, one wavefront per row; r_k from the
-// double-buffered RHS batch [half][ne][B] (column (k-1) mod B)
-__global__ __launch_bounds__(256) void k_raw_combine(int ne, int hs, int k, int B, const double* __restrict__ rb,
-                                                     const double* __restrict__ C1, const double* __restrict__ C2,
-                                                     const double* __restrict__ y1, const double* __restrict__ y2,
-                                                     double* __restrict__ y) {
-    const int lane = threadIdx.x & 63, m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= ne) return;
-    const double* a = C1 + (size_t)m * hs;
-    const double* c = C2 + (size_t)m * hs;
-    double bu = 0, bv = 0;
-    for (int n = lane; n < ne; n += 64) {
-        const double p = a[n], q = c[n];
-        bu = fma(p, y1[n], bu);
-        bu = fma(q, y2[n], bu);
-        bv = fma(p, y1[hs + n], bv);
-        bv = fma(q, y2[hs + n], bv);
-    }
-    bu = wave_sum(bu);
-    bv = wave_sum(bv);
-    if (lane == 0) {
-        const int sc = (k - 1) % B;
-        const double* rr = rb + (size_t)(((k - 1) / B) & 1) * 2 * ne * B;
-        y[m] = rr[(size_t)m * B + sc] - bu;
-        y[hs + m] = rr[(size_t)ne * B + (size_t)m * B + sc] - bv;
-    }
-}
-
 // ------------------------------------------------------------------ GMRES ---
 // Arnoldi with classical Gram-Schmidt and one re-orthogonalisation, Givens
 // rotations and the triangular solve on the device.  Reductions use per-block
@@ -1491,31 +1381,6 @@ void rhs_batch(mot_handle* h, int k0, double* rb, const int* kbase) {
     motk::gemm(h->stream, ne, N, ne, 1.0, h->C1, hs, h->ebar, N, 0.0, rbk, N, 2, (size_t)hs * N, (size_t)ne * N);
     motk::gemm(h->stream, ne, N, ne, 1.0 / h->Tmax, h->C2, hs, h->Ebar, N, 1.0, rbk, N, 2, (size_t)hs * N,
                (size_t)ne * N);
-}
-
-// history_form 1, step h->k: project w_{k-1} into the rings, the raw-family
-// sums y1, y2, then y = r_k - (C1b y1 + C2b y2)
-void raw_history(mot_handle* h) {
-    const int k = h->k, nh = h->nh, ne = h->ne, hs = h->hs, n2 = h->n2;
-    hipStream_t s = h->stream;
-    const dim3 grid((ne + 3) / 4);
-    if (k >= 2) {
-        const size_t off = (size_t)((k - 1) % nh) * n2;
-        hipLaunchKernelGGL(k_raw_project, grid, dim3(256), 0, s, ne, hs, h->PS, h->ring + off, h->rawS + off,
-                           h->rawL + off);
-    }
-    hipLaunchKernelGGL(k_raw_lags, grid, dim3(256), 0, s, ne, hs, k, nh, h->rawZtab, h->rawL, h->rawS, h->ry1,
-                       h->ry2);
-    hipLaunchKernelGGL(k_raw_combine, grid, dim3(256), 0, s, ne, hs, k, h->B, h->rb, h->C1, h->C2, h->ry1, h->ry2,
-                       h->y);
-}
-
-// history_form 1 after a restore: the projections of every ring slot
-void raw_reproject(mot_handle* h) {
-    const size_t n2 = h->n2;
-    for (int j = 0; j < h->nh; ++j)
-        hipLaunchKernelGGL(k_raw_project, dim3((h->ne + 3) / 4), dim3(256), 0, h->stream, h->ne, h->hs, h->PS,
-                           h->ring + j * n2, h->rawS + j * n2, h->rawL + j * n2);
 }
 
 void history(mot_handle* h) {
