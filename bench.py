@@ -563,12 +563,14 @@ def raw_history_bytes(ne, kmax):
 def raw_history_leg(mot, args, K=1000, W_=20):
     """One wave, FP64: the folded lags (speculative windows, and host-driven
     steps like the raw form) against the raw media-summed families of each lag
-    with C1, C2 and the projector applied once per step.  Steps/s, the
-    history's time per step and its algorithmic bytes."""
+    with C1, C2 and the projector applied once per step, on the 3840-unknown
+    sphere, the torus and the star pyramid at c dt / D = 0.1 (5184 unknowns,
+    k_max 23).  Steps/s, the history's time per step and its algorithmic
+    bytes."""
     import torch
     from fixture import gpu as fxgpu
     out = {}
-    for name in ("sphere_1920_r16", "torus_3072"):
+    for name in ("sphere_1920_r16", "torus_3072", "pyramid_2592_fine"):
         prob = fxgpu.build_problem_device(name)
         one = prob["waves"][:1]
         keys = ("folded", "folded_host_driven", "raw")

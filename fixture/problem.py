@@ -57,6 +57,9 @@ CONFIGS = {
     # star-based pyramid (24 base vertices on radii 1 and 0.3, height 0.5), eps_r = 5, c dt = 2 m
     "tiny_pyramid": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 1), eps_r=5.0, mu_r=1.0, dt=2.0, nsteps=60, nrhs=1, sigma=2.0, nq=12),
     "pyramid_648": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 3), eps_r=5.0, mu_r=1.0, dt=2.0, nsteps=300, nrhs=1, sigma=4.0, nq=12),
+    # the same pyramid with c dt / D about 1/8 (k_max 18): thin retarded shells, many lags
+    "pyramid_648_fine": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 3), eps_r=5.0, mu_r=1.0, dt=0.25, nsteps=150, nrhs=1, sigma=4.0, nq=12),
+    "pyramid_2592_fine": dict(mesh=("star_pyramid", 12, 1.0, 0.3, 0.5, 6), eps_r=5.0, mu_r=1.0, dt=0.2, nsteps=1000, nrhs=1, sigma=4.0, nq=12),
     # free-space interior: the exact solution is the projected incident trace
     "sphere_vacuum": dict(mesh=("icosphere", 3), eps_r=1.0, mu_r=1.0, dt=0.2, nsteps=80, nrhs=1, sigma=0.6, nq=7),
 }

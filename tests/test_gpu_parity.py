@@ -200,7 +200,8 @@ def test_kernel_variants(opts):
 
 @pytest.mark.parametrize("name,nsteps,opts", [("tiny", 40, {}), ("sphere_480", 200, dict(precond=2)),
                                                ("sphere_480", 100, dict(precond=0)),
-                                               ("tiny_pyramid", 60, dict(precond=2))])
+                                               ("tiny_pyramid", 60, dict(precond=2)),
+                                               ("pyramid_648_fine", 150, dict(precond=2))])
 def test_raw_family_history_parity(name, nsteps, opts):
     """history_form 1 (Sec. V-B without the fold: the media-summed raw families
     of every lag >= 1 applied to the projected unknowns P^{Lambda H} w and
