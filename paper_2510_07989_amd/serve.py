@@ -445,11 +445,16 @@ class BatchServer:
     its cancel()).  window: steps per batch call; a solve joins or leaves the
     batch between calls.  time_box: seconds after start when every solve still
     running is cancelled and requests not yet admitted are dropped (reported
-    as not served)."""
+    as not served).  setup_timeout: seconds a setup may run (default: the
+    request time limit); a setup past it is reported as stalled and the
+    server stops waiting for it.  Its memory stays counted until it returns
+    (its solver is then closed); requests that only a stalled setup keeps out
+    of the budget are not served, so the server ends instead of waiting
+    silently on a setup that never returns."""
 
     def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 128, setup_workers: int = 2,
                  poll: float = 0.002, request_timeout: float = 600.0, time_box: Optional[float] = None,
-                 log: Optional[Callable[[str], None]] = None):
+                 log: Optional[Callable[[str], None]] = None, setup_timeout: Optional[float] = None):
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_active = int(max_active)
@@ -459,7 +464,14 @@ class BatchServer:
         self.request_timeout = float(request_timeout)
         self.time_box = time_box
         self.log = log
+        self.setup_timeout = float(request_timeout if setup_timeout is None else setup_timeout)
         self.trace: List[tuple] = []          # (time, event, rid, active, used bytes)
+
+    def _close_late(self, req, f):
+        try:
+            self.backend.close(req, f.result())
+        except Exception:
+            pass
 
     def run(self, requests: List[Request]):
         """Serve every request; returns (results by rid, summary dict)."""
@@ -485,6 +497,8 @@ class BatchServer:
         queue: List[Request] = []
         setting_up: Dict[int, Any] = {}        # rid -> future
         running: Dict[int, Any] = {}           # rid -> solver
+        stalled: Dict[int, Any] = {}           # rid -> future of a setup past its limit
+        nstalled = 0
         done_steps: Dict[int, int] = {}
         used = 0
         closed = threading.Event()             # the time box has closed
@@ -556,6 +570,33 @@ class BatchServer:
                     self.trace.append((clock(), "admit", req.rid, len(running) + len(setting_up), used))
                     say("request %d admitted (%d steps, %d waves, %.1f MB)" % (
                         req.rid, req.nsteps, len(req.problem["waves"]), fp[req.rid] / 1e6))
+                for rid in [q for q, f in stalled.items() if f.done()]:
+                    # a stalled setup that came back: close its solver, free its bytes
+                    f = stalled.pop(rid)
+                    try:
+                        self.backend.close(byid[rid], f.result())
+                    except Exception:
+                        pass
+                    used -= fp[rid]
+                    say("stalled setup of request %d returned after %.1f s; closed" % (
+                        rid, clock() - results[rid].t_admit))
+                for rid in [q for q, f in setting_up.items()
+                            if not f.done() and clock() - results[q].t_admit > self.setup_timeout]:
+                    stalled[rid] = setting_up.pop(rid)
+                    nstalled += 1
+                    r = results[rid]
+                    r.error = "SetupStalled: setup still running after %.1f s" % (clock() - r.t_admit)
+                    r.t_done = clock()
+                    self.trace.append((clock(), "stalled", rid, len(running) + len(setting_up), used))
+                    say("request %d: %s" % (rid, r.error))
+                if stalled and queue and not running and not setting_up and \
+                        used + fp[queue[0].rid] > self.mem_budget:
+                    # only stalled setups hold the budget the head needs
+                    for req in queue:
+                        results[req.rid].error = "NotServed: the budget is held by a stalled setup"
+                    say("%d queued requests not served: the budget is held by %d stalled setups" % (
+                        len(queue), len(stalled)))
+                    queue = []
                 for rid in [q for q, f in setting_up.items() if f.done()]:
                     f = setting_up.pop(rid)
                     try:
@@ -605,7 +646,11 @@ class BatchServer:
         finally:
             stop_watch.set()
             wd.join()
-            pool.shutdown(wait=True)
+            # a setup that never returns must not hold the caller here; one
+            # that returns later closes its own solver
+            for rid, f in stalled.items():
+                f.add_done_callback(lambda f, req=byid[rid]: self._close_late(req, f))
+            pool.shutdown(wait=not stalled)
         wall = clock()
         nrhs = {q.rid: len(q.problem["waves"]) for q in reqs}
         ok = [r for r in results.values() if r.error is None]
@@ -618,6 +663,7 @@ class BatchServer:
             "not_served": sum(1 for r in results.values() if r.error and r.error.startswith("NotServed")),
             "errors": sum(1 for r in results.values() if r.error and not r.error.startswith(("CancelledRun",
                                                                                              "NotServed"))),
+            "stalled_setups": nstalled,
             "wall_s": wall,
             "steps": steps,
             "steps_marched": sum(len(r.step_latency) for r in results.values()),

@@ -311,3 +311,39 @@ def test_gpu_backend_cancel_bookkeeping_without_a_device():
     be._unregister(1)
     be._unregister(2)
     assert be.cancel(1) is False and be.cancel(2) is False and not be._live
+
+
+def test_batch_server_reports_a_stalled_setup_and_ends():
+    """A setup that does not return within the setup time limit is reported
+    as stalled; the server stops waiting for it, serves the others, reports
+    the requests that only the stalled setup's memory keeps out as not
+    served, and ends. The setup, once it returns, closes its solver."""
+    from paper_2510_07989_amd.serve import BatchServer
+    release = threading.Event()
+
+    class StallingBackend(SleepBatchBackend):
+        def setup(self, req):
+            if req.rid == 1:
+                release.wait(30.0)
+            return super().setup(req)
+
+    be = StallingBackend(step_s=0.001)
+    reqs = [_req(0, 300, 64, 0.0), _req(1, 500, 64, 0.0), _req(2, 300, 64, 0.01), _req(3, 800, 64, 0.02)]
+    lines = []
+    srv = BatchServer(be, mem_budget=1000, max_active=4, window=16, setup_timeout=0.3, log=lines.append)
+    t0 = time.perf_counter()
+    res, summ = srv.run(reqs)
+    assert time.perf_counter() - t0 < 5.0
+    assert summ["stalled_setups"] == 1
+    assert res[1].error.startswith("SetupStalled")
+    assert res[0].error is None and res[2].error is None
+    assert res[3].error.startswith("NotServed")   # 800 B fit only once the stalled 500 B are back
+    assert summ["completed"] == 2
+    assert any("stalled" in l for l in lines)
+    release.set()
+    for _ in range(200):
+        with be.lock:
+            if not be.live:
+                break
+        time.sleep(0.01)
+    assert not be.live                              # the late setup's solver was closed
