@@ -298,11 +298,15 @@ class Server:
 
     def __init__(self, backend, mem_budget: int, max_active: int = 8, window: int = 64, poll: float = 0.001,
                  request_timeout: float = 600.0, time_box: Optional[float] = None,
-                 log: Optional[Callable[[str], None]] = None):
+                 log: Optional[Callable[[str], None]] = None, cancel_grace: float = 60.0):
         """time_box: seconds after start when every request still running is
         cancelled (at its next window boundary; it is then reported as
         cancelled with the steps it completed) and requests not yet admitted
-        are not served."""
+        are not served.  cancel_grace: seconds a cancelled request's thread
+        may take to end; past it the request is reported as stalled and no
+        longer waited on (its memory stays counted, and requests that only
+        stalled ones keep out of the budget are not served), so the server
+        ends instead of waiting silently on a thread that never returns."""
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_active = int(max_active)
@@ -311,6 +315,7 @@ class Server:
         self.time_box = time_box
         self.request_timeout = float(request_timeout)
         self.log = log
+        self.cancel_grace = float(cancel_grace)
         self.trace: List[tuple] = []          # (time, event, rid, active, used bytes)
 
     def run(self, requests: List[Request]):
@@ -333,16 +338,21 @@ class Server:
         used = 0
         lock = threading.Lock()
         finished: List[int] = []
-        cancelled = set()
+        cancelled: Dict[int, float] = {}       # rid -> time of its cancel
+        stalled = set()
 
         def worker(req: Request):
             res = results[req.rid]
+            err = None
             try:
                 self.backend.execute(req, self.window, clock, res)
             except Exception as e:          # reported per request
-                res.error = "%s: %s" % (type(e).__name__, e)
-            res.t_done = clock()
+                err = "%s: %s" % (type(e).__name__, e)
             with lock:
+                if req.rid not in stalled:  # a stalled request keeps its report
+                    if err is not None:
+                        res.error = err
+                    res.t_done = clock()
                 finished.append(req.rid)
 
         boxed = False
@@ -358,7 +368,7 @@ class Server:
                 pending, queue = [], []
                 for rid in list(active):
                     if rid not in cancelled:
-                        cancelled.add(rid)
+                        cancelled[rid] = now
                         results[rid].cancel_requested = True
                         getattr(self.backend, "cancel", lambda _rid: False)(rid)
                 if self.log:
@@ -378,7 +388,7 @@ class Server:
             for rid in list(active):
                 r = results[rid]
                 if r.error is None and rid not in cancelled and clock() - r.t_admit > self.request_timeout:
-                    cancelled.add(rid)
+                    cancelled[rid] = clock()
                     r.cancel_requested = True
                     stopped = (getattr(self.backend, "cancel", lambda _rid: False)(rid)
                                or getattr(self.backend, "honors_cancel_requested", False))
@@ -387,6 +397,29 @@ class Server:
                                                                               ", cancelled" if stopped else ""))
                     if not stopped:
                         r.error = "TimeoutError: still running after %.0f s" % self.request_timeout
+            # a cancelled request whose thread does not end is reported, not waited on
+            for rid in list(active):
+                r = results[rid]
+                with lock:
+                    late = (rid in cancelled and rid not in stalled and rid not in finished
+                            and clock() - cancelled[rid] > self.cancel_grace)
+                    if late:
+                        stalled.add(rid)
+                        r.error = "Stalled: still running %.1f s after its cancel" % (clock() - cancelled[rid])
+                        r.t_done = clock()
+                if late:
+                    self.trace.append((clock(), "stalled", rid, len(active), used))
+                    if self.log:
+                        self.log("[serve %.2fs] request %d: %s" % (clock(), rid, r.error))
+            if stalled and queue and all(rid in stalled for rid in active) and \
+                    used + fp[queue[0].rid] > self.mem_budget:
+                # only stalled requests hold the budget the head needs
+                for req in queue:
+                    results[req.rid].error = "NotServed: the budget is held by a stalled request"
+                if self.log:
+                    self.log("[serve %.2fs] %d queued requests not served: the budget is held by %d stalled"
+                             % (clock(), len(queue), len(stalled)))
+                queue = []
             if active and all(results[rid].error for rid in active) and not queue and not pending:
                 break
             # strict arrival order: the head waits until it fits
@@ -421,6 +454,7 @@ class Server:
             "cancelled": sum(1 for r in results.values() if r.error and r.error.startswith("CancelledRun")),
             "not_served": sum(1 for r in results.values() if r.error and r.error.startswith("NotServed")),
             "errors": sum(1 for r in results.values() if r.error and not r.error.startswith(stopped)),
+            "stalled": len(stalled),
             "wall_s": wall,
             "steps": steps,
             "steps_marched": marched,

@@ -279,6 +279,38 @@ def test_thread_server_time_box_cancels_and_drops():
     assert summ["wall_s"] < 0.3 + 0.5
 
 
+def test_thread_server_reports_a_request_that_ignores_its_cancel():
+    """A cancelled request whose thread does not end within the grace period
+    is reported as stalled and no longer waited on; the request that only its
+    memory keeps out is not served, the others complete, and the server ends.
+    The thread's later end does not overwrite the report."""
+    release = threading.Event()
+
+    class StuckBackend(CancellableSleepBackend):
+        def execute(self, req, window, clock, res):
+            if req.rid == 0:
+                res.t_ready = clock()
+                release.wait(30.0)             # never looks at its cancel flag
+                raise RuntimeError("ended late")
+            return super().execute(req, window, clock, res)
+
+    be = StuckBackend(step_s=0.001)
+    reqs = [_req(0, 600, 100000, 0.0), _req(1, 300, 40, 0.01), _req(2, 700, 40, 0.02)]
+    lines = []
+    srv = Server(be, mem_budget=1000, max_active=3, window=16, request_timeout=0.2, cancel_grace=0.2,
+                 log=lines.append)
+    t0 = time.perf_counter()
+    res, summ = srv.run(reqs)
+    assert time.perf_counter() - t0 < 5.0
+    assert res[0].error.startswith("Stalled") and summ["stalled"] == 1
+    assert res[1].error is None
+    assert res[2].error.startswith("NotServed")     # 700 B fit only once the stalled 600 B are back
+    assert any("Stalled" in l for l in lines)
+    release.set()
+    time.sleep(0.1)
+    assert res[0].error.startswith("Stalled")
+
+
 def test_gpu_backend_cancel_bookkeeping_without_a_device():
     """The GPU backend's cancel path on the host: a request flagged before its
     solver exists is stopped when the solver registers (mot_cancel and the
