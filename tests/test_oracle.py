@@ -587,3 +587,64 @@ def test_lag0_tilde_k_is_the_static_double_layer_when_kmax_is_1(name):
     print(name, "cond with the block dropped", conds, "kept", full)
     assert max(conds) / min(conds) < 1.05
     assert full[1] > 2 * full[0]
+
+
+def _moved_problem(name, nsteps, move, wave_map=None):
+    """The inputs of configuration name with every vertex moved by move(V) and
+    the incident waves mapped by wave_map (the same mesh connectivity)."""
+    import fixture.problem as fp
+    orig = fp.make_mesh
+
+    def moved_mesh(spec):
+        V, F, E = orig(spec)
+        return move(V), F, E
+    fp.make_mesh = moved_mesh
+    try:
+        prob = fp.build_problem(name, nsteps=nsteps)
+    finally:
+        fp.make_mesh = orig
+    if wave_map is not None:
+        prob["waves"] = [wave_map(w) for w in prob["waves"]]
+    return prob
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_march_invariant_under_rotation_and_translation():
+    """Sec. II and Sec. V-C: the operators depend on the geometry only through
+    distances and through vectors that turn with the surface, and the incident
+    field of eq. (hin) only through t - k.r / c. So turning the torus and the
+    wave together, or moving the torus normal to k, leaves every RWG
+    coefficient of w, and the loop and star parts of eq. (dis_jm), unchanged
+    (rounding only). Moving it by m c dt along k delays the whole march by m
+    steps, up to the Gaussian's tail before t = 0 (about 1e-8 here). A mesh
+    turned without its wave must fail the first check."""
+    from fixture.problem import Wave
+    n, m = 40, 4
+    ref = oracle("tiny_torus").run(n)
+    rng = np.random.Generator(np.random.PCG64(7))
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1                              # a rotation, not a reflection
+    rot = mo.Oracle(_moved_problem("tiny_torus", n, lambda V: V @ Q.T,
+                                   lambda w: Wave(w.amp, Q @ w.pol, Q @ w.dir, w.width, w.t0))).run(n)
+    for k in ("W", "loop", "star"):
+        assert _rel(rot[k], ref[k]) < 1e-10, k
+    wrong = mo.Oracle(_moved_problem("tiny_torus", n, lambda V: V @ Q.T)).run(n)
+    assert _rel(wrong["W"], ref["W"]) > 0.1
+    prob = problem("tiny_torus")
+    kdir = prob["waves"][0].dir
+    from fixture.problem import medium
+    c = medium(prob["eps_r"], prob["mu_r"])[0]     # exterior wave speed
+    d = np.cross(kdir, [0.3, -0.8, 0.5])           # normal to k
+    side = mo.Oracle(_moved_problem("tiny_torus", n, lambda V: V + d)).run(n)
+    for k in ("W", "loop", "star"):
+        assert _rel(side[k], ref[k]) < 1e-10, k
+    ahead = mo.Oracle(_moved_problem("tiny_torus", n, lambda V: V + m * c * prob["dt"] * kdir)).run(n)
+    for k in ("W", "loop", "star"):
+        a, b = ahead[k], ref[k]
+        assert _rel(a[m:], b[:-m]) < 1e-6, k
+        assert np.abs(a[:m]).max() < 1e-6 * np.abs(b).max(), k
+        assert _rel(a[m + 1:], b[:-(m + 1)]) > 1e-2, k   # one step off is not the delay
