@@ -589,9 +589,10 @@ def test_lag0_tilde_k_is_the_static_double_layer_when_kmax_is_1(name):
     assert full[1] > 2 * full[0]
 
 
-def _moved_problem(name, nsteps, move, wave_map=None):
-    """The inputs of configuration name with every vertex moved by move(V) and
-    the incident waves mapped by wave_map (the same mesh connectivity)."""
+def _moved_problem(name, nsteps, move, wave_map=None, cfg=None):
+    """The inputs of configuration name (or of cfg) with every vertex moved by
+    move(V) and the incident waves mapped by wave_map (the same mesh
+    connectivity)."""
     import fixture.problem as fp
     orig = fp.make_mesh
 
@@ -600,7 +601,7 @@ def _moved_problem(name, nsteps, move, wave_map=None):
         return move(V), F, E
     fp.make_mesh = moved_mesh
     try:
-        prob = fp.build_problem(name, nsteps=nsteps)
+        prob = fp.build_problem(name, cfg=cfg, nsteps=nsteps)
     finally:
         fp.make_mesh = orig
     if wave_map is not None:
@@ -648,3 +649,40 @@ def test_march_invariant_under_rotation_and_translation():
         assert _rel(a[m:], b[:-m]) < 1e-6, k
         assert np.abs(a[:m]).max() < 1e-6 * np.abs(b).max(), k
         assert _rel(a[m + 1:], b[:-(m + 1)]) > 1e-2, k   # one step off is not the delay
+
+
+def test_march_invariant_under_scaling(monkeypatch):
+    """Sec. III-V: the qHP unknowns are dimensionless. The RHS divides Ebar by
+    T_max (eq. (rhs)), the hat and tilde families carry T_max and 1 / T_max
+    (Sec. V-B), and the star part is scaled by T_max / dt (eq. (dis_jm)). So
+    the box s times larger, marched with s times the step and an s times
+    longer pulse (same media), gives the same w, loop and star parts. Two
+    planted mistakes in the oracle, a dropped 1 / T_max in the RHS and the hat
+    family without its T_max, each break the pin."""
+    from fixture.problem import CONFIGS
+    n, s = 40, 2.5
+    cfg = dict(CONFIGS["tiny_box"])
+    cfg_s = dict(cfg, dt=cfg["dt"] * s, sigma=cfg["sigma"] * s)
+    prob = problem("tiny_box")
+    prob_s = _moved_problem("tiny_box", n, lambda V: V * s, cfg=cfg_s)
+    ref = oracle("tiny_box").run(n)
+    big = mo.Oracle(prob_s).run(n)
+    for k in ("W", "loop", "star"):
+        assert _rel(big[k], ref[k]) < 1e-10, k
+
+    def mismatch():
+        a, b = mo.Oracle(prob_s).run(n), mo.Oracle(prob).run(n)
+        return _rel(a["W"], b["W"])
+    rhs, lag_blocks = mo.rhs, mo.lag_blocks
+
+    def rhs_without_tmax(pre, Tmax, ebar, Ebar):
+        return rhs(pre, 1.0, ebar, Ebar)
+
+    def hat_without_tmax(raw, eps_r, mu_r, Tmax, kmax, i):
+        Zh, _, Ztil = lag_blocks(raw, eps_r, mu_r, Tmax, kmax, i)
+        return Zh, lag_blocks(raw, eps_r, mu_r, 1.0, kmax, i)[1], Ztil
+    monkeypatch.setattr(mo, "rhs", rhs_without_tmax)
+    assert mismatch() > 1e-3
+    monkeypatch.setattr(mo, "rhs", rhs)
+    monkeypatch.setattr(mo, "lag_blocks", hat_without_tmax)
+    assert mismatch() > 1e-3
