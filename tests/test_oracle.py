@@ -686,3 +686,47 @@ def test_march_invariant_under_scaling(monkeypatch):
     monkeypatch.setattr(mo, "rhs", rhs)
     monkeypatch.setattr(mo, "lag_blocks", hat_without_tmax)
     assert mismatch() > 1e-3
+
+
+def test_march_dual_under_swapped_media(monkeypatch):
+    """Sec. II: the PMCHWT is symmetric under duality. Swapping eps' and mu'
+    (the interior speed stays, eta' becomes 1 / eta'; eta = 1 outside) and
+    turning the wave's polarisation from p to k x p (its magnetic field, as
+    eq. (hin) gives it) exchanges the electric and magnetic roles. With the
+    folded blocks [[q1, -qk], [qk, q2]] the marched unknowns of the second
+    problem are (v; -u) of the first, for w and for the loop and star parts
+    of eq. (dis_jm) (rounding only). A planted mistake in the oracle, the
+    magnetic half of the tested fields with the wrong sign (h_in = e_in x k),
+    breaks the pin."""
+    from fixture.problem import CONFIGS, Wave
+    n = 40
+    cfg = dict(CONFIGS["tiny_torus"])
+    pa = _torus_with_media(cfg, 3.0, 1.5, n)
+    pb = _torus_with_media(cfg, 1.5, 3.0, n)
+    pb["waves"] = [Wave(w.amp, np.cross(w.dir, w.pol), w.dir, w.width, w.t0) for w in pa["waves"]]
+    ne = pa["E"].shape[0]
+
+    def dual_errors():
+        A, B = mo.Oracle(pa).run(n), mo.Oracle(pb).run(n)
+        out = {}
+        for key in ("W", "loop", "star"):
+            a, b = A[key], B[key]
+            out[key] = (np.linalg.norm(b[:, :ne] - a[:, ne:]) + np.linalg.norm(b[:, ne:] + a[:, :ne])) / \
+                np.linalg.norm(a)
+        return out
+    for key, e in dual_errors().items():
+        assert e < 1e-10, (key, e)
+    rhs = mo.rhs
+
+    def rhs_wrong_h_sign(pre, Tmax, ebar, Ebar):
+        e, E = ebar.copy(), Ebar.copy()
+        e[ne:] *= -1
+        E[ne:] *= -1
+        return rhs(pre, Tmax, e, E)
+    monkeypatch.setattr(mo, "rhs", rhs_wrong_h_sign)
+    assert dual_errors()["W"] > 0.1
+
+
+def _torus_with_media(cfg, eps_r, mu_r, nsteps):
+    from fixture.problem import build_problem
+    return build_problem("tiny_torus", cfg=dict(cfg, eps_r=eps_r, mu_r=mu_r), nsteps=nsteps)
