@@ -41,11 +41,14 @@ def _march(prob, nsteps):
     return out
 
 
-def test_turned_and_scaled_sphere_marches_the_same():
+@pytest.mark.parametrize("name,n,scale,seed", [("sphere_480", 200, 1.7, 11),
+                                               ("sphere_1920_r16", 60, 0.6, 13)])
+def test_turned_and_scaled_sphere_marches_the_same(name, n, scale, seed):
+    """One wave on the 960-unknown sphere; 16 waves (the multi-RHS tile
+    products) on the 3840-unknown sphere."""
     from fixture.problem import CONFIGS, Wave
-    name, n, scale = "sphere_480", 200, 1.7
     print("case", name, n, scale, flush=True)
-    rng = np.random.Generator(np.random.PCG64(11))
+    rng = np.random.Generator(np.random.PCG64(seed))
     Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
     if np.linalg.det(Q) < 0:
         Q[:, 0] *= -1
