@@ -1,8 +1,9 @@
 """The GPU march against itself under the invariances the oracle is pinned
 to (MI355X only): the sphere turned and scaled, with the step, the pulse and
-the wave scaled and turned with it, marches to the same unknowns. The
-property holds at any size, so it checks the path where the oracle does not
-march."""
+the wave scaled and turned with it, marches to the same unknowns; with the
+media swapped and the wave's polarisation turned, to the dual unknowns. The
+properties hold at any size, so they check the path where the oracle does
+not march."""
 import numpy as np
 import pytest
 
@@ -60,5 +61,25 @@ def test_turned_and_scaled_sphere_marches_the_same(name, n, scale, seed):
     got = _march(prob, n)
     for k in ("w", "loop", "star"):
         e = _rel(got[k], ref[k])
+        print(k, "%.2e" % e, flush=True)
+        assert e < 1e-10, (k, e)
+
+
+def test_swapped_media_march_is_the_dual():
+    """Duality of the PMCHWT: eps' and mu' swapped and the polarisation
+    turned from p to k x p give (v; -u) of the first march, for w and the
+    loop and star parts."""
+    from fixture.problem import CONFIGS, Wave
+    name, n = "sphere_480", 150
+    print("case duality", name, n, flush=True)
+    cfg = dict(CONFIGS[name])
+    pa = _device_problem(name, dict(cfg, eps_r=3.0, mu_r=1.5), lambda V: V)
+    pb = _device_problem(name, dict(cfg, eps_r=1.5, mu_r=3.0), lambda V: V)
+    pb["waves"] = [Wave(w.amp, np.cross(w.dir, w.pol), w.dir, w.width, w.t0) for w in pa["waves"]]
+    ne = pa["E"].shape[0]
+    A, B = _march(pa, n), _march(pb, n)
+    for k in ("w", "loop", "star"):
+        a, b = A[k], B[k]
+        e = (np.linalg.norm(b[:, :ne] - a[:, ne:]) + np.linalg.norm(b[:, ne:] + a[:, :ne])) / np.linalg.norm(a)
         print(k, "%.2e" % e, flush=True)
         assert e < 1e-10, (k, e)
